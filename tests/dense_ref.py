@@ -1,0 +1,101 @@
+"""Independent dense constructions used to pin the oracle (CPU, numpy only).
+
+These build the discrete problem of Section 6.2 as ONE global linear system
+over all time levels (block lower-bidiagonal in time) and solve it with
+numpy.linalg.solve: a different computational route from the oracle's
+column-by-column Thomas march.  Only tiny grids are used.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def transport_matrix(nx, nv, nt, T):
+    """Dense matrix of the upwind x-transport acting on the interior rows
+    1..nv-1 (unknown vector ordered [row][x]).  Built from the definition of
+    (6.4)/(6.5): weight 1-|nu| on the cell itself, |nu| on the upwind cell."""
+    hx, hv, dt = 1.0 / nx, 2.0 / nv, T / nt
+    n = (nv - 1) * nx
+    B = np.zeros((n, n))
+    for i in range(1, nv):
+        v = -1.0 + i * hv
+        nu = v * dt / hx
+        for m in range(nx):
+            row = (i - 1) * nx + m
+            B[row, row] += 1.0 - abs(nu)
+            if nu > 0:
+                B[row, (i - 1) * nx + (m - 1) % nx] += abs(nu)
+            elif nu < 0:
+                B[row, (i - 1) * nx + (m + 1) % nx] += abs(nu)
+    return B
+
+
+def diffusion_matrix(nx, nv, nt, T):
+    """Dense (I - dt D_vv) on the interior rows with zero data at v = +-1."""
+    hv, dt = 2.0 / nv, T / nt
+    r = dt / hv ** 2
+    n = (nv - 1) * nx
+    A = np.zeros((n, n))
+    for i in range(1, nv):
+        for m in range(nx):
+            row = (i - 1) * nx + m
+            A[row, row] = 1.0 + 2.0 * r
+            if i - 1 >= 1:
+                A[row, (i - 2) * nx + m] = -r
+            if i + 1 <= nv - 1:
+                A[row, i * nx + m] = -r
+    return A
+
+
+def spacetime_mono(u0, f, T, nt, s=None):
+    """All time levels U^1..U^nt of the monodomain scheme from one dense
+    space-time solve of  A U^{n+1} - B U^n = dt s_{n+1} f  (n = 0..nt-1).
+    Returns an array [nt+1][nv+1][nx] (level 0 = u0 with zeroed ends)."""
+    nv, nx = u0.shape[0] - 1, u0.shape[1]
+    dt = T / nt
+    A = diffusion_matrix(nx, nv, nt, T)
+    B = transport_matrix(nx, nv, nt, T)
+    n = (nv - 1) * nx
+    N = n * nt
+    M = np.zeros((N, N))
+    rhs = np.zeros(N)
+    x0 = u0[1:nv].reshape(-1)
+    fi = f[1:nv].reshape(-1)
+    for k in range(nt):
+        M[k * n:(k + 1) * n, k * n:(k + 1) * n] = A
+        sk = 1.0 if s is None else s[k + 1]
+        rhs[k * n:(k + 1) * n] = dt * sk * fi
+        if k == 0:
+            rhs[:n] += B @ x0
+        else:
+            M[k * n:(k + 1) * n, (k - 1) * n:k * n] = -B
+    X = np.linalg.solve(M, rhs)
+    out = np.zeros((nt + 1, nv + 1, nx))
+    out[0] = u0
+    out[0, 0] = 0.0
+    out[0, -1] = 0.0
+    for k in range(nt):
+        out[k + 1, 1:nv] = X[k * n:(k + 1) * n].reshape(nv - 1, nx)
+    return out
+
+
+def interface_data(U, a, b, nv, transmission, p):
+    """Interface variables (6.7) of a glued field history U [nt+1][nv+1][nx]
+    for the partition a, b: plane 2j = Q_2 U at a_{j+1}, plane 2j+1 = Q_1 U at
+    b_j, levels 1..nt.  Q = I (Dirichlet) or Q_1 = p + d/dv, Q_2 = p - d/dv
+    with one-sided differences pointing into the subdomain that receives it."""
+    hv = 2.0 / nv
+    J = len(a)
+    nt = U.shape[0] - 1
+    nx = U.shape[2]
+    lam = np.zeros((2 * (J - 1), nt, nx))
+    for j in range(J - 1):
+        al, be = a[j + 1], b[j]
+        for n in range(1, nt + 1):
+            if transmission == 0:
+                lam[2 * j, n - 1] = U[n, al]
+                lam[2 * j + 1, n - 1] = U[n, be]
+            else:
+                lam[2 * j, n - 1] = p * U[n, al] - (U[n, al + 1] - U[n, al]) / hv
+                lam[2 * j + 1, n - 1] = p * U[n, be] + (U[n, be] - U[n, be - 1]) / hv
+    return lam
