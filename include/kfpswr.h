@@ -1,0 +1,186 @@
+/*
+ * kfpswr.h -- C ABI of libkfpswr, a gfx950 (MI355X) library for Schwarz
+ * waveform relaxation (SWR) applied to the Kolmogorov equation
+ *
+ *     u_t + v u_x - u_vv = f   on (0,T) x [0,1)_periodic x [-1,1],
+ *
+ * (Section 6.1, eq. (6.1)), with u = 0 at v = -1 and v = +1.
+ *
+ * Discrete problem (Section 6.2, read as one IMEX Euler step per dt):
+ *   h_x = 1/nx, x_m = m h_x (m = 0..nx-1); h_v = 2/nv, v_i = -1 + i h_v
+ *   (i = 0..nv); dt = T/nt.  One step maps U^n to U^{n+1}:
+ *     rhs = (1-|nu_i|) U_{i,m} + |nu_i| U_{i,m-sgn(v_i)} + dt s_{n+1} f_{i,m}
+ *           (upwind transport, eqs. (6.4)/(6.5), nu_i = v_i dt/h_x),
+ *     -r U_{i-1} + (1+2r) U_i - r U_{i+1} = rhs_i,  r = dt/h_v^2
+ *           (implicit diffusion in v, eq. (6.2)).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer unless marked [host].
+ *   - Fields are FP64, row-major [nv+1][nx] (v-node i is the row, x is
+ *     contiguous).  Rows 0 and nv of an output are zero.
+ *   - Interface traces ("lambda", eq. (6.7)) are FP64 [2(J-1)][nt][nx]:
+ *     plane 2j is the data subdomain j+1 receives at its lower node a_{j+1}
+ *     (Q_2 u_j, eq. (6.9)); plane 2j+1 is the data subdomain j receives at
+ *     its upper node b_j (Q_1 u_{j+1}, eq. (6.11)); row n-1 is time level n.
+ *   - Partition (eq. (6.6) generalised to J pieces): core cuts c_j = j nv/J;
+ *     a_0 = 0, b_{J-1} = nv; b_j = c_{j+1} + ceil(o/2), a_{j+1} = c_{j+1} -
+ *     floor(o/2), so neighbours share o cells.
+ *   - Transmission (Section 6.3): KFP_DIRICHLET is Q = I (classical SWR);
+ *     KFP_ROBIN is Q_1 = p + d/dv at b_j and Q_2 = p - d/dv at a_{j+1}
+ *     (one-sided optimized SWR, q = p, Section 6.4.1); the derivative is a
+ *     one-sided first-order difference inside the receiving subdomain.
+ *   - Iterations are the parallel (Jacobi) form of the Remark after (6.12):
+ *     iteration k reads only the traces of iteration k-1.
+ *   - The stopping test is (6.12): the largest |u_j - u_{j+1}| over the
+ *     overlap and the whole space-time window, absolute, in FP64.
+ *   - stream is a hipStream_t (NULL = the null stream).  The library owns its
+ *     workspace (state ping-pong, trace windows, tables); the caller owns all
+ *     argument buffers.  Calls on one process are serialised internally.
+ *   - Errors: every call returns a kfp_status; on failure kfp_last_error()
+ *     describes it.  KFP_EINVAL is returned before any device work.
+ */
+#ifndef KFPSWR_H
+#define KFPSWR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KFP_OK = 0,
+  KFP_EINVAL = 1,  /* invalid argument: nothing was written                  */
+  KFP_ENOMEM = 2,  /* device or host allocation failed                       */
+  KFP_EDEVICE = 3, /* a HIP call failed; message in kfp_last_error()         */
+  KFP_ENOCONV = 4  /* max_iter reached: outputs hold the last iterate        */
+} kfp_status;
+
+typedef enum { KFP_DIRICHLET = 0, KFP_ROBIN = 1 } kfp_transmission;
+
+/* The space-time grid of Section 6.2.  x in [0,1) periodic with nx cells,
+ * v in [-1,1] with nv cells (nv+1 nodes), nt steps of dt = T/nt. */
+typedef struct {
+  int32_t nx, nv, nt;
+  double T;
+} kfp_grid;
+
+/* Per-solve statistics ([host]). */
+typedef struct {
+  int32_t iters;        /* SWR iterations performed (k at the stop)          */
+  int32_t restarted;    /* 1 if a non-finite initial guess was replaced by 0 */
+  double residual;      /* r^k of the last iteration (eq. (6.12))            */
+  double seconds;       /* wall time of the call                             */
+  double device_seconds;/* device time of the iteration graphs (HIP events)  */
+  double cell_steps;    /* subdomain cell-steps executed (all iterations)    */
+  double alg_bytes;     /* algorithmic HBM bytes of those cell-steps         */
+  double *res_history;  /* [host] optional, length max_iter: r^1..r^iters   */
+} kfp_swr_stats;
+
+/*
+ * kfp_mono_solve -- the monodomain discrete solution at t = T (Section 6.2):
+ * nt steps of transport + source + implicit diffusion on rows 1..nv-1.
+ *   g:   grid (nx >= 2, nv >= 4, nt >= 1, T > 0, dt/h_x <= 1)
+ *   u0:  [nv+1][nx] initial data (rows 0 and nv are treated as 0)
+ *   f:   [nv+1][nx] source shape; the source at t_n is s[n] * f
+ *   s:   [host] nt+1 time factors s(t_n), or NULL for s = 1
+ *   uT:  [nv+1][nx] output U^nt
+ * Asynchronous on `stream`.
+ */
+kfp_status kfp_mono_solve(const kfp_grid *g, const double *u0, const double *f,
+                          const double *s, double *uT, void *stream);
+
+/*
+ * kfp_swr_solve -- parallel SWR (Section 6.3, eqs. (6.8)-(6.12)) over J
+ * subdomains split in v with an overlap of `overlap` cells.
+ *   J:           1 <= J, nv % J == 0, nv/J >= overlap + 2
+ *   overlap:     >= 1 when J > 1 (classical SWR cannot converge without it,
+ *                Section 6.5; the Robin stencil needs one cell)
+ *   tr, p:       transmission; Robin needs p > 0 (Section 2)
+ *   tol:         > 0, absolute tolerance on r^k
+ *   max_iter:    >= 1
+ *   lambda_init: [2(J-1)][nt][nx] initial traces lambda^0, or NULL for 0.
+ *                A guess holding NaN/Inf is replaced by 0 (stats.restarted).
+ *   uT:          [nv+1][nx] output: the glued iterate at t = T (node i comes
+ *                from the subdomain whose core [c_j, c_{j+1}) holds it)
+ *   lambda_out:  same shape as lambda_init (the last traces), or NULL.
+ *                Passing them back as lambda_init resumes the iteration.
+ *   stats:       [host] or NULL
+ * Returns KFP_OK when r^k < tol, KFP_ENOCONV after max_iter iterations.
+ * Synchronises with the device once per iteration (8-byte residual read).
+ */
+kfp_status kfp_swr_solve(const kfp_grid *g, const double *u0, const double *f,
+                         const double *s, int32_t J, int32_t overlap, int32_t tr, double p,
+                         double tol, int32_t max_iter, const double *lambda_init, double *uT,
+                         double *lambda_out, kfp_swr_stats *stats, void *stream);
+
+/*
+ * kfp_u0_guess -- the compatible initial traces lambda^0(n) = Q(u0) at each
+ * interface node, for every time level n (Section 2: initial guesses must
+ * agree with u0 at t = 0).  Same argument rules as kfp_swr_solve; writes
+ * lambda [2(J-1)][nt][nx].  Asynchronous.
+ */
+kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
+                        int32_t tr, double p, double *lambda, void *stream);
+
+/* One instance of a batch ([host] struct, device pointers inside). */
+typedef struct {
+  kfp_grid g;
+  int32_t J, overlap, tr;
+  double p;
+  const double *u0, *f;
+  const double *s;           /* [host] nt+1 factors or NULL */
+  const double *lambda_init; /* or NULL */
+  double *uT;
+  double *lambda_out;        /* or NULL */
+} kfp_instance;
+
+/*
+ * kfp_swr_batch -- n independent SWR instances of uneven nx, nv, J (same
+ * rules per instance as kfp_swr_solve) advanced together: every time step of
+ * every active instance runs in one persistent launch, one iteration is one
+ * captured HIP graph, and an instance stops (its buffers freeze) as soon as
+ * its own r^k < tol.  stats: [host] array of n, or NULL.
+ * Returns KFP_OK if every instance converged, KFP_ENOCONV otherwise.
+ */
+kfp_status kfp_swr_batch(int32_t n, const kfp_instance *inst, double tol, int32_t max_iter,
+                         kfp_swr_stats *stats, void *stream);
+
+/*
+ * Launch configuration of the fused step kernel.  waves = wavefronts per
+ * workgroup, each owning one contiguous segment of a subdomain's unknown
+ * rows for 64 x-columns (the segments are coupled through a small reduced
+ * tridiagonal system); seg_max = largest segment the kernel holds in
+ * registers.  kfp_tune times the candidates on the device for one shape and
+ * stores the winner in the tuning cache (file named by $KFP_TUNE_CACHE,
+ * default ~/.cache/kfpswr_tune.json); solves look the cache up.
+ * kfp_set_config forces a configuration for subsequent calls (waves = 0
+ * returns to automatic choice).
+ */
+kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, double p,
+                    int32_t *waves_out, int32_t *seg_max_out, void *stream);
+kfp_status kfp_set_config(int32_t waves, int32_t seg_max);
+kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                          int32_t *waves_out, int32_t *seg_max_out);
+
+/* Unknown rows summed over the subdomains (the cell-steps of one SWR
+ * iteration are nx * nt * rows).  [host] out. */
+kfp_status kfp_subdomain_rows(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                              int64_t *rows_out);
+
+/*
+ * kfp_bw_probe -- streaming copy of `bytes` bytes (multiple of 16) from src
+ * to dst, used to measure the attainable HBM bandwidth.  Asynchronous.
+ */
+kfp_status kfp_bw_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
+/* Frees all cached workspace (plans, graphs, trace windows). */
+void kfp_release_workspace(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *kfp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFPSWR_H */

@@ -1,0 +1,28 @@
+"""libkfpswr: Schwarz waveform relaxation for the Kolmogorov equation on MI355X.
+
+Thin Python binding over the C ABI of ``include/kfpswr.h``.  Every step of the
+method runs in the library's HIP kernels; this module only marshals torch
+tensors (device memory) and the current HIP stream into the C calls.  The
+shared library must have been built (``python -m paper_1306_4596_amd.build``);
+a missing library raises, there is no other code path.
+"""
+from __future__ import annotations
+
+from .binding import (  # noqa: F401
+    DIRICHLET,
+    ROBIN,
+    KfpError,
+    SWRStats,
+    bw_probe,
+    get_config,
+    lib_path,
+    load_library,
+    mono_solve,
+    release_workspace,
+    set_config,
+    subdomain_rows,
+    swr_batch,
+    swr_solve,
+    tune,
+    u0_guess,
+)

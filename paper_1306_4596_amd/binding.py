@@ -1,0 +1,294 @@
+"""ctypes binding of libkfpswr (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(PKG, "_lib", "libkfpswr.so")
+
+DIRICHLET = 0
+ROBIN = 1
+
+KFP_OK, KFP_EINVAL, KFP_ENOMEM, KFP_EDEVICE, KFP_ENOCONV = range(5)
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV"}
+
+
+class KfpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"kfp {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nv", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("T", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarted", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("device_seconds", ctypes.c_double), ("cell_steps", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("res_history", ctypes.POINTER(ctypes.c_double))]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("g", Grid), ("J", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("tr", ctypes.c_int32), ("p", ctypes.c_double),
+                ("u0", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("s", ctypes.POINTER(ctypes.c_double)), ("lambda_init", ctypes.c_void_p),
+                ("uT", ctypes.c_void_p), ("lambda_out", ctypes.c_void_p)]
+
+
+class SWRStats:
+    """Per-solve statistics returned by swr_solve / swr_batch."""
+
+    def __init__(self, st: Stats, history):
+        self.iters = st.iters
+        self.restarted = bool(st.restarted)
+        self.residual = st.residual
+        self.seconds = st.seconds
+        self.device_seconds = st.device_seconds
+        self.cell_steps = st.cell_steps
+        self.alg_bytes = st.alg_bytes
+        self.res_history = history
+
+    def __repr__(self):
+        return (f"SWRStats(iters={self.iters}, residual={self.residual:.3e}, "
+                f"seconds={self.seconds:.4f}, device_seconds={self.device_seconds:.4f})")
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Loads the built HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            f"libkfpswr is not built ({_LIB_PATH} missing); run "
+            "`python -m paper_1306_4596_amd.build` (needs hipcc for gfx950)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    G = ctypes.POINTER(Grid)
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.kfp_mono_solve.argtypes = [G, vp, vp, D, vp, vp]
+    lib.kfp_swr_solve.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, i32, vp, vp, vp,
+                                  ctypes.POINTER(Stats), vp]
+    lib.kfp_u0_guess.argtypes = [G, vp, i32, i32, i32, f64, vp, vp]
+    lib.kfp_swr_batch.argtypes = [i32, ctypes.POINTER(Instance), f64, i32,
+                                  ctypes.POINTER(Stats), vp]
+    lib.kfp_tune.argtypes = [G, i32, i32, i32, f64, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.kfp_set_config.argtypes = [i32, i32]
+    lib.kfp_get_config.argtypes = [G, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.kfp_subdomain_rows.argtypes = [G, i32, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.kfp_bw_probe.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.kfp_last_error.restype = ctypes.c_char_p
+    lib.kfp_last_error.argtypes = []
+    lib.kfp_release_workspace.restype = None
+    for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_u0_guess", "kfp_swr_batch", "kfp_tune",
+                 "kfp_set_config", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st, allow_noconv=False):
+    if st == KFP_OK or (allow_noconv and st == KFP_ENOCONV):
+        return st
+    msg = load_library().kfp_last_error().decode(errors="replace")
+    raise KfpError(st, msg)
+
+
+def _grid(nx, nv, nt, T):
+    return Grid(int(nx), int(nv), int(nt), float(T))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError("tensors must live on the GPU")
+    if t.dtype != torch.float64:
+        raise ValueError("tensors must be float64")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host_s(s, nt):
+    if s is None:
+        return None, None
+    import numpy as np
+
+    arr = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
+    if arr.shape != (nt + 1,):
+        raise ValueError(f"s must have nt+1 = {nt + 1} entries")
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _shape(u0):
+    if u0.dim() != 2:
+        raise ValueError("fields are [nv+1][nx]")
+    return u0.shape[0] - 1, u0.shape[1]
+
+
+def mono_solve(u0, f, T, nt, s=None, out=None, stream=None):
+    """Monodomain discrete solution at t = T ([nv+1][nx] float64 on the GPU)."""
+    import torch
+
+    nv, nx = _shape(u0)
+    uT = out if out is not None else torch.empty_like(u0)
+    keep, sp = _host_s(s, nt)
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_mono_solve(ctypes.byref(g), _ptr(u0), _ptr(f), sp, _ptr(uT),
+                                         _stream(stream)))
+    return uT
+
+
+def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter=200,
+              lambda_init=None, s=None, want_lambda=False, history=True, stream=None,
+              raise_noconv=False):
+    """Parallel SWR solve.  Returns (uT, lambda or None, SWRStats)."""
+    import numpy as np
+    import torch
+
+    nv, nx = _shape(u0)
+    uT = torch.empty_like(u0)
+    lam = None
+    if want_lambda and J > 1:
+        lam = torch.empty((2 * (J - 1), nt, nx), dtype=torch.float64, device=u0.device)
+    keep, sp = _host_s(s, nt)
+    hist = np.zeros(max_iter) if history else None
+    st = Stats()
+    if hist is not None:
+        st.res_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    g = _grid(nx, nv, nt, T)
+    rc = load_library().kfp_swr_solve(ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J),
+                                      int(overlap), int(transmission), float(p), float(tol),
+                                      int(max_iter), _ptr(lambda_init), _ptr(uT), _ptr(lam),
+                                      ctypes.byref(st), _stream(stream))
+    _check(rc, allow_noconv=not raise_noconv)
+    h = hist[: st.iters].copy() if hist is not None else None
+    return uT, lam, SWRStats(st, h)
+
+
+def u0_guess(u0, nt, J, overlap, transmission, p=0.0, stream=None):
+    """Initial traces Q(u0) at every interface node and time level."""
+    import torch
+
+    nv, nx = _shape(u0)
+    lam = torch.empty((2 * (J - 1), nt, nx), dtype=torch.float64, device=u0.device)
+    g = _grid(nx, nv, nt, 0.5 * nt / nx)  # the traces do not depend on T; any CFL-valid T
+    _check(load_library().kfp_u0_guess(ctypes.byref(g), _ptr(u0), int(J), int(overlap),
+                                       int(transmission), float(p), _ptr(lam), _stream(stream)))
+    return lam
+
+
+def swr_batch(instances, tol=1e-10, max_iter=200, history=False, stream=None):
+    """Batched SWR.  `instances` is a list of dicts with keys u0, f, T, nt, J,
+    overlap, tr, p and optionally s, lambda_init, want_lambda.  Returns a list
+    of (uT, lambda or None, SWRStats) and the overall status (0 or 4)."""
+    import numpy as np
+    import torch
+
+    n = len(instances)
+    arr = (Instance * n)()
+    keep = []
+    outs = []
+    stats = (Stats * n)()
+    hists = []
+    for i, d in enumerate(instances):
+        u0, f = d["u0"], d["f"]
+        nv, nx = _shape(u0)
+        nt, J = int(d["nt"]), int(d["J"])
+        uT = torch.empty_like(u0)
+        lam = None
+        if d.get("want_lambda") and J > 1:
+            lam = torch.empty((2 * (J - 1), nt, nx), dtype=torch.float64, device=u0.device)
+        sarr, sp = _host_s(d.get("s"), nt)
+        keep.append(sarr)
+        arr[i].g = _grid(nx, nv, nt, d["T"])
+        arr[i].J = J
+        arr[i].overlap = int(d["overlap"])
+        arr[i].tr = int(d["tr"])
+        arr[i].p = float(d.get("p", 0.0))
+        arr[i].u0 = _ptr(u0).value
+        arr[i].f = _ptr(f).value
+        arr[i].s = sp
+        li = d.get("lambda_init")
+        arr[i].lambda_init = _ptr(li).value if li is not None else None
+        arr[i].uT = _ptr(uT).value
+        arr[i].lambda_out = _ptr(lam).value if lam is not None else None
+        h = np.zeros(max_iter) if history else None
+        if h is not None:
+            stats[i].res_history = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        hists.append(h)
+        outs.append((uT, lam))
+    rc = load_library().kfp_swr_batch(n, arr, float(tol), int(max_iter), stats, _stream(stream))
+    _check(rc, allow_noconv=True)
+    res = []
+    for i in range(n):
+        h = hists[i][: stats[i].iters].copy() if hists[i] is not None else None
+        res.append((outs[i][0], outs[i][1], SWRStats(stats[i], h)))
+    return res, rc
+
+
+def tune(nx, nv, nt, T, J, overlap, transmission, p=1.0, stream=None):
+    """Times the compiled launch configurations for one shape; caches the winner."""
+    w, s = ctypes.c_int32(), ctypes.c_int32()
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_tune(ctypes.byref(g), int(J), int(overlap), int(transmission),
+                                   float(p), ctypes.byref(w), ctypes.byref(s), _stream(stream)))
+    return w.value, s.value
+
+
+def set_config(waves=0, seg_max=0):
+    """Forces a step-kernel configuration (waves=0: automatic)."""
+    _check(load_library().kfp_set_config(int(waves), int(seg_max)))
+
+
+def get_config(nx, nv, nt, T, J, overlap, transmission):
+    w, s = ctypes.c_int32(), ctypes.c_int32()
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_get_config(ctypes.byref(g), int(J), int(overlap), int(transmission),
+                                         ctypes.byref(w), ctypes.byref(s)))
+    return w.value, s.value
+
+
+def subdomain_rows(nx, nv, nt, T, J, overlap, transmission):
+    r = ctypes.c_int64()
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_subdomain_rows(ctypes.byref(g), int(J), int(overlap),
+                                             int(transmission), ctypes.byref(r)))
+    return r.value
+
+
+def bw_probe(src, dst, stream=None):
+    nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
+    nbytes -= nbytes % 16
+    _check(load_library().kfp_bw_probe(ctypes.c_void_p(src.data_ptr()),
+                                       ctypes.c_void_p(dst.data_ptr()), int(nbytes),
+                                       _stream(stream)))
+    return nbytes
+
+
+def release_workspace():
+    load_library().kfp_release_workspace()

@@ -1,0 +1,110 @@
+// Internal data structures shared by the host runtime and the gfx950 kernels
+// of libkfpswr.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace kfp {
+
+// How one end of a subdomain's unknown rows meets the outside.
+enum EndKind : int {
+  END_PHYS = 0,  // v = -1 or v = +1: zero Dirichlet data
+  END_DIRI = 1,  // classical interface: the neighbour's trace is a fixed node
+  END_ROBIN = 2  // optimized interface: the end row is a Robin row
+};
+
+// One SWR instance, resident in device memory.  All pointers are device
+// pointers; lam[0]/lam[1] are the two trace windows (read k-1 / write k).
+struct InstDev {
+  double *U[2];                 // state ping-pong: rows of all subdomains, [rows][nx]
+  const double *u0;             // [nv+1][nx]
+  const double *f;              // [nv+1][nx]
+  const double *g;              // [nt]: dt * s(t_{n+1})
+  double *lam[2];               // [2(J-1)][nt][nx] each
+  unsigned long long *res;      // residual of the running iteration (bits of a double >= 0)
+  double r;                     // dt / h_v^2
+  double p, q;                  // Robin parameters (q = p)
+  double hv;                    // h_v
+  int nx, nv, nt, tr;
+  int active;                   // 0: frozen (converged), skipped by every kernel
+  int pad_;
+};
+
+// One subdomain of one instance.  Rows are local: 0 .. n-1 are the unknown
+// rows, row 0 has the smallest v.  Planes index the instance's trace window.
+struct SubDev {
+  int inst;
+  int n;            // unknown rows
+  int row_off;      // first row in InstDev::U
+  int g_lo;         // global v-node of local row 0
+  int tab;          // first RowCoef of this subdomain
+  int seg;          // first entry of the segment-start table (P+1 ints)
+  int red;          // first RedCoef (P-1 entries)
+  int P;            // row segments (one wavefront each)
+  int lo_kind, hi_kind;      // EndKind of row 0 / row n-1
+  int lam_lo, lam_hi;        // incoming planes for the two ends (-1: none)
+  int out_lo_plane, out_lo_row;  // trace Q_1 u at b_{j-1}: plane, local row of b_{j-1}
+  int out_hi_plane, out_hi_row;  // trace Q_2 u at a_{j+1}: plane, local row of a_{j+1}
+  int res_nb;         // subdomain index of the upper neighbour (-1: no interface above)
+  int res_row_a_nb;   // local row of a_{j+1} in the neighbour, -1: fixed node (use plane)
+  int res_row_b_self; // local row of b_j here, -1: fixed node (use plane)
+  int res_row_b_nb;   // local row of b_j in the neighbour
+  int res_plane_a, res_plane_b;  // planes holding the fixed-node values (Dirichlet)
+};
+
+// Per unknown row: transport weight and the factors of the local (segment)
+// Thomas elimination and the two spike vectors of the segment partition.
+struct RowCoef {
+  double nu;  // signed Courant number v_i dt / h_x
+  double fa;  // 1 / pivot
+  double fb;  // -sub / pivot (multiplies the previous forward value)
+  double bc;  // -c' (multiplies the next backward value)
+  double sl;  // spike: response of the segment to its lower separator
+  double sr;  // spike: response of the segment to its upper separator
+};
+
+// Per separator row of the reduced system.
+struct RedCoef {
+  double ra;  // sub-diagonal coefficient of the separator row
+  double rc;  // super-diagonal coefficient of the separator row
+  double g1;  // 1 / pivot of the reduced elimination
+  double g2;  // -alpha / pivot
+  double h;   // -gamma'
+};
+
+// A workgroup's unit of work: subdomain `sub`, x-columns x0 .. x0+63.
+struct Item {
+  int sub;
+  int x0;
+};
+
+struct StepTables {
+  const InstDev *inst;
+  const SubDev *subs;
+  const Item *items;
+  const RowCoef *rows;
+  const RedCoef *reds;
+  const int *segs;
+  int n_items;
+};
+
+// Kernel launchers (swr_kernels.hip).  Return hipSuccess or the launch error.
+// Step launch n: traces and residual of level n (1 <= n <= nt), then the step
+// n -> n+1 (n < nt), for every item; par selects the trace window read.
+hipError_t launch_step(const StepTables &t, int waves, int seg_max, int n, int par, int grid,
+                       hipStream_t s);
+bool step_config_supported(int waves, int seg_max);
+hipError_t launch_reset_res(const InstDev *inst, int n_inst, hipStream_t s);
+hipError_t launch_assemble(const double *Ufinal, const int *rowmap, double *uT, int nv, int nx,
+                           hipStream_t s);
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
+hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_count_nonfinite(const double *p, size_t n, unsigned int *count, hipStream_t s);
+// ab: device [J-1][2] = (a_{j+1}, b_j) per interface.
+hipError_t launch_u0_guess(const double *u0, int nx, int nt, int J, const int *ab, int tr,
+                           double p, double hv, double *lam, hipStream_t s);
+hipError_t launch_bw_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace kfp

@@ -1,0 +1,1287 @@
+// Host runtime of libkfpswr: argument validation, the planner (partition,
+// elimination tables, workspace), the SWR iteration driver with HIP-graph
+// captured iterations, the batch scheduler and the launch-configuration
+// tuner.  Exposes the C ABI declared in include/kfpswr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kfpswr.h"
+#include "../../include/kfpswr_debug.h"
+#include "kfp_internal.h"
+
+namespace kfp {
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string g_err;
+
+static kfp_status fail(kfp_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? KFP_ENOMEM : KFP_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+static std::recursive_mutex g_mu;
+
+// ---------------------------------------------------------------- geometry --
+struct SubGeo {
+  int a, b;    // node range [a_j, b_j]
+  int lo, hi;  // unknown nodes
+  int n;
+  int lo_kind, hi_kind;
+};
+
+struct Geo {
+  int nx, nv, nt, J, o, tr;
+  double T;
+  std::vector<SubGeo> sub;
+  std::vector<int> row_off;
+  std::vector<int> rowmap;  // [nv+1]: absolute row in U of the node's owner, -1 = zero
+  int rows = 0;
+  int n_max = 0;
+};
+
+static kfp_status validate_grid(const kfp_grid *g) {
+  if (!g) return fail(KFP_EINVAL, "grid is NULL");
+  if (g->nx < 2) return fail(KFP_EINVAL, "nx must be >= 2 (got %d)", g->nx);
+  if (g->nv < 4) return fail(KFP_EINVAL, "nv must be >= 4 (got %d)", g->nv);
+  if (g->nt < 1) return fail(KFP_EINVAL, "nt must be >= 1 (got %d)", g->nt);
+  if (!(g->T > 0.0) || !std::isfinite(g->T)) return fail(KFP_EINVAL, "T must be > 0");
+  const double hx = 1.0 / g->nx, dt = g->T / g->nt;
+  // the largest |v| on a transported row is 1 - h_v; the bound is taken over
+  // every node (|v| <= 1), i.e. dt <= h_x, so the upwind weights stay convex
+  if (dt / hx > 1.0 + 1e-12)
+    return fail(KFP_EINVAL, "CFL violated: dt/h_x = %g > 1", dt / hx);
+  return KFP_OK;
+}
+
+static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Geo &geo) {
+  kfp_status st = validate_grid(g);
+  if (st) return st;
+  if (J < 1) return fail(KFP_EINVAL, "J must be >= 1 (got %d)", J);
+  if (tr != KFP_DIRICHLET && tr != KFP_ROBIN) return fail(KFP_EINVAL, "unknown transmission %d", tr);
+  if (g->nv % J) return fail(KFP_EINVAL, "nv %% J != 0 (nv=%d, J=%d)", g->nv, J);
+  if (o < 0) return fail(KFP_EINVAL, "overlap must be >= 0");
+  if (J > 1) {
+    if (o < 1)
+      return fail(KFP_EINVAL, "overlap must be >= 1 for J > 1 (classical SWR does not converge "
+                              "without overlap; the Robin stencil needs one cell)");
+    if (g->nv / J < o + 2) return fail(KFP_EINVAL, "nv/J must be >= overlap + 2");
+    if (tr == KFP_ROBIN && !(p > 0.0 && std::isfinite(p)))
+      return fail(KFP_EINVAL, "Robin parameter p must be > 0 (got %g)", p);
+  }
+  geo.nx = g->nx;
+  geo.nv = g->nv;
+  geo.nt = g->nt;
+  geo.T = g->T;
+  geo.J = J;
+  geo.o = o;
+  geo.tr = tr;
+  const int w = g->nv / J;
+  std::vector<int> a(J), b(J);
+  a[0] = 0;
+  b[J - 1] = g->nv;
+  for (int j = 0; j + 1 < J; ++j) {
+    const int c = (j + 1) * w;
+    b[j] = c + (o + 1) / 2;
+    a[j + 1] = c - o / 2;
+  }
+  geo.sub.resize(J);
+  geo.row_off.resize(J);
+  geo.rows = 0;
+  geo.n_max = 0;
+  for (int j = 0; j < J; ++j) {
+    SubGeo &s = geo.sub[j];
+    s.a = a[j];
+    s.b = b[j];
+    s.lo_kind = j == 0 ? END_PHYS : (tr == KFP_ROBIN ? END_ROBIN : END_DIRI);
+    s.hi_kind = j == J - 1 ? END_PHYS : (tr == KFP_ROBIN ? END_ROBIN : END_DIRI);
+    s.lo = s.lo_kind == END_ROBIN ? s.a : s.a + 1;
+    s.hi = s.hi_kind == END_ROBIN ? s.b : s.b - 1;
+    s.n = s.hi - s.lo + 1;
+    geo.row_off[j] = geo.rows;
+    geo.rows += s.n;
+    geo.n_max = std::max(geo.n_max, s.n);
+  }
+  geo.rowmap.assign(g->nv + 1, -1);
+  for (int i = 1; i < g->nv; ++i) {
+    int j = std::min(J - 1, i / w);
+    if (j > 0 && i == geo.sub[j].a && tr == KFP_DIRICHLET) j -= 1;
+    const SubGeo &s = geo.sub[j];
+    geo.rowmap[i] = geo.row_off[j] + (i - s.lo);
+  }
+  return KFP_OK;
+}
+
+// ---------------------------------------------------------- launch config --
+struct Config {
+  int waves = 0;
+  int seg = 0;
+};
+
+static const int kWaves[] = {1, 2, 4, 8, 16};
+static const int kSegs[] = {8, 16, 24, 32, 48, 64};
+
+static int segs_for(int n, int waves) {
+  const int P = std::max(1, std::min(waves, n / 2));
+  return (n + P - 1) / P;
+}
+
+// Smallest compiled seg_max holding every subdomain with `waves` segments;
+// 0 selects the global-staged variant.
+static int seg_for(int n_max, int waves) {
+  const int need = segs_for(n_max, waves);
+  for (int s : kSegs)
+    if (s >= need && step_config_supported(waves, s)) return s;
+  return 0;
+}
+
+static Config default_config(int n_max) {
+  Config c;
+  for (int w : kWaves) {
+    if (segs_for(n_max, w) <= 24 || w == 16) {
+      c.waves = w;
+      break;
+    }
+  }
+  c.seg = seg_for(n_max, c.waves);
+  return c;
+}
+
+static Config g_forced;  // waves == 0: automatic
+
+// Tuning cache: a flat JSON object {"key": [waves, seg], ...}.
+static std::string tune_path() {
+  const char *e = getenv("KFP_TUNE_CACHE");
+  if (e && *e) return e;
+  const char *h = getenv("HOME");
+  return std::string(h ? h : ".") + "/.cache/kfpswr_tune.json";
+}
+
+static std::map<std::string, Config> load_tune() {
+  std::map<std::string, Config> out;
+  FILE *fp = fopen(tune_path().c_str(), "r");
+  if (!fp) return out;
+  std::string s;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, fp)) > 0) s.append(buf, k);
+  fclose(fp);
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    size_t e = s.find('"', pos + 1);
+    if (e == std::string::npos) break;
+    std::string key = s.substr(pos + 1, e - pos - 1);
+    Config c;
+    if (sscanf(s.c_str() + e + 1, " : [ %d , %d ]", &c.waves, &c.seg) == 2 &&
+        step_config_supported(c.waves, c.seg))
+      out[key] = c;
+    pos = e + 1;
+  }
+  return out;
+}
+
+static void save_tune(const std::map<std::string, Config> &m) {
+  const std::string path = tune_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+    if (system(cmd.c_str()) != 0) return;
+  }
+  std::string tmp = path + ".tmp";
+  FILE *fp = fopen(tmp.c_str(), "w");
+  if (!fp) return;
+  fprintf(fp, "{\n");
+  size_t i = 0;
+  for (auto &kv : m)
+    fprintf(fp, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.seg,
+            ++i < m.size() ? "," : "");
+  fprintf(fp, "}\n");
+  fclose(fp);
+  rename(tmp.c_str(), path.c_str());
+}
+
+static std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static std::string tune_key(const Geo &g) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/nx%d/nmax%d/J%d/tr%d", arch_name().c_str(), g.nx, g.n_max, g.J,
+           g.tr);
+  return buf;
+}
+
+static std::map<std::string, Config> *g_tune = nullptr;
+
+static Config choose_config(const Geo &g) {
+  if (g_forced.waves > 0) {
+    Config c = g_forced;
+    if (c.seg > 0 && segs_for(g.n_max, c.waves) > c.seg) c.seg = seg_for(g.n_max, c.waves);
+    return c;
+  }
+  if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
+  auto it = g_tune->find(tune_key(g));
+  if (it != g_tune->end() && (it->second.seg == 0 || segs_for(g.n_max, it->second.waves) <= it->second.seg))
+    return it->second;
+  return default_config(g.n_max);
+}
+
+// ------------------------------------------------------------------ tables --
+struct HostTables {
+  std::vector<SubDev> subs;
+  std::vector<RowCoef> rows;
+  std::vector<RedCoef> reds;
+  std::vector<int> segs;
+  std::vector<Item> items;
+};
+
+// Row coefficients of subdomain s (local rows 0..n-1):  lo x_{k-1} + di x_k + up x_{k+1}.
+static void row_matrix(const SubGeo &s, double r, double p, double q, double hv,
+                       std::vector<double> &lo, std::vector<double> &di, std::vector<double> &up) {
+  lo.assign(s.n, -r);
+  di.assign(s.n, 1.0 + 2.0 * r);
+  up.assign(s.n, -r);
+  if (s.lo_kind == END_ROBIN) {  // (q - d/dv) u = lambda at the lower interface node
+    lo[0] = 0.0;
+    di[0] = q + 1.0 / hv;
+    up[0] = -1.0 / hv;
+  }
+  if (s.hi_kind == END_ROBIN) {  // (p + d/dv) u = lambda at the upper interface node
+    lo[s.n - 1] = -1.0 / hv;
+    di[s.n - 1] = p + 1.0 / hv;
+    up[s.n - 1] = 0.0;
+  }
+}
+
+// Appends the tables of one subdomain (partitioned into P segments).
+static void add_subdomain(const Geo &g, int j, double p, int waves, int inst, int sub_base,
+                          HostTables &t) {
+  const SubGeo &s = g.sub[j];
+  const double hx = 1.0 / g.nx, hv = 2.0 / g.nv, dt = g.T / g.nt, r = dt / (hv * hv);
+  const double q = p;
+  const int n = s.n;
+  const int P = std::max(1, std::min(waves, n / 2));
+  std::vector<double> lo, di, up;
+  row_matrix(s, r, p, q, hv, lo, di, up);
+
+  SubDev d{};
+  d.inst = inst;
+  d.n = n;
+  d.row_off = g.row_off[j];
+  d.g_lo = s.lo;
+  d.tab = (int)t.rows.size();
+  d.seg = (int)t.segs.size();
+  d.red = (int)t.reds.size();
+  d.P = P;
+  d.lo_kind = s.lo_kind;
+  d.hi_kind = s.hi_kind;
+  d.lam_lo = j > 0 ? 2 * (j - 1) : -1;
+  d.lam_hi = j < g.J - 1 ? 2 * j + 1 : -1;
+  d.out_hi_plane = j < g.J - 1 ? 2 * j : -1;
+  d.out_hi_row = j < g.J - 1 ? g.sub[j + 1].a - s.lo : -1;
+  d.out_lo_plane = j > 0 ? 2 * (j - 1) + 1 : -1;
+  d.out_lo_row = j > 0 ? g.sub[j - 1].b - s.lo : -1;
+  if (j < g.J - 1) {
+    const SubGeo &nb = g.sub[j + 1];
+    d.res_nb = sub_base + j + 1;
+    d.res_row_a_nb = nb.lo_kind == END_ROBIN ? nb.a - nb.lo : -1;
+    d.res_row_b_self = s.hi_kind == END_ROBIN ? s.b - s.lo : -1;
+    d.res_row_b_nb = s.b - nb.lo;
+    d.res_plane_a = 2 * j;
+    d.res_plane_b = 2 * j + 1;
+  } else {
+    d.res_nb = -1;
+    d.res_row_a_nb = d.res_row_b_self = d.res_row_b_nb = -1;
+    d.res_plane_a = d.res_plane_b = -1;
+  }
+  t.subs.push_back(d);
+
+  // segments: P nearly equal pieces; every piece but the last ends with a
+  // separator row
+  std::vector<int> start(P + 1);
+  start[0] = 0;
+  for (int k = 0; k < P; ++k) start[k + 1] = start[k] + n / P + (k < n % P ? 1 : 0);
+  for (int k = 0; k <= P; ++k) t.segs.push_back(start[k]);
+
+  std::vector<RowCoef> rc(n);
+  for (int k = 0; k < n; ++k) {
+    const double v = -1.0 + (s.lo + k) * hv;
+    rc[k].nu = v * dt / hx;
+  }
+  // local Thomas factors and spikes per block
+  std::vector<std::vector<double>> gL(P), gR(P);
+  for (int sgi = 0; sgi < P; ++sgi) {
+    const int r0 = start[sgi];
+    const int r1 = (sgi < P - 1) ? start[sgi + 1] - 2 : n - 1;  // last block row
+    const int nb = r1 - r0 + 1;
+    std::vector<double> cp(nb), piv(nb);
+    for (int k = 0; k < nb; ++k) {
+      const int i = r0 + k;
+      piv[k] = (k == 0) ? di[i] : di[i] - lo[i] * cp[k - 1];
+      cp[k] = (k < nb - 1) ? up[i] / piv[k] : 0.0;
+      rc[i].fa = 1.0 / piv[k];
+      rc[i].fb = (k == 0) ? 0.0 : -lo[i] / piv[k];
+      rc[i].bc = (k < nb - 1) ? -cp[k] : 0.0;
+    }
+    auto solve = [&](std::vector<double> rhs) {
+      std::vector<double> y(nb), x(nb);
+      for (int k = 0; k < nb; ++k) {
+        const int i = r0 + k;
+        y[k] = (k == 0 ? rhs[k] : rhs[k] - lo[i] * y[k - 1]) / piv[k];
+      }
+      for (int k = nb - 1; k >= 0; --k) x[k] = (k == nb - 1) ? y[k] : y[k] - cp[k] * x[k + 1];
+      return x;
+    };
+    std::vector<double> e(nb, 0.0);
+    gL[sgi].assign(nb, 0.0);
+    gR[sgi].assign(nb, 0.0);
+    if (sgi > 0) {
+      e.assign(nb, 0.0);
+      e[0] = lo[r0];
+      gL[sgi] = solve(e);
+    }
+    if (sgi < P - 1) {
+      e.assign(nb, 0.0);
+      e[nb - 1] = up[r1];
+      gR[sgi] = solve(e);
+    }
+    for (int k = 0; k < nb; ++k) {
+      rc[r0 + k].sl = gL[sgi][k];
+      rc[r0 + k].sr = gR[sgi][k];
+    }
+    if (sgi < P - 1) {  // separator row: not part of the block elimination
+      RowCoef &c = rc[r1 + 1];
+      c.fa = c.fb = c.bc = c.sl = c.sr = 0.0;
+    }
+  }
+  for (int k = 0; k < n; ++k) t.rows.push_back(rc[k]);
+
+  // reduced tridiagonal system over the P-1 separators
+  if (P > 1) {
+    const int m = P - 1;
+    std::vector<double> al(m), be(m), ga(m);
+    for (int sgi = 0; sgi < m; ++sgi) {
+      const int rho = start[sgi + 1] - 1;
+      const double a_r = lo[rho], c_r = up[rho];
+      const double gLs_end = gL[sgi].back(), gRs_end = gR[sgi].back();
+      const double gL1_first = gL[sgi + 1].front(), gR1_first = gR[sgi + 1].front();
+      al[sgi] = -a_r * gLs_end;
+      be[sgi] = di[rho] - a_r * gRs_end - c_r * gL1_first;
+      ga[sgi] = -c_r * gR1_first;
+      RedCoef c{};
+      c.ra = a_r;
+      c.rc = c_r;
+      t.reds.push_back(c);
+    }
+    double cprev = 0.0;
+    for (int sgi = 0; sgi < m; ++sgi) {
+      const double piv = (sgi == 0) ? be[0] : be[sgi] - al[sgi] * cprev;
+      const double cpk = (sgi < m - 1) ? ga[sgi] / piv : 0.0;
+      RedCoef &c = t.reds[d.red + sgi];
+      c.g1 = 1.0 / piv;
+      c.g2 = (sgi == 0) ? 0.0 : -al[sgi] / piv;
+      c.h = -cpk;
+      cprev = cpk;
+    }
+  }
+}
+
+static void add_instance(const Geo &g, double p, int waves, int inst, HostTables &t) {
+  const int sub_base = (int)t.subs.size();
+  for (int j = 0; j < g.J; ++j) add_subdomain(g, j, p, waves, inst, sub_base, t);
+}
+
+static void make_items(const Geo &g, int sub_base, std::vector<Item> &items) {
+  // subdomain-fastest order: consecutive workgroups (and so the XCDs they are
+  // dealt to round-robin) take different subdomains of the same x-range
+  const int tiles = (g.nx + 63) / 64;
+  for (int x = 0; x < tiles; ++x)
+    for (int j = 0; j < g.J; ++j) items.push_back(Item{sub_base + j, x * 64});
+}
+
+// ------------------------------------------------------------------ device --
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  hipError_t alloc(size_t count) {
+    if (count <= n && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Device tables of one launch set (single instance or batch).
+struct DevTables {
+  DevBuf<InstDev> inst;
+  DevBuf<SubDev> subs;
+  DevBuf<Item> items;
+  DevBuf<RowCoef> rows;
+  DevBuf<RedCoef> reds;
+  DevBuf<int> segs;
+  StepTables view() const {
+    StepTables t;
+    t.inst = inst.p;
+    t.subs = subs.p;
+    t.items = items.p;
+    t.rows = rows.p;
+    t.reds = reds.p;
+    t.segs = segs.p;
+    t.n_items = (int)items.n;
+    return t;
+  }
+  hipError_t upload(const HostTables &h, const std::vector<InstDev> &in, hipStream_t s) {
+    hipError_t e;
+    if ((e = inst.alloc(in.size())) != hipSuccess) return e;
+    if ((e = subs.alloc(h.subs.size())) != hipSuccess) return e;
+    if ((e = items.alloc(h.items.size())) != hipSuccess) return e;
+    if ((e = rows.alloc(h.rows.size())) != hipSuccess) return e;
+    if ((e = reds.alloc(std::max<size_t>(h.reds.size(), 1))) != hipSuccess) return e;
+    if ((e = segs.alloc(h.segs.size())) != hipSuccess) return e;
+    items.n = h.items.size();
+    auto cp = [&](void *d, const void *src, size_t bytes) {
+      return bytes ? hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    if ((e = cp(inst.p, in.data(), in.size() * sizeof(InstDev))) != hipSuccess) return e;
+    if ((e = cp(subs.p, h.subs.data(), h.subs.size() * sizeof(SubDev))) != hipSuccess) return e;
+    if ((e = cp(items.p, h.items.data(), h.items.size() * sizeof(Item))) != hipSuccess) return e;
+    if ((e = cp(rows.p, h.rows.data(), h.rows.size() * sizeof(RowCoef))) != hipSuccess) return e;
+    if ((e = cp(reds.p, h.reds.data(), h.reds.size() * sizeof(RedCoef))) != hipSuccess) return e;
+    if ((e = cp(segs.p, h.segs.data(), h.segs.size() * sizeof(int))) != hipSuccess) return e;
+    return hipStreamSynchronize(s);  // host vectors may go out of scope
+  }
+  void release() {
+    inst.release();
+    subs.release();
+    items.release();
+    rows.release();
+    reds.release();
+    segs.release();
+  }
+};
+
+static bool use_graphs() {
+  const char *e = getenv("KFP_NO_GRAPH");
+  return !(e && *e && *e != '0');
+}
+
+// A cached single-instance workspace.  The graphs capture kernel launches
+// whose arguments point at device tables only, so later calls with other
+// data pointers, p, T or s refresh the tables and reuse the graphs.
+struct Plan {
+  Geo geo;
+  Config cfg;
+  DevTables dt;
+  DevBuf<double> U0, U1, lam0, lam1, g;
+  DevBuf<int> rowmap, ab;
+  DevBuf<unsigned long long> res;
+  DevBuf<unsigned int> cnt;
+  unsigned long long *h_res = nullptr;  // pinned
+  hipStream_t cs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool captured = false;
+  ~Plan() {
+    for (auto &ge : gexec)
+      if (ge) (void)hipGraphExecDestroy(ge);
+    dt.release();
+    U0.release();
+    U1.release();
+    lam0.release();
+    lam1.release();
+    g.release();
+    rowmap.release();
+    ab.release();
+    res.release();
+    cnt.release();
+    if (h_res) (void)hipHostFree(h_res);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+static std::map<std::string, std::unique_ptr<Plan>> g_plans;
+static std::vector<std::string> g_plan_lru;
+static const size_t kMaxPlans = 3;
+
+static std::string plan_key(const Geo &g, const Config &c) {
+  char buf[200];
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/s%d", g.nx, g.nv, g.nt, g.J, g.o, g.tr, c.waves,
+           c.seg);
+  return buf;
+}
+
+static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
+  const std::string key = plan_key(geo, cfg);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    g_plan_lru.erase(std::find(g_plan_lru.begin(), g_plan_lru.end(), key));
+    g_plan_lru.push_back(key);
+    *out = it->second.get();
+    return KFP_OK;
+  }
+  while (g_plans.size() >= kMaxPlans) {
+    g_plans.erase(g_plan_lru.front());
+    g_plan_lru.erase(g_plan_lru.begin());
+  }
+  std::unique_ptr<Plan> pl(new Plan());
+  pl->geo = geo;
+  pl->cfg = cfg;
+  const size_t state = (size_t)geo.rows * geo.nx;
+  const size_t win = (size_t)2 * (geo.J - 1) * geo.nt * geo.nx;
+  HIP_TRY(pl->U0.alloc(state));
+  HIP_TRY(pl->U1.alloc(state));
+  HIP_TRY(pl->lam0.alloc(std::max<size_t>(win, 1)));
+  HIP_TRY(pl->lam1.alloc(std::max<size_t>(win, 1)));
+  HIP_TRY(pl->g.alloc(geo.nt));
+  HIP_TRY(pl->rowmap.alloc(geo.nv + 1));
+  HIP_TRY(pl->ab.alloc(std::max(2 * (geo.J - 1), 1)));
+  HIP_TRY(pl->res.alloc(1));
+  HIP_TRY(pl->cnt.alloc(1));
+  HIP_TRY(hipHostMalloc((void **)&pl->h_res, sizeof(unsigned long long)));
+  HIP_TRY(hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+  HIP_TRY(hipEventCreate(&pl->ev0));
+  HIP_TRY(hipEventCreate(&pl->ev1));
+  HIP_TRY(hipMemcpy(pl->rowmap.p, geo.rowmap.data(), sizeof(int) * (geo.nv + 1),
+                    hipMemcpyHostToDevice));
+  std::vector<int> ab;
+  for (int j = 0; j + 1 < geo.J; ++j) {
+    ab.push_back(geo.sub[j + 1].a);
+    ab.push_back(geo.sub[j].b);
+  }
+  if (!ab.empty())
+    HIP_TRY(hipMemcpy(pl->ab.p, ab.data(), sizeof(int) * ab.size(), hipMemcpyHostToDevice));
+  *out = pl.get();
+  g_plans[key] = std::move(pl);
+  g_plan_lru.push_back(key);
+  return KFP_OK;
+}
+
+// Uploads the per-call tables (data pointers, p, T, s) of a single instance.
+static kfp_status load_instance(Plan &pl, const double *u0, const double *f, const double *s,
+                                double p) {
+  const Geo &geo = pl.geo;
+  HostTables h;
+  add_instance(geo, p, pl.cfg.waves, 0, h);
+  make_items(geo, 0, h.items);
+  InstDev in{};
+  in.U[0] = pl.U0.p;
+  in.U[1] = pl.U1.p;
+  in.u0 = u0;
+  in.f = f;
+  in.g = pl.g.p;
+  in.lam[0] = pl.lam0.p;
+  in.lam[1] = pl.lam1.p;
+  in.res = pl.res.p;
+  const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt;
+  in.r = dt / (hv * hv);
+  in.p = p;
+  in.q = p;
+  in.hv = hv;
+  in.nx = geo.nx;
+  in.nv = geo.nv;
+  in.nt = geo.nt;
+  in.tr = geo.tr;
+  in.active = 1;
+  std::vector<double> gv(geo.nt);
+  for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
+  HIP_TRY(hipMemcpyAsync(pl.g.p, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, pl.cs));
+  HIP_TRY(pl.dt.upload(h, {in}, pl.cs));
+  return KFP_OK;
+}
+
+static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const InstDev *inst,
+                                          const Config &cfg, int nt, int par, int grid,
+                                          hipStream_t s) {
+  HIP_TRY(launch_reset_res(inst, n_inst, s));
+  for (int n = 0; n <= nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, par, grid, s));
+  return KFP_OK;
+}
+
+static kfp_status capture_graphs(Plan &pl) {
+  if (pl.captured) return KFP_OK;
+  const StepTables t = pl.dt.view();
+  for (int par = 0; par < 2; ++par) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(pl.cs, hipStreamCaptureModeThreadLocal));
+    kfp_status st = launch_iteration_direct(t, 1, pl.dt.inst.p, pl.cfg, pl.geo.nt, par,
+                                            t.n_items, pl.cs);
+    hipError_t e = hipStreamEndCapture(pl.cs, &graph);
+    if (st) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    HIP_TRY(e);
+    e = hipGraphInstantiate(&pl.gexec[par], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e);
+  }
+  pl.captured = true;
+  return KFP_OK;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static double bits_to_double(unsigned long long b) {
+  double d;
+  memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+static kfp_status sync_in(hipStream_t user, Plan &pl) {
+  HIP_TRY(hipEventRecord(pl.ev_in, user));
+  HIP_TRY(hipStreamWaitEvent(pl.cs, pl.ev_in, 0));
+  return KFP_OK;
+}
+
+static kfp_status sync_out(hipStream_t user, Plan &pl) {
+  HIP_TRY(hipEventRecord(pl.ev_out, pl.cs));
+  HIP_TRY(hipStreamWaitEvent(user, pl.ev_out, 0));
+  return KFP_OK;
+}
+
+// ------------------------------------------------------------------ solves --
+static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const double *f,
+                                 const double *s, int J, int o, int tr, double p, double tol,
+                                 int max_iter, const double *lambda_init, double *uT,
+                                 double *lambda_out, kfp_swr_stats *stats, hipStream_t user) {
+  const double t_start = now_s();
+  Geo geo;
+  kfp_status st = make_geo(g, J, o, tr, p, geo);
+  if (st) return st;
+  if (!u0 || !f || !uT) return fail(KFP_EINVAL, "u0, f and uT must be non-NULL");
+  if (!(tol > 0.0)) return fail(KFP_EINVAL, "tol must be > 0");
+  if (max_iter < 1) return fail(KFP_EINVAL, "max_iter must be >= 1");
+  if (s)
+    for (int n = 0; n <= g->nt; ++n)
+      if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
+  const Config cfg = choose_config(geo);
+  Plan *pl = nullptr;
+  if ((st = get_plan(geo, cfg, &pl))) return st;
+  if ((st = sync_in(user, *pl))) return st;
+  if ((st = load_instance(*pl, u0, f, s, p))) return st;
+  const size_t win = (size_t)2 * (J - 1) * geo.nt * geo.nx;
+  int restarted = 0;
+  if (win) {
+    if (lambda_init) {
+      HIP_TRY(launch_copy(lambda_init, pl->lam0.p, win, pl->cs));
+      HIP_TRY(hipMemsetAsync(pl->cnt.p, 0, sizeof(unsigned int), pl->cs));
+      HIP_TRY(launch_count_nonfinite(pl->lam0.p, win, pl->cnt.p, pl->cs));
+      unsigned int bad = 0;
+      HIP_TRY(hipMemcpyAsync(&bad, pl->cnt.p, sizeof bad, hipMemcpyDeviceToHost, pl->cs));
+      HIP_TRY(hipStreamSynchronize(pl->cs));
+      if (bad) {
+        HIP_TRY(launch_fill(pl->lam0.p, win, 0.0, pl->cs));
+        restarted = 1;
+      }
+    } else {
+      HIP_TRY(launch_fill(pl->lam0.p, win, 0.0, pl->cs));
+    }
+  }
+  const bool graphs = use_graphs();
+  if (graphs && (st = capture_graphs(*pl))) return st;
+  const StepTables t = pl->dt.view();
+  double dev_ms = 0.0, r = INFINITY;
+  int k = 0;
+  for (k = 1; k <= max_iter; ++k) {
+    const int par = (k - 1) & 1;
+    HIP_TRY(hipEventRecord(pl->ev0, pl->cs));
+    if (graphs) {
+      HIP_TRY(hipGraphLaunch(pl->gexec[par], pl->cs));
+    } else if ((st = launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt, par, t.n_items,
+                                             pl->cs))) {
+      return st;
+    }
+    HIP_TRY(hipEventRecord(pl->ev1, pl->cs));
+    HIP_TRY(hipMemcpyAsync(pl->h_res, pl->res.p, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           pl->cs));
+    HIP_TRY(hipStreamSynchronize(pl->cs));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+    dev_ms += ms;
+    r = bits_to_double(*pl->h_res);
+    if (J == 1) r = 0.0;
+    if (stats && stats->res_history) stats->res_history[k - 1] = r;
+    if (!std::isfinite(r) && k == 1 && lambda_init && !restarted) {
+      // a finite-looking guess that still produced a non-finite mismatch:
+      // restart once from zero traces
+      HIP_TRY(launch_fill(pl->lam0.p, win, 0.0, pl->cs));
+      restarted = 1;
+      k = 0;
+      continue;
+    }
+    if (r < tol) break;
+  }
+  const bool converged = k <= max_iter;
+  if (!converged) k = max_iter;
+  double *Ufin = (geo.nt & 1) ? pl->U1.p : pl->U0.p;
+  HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
+  if (lambda_out && win) HIP_TRY(launch_copy((k & 1) ? pl->lam1.p : pl->lam0.p, lambda_out, win, pl->cs));
+  if ((st = sync_out(user, *pl))) return st;
+  HIP_TRY(hipStreamSynchronize(pl->cs));
+  if (stats) {
+    stats->iters = k;
+    stats->restarted = restarted;
+    stats->residual = r;
+    stats->device_seconds = dev_ms * 1e-3;
+    stats->cell_steps = (double)k * geo.nt * geo.nx * geo.rows;
+    stats->alg_bytes = 24.0 * stats->cell_steps;
+    stats->seconds = now_s() - t_start;
+  }
+  if (!converged) return fail(KFP_ENOCONV, "no convergence after %d iterations (r = %g)", k, r);
+  return KFP_OK;
+}
+
+static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const double *f,
+                                  const double *s, double *uT, hipStream_t user) {
+  Geo geo;
+  kfp_status st = make_geo(g, 1, 0, KFP_DIRICHLET, 0.0, geo);
+  if (st) return st;
+  if (!u0 || !f || !uT) return fail(KFP_EINVAL, "u0, f and uT must be non-NULL");
+  if (s)
+    for (int n = 0; n <= g->nt; ++n)
+      if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
+  const Config cfg = choose_config(geo);
+  Plan *pl = nullptr;
+  if ((st = get_plan(geo, cfg, &pl))) return st;
+  if ((st = sync_in(user, *pl))) return st;
+  if ((st = load_instance(*pl, u0, f, s, 0.0))) return st;
+  const StepTables t = pl->dt.view();
+  for (int n = 0; n < geo.nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, 0, t.n_items, pl->cs));
+  double *Ufin = (geo.nt & 1) ? pl->U1.p : pl->U0.p;
+  HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
+  return sync_out(user, *pl);
+}
+
+// ------------------------------------------------------------------- batch --
+struct BatchInst {
+  Geo geo;
+  double p;
+  double *U0, *U1, *lam0, *lam1, *g;
+  int *rowmap;
+  size_t win;
+};
+
+static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol, int max_iter,
+                                 kfp_swr_stats *stats, hipStream_t user) {
+  const double t_start = now_s();
+  if (n_inst < 1 || !in) return fail(KFP_EINVAL, "batch needs n >= 1 instances");
+  if (!(tol > 0.0)) return fail(KFP_EINVAL, "tol must be > 0");
+  if (max_iter < 1) return fail(KFP_EINVAL, "max_iter must be >= 1");
+  std::vector<BatchInst> bi(n_inst);
+  int n_max = 0, nt_max = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    kfp_status st = make_geo(&in[i].g, in[i].J, in[i].overlap, in[i].tr, in[i].p, bi[i].geo);
+    if (st) return fail(st, "instance %d: %s", i, g_err.c_str());
+    if (!in[i].u0 || !in[i].f || !in[i].uT)
+      return fail(KFP_EINVAL, "instance %d: u0, f and uT must be non-NULL", i);
+    if (in[i].s)
+      for (int n = 0; n <= in[i].g.nt; ++n)
+        if (!std::isfinite(in[i].s[n])) return fail(KFP_EINVAL, "instance %d: s not finite", i);
+    bi[i].p = in[i].p;
+    n_max = std::max(n_max, bi[i].geo.n_max);
+    nt_max = std::max(nt_max, in[i].g.nt);
+  }
+  Geo probe;
+  probe.nx = 0;
+  probe.n_max = n_max;
+  probe.J = 0;
+  probe.tr = -1;
+  Config cfg = g_forced.waves > 0 ? choose_config(probe) : default_config(n_max);
+  if (g_forced.waves == 0) {
+    if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
+    char key[96];
+    snprintf(key, sizeof key, "%s/batch/nmax%d", arch_name().c_str(), n_max);
+    auto it = g_tune->find(key);
+    if (it != g_tune->end()) cfg = it->second;
+  }
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  struct Guard {
+    std::vector<void *> ptrs;
+    hipStream_t s;
+    std::vector<hipGraphExec_t> ge;
+    ~Guard() {
+      for (auto g : ge)
+        if (g) (void)hipGraphExecDestroy(g);
+      for (void *p : ptrs) (void)hipFree(p);
+      (void)hipStreamDestroy(s);
+    }
+  } guard{{}, cs, {nullptr, nullptr}};
+  auto dalloc = [&](size_t bytes, void **p) -> hipError_t {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+    if (e == hipSuccess) guard.ptrs.push_back(*p);
+    return e;
+  };
+  hipEvent_t ev;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ev, user));
+  HIP_TRY(hipStreamWaitEvent(cs, ev, 0));
+  HIP_TRY(hipEventDestroy(ev));
+
+  // workspace and tables; items sorted largest-first (LPT) for the
+  // persistent grid
+  HostTables h;
+  std::vector<InstDev> idev(n_inst);
+  unsigned long long *res = nullptr;
+  HIP_TRY(dalloc(sizeof(unsigned long long) * n_inst, (void **)&res));
+  std::vector<std::pair<int, Item>> weighted;
+  for (int i = 0; i < n_inst; ++i) {
+    BatchInst &b = bi[i];
+    const Geo &geo = b.geo;
+    const size_t state = (size_t)geo.rows * geo.nx;
+    b.win = (size_t)2 * (geo.J - 1) * geo.nt * geo.nx;
+    HIP_TRY(dalloc(state * 8, (void **)&b.U0));
+    HIP_TRY(dalloc(state * 8, (void **)&b.U1));
+    HIP_TRY(dalloc(b.win * 8, (void **)&b.lam0));
+    HIP_TRY(dalloc(b.win * 8, (void **)&b.lam1));
+    HIP_TRY(dalloc(geo.nt * 8, (void **)&b.g));
+    HIP_TRY(dalloc((geo.nv + 1) * sizeof(int), (void **)&b.rowmap));
+    HIP_TRY(hipMemcpyAsync(b.rowmap, geo.rowmap.data(), (geo.nv + 1) * sizeof(int),
+                           hipMemcpyHostToDevice, cs));
+    std::vector<double> gv(geo.nt);
+    const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt;
+    for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (in[i].s ? in[i].s[n + 1] : 1.0);
+    HIP_TRY(hipMemcpyAsync(b.g, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, cs));
+    HIP_TRY(hipStreamSynchronize(cs));
+    const int sub_base = (int)h.subs.size();
+    add_instance(geo, b.p, cfg.waves, i, h);
+    std::vector<Item> it;
+    make_items(geo, sub_base, it);
+    for (const Item &x : it) weighted.push_back({h.subs[x.sub].n * geo.nt, x});
+    InstDev &d = idev[i];
+    d.U[0] = b.U0;
+    d.U[1] = b.U1;
+    d.u0 = in[i].u0;
+    d.f = in[i].f;
+    d.g = b.g;
+    d.lam[0] = b.lam0;
+    d.lam[1] = b.lam1;
+    d.res = res + i;
+    d.r = dt / (hv * hv);
+    d.p = b.p;
+    d.q = b.p;
+    d.hv = hv;
+    d.nx = geo.nx;
+    d.nv = geo.nv;
+    d.nt = geo.nt;
+    d.tr = geo.tr;
+    d.active = 1;
+    if (b.win) {
+      if (in[i].lambda_init) {
+        HIP_TRY(launch_copy(in[i].lambda_init, b.lam0, b.win, cs));
+      } else {
+        HIP_TRY(launch_fill(b.lam0, b.win, 0.0, cs));
+      }
+    }
+  }
+  std::stable_sort(weighted.begin(), weighted.end(),
+                   [](const std::pair<int, Item> &x, const std::pair<int, Item> &y) {
+                     return x.first > y.first;
+                   });
+  for (auto &w : weighted) h.items.push_back(w.second);
+  DevTables dt;
+  struct DtGuard {
+    DevTables *d;
+    ~DtGuard() { d->release(); }
+  } dtg{&dt};
+  HIP_TRY(dt.upload(h, idev, cs));
+  const StepTables t = dt.view();
+  int dev_count = 0, cus = 256;
+  if (hipGetDevice(&dev_count) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev_count) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  const int grid = std::max(1, std::min<int>((int)h.items.size(), cus * std::max(1, 32 / cfg.waves)));
+
+  // non-finite guesses fall back to zero
+  std::vector<int> restarted(n_inst, 0);
+  {
+    unsigned int *cnt = nullptr;
+    HIP_TRY(dalloc(sizeof(unsigned int) * n_inst, (void **)&cnt));
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(unsigned int) * n_inst, cs));
+    for (int i = 0; i < n_inst; ++i)
+      if (in[i].lambda_init && bi[i].win) HIP_TRY(launch_count_nonfinite(bi[i].lam0, bi[i].win, cnt + i, cs));
+    std::vector<unsigned int> hc(n_inst);
+    HIP_TRY(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned int) * n_inst, hipMemcpyDeviceToHost, cs));
+    HIP_TRY(hipStreamSynchronize(cs));
+    for (int i = 0; i < n_inst; ++i)
+      if (hc[i]) {
+        HIP_TRY(launch_fill(bi[i].lam0, bi[i].win, 0.0, cs));
+        restarted[i] = 1;
+      }
+  }
+
+  const bool graphs = use_graphs();
+  if (graphs) {
+    for (int par = 0; par < 2; ++par) {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      kfp_status st = launch_iteration_direct(t, n_inst, dt.inst.p, cfg, nt_max, par, grid, cs);
+      hipError_t e = hipStreamEndCapture(cs, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      HIP_TRY(e);
+      e = hipGraphInstantiate(&guard.ge[par], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIP_TRY(e);
+    }
+  }
+  unsigned long long *h_res = nullptr;
+  HIP_TRY(hipHostMalloc((void **)&h_res, sizeof(unsigned long long) * n_inst));
+  struct HGuard {
+    void *p;
+    ~HGuard() { (void)hipHostFree(p); }
+  } hg{h_res};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct EGuard {
+    hipEvent_t a, b;
+    ~EGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eg{e0, e1};
+  std::vector<int> iters(n_inst, 0), done(n_inst, 0);
+  std::vector<double> resid(n_inst, INFINITY);
+  double dev_ms = 0.0;
+  int active = n_inst;
+  for (int k = 1; k <= max_iter && active > 0; ++k) {
+    const int par = (k - 1) & 1;
+    HIP_TRY(hipEventRecord(e0, cs));
+    if (graphs) {
+      HIP_TRY(hipGraphLaunch(guard.ge[par], cs));
+    } else {
+      kfp_status st = launch_iteration_direct(t, n_inst, dt.inst.p, cfg, nt_max, par, grid, cs);
+      if (st) return st;
+    }
+    HIP_TRY(hipEventRecord(e1, cs));
+    HIP_TRY(hipMemcpyAsync(h_res, res, sizeof(unsigned long long) * n_inst, hipMemcpyDeviceToHost, cs));
+    HIP_TRY(hipStreamSynchronize(cs));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    dev_ms += ms;
+    bool changed = false;
+    for (int i = 0; i < n_inst; ++i) {
+      if (done[i]) continue;
+      iters[i] = k;
+      const Geo &geo = bi[i].geo;
+      double r = geo.J == 1 ? 0.0 : bits_to_double(h_res[i]);
+      resid[i] = r;
+      if (stats && stats[i].res_history) stats[i].res_history[k - 1] = r;
+      if (r < tol) {
+        done[i] = 1;
+        --active;
+        idev[i].active = 0;
+        changed = true;
+      }
+    }
+    if (changed) {
+      HIP_TRY(hipMemcpyAsync(dt.inst.p, idev.data(), sizeof(InstDev) * n_inst,
+                             hipMemcpyHostToDevice, cs));
+      HIP_TRY(hipStreamSynchronize(cs));
+    }
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    const BatchInst &b = bi[i];
+    const Geo &geo = b.geo;
+    double *Ufin = (geo.nt & 1) ? b.U1 : b.U0;
+    HIP_TRY(launch_assemble(Ufin, b.rowmap, in[i].uT, geo.nv, geo.nx, cs));
+    if (in[i].lambda_out && b.win)
+      HIP_TRY(launch_copy((iters[i] & 1) ? b.lam1 : b.lam0, in[i].lambda_out, b.win, cs));
+  }
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ev, cs));
+  HIP_TRY(hipStreamWaitEvent(user, ev, 0));
+  HIP_TRY(hipStreamSynchronize(cs));
+  HIP_TRY(hipEventDestroy(ev));
+  const double secs = now_s() - t_start;
+  if (stats) {
+    for (int i = 0; i < n_inst; ++i) {
+      const Geo &geo = bi[i].geo;
+      stats[i].iters = iters[i];
+      stats[i].restarted = restarted[i];
+      stats[i].residual = resid[i];
+      stats[i].seconds = secs;
+      stats[i].device_seconds = dev_ms * 1e-3;
+      stats[i].cell_steps = (double)iters[i] * geo.nt * geo.nx * geo.rows;
+      stats[i].alg_bytes = 24.0 * stats[i].cell_steps;
+    }
+  }
+  if (active > 0) return fail(KFP_ENOCONV, "%d of %d instances did not converge", active, n_inst);
+  return KFP_OK;
+}
+
+// -------------------------------------------------------------------- tune --
+static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, int *w_out,
+                            int *s_out, hipStream_t user) {
+  Geo geo;
+  kfp_status st = make_geo(g, J, o, tr, p, geo);
+  if (st) return st;
+  const size_t nfield = (size_t)(g->nv + 1) * g->nx;
+  double *u0 = nullptr, *f = nullptr;
+  HIP_TRY(hipMalloc((void **)&u0, nfield * 8));
+  struct F {
+    double **a, **b;
+    ~F() {
+      if (*a) (void)hipFree(*a);
+      if (*b) (void)hipFree(*b);
+    }
+  } fr{&u0, &f};
+  HIP_TRY(hipMalloc((void **)&f, nfield * 8));
+  HIP_TRY(launch_fill(u0, nfield, 0.5, nullptr));
+  HIP_TRY(launch_fill(f, nfield, 0.25, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  const Config saved = g_forced;
+  Config best;
+  double best_ms = INFINITY;
+  const int steps = std::min(g->nt, 64);
+  for (int w : kWaves) {
+    std::vector<int> cands;
+    const int s0 = seg_for(geo.n_max, w);
+    if (s0 > 0) cands.push_back(s0);
+    cands.push_back(0);
+    for (int sm : cands) {
+      if (!step_config_supported(w, sm)) continue;
+      Config c{w, sm};
+      Plan *pl = nullptr;
+      if ((st = get_plan(geo, c, &pl))) return st;
+      if ((st = load_instance(*pl, u0, f, nullptr, tr == KFP_ROBIN ? p : 1.0))) return st;
+      if (geo.J > 1) HIP_TRY(launch_fill(pl->lam0.p, (size_t)2 * (geo.J - 1) * geo.nt * geo.nx, 0.0, pl->cs));
+      const StepTables t = pl->dt.view();
+      for (int n = 0; n < 4; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
+      HIP_TRY(hipEventRecord(pl->ev0, pl->cs));
+      for (int n = 0; n < steps; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
+      HIP_TRY(hipEventRecord(pl->ev1, pl->cs));
+      HIP_TRY(hipStreamSynchronize(pl->cs));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
+  g_forced = saved;
+  if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
+  (*g_tune)[tune_key(geo)] = best;
+  save_tune(*g_tune);
+  if (w_out) *w_out = best.waves;
+  if (s_out) *s_out = best.seg;
+  (void)user;
+  return KFP_OK;
+}
+
+}  // namespace kfp
+
+// ====================================================================== ABI ==
+using namespace kfp;
+
+extern "C" {
+
+kfp_status kfp_mono_solve(const kfp_grid *g, const double *u0, const double *f, const double *s,
+                          double *uT, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  return mono_solve_impl(g, u0, f, s, uT, (hipStream_t)stream);
+}
+
+kfp_status kfp_swr_solve(const kfp_grid *g, const double *u0, const double *f, const double *s,
+                         int32_t J, int32_t overlap, int32_t tr, double p, double tol,
+                         int32_t max_iter, const double *lambda_init, double *uT,
+                         double *lambda_out, kfp_swr_stats *stats, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  return swr_solve_impl(g, u0, f, s, J, overlap, tr, p, tol, max_iter, lambda_init, uT,
+                        lambda_out, stats, (hipStream_t)stream);
+}
+
+kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
+                        int32_t tr, double p, double *lambda, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  Geo geo;
+  kfp_status st = make_geo(g, J, overlap, tr, p, geo);
+  if (st) return st;
+  if (!u0 || (!lambda && J > 1)) return fail(KFP_EINVAL, "u0 and lambda must be non-NULL");
+  if (J == 1) return KFP_OK;
+  Plan *pl = nullptr;
+  if ((st = get_plan(geo, choose_config(geo), &pl))) return st;
+  if ((st = sync_in((hipStream_t)stream, *pl))) return st;
+  HIP_TRY(launch_u0_guess(u0, geo.nx, geo.nt, J, pl->ab.p, tr, p, 2.0 / geo.nv, lambda, pl->cs));
+  return sync_out((hipStream_t)stream, *pl);
+}
+
+kfp_status kfp_swr_batch(int32_t n, const kfp_instance *inst, double tol, int32_t max_iter,
+                         kfp_swr_stats *stats, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  return swr_batch_impl(n, inst, tol, max_iter, stats, (hipStream_t)stream);
+}
+
+kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, double p,
+                    int32_t *waves_out, int32_t *seg_max_out, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  return tune_impl(g, J, overlap, tr, p, waves_out, seg_max_out, (hipStream_t)stream);
+}
+
+kfp_status kfp_set_config(int32_t waves, int32_t seg_max) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (waves == 0) {
+    g_forced = Config{};
+    return KFP_OK;
+  }
+  if (!step_config_supported(waves, seg_max))
+    return fail(KFP_EINVAL, "configuration waves=%d seg_max=%d is not compiled", waves, seg_max);
+  g_forced = Config{waves, seg_max};
+  return KFP_OK;
+}
+
+kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                          int32_t *waves_out, int32_t *seg_max_out) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  Geo geo;
+  kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo);
+  if (st) return st;
+  const Config c = choose_config(geo);
+  if (waves_out) *waves_out = c.waves;
+  if (seg_max_out) *seg_max_out = c.seg;
+  return KFP_OK;
+}
+
+kfp_status kfp_subdomain_rows(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                              int64_t *rows_out) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  Geo geo;
+  kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo);
+  if (st) return st;
+  if (!rows_out) return fail(KFP_EINVAL, "rows_out is NULL");
+  *rows_out = geo.rows;
+  return KFP_OK;
+}
+
+kfp_status kfp_bw_probe(const void *src, void *dst, int64_t bytes, void *stream) {
+  g_err.clear();
+  if (!src || !dst || bytes < 0 || bytes % 16) return fail(KFP_EINVAL, "bad probe arguments");
+  HIP_TRY(launch_bw_probe(src, dst, (size_t)bytes, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+void kfp_release_workspace(void) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_plans.clear();
+  g_plan_lru.clear();
+}
+
+const char *kfp_last_error(void) { return g_err.c_str(); }
+
+kfp_status kfp_debug_tables(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, double p,
+                            int32_t waves, int32_t *sub_info, double *rows, int32_t *segs,
+                            double *reds, double *mat) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  Geo geo;
+  kfp_status st = make_geo(g, J, overlap, tr, p, geo);
+  if (st) return st;
+  if (waves < 1 || waves > 16) return fail(KFP_EINVAL, "waves must be in 1..16");
+  if (!sub_info || !rows || !segs || !reds || !mat) return fail(KFP_EINVAL, "NULL output");
+  HostTables h;
+  add_instance(geo, p, waves, 0, h);
+  const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt, r = dt / (hv * hv);
+  for (int j = 0; j < J; ++j) {
+    const SubDev &d = h.subs[j];
+    int32_t *o = sub_info + 8 * j;
+    o[0] = d.n;
+    o[1] = d.row_off;
+    o[2] = d.g_lo;
+    o[3] = d.P;
+    o[4] = d.lo_kind;
+    o[5] = d.hi_kind;
+    o[6] = d.tab;
+    o[7] = d.seg;
+    std::vector<double> lo, di, up;
+    row_matrix(geo.sub[j], r, p, p, hv, lo, di, up);
+    for (int k = 0; k < d.n; ++k) {
+      mat[3 * (d.tab + k) + 0] = lo[k];
+      mat[3 * (d.tab + k) + 1] = di[k];
+      mat[3 * (d.tab + k) + 2] = up[k];
+    }
+  }
+  for (size_t i = 0; i < h.rows.size(); ++i) {
+    const RowCoef &c = h.rows[i];
+    double *o = rows + 6 * i;
+    o[0] = c.nu;
+    o[1] = c.fa;
+    o[2] = c.fb;
+    o[3] = c.bc;
+    o[4] = c.sl;
+    o[5] = c.sr;
+  }
+  for (size_t i = 0; i < h.segs.size(); ++i) segs[i] = h.segs[i];
+  for (size_t i = 0; i < h.reds.size(); ++i) {
+    const RedCoef &c = h.reds[i];
+    double *o = reds + 5 * i;
+    o[0] = c.ra;
+    o[1] = c.rc;
+    o[2] = c.g1;
+    o[3] = c.g2;
+    o[4] = c.h;
+  }
+  return KFP_OK;
+}
+
+}  // extern "C"

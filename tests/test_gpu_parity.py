@@ -1,0 +1,254 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerance: relative L2 <= 1e-10 in FP64 for converged solves (the target the
+method is held to) and <= 1e-12 for fixed iteration counts and the
+monodomain march, where both sides run the same arithmetic up to the
+rounding order of the Thomas elimination (divisions on the CPU, precomputed
+reciprocals and a segment partition on the GPU).
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1306_4596_amd as kfp  # noqa: E402
+from paper_1306_4596_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+D, R = kfp.DIRICHLET, kfp.ROBIN
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(autouse=True)
+def _auto_config():
+    kfp.set_config(0, 0)
+    yield
+    kfp.set_config(0, 0)
+    os.environ.pop("KFP_NO_GRAPH", None)
+
+
+# ------------------------------------------------------------ monodomain ---
+@pytest.mark.parametrize("nx,nv,nt,T", [(64, 64, 200, 0.1), (100, 40, 37, 0.2), (5, 8, 3, 0.3),
+                                        (130, 300, 50, 0.3)])
+def test_mono_matches_oracle(nx, nv, nt, T):
+    print(f"mono nx={nx} nv={nv} nt={nt}", flush=True)
+    u0, f = inputs.random_fields(nx + nv, nx, nv)
+    s = 1.0 + 0.5 * np.sin(np.arange(nt + 1))
+    ref = oracle.mono_solve(u0, f, T, nt, s)
+    out = host(kfp.mono_solve(dev(u0), dev(f), T, nt, s=s))
+    torch.cuda.synchronize()
+    assert rel(out, ref) <= 1e-12
+    assert np.all(out[0] == 0) and np.all(out[-1] == 0)
+
+
+def test_mono_manufactured_cfg0():
+    nx = nv = 64
+    nt, T = 200, 0.1
+    u0, f, s, ex = inputs.manufactured(nx, nv, nt, T)
+    ref = oracle.mono_solve(u0, f, T, nt, s)
+    out = host(kfp.mono_solve(dev(u0), dev(f), T, nt, s=s))
+    assert rel(out, ref) <= 1e-12
+    assert np.abs(out - ex(T)).max() / np.abs(ex(T)).max() < 2e-2
+
+
+# ---------------------------------------------------------------- SWR -------
+CASES = [
+    # nx, nv, nt, T, J, o, tr, p
+    (64, 64, 200, 0.1, 2, 4, D, 0.0),
+    (64, 64, 60, 0.3, 4, 2, R, 4.0),
+    (100, 96, 40, 0.2, 3, 3, R, 2.5),
+    (70, 120, 30, 0.2, 8, 1, D, 0.0),
+    (200, 128, 64, 0.25, 4, 5, R, 8.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_swr_fixed_iterations_match_oracle(case):
+    nx, nv, nt, T, J, o, tr, p = case
+    print(f"swr fixed K case={case}", flush=True)
+    u0, f = inputs.random_fields(7, nx, nv)
+    K = 4
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-300, max_iter=K)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=K,
+                                want_lambda=True)
+    assert st.iters == K
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_swr_converged_matches_oracle_and_monodomain(case):
+    nx, nv, nt, T, J, o, tr, p = case
+    print(f"swr converged case={case}", flush=True)
+    u0, f = inputs.random_fields(3, nx, nv)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-12, max_iter=2000)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-12, max_iter=2000,
+                                want_lambda=True)
+    assert st.iters == ref.iters
+    assert rel(host(uT), ref.uT) <= 1e-10
+    mono = oracle.mono_solve(u0, f, T, nt)
+    assert rel(host(uT), mono) <= 1e-10
+
+
+def test_cfg0_manufactured_swr():
+    nx = nv = 64
+    nt, T = 200, 0.1
+    u0, f, s, _ = inputs.manufactured(nx, nv, nt, T)
+    ref = oracle.swr_solve(u0, f, T, nt, 2, 4, D, tol=1e-12, max_iter=500, s=s)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 4, D, tol=1e-12, max_iter=500, s=s,
+                                want_lambda=True)
+    assert st.iters == ref.iters and st.residual < 1e-12
+    assert rel(host(uT), ref.uT) <= 1e-10
+    assert rel(host(lam), ref.lam) <= 1e-10
+
+
+def test_error_equation_and_initial_guess():
+    nx, nv, nt, T, J, o = 64, 64, 50, 0.25, 2, 3
+    z = np.zeros((nv + 1, nx))
+    lam0 = inputs.random_traces(1, J, nt, nx)
+    ref = oracle.swr_solve(z, z, T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=6, lambda_init=lam0)
+    uT, lam, st = kfp.swr_solve(dev(z), dev(z), T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=6,
+                                lambda_init=dev(lam0), want_lambda=True)
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=0)
+
+
+def test_u0_guess_matches_oracle():
+    nx, nv, nt = 80, 64, 20
+    u0, _ = inputs.random_fields(4, nx, nv)
+    for tr, p in ((D, 0.0), (R, 3.0)):
+        ref = oracle.u0_guess(u0, nt, 4, 2, tr, p=p)
+        out = host(kfp.u0_guess(dev(u0), nt, 4, 2, tr, p=p))
+        assert rel(out, ref) <= 1e-14
+
+
+def test_nonfinite_guess_restarts_from_zero():
+    nx, nv, nt, T = 64, 32, 20, 0.2
+    u0, f = inputs.random_fields(2, nx, nv)
+    bad = np.zeros((2, nt, nx))
+    bad[0, 3, 5] = np.nan
+    uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 2, R, p=4.0, tol=1e-11, max_iter=300,
+                              lambda_init=dev(bad))
+    assert st.restarted
+    ref = oracle.swr_solve(u0, f, T, nt, 2, 2, R, p=4.0, tol=1e-11, max_iter=300)
+    assert st.iters == ref.iters
+    assert rel(host(uT), ref.uT) <= 1e-10
+
+
+def test_resume_from_returned_traces():
+    nx, nv, nt, T = 64, 64, 30, 0.2
+    u0, f = inputs.random_fields(6, nx, nv)
+    a, la, _ = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=4.0, tol=1e-300, max_iter=6,
+                             want_lambda=True)
+    b1, lb1, _ = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=4.0, tol=1e-300, max_iter=3,
+                               want_lambda=True)
+    b2, lb2, _ = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=4.0, tol=1e-300, max_iter=3,
+                               lambda_init=lb1, want_lambda=True)
+    assert torch.equal(a, b2) and torch.equal(la, lb2)
+
+
+def test_max_iter_returns_last_iterate():
+    nx, nv, nt, T = 64, 64, 30, 0.2
+    u0, f = inputs.random_fields(6, nx, nv)
+    with pytest.raises(kfp.KfpError):
+        kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 2, D, tol=1e-14, max_iter=1, raise_noconv=True)
+    uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 2, D, tol=1e-14, max_iter=1)
+    ref = oracle.swr_solve(u0, f, T, nt, 2, 2, D, tol=1e-14, max_iter=1)
+    assert st.iters == 1 and ref.status == 4
+    assert rel(host(uT), ref.uT) <= 1e-12
+
+
+# ------------------------------------------------- launch configurations ----
+CONFIGS = [(1, 0), (1, 64), (2, 0), (2, 48), (4, 16), (4, 32), (8, 8), (8, 0), (16, 8),
+           (16, 0)]
+
+
+@pytest.mark.parametrize("waves,seg", CONFIGS)
+def test_every_launch_configuration_agrees(waves, seg):
+    nx, nv, nt, T, J, o = 96, 128, 24, 0.2, 2, 2
+    print(f"config waves={waves} seg={seg}", flush=True)
+    u0, f = inputs.random_fields(9, nx, nv)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=3)
+    kfp.set_config(waves, seg)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=3,
+                                want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+
+
+def test_graph_and_direct_launch_agree_and_are_deterministic():
+    nx, nv, nt, T = 128, 128, 40, 0.2
+    u0, f = inputs.random_fields(12, nx, nv)
+    a, la, _ = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=2.0, tol=1e-300, max_iter=5,
+                             want_lambda=True)
+    b, lb, _ = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=2.0, tol=1e-300, max_iter=5,
+                             want_lambda=True)
+    os.environ["KFP_NO_GRAPH"] = "1"
+    c, lc, _ = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=2.0, tol=1e-300, max_iter=5,
+                             want_lambda=True)
+    assert torch.equal(a, b) and torch.equal(la, lb)
+    assert torch.equal(a, c) and torch.equal(la, lc)
+
+
+# ------------------------------------------------------------------ batch --
+def test_batch_matches_single_solves():
+    specs = [
+        (64, 64, 40, 0.2, 2, 2, R, 4.0),
+        (128, 32, 40, 0.1, 4, 2, R, 2.0),
+        (96, 128, 40, 0.3, 8, 2, D, 0.0),
+        (64, 256, 40, 0.2, 2, 3, R, 8.0),
+        (256, 64, 40, 0.15, 1, 0, R, 1.0),
+    ]
+    insts, refs = [], []
+    kfp.set_config(16, 32)  # one configuration for the batch and the singles
+    for i, (nx, nv, nt, T, J, o, tr, p) in enumerate(specs):
+        u0, f = inputs.random_fields(100 + i, nx, nv)
+        insts.append(dict(u0=dev(u0), f=dev(f), T=T, nt=nt, J=J, overlap=o, tr=tr, p=p,
+                          want_lambda=True))
+        refs.append(kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-11, max_iter=400,
+                                  want_lambda=True))
+    out, rc = kfp.swr_batch(insts, tol=1e-11, max_iter=400, history=True)
+    assert rc == 0
+    for (uT, lam, st), (ruT, rlam, rst) in zip(out, refs):
+        assert st.iters == rst.iters
+        assert torch.equal(uT, ruT)
+        if lam is not None:
+            assert torch.equal(lam, rlam)
+    # and against the oracle
+    for (nx, nv, nt, T, J, o, tr, p), (uT, _, st), i in zip(specs, out, range(len(specs))):
+        u0, f = inputs.random_fields(100 + i, nx, nv)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-11, max_iter=400)
+        assert st.iters == ref.iters
+        assert rel(host(uT), ref.uT) <= 1e-10
+
+
+# ------------------------------------------------------ full-size checks ----
+def test_cfg1_shape_fixed_iterations_short_window():
+    """The 1024 x 1024, J = 8, overlap 2, Robin shape of the benchmark, with
+    the same dt but a 200-step window: two iterations against the oracle."""
+    nx = nv = 1024
+    nt, T = 200, 0.05
+    u0, f = inputs.random_fields(0, nx, nv)
+    print("cfg1 shape oracle ...", flush=True)
+    ref = oracle.swr_solve(u0, f, T, nt, 8, 2, R, p=4.0, tol=1e-300, max_iter=2)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 8, 2, R, p=4.0, tol=1e-300, max_iter=2,
+                                want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9)

@@ -1,0 +1,212 @@
+"""CPU tests of the library's host side: exported symbols, argument validation
+(every EINVAL path returns before any device call) and the elimination tables
+of the segment-partitioned tridiagonal solve."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1306_4596_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.lib_path()):
+        pytest.skip("libkfpswr not built")
+    return binding.load_library()
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(kfp_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert {"kfp_mono_solve", "kfp_swr_solve", "kfp_swr_batch"} <= names
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+
+
+G = binding.Grid
+FAKE = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+
+
+def swr(lib, g, J=2, o=2, tr=1, p=4.0, tol=1e-10, max_iter=10, u0=FAKE, f=FAKE, uT=FAKE):
+    return lib.kfp_swr_solve(ctypes.byref(g), u0, f, None, J, o, tr, p, tol, max_iter, None, uT,
+                             None, None, None)
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(g=G(1, 64, 10, 0.1)), "nx"),
+    (dict(g=G(64, 2, 10, 0.1)), "nv"),
+    (dict(g=G(64, 64, 0, 0.1)), "nt"),
+    (dict(g=G(64, 64, 10, -1.0)), "T"),
+    (dict(g=G(1024, 64, 10, 1.0)), "CFL"),
+    (dict(J=3), "nv % J"),
+    (dict(J=16, o=3), "nv/J"),
+    (dict(o=0), "overlap"),
+    (dict(tr=0, o=0), "overlap"),
+    (dict(p=0.0), "p must be"),
+    (dict(p=-1.0), "p must be"),
+    (dict(tr=7), "transmission"),
+    (dict(tol=0.0), "tol"),
+    (dict(max_iter=0), "max_iter"),
+    (dict(u0=None), "non-NULL"),
+    (dict(uT=None), "non-NULL"),
+])
+def test_swr_invalid_arguments(lib, kw, frag):
+    args = dict(g=G(64, 64, 10, 0.1))
+    args.update(kw)
+    st = swr(lib, **args)
+    assert st == binding.KFP_EINVAL
+    assert frag in lib.kfp_last_error().decode()
+
+
+def test_mono_and_batch_invalid_arguments(lib):
+    g = G(64, 64, 10, 0.1)
+    assert lib.kfp_mono_solve(ctypes.byref(g), None, FAKE, None, FAKE, None) == binding.KFP_EINVAL
+    bad = G(64, 64, 10, 100.0)
+    assert lib.kfp_mono_solve(ctypes.byref(bad), FAKE, FAKE, None, FAKE, None) == binding.KFP_EINVAL
+    inst = (binding.Instance * 1)()
+    inst[0].g = G(64, 64, 10, 0.1)
+    inst[0].J, inst[0].overlap, inst[0].tr, inst[0].p = 3, 2, 1, 4.0
+    assert lib.kfp_swr_batch(1, inst, 1e-10, 10, None, None) == binding.KFP_EINVAL
+    assert "instance 0" in lib.kfp_last_error().decode()
+    assert lib.kfp_swr_batch(0, inst, 1e-10, 10, None, None) == binding.KFP_EINVAL
+    assert lib.kfp_set_config(3, 8) == binding.KFP_EINVAL
+    assert lib.kfp_bw_probe(FAKE, FAKE, 10, None) == binding.KFP_EINVAL
+
+
+def test_subdomain_rows(lib):
+    r = ctypes.c_int64()
+    g = G(1024, 1024, 2000, 0.5)
+    assert lib.kfp_subdomain_rows(ctypes.byref(g), 8, 2, 1, ctypes.byref(r)) == 0
+    assert r.value == 1023 + 7 * 3  # (nv - 1) + (J - 1)(o + 1) for Robin
+    assert lib.kfp_subdomain_rows(ctypes.byref(g), 8, 2, 0, ctypes.byref(r)) == 0
+    assert r.value == 1023 + 7 * 1  # (nv - 1) + (J - 1)(o - 1) for Dirichlet
+
+
+def get_tables(lib, nx, nv, nt, T, J, o, tr, p, waves):
+    g = G(nx, nv, nt, T)
+    r = ctypes.c_int64()
+    assert lib.kfp_subdomain_rows(ctypes.byref(g), J, o, tr, ctypes.byref(r)) == 0
+    rows = np.zeros((r.value, 6))
+    mat = np.zeros((r.value, 3))
+    info = np.zeros((J, 8), dtype=np.int32)
+    segs = np.zeros(J * (waves + 1), dtype=np.int32)
+    reds = np.zeros((J * waves, 5))
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    lib.kfp_debug_tables.argtypes = [ctypes.POINTER(G), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+    st = lib.kfp_debug_tables(ctypes.byref(g), J, o, tr, p, waves, P(info), P(rows), P(segs),
+                              P(reds), P(mat))
+    assert st == 0, lib.kfp_last_error()
+    return info, rows, segs, reds, mat
+
+
+def paper_matrix(nv, nt, T, lo_node, n, lo_kind, hi_kind, p):
+    """Tridiagonal matrix of one subdomain's unknown rows from Section 6.2/6.3:
+    implicit-Euler diffusion rows [-r, 1+2r, -r]; a Robin row (q - d/dv) at a
+    lower interface, (p + d/dv) at an upper one (q = p)."""
+    hv = 2.0 / nv
+    r = (T / nt) / hv ** 2
+    A = np.zeros((n, n))
+    for k in range(n):
+        A[k, k] = 1 + 2 * r
+        if k > 0:
+            A[k, k - 1] = -r
+        if k < n - 1:
+            A[k, k + 1] = -r
+    if lo_kind == 2:
+        A[0, :] = 0
+        A[0, 0], A[0, 1] = p + 1 / hv, -1 / hv
+    if hi_kind == 2:
+        A[n - 1, :] = 0
+        A[n - 1, n - 2], A[n - 1, n - 1] = -1 / hv, p + 1 / hv
+    return A
+
+
+def emulate_partitioned_solve(rows, segs, reds, P, d):
+    """The kernel's algorithm, step by step: local Thomas per segment with the
+    precomputed factors, reduced separator system, spike correction."""
+    n = len(d)
+    ys, first, last, sep = [], np.zeros(P), np.zeros(P), np.zeros(P)
+    for w in range(P):
+        s0, s1 = segs[w], segs[w + 1]
+        blk = (s1 - s0 - 1) if w < P - 1 else (s1 - s0)
+        y = np.zeros(blk)
+        for k in range(blk):
+            fa, fb = rows[s0 + k, 1], rows[s0 + k, 2]
+            y[k] = d[s0 + k] * fa if k == 0 else fb * y[k - 1] + d[s0 + k] * fa
+        for k in range(blk - 1, -1, -1):
+            if k < blk - 1:
+                y[k] = rows[s0 + k, 3] * y[k + 1] + y[k]
+        ys.append(y)
+        first[w], last[w] = y[0], y[-1]
+        if w < P - 1:
+            sep[w] = d[s1 - 1]
+    xi = np.zeros(max(P - 1, 0))
+    z = np.zeros(max(P - 1, 0))
+    for s in range(P - 1):
+        ra, rc, g1, g2, h = reds[s]
+        D = sep[s] - ra * last[s] - rc * first[s + 1]
+        z[s] = D * g1 if s == 0 else g2 * z[s - 1] + D * g1
+    for s in range(P - 2, -1, -1):
+        xi[s] = z[s] if s == P - 2 else reds[s, 4] * xi[s + 1] + z[s]
+    x = np.zeros(n)
+    for w in range(P):
+        s0 = segs[w]
+        xlo = xi[w - 1] if w >= 1 else 0.0
+        xhi = xi[w] if w < P - 1 else 0.0
+        y = ys[w]
+        for k in range(len(y)):
+            x[s0 + k] = y[k] - rows[s0 + k, 4] * xlo - rows[s0 + k, 5] * xhi
+        if w < P - 1:
+            x[s0 + len(y)] = xhi
+    return x
+
+
+@pytest.mark.parametrize("nx,nv,nt,T,J,o,tr,p", [
+    (64, 64, 200, 0.1, 2, 4, 0, 0.0),
+    (1024, 1024, 2000, 0.5, 8, 2, 1, 4.0),
+    (256, 256, 512, 0.5, 4, 2, 1, 4.0),
+    (128, 1024, 512, 0.25, 2, 2, 1, 4.0),
+    (64, 48, 100, 0.1, 3, 5, 1, 0.7),
+    (16, 16, 10, 0.1, 1, 0, 0, 0.0),
+])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16])
+def test_partitioned_tables_solve_the_paper_matrix(lib, nx, nv, nt, T, J, o, tr, p, waves):
+    info, rows, segs, reds, mat = get_tables(lib, nx, nv, nt, T, J, o, tr, p, waves)
+    rng = np.random.default_rng(waves + 10 * J)
+    hx, hv, dt = 1.0 / nx, 2.0 / nv, T / nt
+    red_off = 0
+    for j in range(J):
+        n, row_off, g_lo, P, lo_kind, hi_kind, tab, seg = info[j]
+        A = paper_matrix(nv, nt, T, g_lo, n, lo_kind, hi_kind, p)
+        sub = mat[tab:tab + n]
+        assert np.array_equal(np.diag(A), sub[:, 1])
+        assert np.array_equal(np.diag(A, -1), sub[1:, 0])
+        assert np.array_equal(np.diag(A, 1), sub[:-1, 2])
+        nu = (-1.0 + (g_lo + np.arange(n)) * hv) * dt / hx
+        assert np.allclose(rows[tab:tab + n, 0], nu, rtol=0, atol=1e-15)
+        assert P == max(1, min(waves, n // 2))
+        sg = segs[seg:seg + P + 1] - 0
+        assert sg[0] == 0 and sg[-1] == n and np.all(np.diff(sg) >= (1 if P == 1 else 1))
+        d = rng.standard_normal(n)
+        x = emulate_partitioned_solve(rows[tab:tab + n], sg, reds[red_off:red_off + P - 1], P, d)
+        ref = np.linalg.solve(A, d)
+        assert np.allclose(x, ref, rtol=0, atol=1e-12 * np.abs(ref).max()), (j, P)
+        red_off += P - 1
