@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the SWR hot path on one MI355X.
+
+Workload: x in [0,1) periodic with Nx = 1024, v in [-1,1] with Nv = 1024,
+T = 0.5, Nt = 2000, J = 8 equal v-subdomains, overlap 2 cells, Robin
+transmission; f and u0 each a sum of 16 Fourier x Legendre modes with N(0,1)
+coefficients from seed 0.  One step = one complete SWR solve to an absolute
+interface residual below 1e-10 (p = 8).  The p sweep {1, 2, 4, 8, 16} is
+reported beside the timed steps.
+
+Prints ONE JSON line.  `value` is subdomain cell-steps per second over the
+timed steps (inputs resident in HBM).  The roofline block is for the fused
+step kernel, timed live with HIP events on the stream it runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NX = NV = 1024
+NT, T = 2000, 0.5
+J, OVERLAP, TR = 8, 2, 1
+P_MAIN = 8.0
+P_SWEEP = (1.0, 2.0, 4.0, 8.0, 16.0)
+TOL = 1e-10
+HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BYTES_PER_CELL_STEP = 24.0  # one-step streaming: read U^n, read f, write U^{n+1} (FP64)
+# FP64 flops per cell-step of the fused step: transport + source (1 mul,
+# 2 fma), forward elimination (1 fma), back substitution (1 fma), segment
+# correction (2 fma) = 13 flops; the reduced separator system is not counted
+FLOPS_PER_CELL_STEP = 13.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-gb", type=float, default=None,
+                    help="HBM bytes per step-kernel launch measured by counters (GB)")
+    return ap.parse_args()
+
+
+def cpu_baseline():
+    """The oracle, untuned, on the host cores: one SWR iteration of the same
+    1024 x 1024, J = 8, Robin shape over the first 1000 time steps (same dt)."""
+    import oracle
+    from paper_1306_4596_amd import inputs
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    nt_s = 1000
+    u0, f = inputs.random_fields(0, NX, NV)
+    t0 = time.perf_counter()
+    oracle.swr_solve(u0, f, T * nt_s / NT, nt_s, J, OVERLAP, TR, p=P_MAIN, tol=1e-300,
+                     max_iter=1)
+    dt = time.perf_counter() - t0
+    rows = (NV - 1) + (J - 1) * (OVERLAP + 1)
+    cells = float(nt_s) * NX * rows
+    return {"value": cells / dt, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 SWR iteration, 1024x1024, J=8, Robin p=8, first {nt_s} of 2000 steps "
+                      f"({cells:.3e} cell-steps, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
+                                   "decomposition is described in DESIGN.md and not run",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_1306_4596_amd as kfp
+    from paper_1306_4596_amd import inputs
+
+    kfp.load_library()
+    dev = torch.device("cuda:0")
+    u0, f = inputs.random_fields(0, NX, NV)
+    U0 = torch.from_numpy(u0).to(dev)
+    F = torch.from_numpy(f).to(dev)
+    rows = kfp.subdomain_rows(NX, NV, NT, T, J, OVERLAP, TR)
+    waves, seg, kper = kfp.get_config(NX, NV, NT, T, J, OVERLAP, TR)
+
+    def solve(p):
+        return kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=p, tol=TOL, max_iter=1000,
+                             history=False)
+
+    for _ in range(args.warmup):
+        solve(P_MAIN)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cells = dev_s = 0.0
+    iters = []
+    for _ in range(args.steps):
+        _, _, st = solve(P_MAIN)
+        cells += st.cell_steps
+        dev_s += st.device_seconds
+        iters.append(st.iters)
+        if not st.residual < TOL:
+            raise SystemExit(f"solve did not converge: {st}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = cells / wall
+    # dominant kernel: the multi-step march kernel (steps per launch > 1) or
+    # the one-step kernel; its average duration comes from the library's HIP
+    # events on the stream the iteration graphs run on
+    if kper > 1:
+        launches = sum(iters) * (-(-NT // kper))
+        kname = "kfp::march_kernel"
+    else:
+        launches = sum(iters) * (NT + 1)
+        kname = "kfp::step_kernel"
+    avg_launch_s = dev_s / launches
+    steps_launch = NT / (launches / sum(iters))
+    cells_launch = NX * rows * steps_launch
+    flops_launch = FLOPS_PER_CELL_STEP * cells_launch
+    achieved = flops_launch / avg_launch_s / 1e12
+    stream_equiv = BYTES_PER_CELL_STEP * cells_launch / avg_launch_s / 1e9
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": args.traffic_gb, "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "flops_per_cell_step": FLOPS_PER_CELL_STEP, "cell_steps_per_launch": cells_launch,
+            "streaming_equivalent_GBps": round(stream_equiv, 1),
+            "streaming_equivalent_frac_of_hbm": round(stream_equiv / HBM_PEAK_GBPS, 4)}
+    out = {
+        "metric": "subdomain cell-timesteps/sec",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "SWR Kolmogorov 1024x1024 Nt=2000 T=0.5 J=8 overlap=2 Robin p=8 "
+                               "tol=1e-10, random Fourier-Legendre f,u0 seed 0",
+                   "nx": NX, "nv": NV, "nt": NT, "J": J, "overlap": OVERLAP, "p": P_MAIN,
+                   "tol": TOL, "waves": waves, "seg_max": seg, "steps_per_launch": kper},
+        "iters": iters,
+        "time_to_tol_s": wall / args.steps,
+        "effective_GBps": value * BYTES_PER_CELL_STEP / 1e9,
+        "roofline": roof,
+    }
+    if not args.no_sweep:
+        sweep = {}
+        for p in P_SWEEP:
+            t1 = time.perf_counter()
+            _, _, st = solve(p)
+            torch.cuda.synchronize()
+            sweep[str(p)] = {"iters": st.iters, "seconds": round(time.perf_counter() - t1, 4),
+                             "residual": st.residual}
+        out["p_sweep"] = sweep
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

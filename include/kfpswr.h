@@ -147,21 +147,25 @@ kfp_status kfp_swr_batch(int32_t n, const kfp_instance *inst, double tol, int32_
                          kfp_swr_stats *stats, void *stream);
 
 /*
- * Launch configuration of the fused step kernel.  waves = wavefronts per
- * workgroup, each owning one contiguous segment of a subdomain's unknown
- * rows for 64 x-columns (the segments are coupled through a small reduced
- * tridiagonal system); seg_max = largest segment the kernel holds in
- * registers.  kfp_tune times the candidates on the device for one shape and
- * stores the winner in the tuning cache (file named by $KFP_TUNE_CACHE,
- * default ~/.cache/kfpswr_tune.json); solves look the cache up.
- * kfp_set_config forces a configuration for subsequent calls (waves = 0
- * returns to automatic choice).
+ * Launch configuration.  waves = wavefronts per workgroup, each owning one
+ * contiguous segment of a subdomain's unknown rows for 64 x-columns (the
+ * segments are coupled through a small reduced tridiagonal system);
+ * seg_max = largest segment the kernel holds in registers (0: segments of
+ * any length staged through memory); steps = time steps per launch (1: one
+ * launch per step, the state streamed through memory; > 1: the multi-step
+ * kernel keeps the state on chip for `steps` steps, with a halo of `steps`
+ * columns on each side of a tile).  kfp_tune times the candidates on the
+ * device for one shape and stores the winner in the tuning cache (file named
+ * by $KFP_TUNE_CACHE, default ~/.cache/kfpswr_tune.json); solves look the
+ * cache up, else use a built-in choice.  kfp_set_config forces a
+ * configuration for subsequent calls (waves = 0 returns to automatic
+ * choice); KFP_EINVAL if it is not compiled.
  */
 kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, double p,
-                    int32_t *waves_out, int32_t *seg_max_out, void *stream);
-kfp_status kfp_set_config(int32_t waves, int32_t seg_max);
+                    int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out, void *stream);
+kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps);
 kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
-                          int32_t *waves_out, int32_t *seg_max_out);
+                          int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out);
 
 /* Unknown rows summed over the subdomains (the cell-steps of one SWR
  * iteration are nx * nt * rows).  [host] out. */

@@ -84,9 +84,10 @@ def load_library():
     lib.kfp_u0_guess.argtypes = [G, vp, i32, i32, i32, f64, vp, vp]
     lib.kfp_swr_batch.argtypes = [i32, ctypes.POINTER(Instance), f64, i32,
                                   ctypes.POINTER(Stats), vp]
-    lib.kfp_tune.argtypes = [G, i32, i32, i32, f64, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
-    lib.kfp_set_config.argtypes = [i32, i32]
-    lib.kfp_get_config.argtypes = [G, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    pi = ctypes.POINTER(i32)
+    lib.kfp_tune.argtypes = [G, i32, i32, i32, f64, pi, pi, pi, vp]
+    lib.kfp_set_config.argtypes = [i32, i32, i32]
+    lib.kfp_get_config.argtypes = [G, i32, i32, i32, pi, pi, pi]
     lib.kfp_subdomain_rows.argtypes = [G, i32, i32, i32, ctypes.POINTER(ctypes.c_int64)]
     lib.kfp_bw_probe.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.kfp_last_error.restype = ctypes.c_char_p
@@ -252,25 +253,28 @@ def swr_batch(instances, tol=1e-10, max_iter=200, history=False, stream=None):
 
 
 def tune(nx, nv, nt, T, J, overlap, transmission, p=1.0, stream=None):
-    """Times the compiled launch configurations for one shape; caches the winner."""
-    w, s = ctypes.c_int32(), ctypes.c_int32()
+    """Times the compiled launch configurations for one shape; caches the
+    winner.  Returns (waves, seg_max, steps)."""
+    w, s, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     g = _grid(nx, nv, nt, T)
     _check(load_library().kfp_tune(ctypes.byref(g), int(J), int(overlap), int(transmission),
-                                   float(p), ctypes.byref(w), ctypes.byref(s), _stream(stream)))
-    return w.value, s.value
+                                   float(p), ctypes.byref(w), ctypes.byref(s), ctypes.byref(k),
+                                   _stream(stream)))
+    return w.value, s.value, k.value
 
 
-def set_config(waves=0, seg_max=0):
-    """Forces a step-kernel configuration (waves=0: automatic)."""
-    _check(load_library().kfp_set_config(int(waves), int(seg_max)))
+def set_config(waves=0, seg_max=0, steps=1):
+    """Forces a launch configuration (waves=0: automatic)."""
+    _check(load_library().kfp_set_config(int(waves), int(seg_max), int(steps)))
 
 
 def get_config(nx, nv, nt, T, J, overlap, transmission):
-    w, s = ctypes.c_int32(), ctypes.c_int32()
+    """(waves, seg_max, steps) a solve of this shape would use."""
+    w, s, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     g = _grid(nx, nv, nt, T)
     _check(load_library().kfp_get_config(ctypes.byref(g), int(J), int(overlap), int(transmission),
-                                         ctypes.byref(w), ctypes.byref(s)))
-    return w.value, s.value
+                                         ctypes.byref(w), ctypes.byref(s), ctypes.byref(k)))
+    return w.value, s.value, k.value
 
 
 def subdomain_rows(nx, nv, nt, T, J, overlap, transmission):

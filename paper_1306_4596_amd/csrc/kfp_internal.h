@@ -24,6 +24,7 @@ struct InstDev {
   const double *g;              // [nt]: dt * s(t_{n+1})
   double *lam[2];               // [2(J-1)][nt][nx] each
   unsigned long long *res;      // residual of the running iteration (bits of a double >= 0)
+  double *V;                    // multi-step path: interface-node values [J-1][6][nt][nx]
   double r;                     // dt / h_v^2
   double p, q;                  // Robin parameters (q = p)
   double hv;                    // h_v
@@ -52,6 +53,8 @@ struct SubDev {
   int res_row_b_self; // local row of b_j here, -1: fixed node (use plane)
   int res_row_b_nb;   // local row of b_j in the neighbour
   int res_plane_a, res_plane_b;  // planes holding the fixed-node values (Dirichlet)
+  int pad;            // multi-step layout: leading identity rows of the last segment
+  int vsplit;         // first local row with v >= 0 (upwind neighbour at m-1)
 };
 
 // Per unknown row: transport weight and the factors of the local (segment)
@@ -63,6 +66,22 @@ struct RowCoef {
   double bc;  // -c' (multiplies the next backward value)
   double sl;  // spike: response of the segment to its lower separator
   double sr;  // spike: response of the segment to its upper separator
+};
+
+// Per padded row of the multi-step layout (every segment exactly SEG rows;
+// the last row of a non-final segment is its separator, the last segment
+// starts with `pad` identity rows).  The forward elimination is folded into
+// the transport: y_k = alpha u_k + beta u_nb + g fs_k + fb y_{k-1}, with
+// fs = fa f pre-scaled once per launch; the upwind neighbour u_nb is the
+// column at m-1 for v >= 0 and at m+1 for v < 0 (SubDev::vsplit).
+struct MarchCoef {
+  double alpha;  // fa (1 - |nu|)
+  double beta;   // fa |nu|
+  double fb;     // -sub / pivot
+  double bc;     // -c'
+  double sl, sr; // spikes (zero on separator and identity rows)
+  double fa;     // 1 / pivot (0 on Robin and identity rows: no source there)
+  double fab;    // 1 / pivot of an end row that takes boundary data, else 0
 };
 
 // Per separator row of the reduced system.
@@ -80,6 +99,12 @@ struct Item {
   int x0;
 };
 
+// One interface of one instance, for the exchange pass of the multi-step path.
+struct ExItem {
+  int inst;
+  int j;      // interface between subdomains j and j+1
+};
+
 struct StepTables {
   const InstDev *inst;
   const SubDev *subs;
@@ -87,8 +112,16 @@ struct StepTables {
   const RowCoef *rows;
   const RedCoef *reds;
   const int *segs;
+  const ExItem *ex;
+  const MarchCoef *mrows;
   int n_items;
+  int n_ex;
 };
+
+// Slots of the interface-node value planes written by the multi-step kernel:
+// the lower subdomain j gives u_j(a_{j+1}), u_j(a_{j+1}+1), u_j(b_j); the
+// upper one gives u_{j+1}(a_{j+1}), u_{j+1}(b_j), u_{j+1}(b_j - 1).
+enum VSlot : int { V_A_LO = 0, V_A1_LO = 1, V_B_LO = 2, V_A_HI = 3, V_B_HI = 4, V_B1_HI = 5 };
 
 // Kernel launchers (swr_kernels.hip).  Return hipSuccess or the launch error.
 // Step launch n: traces and residual of level n (1 <= n <= nt), then the step
@@ -96,6 +129,15 @@ struct StepTables {
 hipError_t launch_step(const StepTables &t, int waves, int seg_max, int n, int par, int grid,
                        hipStream_t s);
 bool step_config_supported(int waves, int seg_max);
+// Multi-step launch: advances every item by min(S, nt - n0) steps from level
+// n0, reading state parity `src` (u0 when n0 == 0) and writing 1 - src; the
+// tiles carry a halo of H >= S columns on both sides.
+hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int S, int H,
+                        int src, int par, int grid, hipStream_t s);
+bool march_config_supported(int waves, int seg_max);
+// Exchange pass of the multi-step path: traces (6.9)/(6.11) of every level
+// and the residual (6.12) from the interface-node value planes.
+hipError_t launch_exchange(const StepTables &t, int par, int nt_max, hipStream_t s);
 hipError_t launch_reset_res(const InstDev *inst, int n_inst, hipStream_t s);
 hipError_t launch_assemble(const double *Ufinal, const int *rowmap, double *uT, int nv, int nx,
                            hipStream_t s);

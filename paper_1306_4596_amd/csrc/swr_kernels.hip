@@ -18,6 +18,8 @@
 // 64 lanes read 512 contiguous bytes per row.  All arithmetic is FP64.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kfp_internal.h"
 
 namespace kfp {
@@ -181,12 +183,28 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
     if constexpr (SEGMAX > 0) {
       double d[SEGMAX];
       if (w < P) {
+        // rows past the segment re-read its last row, so every load is
+        // unconditional and the whole segment's loads are in flight at once
 #pragma unroll
         for (int k = 0; k < SEGMAX; ++k) {
-          if (k < len) {
-            const RowCoef c = rows[s0 + k];
-            d[k] = row_rhs(sd, I, c, s0 + k, src, fr, lin, plane, n, mc, gn);
-          }
+          const int i = s0 + (k < len ? k : len - 1);
+          const double nu = rows[i].nu;
+          int mn = mc + (nu > 0.0 ? -1 : (nu < 0.0 ? 1 : 0));
+          mn = mn < 0 ? mn + nx : (mn >= nx ? mn - nx : mn);
+          const double wgt = fabs(nu);
+          const double u = src[(size_t)i * nx + mc];
+          const double un = src[(size_t)i * nx + mn];
+          d[k] = (1.0 - wgt) * u + wgt * un + gn * fr[(size_t)i * nx + mc];
+        }
+        if (w == 0 && sd.lo_kind != END_PHYS) {
+          const double l = lin[(size_t)sd.lam_lo * plane + (size_t)n * nx + mc];
+          d[0] = sd.lo_kind == END_ROBIN ? l : d[0] + I.r * l;
+        }
+        if (w == P - 1 && sd.hi_kind != END_PHYS) {
+          const double l = lin[(size_t)sd.lam_hi * plane + (size_t)n * nx + mc];
+#pragma unroll
+          for (int k = 0; k < SEGMAX; ++k)
+            if (k == len - 1) d[k] = sd.hi_kind == END_ROBIN ? l : d[k] + I.r * l;
         }
         // local forward elimination
         double y = 0.0;
@@ -278,6 +296,366 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
       // the clamp keeps every access inside the row.
     }
     __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multi-step (temporally blocked) march kernel.  A workgroup owns one
+// subdomain's tile of 64 x-columns (one per lane) including a halo of H
+// columns on each side, keeps its column segments and the source rows in
+// registers, and advances S <= H steps without leaving the chip: the upwind
+// neighbour comes from the adjacent lane, and every step the valid lanes
+// shrink by one on each side, so lanes H .. 63-H are exact after S steps.
+// Interface-node values of every level go to value planes; the exchange
+// pass turns them into traces and the residual.
+// ---------------------------------------------------------------------------
+template <class T>
+using KConst = __attribute__((address_space(4))) const T;
+template <class T>
+__device__ __forceinline__ KConst<T> *as_const(const T *p) {
+  return (KConst<T> *)p;
+}
+
+// Upwind neighbour of every lane: lane i receives lane i-1 (v > 0, the cell
+// at m-1) or lane i+1 (v < 0, the cell at m+1) through a wave-wide DPP shift;
+// the edge lane keeps its own value (it is halo and becomes invalid anyway).
+__device__ __forceinline__ double from_lower_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), 0x138, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), 0x138, 0xf,
+                                             0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_upper_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), 0x130, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), 0x130, 0xf,
+                                             0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// A wave's column segment of SEG <= 32 rows held in registers.  Two vectors
+// of at most 16 doubles, so that a wave-uniform run-time index compiles to
+// relative register addressing (longer vectors would be spilled to scratch).
+template <int SEG>
+struct SegRegs {
+  static constexpr int NA = SEG < 16 ? SEG : 16;
+  static constexpr int NB = SEG > 16 ? SEG - 16 : 1;
+  typedef double va __attribute__((ext_vector_type(NA)));
+  typedef double vb __attribute__((ext_vector_type(NB)));
+  va a;
+  vb b;
+  template <int K>
+  __device__ __forceinline__ double ld() const {
+    if constexpr (K < 16) return a[K];
+    else return b[K - 16];
+  }
+  template <int K>
+  __device__ __forceinline__ void st(double v) {
+    if constexpr (K < 16) a[K] = v;
+    else b[K - 16] = v;
+  }
+  __device__ __forceinline__ double get(int k) const {
+    if (SEG <= 16 || k < 16) return a[k];
+    return b[k - 16];
+  }
+  __device__ __forceinline__ void set(int k, double v) {
+    if (SEG <= 16 || k < 16) a[k] = v;
+    else b[k - 16] = v;
+  }
+};
+
+template <int K, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (K < N) {
+    f(std::integral_constant<int, K>{});
+    static_for<K + 1, N>(f);
+  }
+}
+
+template <class T>
+using KGlob = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ KGlob<T> *as_glob(T *p) {
+  return (KGlob<T> *)p;
+}
+
+// Upwind direction of a wave's rows: all v < 0 (neighbour at m+1), all
+// v >= 0 (neighbour at m-1), or mixed (the wave holding v = 0).
+enum Dir : int { DIR_UP = 0, DIR_LO = 1, DIR_MIX = 2 };
+
+template <int SEG, int NW, int DIR>
+__device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG> &fs,
+                                              KConst<MarchCoef> *mc, double gn, int k0,
+                                              double blo, double bhi, int vsplit) {
+  double y = 0.0;
+  double na = mc[0].alpha, nbt = mc[0].beta, nf = mc[0].fb;
+  static_for<0, SEG>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double al = na, be = nbt, fbk = nf;
+    if constexpr (k + 1 < SEG) {
+      na = mc[k + 1].alpha;
+      nbt = mc[k + 1].beta;
+      nf = mc[k + 1].fb;
+    }
+    const double u = d.template ld<k>();
+    double nb;
+    if constexpr (DIR == DIR_LO) {
+      nb = from_lower_lane(u);
+    } else if constexpr (DIR == DIR_UP) {
+      nb = from_upper_lane(u);
+    } else {
+      const double a = from_lower_lane(u), c = from_upper_lane(u);
+      nb = (k >= vsplit) ? a : c;
+    }
+    double tk = fma(al, u, fma(be, nb, gn * fs.template ld<k>()));
+    if (k == k0) tk += blo;
+    if constexpr (k == SEG - 1) tk += bhi;
+    y = fma(fbk, y, tk);
+    d.template st<k>(y);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
+template <int SEG, int NW>
+__global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, int S, int H,
+                                                        int src_par, int par) {
+  __shared__ double sh_first[NW][64];
+  __shared__ double sh_last[NW][64];
+  __shared__ double sh_sep[NW][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  KConst<Item> *items = as_const(t.items);
+  KConst<SubDev> *subs = as_const(t.subs);
+  KConst<InstDev> *insts = as_const(t.inst);
+  for (int it = blockIdx.x; it < t.n_items; it += gridDim.x) {
+    const int sub = items[it].sub;
+    const int x0 = items[it].x0;
+    KConst<SubDev> *sd = subs + sub;
+    KConst<InstDev> *I = insts + sd->inst;
+    if (!I->active) continue;
+    const int nx = I->nx;
+    const int nt = I->nt;
+    if (n0 >= nt) continue;
+    const int steps = min(S, nt - n0);
+    const int rel = lane - H;
+    int col = (x0 + rel) % nx;
+    if (col < 0) col += nx;
+    const bool out = rel >= 0 && rel < 64 - 2 * H && x0 + rel < nx;
+    const size_t plane = (size_t)nt * nx;
+    const int n_rows = sd->n;
+    const int row_off = sd->row_off;
+    const int g_lo = sd->g_lo;
+    KGlob<const double> *src = as_glob((n0 == 0) ? I->u0 + (size_t)g_lo * nx
+                                                 : I->U[src_par] + (size_t)row_off * nx);
+    KGlob<double> *dst = as_glob(I->U[src_par ^ 1] + (size_t)row_off * nx);
+    KGlob<const double> *fr = as_glob(I->f + (size_t)g_lo * nx);
+    KGlob<const double> *lin = as_glob((const double *)I->lam[par]);
+    KGlob<const double> *gtab = as_glob(I->g);
+    KGlob<double> *Vbase = as_glob(I->V);
+    const double rr = I->r;
+    const bool robin = I->tr == 1;
+    const int P = sd->P;
+    const bool active = w < P;
+    const bool last = w == P - 1;
+    const int k0 = last ? sd->pad : 0;  // first real row in this wave's registers
+    const int base = w * SEG - k0;      // local row of register k is base + k
+    // rows with local index >= vsplit have v >= 0: upwind neighbour at m-1
+    const int vsplit = sd->vsplit - base;
+    const int dir = vsplit <= 0 ? DIR_LO : (vsplit >= SEG ? DIR_UP : DIR_MIX);
+    // coefficient tables are read through the constant address space, so
+    // every (wave-uniform) access is a scalar load
+    KConst<MarchCoef> *mc0 = as_const(t.mrows) + sd->tab + w * SEG;
+    KConst<RedCoef> *rc0 = as_const(t.reds) + sd->red;
+    const int lo_kind = sd->lo_kind, hi_kind = sd->hi_kind;
+    const int lam_lo = sd->lam_lo, lam_hi = sd->lam_hi;
+    const int out_hi_plane = sd->out_hi_plane, out_hi_row = sd->out_hi_row;
+    const int out_lo_plane = sd->out_lo_plane, out_lo_row = sd->out_lo_row;
+    SegRegs<SEG> d, fs;
+    if (active) {
+      static_for<0, SEG>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int r = max(base + k, 0);
+        d.template st<k>(src[(size_t)r * nx + col]);
+        fs.template st<k>(mc0[k].fa * fr[(size_t)r * nx + col]);
+      });
+    }
+    // end rows taking boundary data: row 0 in wave 0, row n-1 in the last wave
+    const bool lo_end = active && w == 0 && lo_kind != END_PHYS;
+    const bool hi_end = active && last && hi_kind != END_PHYS;
+    const double lo_scale = lo_end ? mc0[k0].fab * (lo_kind == END_ROBIN ? 1.0 : rr) : 0.0;
+    const double hi_scale = hi_end ? mc0[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : rr) : 0.0;
+    KGlob<const double> *lin_lo = lin + (size_t)(lam_lo > 0 ? lam_lo : 0) * plane + col;
+    KGlob<const double> *lin_hi = lin + (size_t)(lam_hi > 0 ? lam_hi : 0) * plane + col;
+    // boundary data of the first step, then prefetched one step ahead
+    double nlo = lo_end ? lin_lo[(size_t)n0 * nx] : 0.0;
+    double nhi = hi_end ? lin_hi[(size_t)n0 * nx] : 0.0;
+    for (int s = 0; s < steps; ++s) {
+      const int n = n0 + s;
+      double xlo = 0.0, xhi = 0.0;
+      // loop-variant table pointers: the tables are re-read row by row
+      // through the scalar cache instead of being pinned in registers
+      int zoff = 0;
+      asm volatile("" : "+s"(zoff));
+      KConst<MarchCoef> *mc = mc0 + zoff;
+      KConst<RedCoef> *rcs = rc0 + zoff;
+      if (active) {
+        const double gn = gtab[n];
+        const double blo = lo_scale * nlo;
+        const double bhi = hi_scale * nhi;
+        if (s + 1 < steps) {
+          if (lo_end) nlo = lin_lo[(size_t)(n + 1) * nx];
+          if (hi_end) nhi = lin_hi[(size_t)(n + 1) * nx];
+        }
+        // transport + source + forward elimination, one pass
+        if (dir == DIR_LO)
+          march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, k0, blo, bhi, vsplit);
+        else if (dir == DIR_UP)
+          march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, k0, blo, bhi, vsplit);
+        else
+          march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, k0, blo, bhi, vsplit);
+        // back substitution
+        double x = d.template ld<SEG - 1>();
+        double nbc = mc[SEG - 2 >= 0 ? SEG - 2 : 0].bc;
+        static_for<0, SEG - 1>([&](auto kc) {
+          constexpr int k = SEG - 2 - decltype(kc)::value;
+          const double bck = nbc;
+          if constexpr (k - 1 >= 0) nbc = mc[k - 1].bc;
+          x = fma(bck, x, d.template ld<k>());
+          d.template st<k>(x);
+          __builtin_amdgcn_sched_barrier(0);
+        });
+        if (P > 1) {
+          sh_first[w][lane] = d.get(k0);
+          sh_last[w][lane] = d.template ld<SEG - 2>();
+          sh_sep[w][lane] = d.template ld<SEG - 1>();
+        }
+      }
+      if (P > 1) {
+        __syncthreads();
+        if (active) {
+          // reduced separator system, per column, from LDS
+          double z[NW > 1 ? NW - 1 : 1];
+          double prev = 0.0;
+#pragma unroll
+          for (int q = 0; q < NW - 1; ++q) {
+            if (q < P - 1) {
+              const double D = sh_sep[q][lane] - rcs[q].ra * sh_last[q][lane] -
+                               rcs[q].rc * sh_first[q + 1][lane];
+              prev = (q == 0) ? D * rcs[q].g1 : fma(rcs[q].g2, prev, D * rcs[q].g1);
+              z[q] = prev;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          double nxt = 0.0;
+#pragma unroll
+          for (int q = NW - 2; q >= 0; --q) {
+            if (q < P - 1) {
+              nxt = (q == P - 2) ? z[q] : fma(rcs[q].h, nxt, z[q]);
+              if (q == w - 1) xlo = nxt;
+              if (q == w) xhi = nxt;
+            }
+          }
+        }
+      }
+      if (active) {
+        double nsl = mc[0].sl, nsr = mc[0].sr;
+        static_for<0, SEG>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double slk = nsl, srk = nsr;
+          if constexpr (k + 1 < SEG) {
+            nsl = mc[k + 1].sl;
+            nsr = mc[k + 1].sr;
+          }
+          d.template st<k>(fma(-slk, xlo, fma(-srk, xhi, d.template ld<k>())));
+          __builtin_amdgcn_sched_barrier(0);
+        });
+        if (!last) d.template st<SEG - 1>(xhi);
+        // interface-node values of level n+1
+        const size_t lvl = (size_t)n * nx + col;
+        if (out_hi_plane >= 0) {
+          KGlob<double> *Vj = Vbase + (size_t)(out_hi_plane >> 1) * 6 * plane + lvl;
+          int r = out_hi_row - base;
+          if (r >= k0 && r < SEG && out) Vj[V_A_LO * plane] = d.get(r);
+          if (robin) {
+            r = out_hi_row + 1 - base;
+            if (r >= k0 && r < SEG && out) Vj[V_A1_LO * plane] = d.get(r);
+            r = n_rows - 1 - base;
+            if (r >= k0 && r < SEG && out) Vj[V_B_LO * plane] = d.get(r);
+          }
+        }
+        if (out_lo_plane >= 0) {
+          KGlob<double> *Vj = Vbase + (size_t)((out_lo_plane - 1) >> 1) * 6 * plane + lvl;
+          int r = out_lo_row - base;
+          if (r >= k0 && r < SEG && out) Vj[V_B_HI * plane] = d.get(r);
+          if (robin) {
+            r = out_lo_row - 1 - base;
+            if (r >= k0 && r < SEG && out) Vj[V_B1_HI * plane] = d.get(r);
+            r = -base;
+            if (r >= k0 && r < SEG && out) Vj[V_A_HI * plane] = d.get(r);
+          }
+        }
+      }
+      if (P > 1) __syncthreads();  // the next step rewrites the LDS slots
+    }
+    if (active && out) {
+      static_for<0, SEG>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (k >= k0) dst[(size_t)(base + k) * nx + col] = d.template ld<k>();
+      });
+    }
+  }
+}
+
+// Traces of every level and the residual of one interface, from the value
+// planes: lambda_{j->j+1} = Q_2 u_j at a_{j+1}, lambda_{j+1->j} = Q_1 u_{j+1}
+// at b_j, and max |u_j - u_{j+1}| at the two end nodes of the overlap.
+__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par) {
+  __shared__ unsigned long long red[4];
+  const ExItem ex = t.ex[blockIdx.y];
+  const InstDev &I = t.inst[ex.inst];
+  if (!I.active) return;
+  const size_t plane = (size_t)I.nt * I.nx;
+  const int j = ex.j;
+  const double *V = I.V + (size_t)j * 6 * plane;
+  const double *lin = I.lam[par];
+  double *lout = I.lam[par ^ 1];
+  const bool robin = I.tr == 1;
+  unsigned long long r = 0ull;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double ua = V[V_A_LO * plane + e];
+    const double ubh = V[V_B_HI * plane + e];
+    double toR = ua, toL = ubh, ub_lo, ua_hi;
+    if (robin) {
+      const double ua1 = V[V_A1_LO * plane + e];
+      const double ub1h = V[V_B1_HI * plane + e];
+      toR = I.q * ua - (ua1 - ua) / I.hv;
+      toL = I.p * ubh + (ubh - ub1h) / I.hv;
+      ub_lo = V[V_B_LO * plane + e];
+      ua_hi = V[V_A_HI * plane + e];
+    } else {
+      ub_lo = lin[(size_t)(2 * j + 1) * plane + e];
+      ua_hi = lin[(size_t)(2 * j) * plane + e];
+    }
+    lout[(size_t)(2 * j) * plane + e] = toR;
+    lout[(size_t)(2 * j + 1) * plane + e] = toL;
+    const unsigned long long ra = (unsigned long long)__double_as_longlong(fabs(ua - ua_hi));
+    const unsigned long long rb = (unsigned long long)__double_as_longlong(fabs(ub_lo - ubh));
+    r = ra > r ? ra : r;
+    r = rb > r ? rb : r;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(r, off, 64);
+    r = o > r ? o : r;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = red[0];
+    for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
+    if (m) atomicMax(I.res, m);
   }
 }
 
@@ -427,6 +805,41 @@ bool step_config_supported(int waves, int seg_max) {
   KFP_STEP_CONFIGS(KFP_CHECK)
 #undef KFP_CHECK
   return false;
+}
+
+#define KFP_MARCH_CONFIGS(X) \
+  X(1, 4) X(1, 8) X(1, 12) X(1, 16) X(1, 24) X(1, 32) \
+  X(2, 4) X(2, 8) X(2, 12) X(2, 16) X(2, 24) X(2, 32) \
+  X(4, 4) X(4, 6) X(4, 8) X(4, 12) X(4, 16) X(4, 20) X(4, 24) X(4, 32) \
+  X(8, 4) X(8, 6) X(8, 8) X(8, 10) X(8, 12) X(8, 14) X(8, 17) X(8, 20) X(8, 24) \
+  X(16, 4) X(16, 6) X(16, 8) X(16, 9) X(16, 10) X(16, 12)
+
+bool march_config_supported(int waves, int seg_max) {
+#define KFP_CHECK(W, S) \
+  if (waves == W && seg_max == S) return true;
+  KFP_MARCH_CONFIGS(KFP_CHECK)
+#undef KFP_CHECK
+  return false;
+}
+
+hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int S, int H,
+                        int src, int par, int grid, hipStream_t s) {
+#define KFP_LAUNCH(W, SM)                                                                   \
+  if (waves == W && seg_max == SM) {                                                       \
+    hipLaunchKernelGGL((march_kernel<SM, W>), dim3(grid), dim3(W * 64), 0, s, t, n0, S, H, \
+                       src, par);                                                          \
+    return hipGetLastError();                                                              \
+  }
+  KFP_MARCH_CONFIGS(KFP_LAUNCH)
+#undef KFP_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_exchange(const StepTables &t, int par, int nt_max, hipStream_t s) {
+  (void)nt_max;
+  if (t.n_ex == 0) return hipSuccess;
+  hipLaunchKernelGGL(exchange_kernel, dim3(256, t.n_ex), dim3(256), 0, s, t, par);
+  return hipGetLastError();
 }
 
 hipError_t launch_step(const StepTables &t, int waves, int seg_max, int n, int par, int grid,

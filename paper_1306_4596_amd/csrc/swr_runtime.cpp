@@ -140,10 +140,28 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
 struct Config {
   int waves = 0;
   int seg = 0;
+  int steps = 1;  // time steps per launch: 1 = step kernel, > 1 = march kernel
 };
+
+static bool config_supported(const Config &c) {
+  return c.steps == 1 ? step_config_supported(c.waves, c.seg)
+                      : (c.steps >= 2 && c.steps <= 24 && march_config_supported(c.waves, c.seg));
+}
 
 static const int kWaves[] = {1, 2, 4, 8, 16};
 static const int kSegs[] = {8, 16, 24, 32, 48, 64};
+
+// Does a multi-step configuration hold every subdomain (P = ceil(n/SEG) <= waves)?
+static bool march_fits(int n_max, int waves, int seg) {
+  return seg >= 2 && (n_max + seg - 1) / seg <= waves;
+}
+
+// Smallest compiled multi-step segment length for `waves` wavefronts, 0 if none.
+static int march_seg_for(int n_max, int waves) {
+  for (int sm = 2; sm <= 64; ++sm)
+    if (march_fits(n_max, waves, sm) && march_config_supported(waves, sm)) return sm;
+  return 0;
+}
 
 static int segs_for(int n, int waves) {
   const int P = std::max(1, std::min(waves, n / 2));
@@ -196,8 +214,8 @@ static std::map<std::string, Config> load_tune() {
     if (e == std::string::npos) break;
     std::string key = s.substr(pos + 1, e - pos - 1);
     Config c;
-    if (sscanf(s.c_str() + e + 1, " : [ %d , %d ]", &c.waves, &c.seg) == 2 &&
-        step_config_supported(c.waves, c.seg))
+    if (sscanf(s.c_str() + e + 1, " : [ %d , %d , %d ]", &c.waves, &c.seg, &c.steps) == 3 &&
+        config_supported(c))
       out[key] = c;
     pos = e + 1;
   }
@@ -218,8 +236,8 @@ static void save_tune(const std::map<std::string, Config> &m) {
   fprintf(fp, "{\n");
   size_t i = 0;
   for (auto &kv : m)
-    fprintf(fp, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.seg,
-            ++i < m.size() ? "," : "");
+    fprintf(fp, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.seg,
+            kv.second.steps, ++i < m.size() ? "," : "");
   fprintf(fp, "}\n");
   fclose(fp);
   rename(tmp.c_str(), path.c_str());
@@ -247,13 +265,30 @@ static std::map<std::string, Config> *g_tune = nullptr;
 static Config choose_config(const Geo &g) {
   if (g_forced.waves > 0) {
     Config c = g_forced;
-    if (c.seg > 0 && segs_for(g.n_max, c.waves) > c.seg) c.seg = seg_for(g.n_max, c.waves);
+    if (c.steps > 1 && !march_fits(g.n_max, c.waves, c.seg)) {
+      const int sm = march_seg_for(g.n_max, c.waves);
+      if (sm) {
+        c.seg = sm;  // widen to the next compiled segment length
+      } else {
+        c.steps = 1;  // no register segment holds it: one launch per step
+        c.seg = seg_for(g.n_max, c.waves);
+      }
+    }
+    if (c.steps == 1 && c.seg > 0 && segs_for(g.n_max, c.waves) > c.seg)
+      c.seg = seg_for(g.n_max, c.waves);
     return c;
   }
   if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
   auto it = g_tune->find(tune_key(g));
   if (it != g_tune->end() && (it->second.seg == 0 || segs_for(g.n_max, it->second.waves) <= it->second.seg))
     return it->second;
+  if (g.J > 0 && g.nx > 0) {
+    // multi-step march by default when a segment of at most 24 rows fits
+    for (int w : kWaves) {
+      const int sm = march_seg_for(g.n_max, w);
+      if (sm && sm <= 24) return Config{w, sm, g.nx >= 128 ? 16 : 8};
+    }
+  }
   return default_config(g.n_max);
 }
 
@@ -261,9 +296,11 @@ static Config choose_config(const Geo &g) {
 struct HostTables {
   std::vector<SubDev> subs;
   std::vector<RowCoef> rows;
+  std::vector<MarchCoef> mrows;
   std::vector<RedCoef> reds;
   std::vector<int> segs;
   std::vector<Item> items;
+  std::vector<ExItem> ex;
 };
 
 // Row coefficients of subdomain s (local rows 0..n-1):  lo x_{k-1} + di x_k + up x_{k+1}.
@@ -306,6 +343,13 @@ static void add_subdomain(const Geo &g, int j, double p, int waves, int inst, in
   d.P = P;
   d.lo_kind = s.lo_kind;
   d.hi_kind = s.hi_kind;
+  {
+    // v_i = -1 + i h_v >= 0 from the first node at or above v = 0
+    const double hv = 2.0 / g.nv;
+    int i = 0;
+    while (i <= g.nv && -1.0 + i * hv < 0.0) ++i;
+    d.vsplit = i - s.lo;
+  }
   d.lam_lo = j > 0 ? 2 * (j - 1) : -1;
   d.lam_hi = j < g.J - 1 ? 2 * j + 1 : -1;
   d.out_hi_plane = j < g.J - 1 ? 2 * j : -1;
@@ -417,17 +461,206 @@ static void add_subdomain(const Geo &g, int j, double p, int waves, int inst, in
   }
 }
 
+// Thomas factors of the block [r0, r1] of a tridiagonal matrix and the two
+// spikes (responses to the couplings lo[r0] below and up[r1] above).
+struct BlockFactors {
+  std::vector<double> piv, cp, gL, gR;
+};
+
+static BlockFactors factor_block(const std::vector<double> &lo, const std::vector<double> &di,
+                                 const std::vector<double> &up, int r0, int r1, bool below,
+                                 bool above) {
+  BlockFactors b;
+  const int nb = r1 - r0 + 1;
+  b.piv.resize(nb);
+  b.cp.resize(nb);
+  for (int k = 0; k < nb; ++k) {
+    const int i = r0 + k;
+    b.piv[k] = (k == 0) ? di[i] : di[i] - lo[i] * b.cp[k - 1];
+    b.cp[k] = (k < nb - 1) ? up[i] / b.piv[k] : 0.0;
+  }
+  auto solve = [&](std::vector<double> rhs) {
+    std::vector<double> y(nb), x(nb);
+    for (int k = 0; k < nb; ++k) y[k] = (k == 0 ? rhs[k] : rhs[k] - lo[r0 + k] * y[k - 1]) / b.piv[k];
+    for (int k = nb - 1; k >= 0; --k) x[k] = (k == nb - 1) ? y[k] : y[k] - b.cp[k] * x[k + 1];
+    return x;
+  };
+  b.gL.assign(nb, 0.0);
+  b.gR.assign(nb, 0.0);
+  if (below) {
+    std::vector<double> e(nb, 0.0);
+    e[0] = lo[r0];
+    b.gL = solve(e);
+  }
+  if (above) {
+    std::vector<double> e(nb, 0.0);
+    e[nb - 1] = up[r1];
+    b.gR = solve(e);
+  }
+  return b;
+}
+
+// Subdomain descriptor fields shared by both layouts.
+static SubDev sub_descriptor(const Geo &g, int j, int inst, int sub_base) {
+  const SubGeo &s = g.sub[j];
+  SubDev d{};
+  d.inst = inst;
+  d.n = s.n;
+  d.row_off = g.row_off[j];
+  d.g_lo = s.lo;
+  d.lo_kind = s.lo_kind;
+  d.hi_kind = s.hi_kind;
+  {
+    // v_i = -1 + i h_v >= 0 from the first node at or above v = 0
+    const double hv = 2.0 / g.nv;
+    int i = 0;
+    while (i <= g.nv && -1.0 + i * hv < 0.0) ++i;
+    d.vsplit = i - s.lo;
+  }
+  d.lam_lo = j > 0 ? 2 * (j - 1) : -1;
+  d.lam_hi = j < g.J - 1 ? 2 * j + 1 : -1;
+  d.out_hi_plane = j < g.J - 1 ? 2 * j : -1;
+  d.out_hi_row = j < g.J - 1 ? g.sub[j + 1].a - s.lo : -1;
+  d.out_lo_plane = j > 0 ? 2 * (j - 1) + 1 : -1;
+  d.out_lo_row = j > 0 ? g.sub[j - 1].b - s.lo : -1;
+  if (j < g.J - 1) {
+    const SubGeo &nb = g.sub[j + 1];
+    d.res_nb = sub_base + j + 1;
+    d.res_row_a_nb = nb.lo_kind == END_ROBIN ? nb.a - nb.lo : -1;
+    d.res_row_b_self = s.hi_kind == END_ROBIN ? s.b - s.lo : -1;
+    d.res_row_b_nb = s.b - nb.lo;
+    d.res_plane_a = 2 * j;
+    d.res_plane_b = 2 * j + 1;
+  } else {
+    d.res_nb = -1;
+    d.res_row_a_nb = d.res_row_b_self = d.res_row_b_nb = -1;
+    d.res_plane_a = d.res_plane_b = -1;
+  }
+  return d;
+}
+
+// Tables of one subdomain in the multi-step layout: P = ceil(n / SEG)
+// segments of exactly SEG rows; a non-final segment ends with its separator;
+// the final one starts with pad = P SEG - n identity rows.
+static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst, int sub_base,
+                                HostTables &t) {
+  const SubGeo &s = g.sub[j];
+  const double hx = 1.0 / g.nx, hv = 2.0 / g.nv, dt = g.T / g.nt, r = dt / (hv * hv);
+  const int n = s.n;
+  const int P = (n + seg - 1) / seg;
+  const int pad = P * seg - n;
+  std::vector<double> lo, di, up;
+  row_matrix(s, r, p, p, hv, lo, di, up);
+  SubDev d = sub_descriptor(g, j, inst, sub_base);
+  d.tab = (int)t.mrows.size();
+  d.seg = -1;
+  d.red = (int)t.reds.size();
+  d.P = P;
+  d.pad = pad;
+  t.subs.push_back(d);
+  std::vector<MarchCoef> mc((size_t)P * seg);
+  for (auto &c : mc) c = MarchCoef{0, 0, 0, 0, 0, 0, 0, 0};
+  // block w covers real rows [b0, b1]; separators at w*seg + seg - 1
+  std::vector<BlockFactors> bf(P);
+  std::vector<int> b0(P), b1(P);
+  for (int w = 0; w < P; ++w) {
+    b0[w] = w * seg;
+    b1[w] = (w < P - 1) ? w * seg + seg - 2 : n - 1;
+    bf[w] = factor_block(lo, di, up, b0[w], b1[w], w > 0, w < P - 1);
+  }
+  auto is_robin = [&](int i) {
+    return (i == 0 && s.lo_kind == END_ROBIN) || (i == n - 1 && s.hi_kind == END_ROBIN);
+  };
+  auto takes_data = [&](int i) {
+    return (i == 0 && s.lo_kind != END_PHYS) || (i == n - 1 && s.hi_kind != END_PHYS);
+  };
+  for (int w = 0; w < P; ++w) {
+    const int k0 = (w == P - 1) ? pad : 0;
+    for (int k = k0; k < seg; ++k) {
+      const int i = w * seg + k - k0;  // local row
+      MarchCoef &c = mc[(size_t)w * seg + k];
+      const double nu = (-1.0 + (s.lo + i) * hv) * dt / hx;
+      const double wgt = std::fabs(nu);
+      if (w < P - 1 && k == seg - 1) {  // separator: identity in the local solve
+        c.alpha = 1.0 - wgt;
+        c.beta = wgt;
+        c.fa = 1.0;
+        c.fb = c.bc = c.sl = c.sr = 0.0;
+        c.fab = takes_data(i) ? 1.0 : 0.0;
+        continue;
+      }
+      const int kb = i - b0[w];
+      const double fa = 1.0 / bf[w].piv[kb];
+      const bool rob = is_robin(i);
+      c.alpha = rob ? 0.0 : fa * (1.0 - wgt);
+      c.beta = rob ? 0.0 : fa * wgt;
+      c.fa = rob ? 0.0 : fa;
+      c.fb = (kb == 0) ? 0.0 : -lo[i] * fa;
+      c.bc = (i < b1[w]) ? -bf[w].cp[kb] : 0.0;
+      c.sl = bf[w].gL[kb];
+      c.sr = bf[w].gR[kb];
+      c.fab = takes_data(i) ? fa : 0.0;
+    }
+  }
+  for (auto &c : mc) t.mrows.push_back(c);
+  if (P > 1) {
+    const int m = P - 1;
+    std::vector<double> al(m), be(m), ga(m);
+    for (int sgi = 0; sgi < m; ++sgi) {
+      const int rho = sgi * seg + seg - 1;
+      const double a_r = lo[rho], c_r = up[rho];
+      al[sgi] = -a_r * bf[sgi].gL.back();
+      be[sgi] = di[rho] - a_r * bf[sgi].gR.back() - c_r * bf[sgi + 1].gL.front();
+      ga[sgi] = -c_r * bf[sgi + 1].gR.front();
+      RedCoef c{};
+      c.ra = a_r;
+      c.rc = c_r;
+      t.reds.push_back(c);
+    }
+    double cprev = 0.0;
+    for (int sgi = 0; sgi < m; ++sgi) {
+      const double piv = (sgi == 0) ? be[0] : be[sgi] - al[sgi] * cprev;
+      const double cpk = (sgi < m - 1) ? ga[sgi] / piv : 0.0;
+      RedCoef &c = t.reds[d.red + sgi];
+      c.g1 = 1.0 / piv;
+      c.g2 = (sgi == 0) ? 0.0 : -al[sgi] / piv;
+      c.h = -cpk;
+      cprev = cpk;
+    }
+  }
+}
+
 static void add_instance(const Geo &g, double p, int waves, int inst, HostTables &t) {
   const int sub_base = (int)t.subs.size();
   for (int j = 0; j < g.J; ++j) add_subdomain(g, j, p, waves, inst, sub_base, t);
 }
 
-static void make_items(const Geo &g, int sub_base, std::vector<Item> &items) {
+static void add_instance_cfg(const Geo &g, double p, int waves, int seg, int steps, int inst,
+                             HostTables &t) {
+  if (steps == 1) {
+    add_instance(g, p, waves, inst, t);
+    return;
+  }
+  const int sub_base = (int)t.subs.size();
+  for (int j = 0; j < g.J; ++j) add_subdomain_march(g, j, p, seg, inst, sub_base, t);
+}
+
+
+
+// Output tile width of a configuration: 64 lanes, minus the halo of the
+// multi-step kernel on both sides.
+static int tile_width(const Config &c) { return c.steps > 1 ? 64 - 2 * c.steps : 64; }
+
+static void make_items(const Geo &g, int sub_base, int width, std::vector<Item> &items) {
   // subdomain-fastest order: consecutive workgroups (and so the XCDs they are
   // dealt to round-robin) take different subdomains of the same x-range
-  const int tiles = (g.nx + 63) / 64;
+  const int tiles = (g.nx + width - 1) / width;
   for (int x = 0; x < tiles; ++x)
-    for (int j = 0; j < g.J; ++j) items.push_back(Item{sub_base + j, x * 64});
+    for (int j = 0; j < g.J; ++j) items.push_back(Item{sub_base + j, x * width});
+}
+
+static void make_ex(const Geo &g, int inst, std::vector<ExItem> &ex) {
+  for (int j = 0; j + 1 < g.J; ++j) ex.push_back(ExItem{inst, j});
 }
 
 // ------------------------------------------------------------------ device --
@@ -459,6 +692,8 @@ struct DevTables {
   DevBuf<RowCoef> rows;
   DevBuf<RedCoef> reds;
   DevBuf<int> segs;
+  DevBuf<ExItem> ex;
+  DevBuf<MarchCoef> mrows;
   StepTables view() const {
     StepTables t;
     t.inst = inst.p;
@@ -467,7 +702,10 @@ struct DevTables {
     t.rows = rows.p;
     t.reds = reds.p;
     t.segs = segs.p;
+    t.ex = ex.p;
+    t.mrows = mrows.p;
     t.n_items = (int)items.n;
+    t.n_ex = (int)ex.n;
     return t;
   }
   hipError_t upload(const HostTables &h, const std::vector<InstDev> &in, hipStream_t s) {
@@ -478,7 +716,10 @@ struct DevTables {
     if ((e = rows.alloc(h.rows.size())) != hipSuccess) return e;
     if ((e = reds.alloc(std::max<size_t>(h.reds.size(), 1))) != hipSuccess) return e;
     if ((e = segs.alloc(h.segs.size())) != hipSuccess) return e;
+    if ((e = ex.alloc(std::max<size_t>(h.ex.size(), 1))) != hipSuccess) return e;
+    if ((e = mrows.alloc(std::max<size_t>(h.mrows.size(), 1))) != hipSuccess) return e;
     items.n = h.items.size();
+    ex.n = h.ex.size();
     auto cp = [&](void *d, const void *src, size_t bytes) {
       return bytes ? hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
@@ -488,6 +729,9 @@ struct DevTables {
     if ((e = cp(rows.p, h.rows.data(), h.rows.size() * sizeof(RowCoef))) != hipSuccess) return e;
     if ((e = cp(reds.p, h.reds.data(), h.reds.size() * sizeof(RedCoef))) != hipSuccess) return e;
     if ((e = cp(segs.p, h.segs.data(), h.segs.size() * sizeof(int))) != hipSuccess) return e;
+    if ((e = cp(ex.p, h.ex.data(), h.ex.size() * sizeof(ExItem))) != hipSuccess) return e;
+    if ((e = cp(mrows.p, h.mrows.data(), h.mrows.size() * sizeof(MarchCoef))) != hipSuccess)
+      return e;
     return hipStreamSynchronize(s);  // host vectors may go out of scope
   }
   void release() {
@@ -497,6 +741,8 @@ struct DevTables {
     rows.release();
     reds.release();
     segs.release();
+    ex.release();
+    mrows.release();
   }
 };
 
@@ -512,7 +758,7 @@ struct Plan {
   Geo geo;
   Config cfg;
   DevTables dt;
-  DevBuf<double> U0, U1, lam0, lam1, g;
+  DevBuf<double> U0, U1, lam0, lam1, g, V;
   DevBuf<int> rowmap, ab;
   DevBuf<unsigned long long> res;
   DevBuf<unsigned int> cnt;
@@ -530,6 +776,7 @@ struct Plan {
     lam0.release();
     lam1.release();
     g.release();
+    V.release();
     rowmap.release();
     ab.release();
     res.release();
@@ -549,8 +796,8 @@ static const size_t kMaxPlans = 3;
 
 static std::string plan_key(const Geo &g, const Config &c) {
   char buf[200];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/s%d", g.nx, g.nv, g.nt, g.J, g.o, g.tr, c.waves,
-           c.seg);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/s%d/k%d", g.nx, g.nv, g.nt, g.J, g.o, g.tr,
+           c.waves, c.seg, c.steps);
   return buf;
 }
 
@@ -577,6 +824,7 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
   HIP_TRY(pl->lam0.alloc(std::max<size_t>(win, 1)));
   HIP_TRY(pl->lam1.alloc(std::max<size_t>(win, 1)));
   HIP_TRY(pl->g.alloc(geo.nt));
+  if (cfg.steps > 1 && geo.J > 1) HIP_TRY(pl->V.alloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx));
   HIP_TRY(pl->rowmap.alloc(geo.nv + 1));
   HIP_TRY(pl->ab.alloc(std::max(2 * (geo.J - 1), 1)));
   HIP_TRY(pl->res.alloc(1));
@@ -607,8 +855,9 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
                                 double p) {
   const Geo &geo = pl.geo;
   HostTables h;
-  add_instance(geo, p, pl.cfg.waves, 0, h);
-  make_items(geo, 0, h.items);
+  add_instance_cfg(geo, p, pl.cfg.waves, pl.cfg.seg, pl.cfg.steps, 0, h);
+  make_items(geo, 0, tile_width(pl.cfg), h.items);
+  make_ex(geo, 0, h.ex);
   InstDev in{};
   in.U[0] = pl.U0.p;
   in.U[1] = pl.U1.p;
@@ -618,6 +867,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   in.lam[0] = pl.lam0.p;
   in.lam[1] = pl.lam1.p;
   in.res = pl.res.p;
+  in.V = pl.V.p;
   const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt;
   in.r = dt / (hv * hv);
   in.p = p;
@@ -635,11 +885,25 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   return KFP_OK;
 }
 
+// Number of state ping-pong flips of one window: the parity of U holding the
+// final state is launches & 1.
+static int march_launches(int nt, const Config &cfg) {
+  return cfg.steps > 1 ? (nt + cfg.steps - 1) / cfg.steps : nt;
+}
+
 static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const InstDev *inst,
                                           const Config &cfg, int nt, int par, int grid,
                                           hipStream_t s) {
   HIP_TRY(launch_reset_res(inst, n_inst, s));
-  for (int n = 0; n <= nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, par, grid, s));
+  if (cfg.steps == 1) {
+    for (int n = 0; n <= nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, par, grid, s));
+  } else {
+    const int L = march_launches(nt, cfg);
+    for (int l = 0; l < L; ++l)
+      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, cfg.steps, l & 1, par,
+                           grid, s));
+    HIP_TRY(launch_exchange(t, par, nt, s));
+  }
   return KFP_OK;
 }
 
@@ -761,7 +1025,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   }
   const bool converged = k <= max_iter;
   if (!converged) k = max_iter;
-  double *Ufin = (geo.nt & 1) ? pl->U1.p : pl->U0.p;
+  double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
   HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
   if (lambda_out && win) HIP_TRY(launch_copy((k & 1) ? pl->lam1.p : pl->lam0.p, lambda_out, win, pl->cs));
   if ((st = sync_out(user, *pl))) return st;
@@ -794,8 +1058,16 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
   if ((st = sync_in(user, *pl))) return st;
   if ((st = load_instance(*pl, u0, f, s, 0.0))) return st;
   const StepTables t = pl->dt.view();
-  for (int n = 0; n < geo.nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, 0, t.n_items, pl->cs));
-  double *Ufin = (geo.nt & 1) ? pl->U1.p : pl->U0.p;
+  if (cfg.steps == 1) {
+    for (int n = 0; n < geo.nt; ++n)
+      HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, 0, t.n_items, pl->cs));
+  } else {
+    const int L = march_launches(geo.nt, cfg);
+    for (int l = 0; l < L; ++l)
+      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, cfg.steps, l & 1, 0,
+                           t.n_items, pl->cs));
+  }
+  double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
   HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
   return sync_out(user, *pl);
 }
@@ -804,7 +1076,7 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
 struct BatchInst {
   Geo geo;
   double p;
-  double *U0, *U1, *lam0, *lam1, *g;
+  double *U0, *U1, *lam0, *lam1, *g, *V = nullptr;
   int *rowmap;
   size_t win;
 };
@@ -835,6 +1107,15 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
   probe.J = 0;
   probe.tr = -1;
   Config cfg = g_forced.waves > 0 ? choose_config(probe) : default_config(n_max);
+  if (g_forced.waves == 0) {
+    for (int w : kWaves) {
+      const int sm = march_seg_for(n_max, w);
+      if (sm && sm <= 24) {
+        cfg = Config{w, sm, 8};
+        break;
+      }
+    }
+  }
   if (g_forced.waves == 0) {
     if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
     char key[96];
@@ -891,10 +1172,13 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (in[i].s ? in[i].s[n + 1] : 1.0);
     HIP_TRY(hipMemcpyAsync(b.g, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, cs));
     HIP_TRY(hipStreamSynchronize(cs));
+    if (cfg.steps > 1 && geo.J > 1)
+      HIP_TRY(dalloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx * 8, (void **)&b.V));
     const int sub_base = (int)h.subs.size();
-    add_instance(geo, b.p, cfg.waves, i, h);
+    add_instance_cfg(geo, b.p, cfg.waves, cfg.seg, cfg.steps, i, h);
+    make_ex(geo, i, h.ex);
     std::vector<Item> it;
-    make_items(geo, sub_base, it);
+    make_items(geo, sub_base, tile_width(cfg), it);
     for (const Item &x : it) weighted.push_back({h.subs[x.sub].n * geo.nt, x});
     InstDev &d = idev[i];
     d.U[0] = b.U0;
@@ -905,6 +1189,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     d.lam[0] = b.lam0;
     d.lam[1] = b.lam1;
     d.res = res + i;
+    d.V = b.V;
     d.r = dt / (hv * hv);
     d.p = b.p;
     d.q = b.p;
@@ -1035,7 +1320,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
   for (int i = 0; i < n_inst; ++i) {
     const BatchInst &b = bi[i];
     const Geo &geo = b.geo;
-    double *Ufin = (geo.nt & 1) ? b.U1 : b.U0;
+    double *Ufin = (march_launches(geo.nt, cfg) & 1) ? b.U1 : b.U0;
     HIP_TRY(launch_assemble(Ufin, b.rowmap, in[i].uT, geo.nv, geo.nx, cs));
     if (in[i].lambda_out && b.win)
       HIP_TRY(launch_copy((iters[i] & 1) ? b.lam1 : b.lam0, in[i].lambda_out, b.win, cs));
@@ -1064,7 +1349,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
 
 // -------------------------------------------------------------------- tune --
 static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, int *w_out,
-                            int *s_out, hipStream_t user) {
+                            int *s_out, int *k_out, hipStream_t user) {
   Geo geo;
   kfp_status st = make_geo(g, J, o, tr, p, geo);
   if (st) return st;
@@ -1085,27 +1370,52 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
   const Config saved = g_forced;
   Config best;
   double best_ms = INFINITY;
-  const int steps = std::min(g->nt, 64);
+  const int steps = std::min(g->nt, 96);
+  std::vector<Config> cands;
   for (int w : kWaves) {
-    std::vector<int> cands;
     const int s0 = seg_for(geo.n_max, w);
-    if (s0 > 0) cands.push_back(s0);
-    cands.push_back(0);
-    for (int sm : cands) {
-      if (!step_config_supported(w, sm)) continue;
-      Config c{w, sm};
+    if (s0 > 0) cands.push_back(Config{w, s0, 1});
+    cands.push_back(Config{w, 0, 1});
+    const int sm = march_seg_for(geo.n_max, w);
+    if (sm)
+      for (int k : {4, 8, 12, 16}) cands.push_back(Config{w, sm, k});
+  }
+  {
+    for (const Config &c : cands) {
+      const int w = c.waves, sm = c.seg;
+      if (!config_supported(c)) continue;
       Plan *pl = nullptr;
       if ((st = get_plan(geo, c, &pl))) return st;
       if ((st = load_instance(*pl, u0, f, nullptr, tr == KFP_ROBIN ? p : 1.0))) return st;
       if (geo.J > 1) HIP_TRY(launch_fill(pl->lam0.p, (size_t)2 * (geo.J - 1) * geo.nt * geo.nx, 0.0, pl->cs));
       const StepTables t = pl->dt.view();
-      for (int n = 0; n < 4; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
+      auto run = [&](int nsteps) -> kfp_status {
+        if (c.steps == 1) {
+          for (int n = 0; n < nsteps; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
+        } else {
+          for (int n = 0; n < nsteps; n += c.steps)
+            HIP_TRY(launch_march(t, w, sm, n, c.steps, c.steps, (n / c.steps) & 1, 0, t.n_items,
+                                 pl->cs));
+        }
+        return KFP_OK;
+      };
+      if ((st = run(std::min(steps, 16)))) return st;
       HIP_TRY(hipEventRecord(pl->ev0, pl->cs));
-      for (int n = 0; n < steps; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
+      if ((st = run(steps))) return st;
       HIP_TRY(hipEventRecord(pl->ev1, pl->cs));
       HIP_TRY(hipStreamSynchronize(pl->cs));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+      if (c.steps > 1 && geo.J > 1) {
+        // the exchange pass runs once per window: charge its share
+        float ex_ms = 0.f;
+        HIP_TRY(hipEventRecord(pl->ev0, pl->cs));
+        HIP_TRY(launch_exchange(t, 0, geo.nt, pl->cs));
+        HIP_TRY(hipEventRecord(pl->ev1, pl->cs));
+        HIP_TRY(hipStreamSynchronize(pl->cs));
+        HIP_TRY(hipEventElapsedTime(&ex_ms, pl->ev0, pl->ev1));
+        ms += ex_ms * (float)steps / (float)geo.nt;
+      }
       if (ms < best_ms) {
         best_ms = ms;
         best = c;
@@ -1118,6 +1428,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
   save_tune(*g_tune);
   if (w_out) *w_out = best.waves;
   if (s_out) *s_out = best.seg;
+  if (k_out) *k_out = best.steps;
   (void)user;
   return KFP_OK;
 }
@@ -1170,27 +1481,29 @@ kfp_status kfp_swr_batch(int32_t n, const kfp_instance *inst, double tol, int32_
 }
 
 kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, double p,
-                    int32_t *waves_out, int32_t *seg_max_out, void *stream) {
+                    int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out, void *stream) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
-  return tune_impl(g, J, overlap, tr, p, waves_out, seg_max_out, (hipStream_t)stream);
+  return tune_impl(g, J, overlap, tr, p, waves_out, seg_max_out, steps_out, (hipStream_t)stream);
 }
 
-kfp_status kfp_set_config(int32_t waves, int32_t seg_max) {
+kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   if (waves == 0) {
     g_forced = Config{};
     return KFP_OK;
   }
-  if (!step_config_supported(waves, seg_max))
-    return fail(KFP_EINVAL, "configuration waves=%d seg_max=%d is not compiled", waves, seg_max);
-  g_forced = Config{waves, seg_max};
+  const Config c{waves, seg_max, steps};
+  if (!config_supported(c))
+    return fail(KFP_EINVAL, "configuration waves=%d seg_max=%d steps=%d is not compiled", waves,
+                seg_max, steps);
+  g_forced = c;
   return KFP_OK;
 }
 
 kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
-                          int32_t *waves_out, int32_t *seg_max_out) {
+                          int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
@@ -1199,6 +1512,7 @@ kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
   const Config c = choose_config(geo);
   if (waves_out) *waves_out = c.waves;
   if (seg_max_out) *seg_max_out = c.seg;
+  if (steps_out) *steps_out = c.steps;
   return KFP_OK;
 }
 

@@ -36,9 +36,9 @@ def rel(a, b):
 
 @pytest.fixture(autouse=True)
 def _auto_config():
-    kfp.set_config(0, 0)
+    kfp.set_config(0)
     yield
-    kfp.set_config(0, 0)
+    kfp.set_config(0)
     os.environ.pop("KFP_NO_GRAPH", None)
 
 
@@ -175,21 +175,43 @@ def test_max_iter_returns_last_iterate():
 
 
 # ------------------------------------------------- launch configurations ----
-CONFIGS = [(1, 0), (1, 64), (2, 0), (2, 48), (4, 16), (4, 32), (8, 8), (8, 0), (16, 8),
-           (16, 0)]
+CONFIGS = [(1, 0, 1), (1, 64, 1), (2, 0, 1), (2, 48, 1), (4, 16, 1), (4, 32, 1), (8, 8, 1),
+           (8, 0, 1), (16, 8, 1), (16, 0, 1),
+           # multi-step march kernel: (waves, seg_max, steps per launch)
+           (4, 24, 2), (4, 24, 8), (8, 10, 4), (8, 10, 7), (16, 8, 8), (16, 6, 16),
+           (8, 24, 12), (4, 32, 5), (16, 12, 9)]
 
 
-@pytest.mark.parametrize("waves,seg", CONFIGS)
-def test_every_launch_configuration_agrees(waves, seg):
+@pytest.mark.parametrize("waves,seg,steps", CONFIGS)
+@pytest.mark.parametrize("tr", [D, R])
+def test_every_launch_configuration_agrees(waves, seg, steps, tr):
     nx, nv, nt, T, J, o = 96, 128, 24, 0.2, 2, 2
-    print(f"config waves={waves} seg={seg}", flush=True)
+    print(f"config waves={waves} seg={seg} steps={steps} tr={tr}", flush=True)
     u0, f = inputs.random_fields(9, nx, nv)
-    ref = oracle.swr_solve(u0, f, T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=3)
-    kfp.set_config(waves, seg)
-    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=3,
+    p = 4.0 if tr == R else 0.0
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3)
+    kfp.set_config(waves, seg, steps)
+    got = kfp.get_config(nx, nv, nt, T, J, o, tr)
+    # a forced register segment too short for the subdomain is widened to the
+    # next compiled size (or the memory-staged variant)
+    assert got[0] == waves and got[2] == steps and (got[1] == 0 or got[1] >= seg)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3,
                                 want_lambda=True)
     assert rel(host(uT), ref.uT) <= 1e-12
     assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("steps", [1, 8])
+def test_mono_multi_step_and_tiny_grids(steps):
+    """The march kernel on grids narrower than its tiles (lanes wrap around
+    the periodic x-range) and with a window shorter than one launch."""
+    for nx, nv, nt, T in ((5, 8, 3, 0.3), (40, 16, 11, 0.2), (64, 64, 20, 0.2)):
+        u0, f = inputs.random_fields(nx + 3 * nv, nx, nv)
+        ref = oracle.mono_solve(u0, f, T, nt)
+        kfp.set_config(4, 8, steps) if nv // 2 - 1 <= 32 else kfp.set_config(0)
+        out = host(kfp.mono_solve(dev(u0), dev(f), T, nt))
+        assert rel(out, ref) <= 1e-12, (nx, nv, nt, steps)
 
 
 def test_graph_and_direct_launch_agree_and_are_deterministic():
@@ -207,7 +229,8 @@ def test_graph_and_direct_launch_agree_and_are_deterministic():
 
 
 # ------------------------------------------------------------------ batch --
-def test_batch_matches_single_solves():
+@pytest.mark.parametrize("cfg", [(16, 32, 1), (16, 12, 6)])
+def test_batch_matches_single_solves(cfg):
     specs = [
         (64, 64, 40, 0.2, 2, 2, R, 4.0),
         (128, 32, 40, 0.1, 4, 2, R, 2.0),
@@ -216,7 +239,7 @@ def test_batch_matches_single_solves():
         (256, 64, 40, 0.15, 1, 0, R, 1.0),
     ]
     insts, refs = [], []
-    kfp.set_config(16, 32)  # one configuration for the batch and the singles
+    kfp.set_config(*cfg)  # one configuration for the batch and the singles
     for i, (nx, nv, nt, T, J, o, tr, p) in enumerate(specs):
         u0, f = inputs.random_fields(100 + i, nx, nv)
         insts.append(dict(u0=dev(u0), f=dev(f), T=T, nt=nt, J=J, overlap=o, tr=tr, p=p,
@@ -225,6 +248,7 @@ def test_batch_matches_single_solves():
                                   want_lambda=True))
     out, rc = kfp.swr_batch(insts, tol=1e-11, max_iter=400, history=True)
     assert rc == 0
+    kfp.set_config(0)
     for (uT, lam, st), (ruT, rlam, rst) in zip(out, refs):
         assert st.iters == rst.iters
         assert torch.equal(uT, ruT)

@@ -84,7 +84,9 @@ def test_mono_and_batch_invalid_arguments(lib):
     assert lib.kfp_swr_batch(1, inst, 1e-10, 10, None, None) == binding.KFP_EINVAL
     assert "instance 0" in lib.kfp_last_error().decode()
     assert lib.kfp_swr_batch(0, inst, 1e-10, 10, None, None) == binding.KFP_EINVAL
-    assert lib.kfp_set_config(3, 8) == binding.KFP_EINVAL
+    assert lib.kfp_set_config(3, 8, 1) == binding.KFP_EINVAL
+    assert lib.kfp_set_config(4, 24, 40) == binding.KFP_EINVAL
+    assert lib.kfp_set_config(4, 48, 4) == binding.KFP_EINVAL
     assert lib.kfp_bw_probe(FAKE, FAKE, 10, None) == binding.KFP_EINVAL
 
 
