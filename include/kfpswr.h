@@ -178,6 +178,63 @@ kfp_status kfp_subdomain_rows(const kfp_grid *g, int32_t J, int32_t overlap, int
  */
 kfp_status kfp_bw_probe(const void *src, void *dst, int64_t bytes, void *stream);
 
+/* ======================================================================
+ * Learned initial interface traces.
+ *
+ * A multilayer perceptron maps the 64 coefficients of the seeded fields
+ * (u0, f) to the converged interface traces of one problem shape
+ * (standardised per output).  Its prediction is passed to kfp_swr_solve as
+ * lambda_init.  The SWR iteration still runs to the same tolerance, so it is
+ * both the fallback and the judge of the network's error.
+ *
+ * Network: depth hidden layers Linear(hidden) -> GELU (erf form), then
+ * Linear(out).  Weights W[out][in] with FP32 master copies and BF16 copies
+ * used by the products (BF16 operands, FP32 accumulation); biases FP32.
+ * Loss: mean squared error over the batch and the outputs.  Optimizer:
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * All X, Y, T buffers are device FP32, row-major [B][width].
+ * ==================================================================== */
+typedef struct kfp_mlp kfp_mlp;
+
+/* in, hidden, out: positive multiples of 8; depth 0..16.  Weights drawn
+ * N(0, 1/in) from a counter-based generator seeded by `seed`; biases 0.
+ * The handle is owned by the caller (kfp_mlp_destroy). */
+kfp_status kfp_mlp_create(int32_t in, int32_t hidden, int32_t depth, int64_t out, uint64_t seed,
+                          kfp_mlp **mlp);
+void kfp_mlp_destroy(kfp_mlp *mlp);
+/* Y[B][out] = net(X[B][in]).  Asynchronous. */
+kfp_status kfp_mlp_forward(kfp_mlp *mlp, int32_t B, const float *X, float *Y, void *stream);
+/* Gradients of the loss at (X, T) into the handle's gradient buffers;
+ * loss: [host] or NULL (synchronises when given).  B: multiple of 8. */
+kfp_status kfp_mlp_backward(kfp_mlp *mlp, int32_t B, const float *X, const float *T,
+                            double *loss, void *stream);
+/* One Adam step with the stored gradients (learning rate lr). */
+kfp_status kfp_mlp_adam(kfp_mlp *mlp, float lr, void *stream);
+/* backward + adam */
+kfp_status kfp_mlp_train_step(kfp_mlp *mlp, int32_t B, const float *X, const float *T, float lr,
+                              double *loss, void *stream);
+/* Layers are 0..depth; [host] outputs. */
+kfp_status kfp_mlp_layer_shape(const kfp_mlp *mlp, int32_t layer, int32_t *in, int64_t *out);
+/* Copy a parameter to (set = 0) or from (set = 1) a device FP32 buffer:
+ * which 0 = W [out][in], 1 = b [out], 2 = dW (read only), 3 = db (read only). */
+kfp_status kfp_mlp_param(kfp_mlp *mlp, int32_t layer, int32_t which, int32_t set, float *buf,
+                         void *stream);
+/* Checkpoint: FP32 masters, Adam moments and step count. */
+kfp_status kfp_mlp_save(const kfp_mlp *mlp, const char *path);
+kfp_status kfp_mlp_load(const char *path, kfp_mlp **mlp);
+
+/* Data helpers for building training sets from solver output.  All device
+ * pointers, asynchronous.  kfp_column_stats: per-column mean and standard
+ * deviation (at least floor_) of X[rows][cols]; kfp_standardize: X = (X -
+ * mean) / std in place; kfp_destandardize: lam = mean + std * Y (FP64 out). */
+kfp_status kfp_cast_f64_f32(const double *src, float *dst, int64_t n, void *stream);
+kfp_status kfp_column_stats(const float *X, int32_t rows, int64_t cols, float floor_,
+                            float *mean, float *stdv, void *stream);
+kfp_status kfp_standardize(float *X, int32_t rows, int64_t cols, const float *mean,
+                           const float *stdv, void *stream);
+kfp_status kfp_destandardize(const float *Y, int32_t rows, int64_t cols, const float *mean,
+                             const float *stdv, double *lam, void *stream);
+
 /* Frees all cached workspace (plans, graphs, trace windows). */
 void kfp_release_workspace(void);
 

@@ -10,16 +10,21 @@ from __future__ import annotations
 
 from .binding import (  # noqa: F401
     DIRICHLET,
+    MLP,
     ROBIN,
     KfpError,
     SWRStats,
     bw_probe,
+    cast_f64_f32,
+    column_stats,
+    destandardize,
     get_config,
     lib_path,
     load_library,
     mono_solve,
     release_workspace,
     set_config,
+    standardize,
     subdomain_rows,
     swr_batch,
     swr_solve,

@@ -296,3 +296,178 @@ def bw_probe(src, dst, stream=None):
 
 def release_workspace():
     load_library().kfp_release_workspace()
+
+
+# ------------------------------------------------------------- learned part --
+def _fptr(t, dtype=None):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+        raise ValueError("expected a contiguous GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _mlp_sigs(lib):
+    if getattr(lib, "_mlp_sigs", False):
+        return lib
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    pd = ctypes.POINTER(ctypes.c_double)
+    lib.kfp_mlp_create.argtypes = [i32, i32, i32, i64, ctypes.c_uint64, ctypes.POINTER(vp)]
+    lib.kfp_mlp_destroy.argtypes = [vp]
+    lib.kfp_mlp_destroy.restype = None
+    lib.kfp_mlp_forward.argtypes = [vp, i32, vp, vp, vp]
+    lib.kfp_mlp_backward.argtypes = [vp, i32, vp, vp, pd, vp]
+    lib.kfp_mlp_adam.argtypes = [vp, f32, vp]
+    lib.kfp_mlp_train_step.argtypes = [vp, i32, vp, vp, f32, pd, vp]
+    lib.kfp_mlp_layer_shape.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.kfp_mlp_param.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.kfp_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    lib.kfp_mlp_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    lib.kfp_cast_f64_f32.argtypes = [vp, vp, i64, vp]
+    lib.kfp_column_stats.argtypes = [vp, i32, i64, f32, vp, vp, vp]
+    lib.kfp_standardize.argtypes = [vp, i32, i64, vp, vp, vp]
+    lib.kfp_destandardize.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    for n in ("kfp_mlp_create", "kfp_mlp_forward", "kfp_mlp_backward", "kfp_mlp_adam",
+              "kfp_mlp_train_step", "kfp_mlp_layer_shape", "kfp_mlp_param", "kfp_mlp_save",
+              "kfp_mlp_load", "kfp_cast_f64_f32", "kfp_column_stats", "kfp_standardize",
+              "kfp_destandardize"):
+        getattr(lib, n).restype = ctypes.c_int
+    lib._mlp_sigs = True
+    return lib
+
+
+class MLP:
+    """Handle of the library's network (BF16 weights, FP32 accumulation)."""
+
+    def __init__(self, n_in=64, hidden=512, depth=3, n_out=786432, seed=0, _handle=None):
+        lib = _mlp_sigs(load_library())
+        self._lib = lib
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib.kfp_mlp_create(int(n_in), int(hidden), int(depth), int(n_out), int(seed),
+                                      ctypes.byref(h)))
+            _handle = h
+        self._h = _handle
+        self.depth = self.layers() - 1
+
+    @classmethod
+    def load(cls, path):
+        lib = _mlp_sigs(load_library())
+        h = ctypes.c_void_p()
+        _check(lib.kfp_mlp_load(str(path).encode(), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path):
+        _check(self._lib.kfp_mlp_save(self._h, str(path).encode()))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._lib.kfp_mlp_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layers(self):
+        n = 0
+        i, o = ctypes.c_int32(), ctypes.c_int64()
+        while self._lib.kfp_mlp_layer_shape(self._h, n, ctypes.byref(i), ctypes.byref(o)) == 0:
+            n += 1
+        return n
+
+    def shape(self, layer):
+        i, o = ctypes.c_int32(), ctypes.c_int64()
+        _check(self._lib.kfp_mlp_layer_shape(self._h, int(layer), ctypes.byref(i), ctypes.byref(o)))
+        return i.value, o.value
+
+    def forward(self, X, out=None, stream=None):
+        import torch
+
+        B = X.shape[0]
+        n_out = self.shape(self.layers() - 1)[1]
+        Y = out if out is not None else torch.empty((B, n_out), dtype=torch.float32, device=X.device)
+        _check(self._lib.kfp_mlp_forward(self._h, int(B), _fptr(X, torch.float32),
+                                         _fptr(Y, torch.float32), _stream(stream)))
+        return Y
+
+    def backward(self, X, T, stream=None):
+        import torch
+
+        loss = ctypes.c_double()
+        _check(self._lib.kfp_mlp_backward(self._h, int(X.shape[0]), _fptr(X, torch.float32),
+                                          _fptr(T, torch.float32), ctypes.byref(loss),
+                                          _stream(stream)))
+        return loss.value
+
+    def adam(self, lr, stream=None):
+        _check(self._lib.kfp_mlp_adam(self._h, float(lr), _stream(stream)))
+
+    def train_step(self, X, T, lr, stream=None):
+        import torch
+
+        loss = ctypes.c_double()
+        _check(self._lib.kfp_mlp_train_step(self._h, int(X.shape[0]), _fptr(X, torch.float32),
+                                            _fptr(T, torch.float32), float(lr),
+                                            ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def get(self, layer, which, stream=None):
+        """which: 'W', 'b', 'dW', 'db' -> float32 GPU tensor."""
+        import torch
+
+        code = {"W": 0, "b": 1, "dW": 2, "db": 3}[which]
+        i, o = self.shape(layer)
+        shape = (o, i) if code in (0, 2) else (o,)
+        buf = torch.empty(shape, dtype=torch.float32, device="cuda")
+        _check(self._lib.kfp_mlp_param(self._h, int(layer), code, 0, _fptr(buf), _stream(stream)))
+        return buf
+
+    def set(self, layer, which, value, stream=None):
+        import torch
+
+        code = {"W": 0, "b": 1}[which]
+        v = value.to(device="cuda", dtype=torch.float32).contiguous()
+        _check(self._lib.kfp_mlp_param(self._h, int(layer), code, 1, _fptr(v), _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+
+
+def cast_f64_f32(src, dst, stream=None):
+    lib = _mlp_sigs(load_library())
+    _check(lib.kfp_cast_f64_f32(_fptr(src), _fptr(dst), int(src.numel()), _stream(stream)))
+
+
+def column_stats(X, floor=1e-6, stream=None):
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    rows, cols = X.shape
+    mean = torch.empty(cols, dtype=torch.float32, device=X.device)
+    std = torch.empty(cols, dtype=torch.float32, device=X.device)
+    _check(lib.kfp_column_stats(_fptr(X, torch.float32), int(rows), int(cols), float(floor),
+                                _fptr(mean), _fptr(std), _stream(stream)))
+    return mean, std
+
+
+def standardize(X, mean, std, stream=None):
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    rows, cols = X.shape
+    _check(lib.kfp_standardize(_fptr(X, torch.float32), int(rows), int(cols), _fptr(mean),
+                               _fptr(std), _stream(stream)))
+
+
+def destandardize(Y, mean, std, out=None, stream=None):
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    rows, cols = Y.shape
+    lam = out if out is not None else torch.empty((rows, cols), dtype=torch.float64, device=Y.device)
+    _check(lib.kfp_destandardize(_fptr(Y, torch.float32), int(rows), int(cols), _fptr(mean),
+                                 _fptr(std), _fptr(lam, torch.float64), _stream(stream)))
+    return lam

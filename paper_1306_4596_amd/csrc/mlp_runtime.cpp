@@ -1,0 +1,542 @@
+// Host runtime of the learned initial-trace network: parameter storage
+// (FP32 masters, BF16 copies in both layouts, Adam moments), the forward
+// pass, the backward pass, Adam, checkpoints, and the data helpers
+// (casts, standardisation) around it.  C ABI in include/kfpswr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kfpswr.h"
+#include "mlp_internal.h"
+
+namespace kfp {
+
+// the library's one error slot (kfp_last_error), defined in swr_runtime.cpp
+extern thread_local std::string g_err;
+#define m_err g_err
+
+static kfp_status mfail(kfp_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  m_err = buf;
+  return st;
+}
+
+#define MHIP(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return mfail(e_ == hipErrorOutOfMemory ? KFP_ENOMEM : KFP_EDEVICE, "%s: %s (%s:%d)", \
+                   #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+template <class T>
+static hipError_t dmalloc(T **p, size_t n) {
+  *p = nullptr;
+  return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+struct Layer {
+  int in = 0;
+  long out = 0;
+  float *W = nullptr, *b = nullptr;      // FP32 masters: W [out][in]
+  __bf16 *Wb = nullptr, *Wt = nullptr;   // BF16 copies: [out][in], [in][out]
+  float *mW = nullptr, *vW = nullptr, *mb = nullptr, *vb = nullptr;
+  float *gW = nullptr, *gb = nullptr;    // gradients
+};
+
+struct Acts {
+  int cap = 0;
+  __bf16 *Xb = nullptr, *Xt = nullptr;         // input [B][in0], [in0][B]
+  std::vector<float *> Z;                      // pre-activations [B][h] (hidden layers)
+  std::vector<__bf16 *> Ab, At;                // GELU outputs [B][h] and [h][B]
+  float *Y = nullptr;                          // training output [B][out]
+  float *d32 = nullptr;                        // output gradient FP32 [B][out]
+  __bf16 *db = nullptr, *dt = nullptr;         // output gradient BF16 [B][out], [out][B]
+  float *dA = nullptr, *dZ32 = nullptr;        // hidden gradients [B][h]
+  __bf16 *dZb = nullptr, *dZt = nullptr;
+  float *P = nullptr;                          // split-K partials
+  size_t P_n = 0;
+  double *loss = nullptr;
+};
+
+}  // namespace kfp
+
+struct kfp_mlp {
+  int in = 0, hidden = 0, depth = 0;
+  long out = 0;
+  long long step = 0;
+  std::vector<kfp::Layer> L;
+  kfp::Acts A;
+};
+
+namespace kfp {
+
+static std::recursive_mutex m_mu;
+
+static void free_acts(Acts &a) {
+  auto f = [](void *p) {
+    if (p) (void)hipFree(p);
+  };
+  f(a.Xb);
+  f(a.Xt);
+  for (auto p : a.Z) f(p);
+  for (auto p : a.Ab) f(p);
+  for (auto p : a.At) f(p);
+  f(a.Y);
+  f(a.d32);
+  f(a.db);
+  f(a.dt);
+  f(a.dA);
+  f(a.dZ32);
+  f(a.dZb);
+  f(a.dZt);
+  f(a.P);
+  f(a.loss);
+  a = Acts{};
+}
+
+static void free_mlp(kfp_mlp *m) {
+  for (auto &l : m->L) {
+    for (void *p : {(void *)l.W, (void *)l.b, (void *)l.Wb, (void *)l.Wt, (void *)l.mW,
+                    (void *)l.vW, (void *)l.mb, (void *)l.vb, (void *)l.gW, (void *)l.gb})
+      if (p) (void)hipFree(p);
+  }
+  free_acts(m->A);
+}
+
+static kfp_status ensure_acts(kfp_mlp *m, int B) {
+  if (m->A.cap >= B) return KFP_OK;
+  free_acts(m->A);
+  Acts &a = m->A;
+  const int nh = m->depth;
+  MHIP(dmalloc(&a.Xb, (size_t)B * m->in));
+  MHIP(dmalloc(&a.Xt, (size_t)B * m->in));
+  a.Z.assign(nh, nullptr);
+  a.Ab.assign(nh, nullptr);
+  a.At.assign(nh, nullptr);
+  for (int l = 0; l < nh; ++l) {
+    MHIP(dmalloc(&a.Z[l], (size_t)B * m->hidden));
+    MHIP(dmalloc(&a.Ab[l], (size_t)B * m->hidden));
+    MHIP(dmalloc(&a.At[l], (size_t)B * m->hidden));
+  }
+  MHIP(dmalloc(&a.Y, (size_t)B * m->out));
+  MHIP(dmalloc(&a.d32, (size_t)B * m->out));
+  MHIP(dmalloc(&a.db, (size_t)B * m->out));
+  MHIP(dmalloc(&a.dt, (size_t)B * m->out));
+  const size_t hmax = std::max(m->hidden, m->in);
+  MHIP(dmalloc(&a.dA, (size_t)B * hmax));
+  MHIP(dmalloc(&a.dZ32, (size_t)B * hmax));
+  MHIP(dmalloc(&a.dZb, (size_t)B * hmax));
+  MHIP(dmalloc(&a.dZt, (size_t)B * hmax));
+  MHIP(dmalloc(&a.loss, 1));
+  a.cap = B;
+  return KFP_OK;
+}
+
+// C = A B^T (NT) with the split-K decision: long reductions over small
+// outputs are cut into chunks whose partials a second pass sums in order.
+static kfp_status gemm(kfp_mlp *m, GemmArgs g, hipStream_t s) {
+  if (g.K % 8 || g.lda % 8 || g.ldb % 8)
+    return mfail(KFP_EINVAL, "GEMM needs K, lda, ldb multiples of 8 (K=%d)", g.K);
+  const long tiles = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+  int splits = 1;
+  if (tiles < 512 && g.K >= 4096) {
+    splits = (int)std::min<long>((g.K + 2047) / 2048, std::max<long>(1, 2048 / tiles));
+  }
+  int kchunk = (g.K + splits - 1) / splits;
+  kchunk = (kchunk + 31) / 32 * 32;
+  splits = (g.K + kchunk - 1) / kchunk;
+  g.kchunk = kchunk;
+  if (splits > 1) {
+    const size_t need = (size_t)splits * g.M * g.N;
+    if (m->A.P_n < need) {
+      if (m->A.P) (void)hipFree(m->A.P);
+      m->A.P = nullptr;
+      m->A.P_n = 0;
+      MHIP(dmalloc(&m->A.P, need));
+      m->A.P_n = need;
+    }
+    g.P = m->A.P;
+  } else {
+    g.P = nullptr;
+  }
+  MHIP(launch_gemm_nt(g, splits, s));
+  return KFP_OK;
+}
+
+static GemmArgs gargs(int M, int N, int K, const __bf16 *A, long lda, const __bf16 *B, long ldb) {
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  return g;
+}
+
+// Forward pass; the output goes to Y (FP32 [B][out]).
+static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream_t s) {
+  kfp_status st = ensure_acts(m, B);
+  if (st) return st;
+  Acts &a = m->A;
+  MHIP(launch_f32_to_bf16(X, a.Xb, (size_t)B * m->in, s));
+  const __bf16 *cur = a.Xb;
+  int cur_w = m->in;
+  const int nl = (int)m->L.size();
+  for (int l = 0; l < nl; ++l) {
+    Layer &L = m->L[l];
+    GemmArgs g = gargs(B, (int)L.out, L.in, cur, cur_w, L.Wb, L.in);
+    g.bias = L.b;
+    if (l < nl - 1) {
+      g.C = a.Z[l];
+      g.ldc = L.out;
+      g.Cb = a.Ab[l];
+      g.ldcb = L.out;
+      g.gelu = 1;
+    } else {
+      g.C = Y;
+      g.ldc = L.out;
+    }
+    if ((st = gemm(m, g, s))) return st;
+    if (l < nl - 1) {
+      cur = a.Ab[l];
+      cur_w = (int)L.out;
+    }
+  }
+  return KFP_OK;
+}
+
+static kfp_status backward(kfp_mlp *m, int B, const float *X, const float *T, double *loss_out,
+                           hipStream_t s) {
+  kfp_status st = ensure_acts(m, B);
+  if (st) return st;
+  if ((st = forward(m, B, X, m->A.Y, s))) return st;
+  Acts &a = m->A;
+  const int nl = (int)m->L.size();
+  const size_t nout = (size_t)B * m->out;
+  MHIP(hipMemsetAsync(a.loss, 0, sizeof(double), s));
+  MHIP(launch_mse_grad(a.Y, T, a.d32, a.db, nout, 2.0f / (float)nout, a.loss, s));
+  // gradient w.r.t. the pre-activation of layer l: FP32 (bias) and BF16
+  const float *d32 = a.d32;
+  const __bf16 *dbf = a.db;
+  __bf16 *dtr = a.dt;
+  for (int l = nl - 1; l >= 0; --l) {
+    Layer &L = m->L[l];
+    const int outw = (int)L.out;
+    MHIP(launch_colsum(d32, B, outw, L.gb, s));
+    // weight gradient: dW[o][i] = sum_b d^T[o][b] act^T[i][b]
+    MHIP(launch_transpose_bf16(dbf, dtr, B, outw, s));
+    const __bf16 *act = (l == 0) ? a.Xb : a.Ab[l - 1];
+    __bf16 *actT = (l == 0) ? a.Xt : a.At[l - 1];
+    MHIP(launch_transpose_bf16(act, actT, B, L.in, s));
+    GemmArgs gw = gargs(outw, L.in, B, dtr, B, actT, B);
+    gw.C = L.gW;
+    gw.ldc = L.in;
+    if ((st = gemm(m, gw, s))) return st;
+    if (l == 0) break;
+    // input gradient: dA[b][i] = sum_o d[b][o] W^T[i][o]
+    GemmArgs gx = gargs(B, L.in, outw, dbf, outw, L.Wt, outw);
+    gx.C = a.dA;
+    gx.ldc = L.in;
+    if ((st = gemm(m, gx, s))) return st;
+    MHIP(launch_gelu_back(a.dA, a.Z[l - 1], a.dZ32, a.dZb, (size_t)B * L.in, s));
+    d32 = a.dZ32;
+    dbf = a.dZb;
+    dtr = a.dZt;
+  }
+  if (loss_out) {
+    double h = 0.0;
+    MHIP(hipMemcpyAsync(&h, a.loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    MHIP(hipStreamSynchronize(s));
+    *loss_out = h / (double)nout;
+  }
+  return KFP_OK;
+}
+
+static kfp_status adam(kfp_mlp *m, float lr, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  m->step += 1;
+  const float c1 = 1.f - std::pow(b1, (float)m->step);
+  const float c2 = 1.f - std::pow(b2, (float)m->step);
+  for (auto &L : m->L) {
+    const size_t nw = (size_t)L.out * L.in;
+    MHIP(launch_adam(L.W, L.gW, L.mW, L.vW, L.Wb, nw, lr, b1, b2, eps, c1, c2, s));
+    MHIP(launch_adam(L.b, L.gb, L.mb, L.vb, nullptr, (size_t)L.out, lr, b1, b2, eps, c1, c2, s));
+    MHIP(launch_transpose_bf16(L.Wb, L.Wt, (int)L.out, L.in, s));
+  }
+  return KFP_OK;
+}
+
+static kfp_status refresh_copies(kfp_mlp *m, hipStream_t s) {
+  for (auto &L : m->L) {
+    const size_t nw = (size_t)L.out * L.in;
+    MHIP(launch_f32_to_bf16(L.W, L.Wb, nw, s));
+    MHIP(launch_transpose_bf16(L.Wb, L.Wt, (int)L.out, L.in, s));
+  }
+  return KFP_OK;
+}
+
+static kfp_status create(int in, int hidden, int depth, long out, unsigned long long seed,
+                         bool init, kfp_mlp **res) {
+  if (in < 8 || in % 8 || hidden < 8 || hidden % 8 || depth < 0 || depth > 16 || out < 1 ||
+      out % 8)
+    return mfail(KFP_EINVAL,
+                 "network shape: in, hidden and out must be positive multiples of 8, depth 0..16");
+  std::unique_ptr<kfp_mlp> m(new kfp_mlp());
+  m->in = in;
+  m->hidden = hidden;
+  m->depth = depth;
+  m->out = out;
+  const int nl = depth + 1;
+  m->L.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    Layer &L = m->L[l];
+    L.in = (l == 0) ? in : hidden;
+    L.out = (l == nl - 1) ? out : hidden;
+    const size_t nw = (size_t)L.out * L.in;
+    auto bad = [&](hipError_t e) {
+      if (e != hipSuccess) {
+        free_mlp(m.get());
+        return true;
+      }
+      return false;
+    };
+    if (bad(dmalloc(&L.W, nw)) || bad(dmalloc(&L.b, L.out)) || bad(dmalloc(&L.Wb, nw)) ||
+        bad(dmalloc(&L.Wt, nw)) || bad(dmalloc(&L.mW, nw)) || bad(dmalloc(&L.vW, nw)) ||
+        bad(dmalloc(&L.mb, L.out)) || bad(dmalloc(&L.vb, L.out)) || bad(dmalloc(&L.gW, nw)) ||
+        bad(dmalloc(&L.gb, L.out)))
+      return mfail(KFP_ENOMEM, "device allocation of the network failed");
+    hipError_t e = hipSuccess;
+    if (init) {
+      e = launch_init_normal(L.W, nw, 1.0f / std::sqrt((float)L.in), seed * 131 + l, nullptr);
+      if (e == hipSuccess) e = hipMemset(L.b, 0, sizeof(float) * L.out);
+    }
+    if (e == hipSuccess) e = hipMemset(L.mW, 0, sizeof(float) * nw);
+    if (e == hipSuccess) e = hipMemset(L.vW, 0, sizeof(float) * nw);
+    if (e == hipSuccess) e = hipMemset(L.mb, 0, sizeof(float) * L.out);
+    if (e == hipSuccess) e = hipMemset(L.vb, 0, sizeof(float) * L.out);
+    if (e != hipSuccess) {
+      free_mlp(m.get());
+      return mfail(KFP_EDEVICE, "network initialisation: %s", hipGetErrorString(e));
+    }
+  }
+  if (init) {
+    kfp_status st = refresh_copies(m.get(), nullptr);
+    if (st) {
+      free_mlp(m.get());
+      return st;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+      free_mlp(m.get());
+      return mfail(KFP_EDEVICE, "network initialisation failed");
+    }
+  }
+  *res = m.release();
+  return KFP_OK;
+}
+
+}  // namespace kfp
+
+using namespace kfp;
+
+extern "C" {
+
+kfp_status kfp_mlp_create(int32_t in, int32_t hidden, int32_t depth, int64_t out, uint64_t seed,
+                          kfp_mlp **mlp) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!mlp) return mfail(KFP_EINVAL, "mlp is NULL");
+  return create(in, hidden, depth, (long)out, seed, true, mlp);
+}
+
+void kfp_mlp_destroy(kfp_mlp *m) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  free_mlp(m);
+  delete m;
+}
+
+kfp_status kfp_mlp_forward(kfp_mlp *m, int32_t B, const float *X, float *Y, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!m || !X || !Y || B < 1) return mfail(KFP_EINVAL, "forward: bad arguments");
+  return forward(m, B, X, Y, (hipStream_t)stream);
+}
+
+kfp_status kfp_mlp_backward(kfp_mlp *m, int32_t B, const float *X, const float *T, double *loss,
+                            void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!m || !X || !T || B < 8 || B % 8)
+    return mfail(KFP_EINVAL, "backward: bad arguments (batch must be a multiple of 8)");
+  return backward(m, B, X, T, loss, (hipStream_t)stream);
+}
+
+kfp_status kfp_mlp_adam(kfp_mlp *m, float lr, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!m || !(lr >= 0.f)) return mfail(KFP_EINVAL, "adam: bad arguments");
+  return adam(m, lr, (hipStream_t)stream);
+}
+
+kfp_status kfp_mlp_train_step(kfp_mlp *m, int32_t B, const float *X, const float *T, float lr,
+                              double *loss, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!m || !X || !T || B < 8 || B % 8 || !(lr >= 0.f))
+    return mfail(KFP_EINVAL, "train_step: bad arguments (batch must be a multiple of 8)");
+  kfp_status st = backward(m, B, X, T, loss, (hipStream_t)stream);
+  if (st) return st;
+  return adam(m, lr, (hipStream_t)stream);
+}
+
+kfp_status kfp_mlp_layer_shape(const kfp_mlp *m, int32_t layer, int32_t *in, int64_t *out) {
+  m_err.clear();
+  if (!m || layer < 0 || layer >= (int)m->L.size()) return mfail(KFP_EINVAL, "bad layer");
+  if (in) *in = m->L[layer].in;
+  if (out) *out = m->L[layer].out;
+  return KFP_OK;
+}
+
+kfp_status kfp_mlp_param(kfp_mlp *m, int32_t layer, int32_t which, int32_t set, float *buf,
+                         void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!m || !buf || layer < 0 || layer >= (int)m->L.size() || which < 0 || which > 3)
+    return mfail(KFP_EINVAL, "param: bad arguments");
+  Layer &L = m->L[layer];
+  float *p = which == 0 ? L.W : which == 1 ? L.b : which == 2 ? L.gW : L.gb;
+  const size_t n = (which == 0 || which == 2) ? (size_t)L.out * L.in : (size_t)L.out;
+  hipStream_t s = (hipStream_t)stream;
+  if (set) {
+    if (which > 1) return mfail(KFP_EINVAL, "param: gradients are read-only");
+    MHIP(hipMemcpyAsync(p, buf, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (which == 0) {
+      MHIP(launch_f32_to_bf16(L.W, L.Wb, n, s));
+      MHIP(launch_transpose_bf16(L.Wb, L.Wt, (int)L.out, L.in, s));
+    }
+  } else {
+    MHIP(hipMemcpyAsync(buf, p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  return KFP_OK;
+}
+
+kfp_status kfp_mlp_save(const kfp_mlp *m, const char *path) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!m || !path) return mfail(KFP_EINVAL, "save: bad arguments");
+  FILE *fp = fopen(path, "wb");
+  if (!fp) return mfail(KFP_EINVAL, "save: cannot open %s", path);
+  const char magic[8] = {'K', 'F', 'P', 'M', 'L', 'P', '1', 0};
+  long long hdr[5] = {m->in, m->hidden, m->depth, m->out, m->step};
+  bool ok = fwrite(magic, 1, 8, fp) == 8 && fwrite(hdr, sizeof hdr, 1, fp) == 1;
+  std::vector<float> h;
+  for (const auto &L : m->L) {
+    const size_t nw = (size_t)L.out * L.in;
+    for (auto pr : {std::make_pair(L.W, nw), std::make_pair(L.b, (size_t)L.out),
+                    std::make_pair(L.mW, nw), std::make_pair(L.vW, nw),
+                    std::make_pair(L.mb, (size_t)L.out), std::make_pair(L.vb, (size_t)L.out)}) {
+      if (!ok) break;
+      h.resize(pr.second);
+      ok = hipMemcpy(h.data(), pr.first, pr.second * sizeof(float), hipMemcpyDeviceToHost) ==
+               hipSuccess &&
+           fwrite(h.data(), sizeof(float), pr.second, fp) == pr.second;
+    }
+  }
+  fclose(fp);
+  return ok ? KFP_OK : mfail(KFP_EDEVICE, "save: write failed");
+}
+
+kfp_status kfp_mlp_load(const char *path, kfp_mlp **res) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!path || !res) return mfail(KFP_EINVAL, "load: bad arguments");
+  FILE *fp = fopen(path, "rb");
+  if (!fp) return mfail(KFP_EINVAL, "load: cannot open %s", path);
+  char magic[8];
+  long long hdr[5];
+  if (fread(magic, 1, 8, fp) != 8 || memcmp(magic, "KFPMLP1", 8) != 0 ||
+      fread(hdr, sizeof hdr, 1, fp) != 1) {
+    fclose(fp);
+    return mfail(KFP_EINVAL, "load: %s is not a network checkpoint", path);
+  }
+  kfp_mlp *m = nullptr;
+  kfp_status st = create((int)hdr[0], (int)hdr[1], (int)hdr[2], (long)hdr[3], 0, false, &m);
+  if (st) {
+    fclose(fp);
+    return st;
+  }
+  m->step = hdr[4];
+  bool ok = true;
+  std::vector<float> h;
+  for (auto &L : m->L) {
+    const size_t nw = (size_t)L.out * L.in;
+    for (auto pr : {std::make_pair(L.W, nw), std::make_pair(L.b, (size_t)L.out),
+                    std::make_pair(L.mW, nw), std::make_pair(L.vW, nw),
+                    std::make_pair(L.mb, (size_t)L.out), std::make_pair(L.vb, (size_t)L.out)}) {
+      if (!ok) break;
+      h.resize(pr.second);
+      ok = fread(h.data(), sizeof(float), pr.second, fp) == pr.second &&
+           hipMemcpy(pr.first, h.data(), pr.second * sizeof(float), hipMemcpyHostToDevice) ==
+               hipSuccess;
+    }
+  }
+  fclose(fp);
+  if (ok) ok = refresh_copies(m, nullptr) == KFP_OK && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    kfp_mlp_destroy(m);
+    return mfail(KFP_EINVAL, "load: truncated or unreadable checkpoint %s", path);
+  }
+  *res = m;
+  return KFP_OK;
+}
+
+kfp_status kfp_cast_f64_f32(const double *src, float *dst, int64_t n, void *stream) {
+  m_err.clear();
+  if ((!src || !dst) && n > 0) return mfail(KFP_EINVAL, "cast: NULL pointer");
+  MHIP(launch_f64_to_f32(src, dst, (size_t)n, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_column_stats(const float *X, int32_t rows, int64_t cols, float floor_,
+                            float *mean, float *stdv, void *stream) {
+  m_err.clear();
+  if (!X || !mean || !stdv || rows < 1 || cols < 1) return mfail(KFP_EINVAL, "stats: bad args");
+  MHIP(launch_colstats(X, rows, (size_t)cols, mean, stdv, floor_, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_standardize(float *X, int32_t rows, int64_t cols, const float *mean,
+                           const float *stdv, void *stream) {
+  m_err.clear();
+  if (!X || !mean || !stdv || rows < 1 || cols < 1) return mfail(KFP_EINVAL, "standardize: bad args");
+  MHIP(launch_standardize(X, (size_t)cols, (size_t)rows * cols, mean, stdv, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_destandardize(const float *Y, int32_t rows, int64_t cols, const float *mean,
+                             const float *stdv, double *lam, void *stream) {
+  m_err.clear();
+  if (!Y || !mean || !stdv || !lam || rows < 1 || cols < 1)
+    return mfail(KFP_EINVAL, "destandardize: bad args");
+  MHIP(launch_destandardize(Y, mean, stdv, (size_t)cols, (size_t)rows * cols, lam,
+                            (hipStream_t)stream));
+  return KFP_OK;
+}
+
+}  // extern "C"

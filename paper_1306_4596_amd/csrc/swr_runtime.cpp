@@ -24,7 +24,7 @@
 namespace kfp {
 
 // ------------------------------------------------------------------ errors --
-static thread_local std::string g_err;
+thread_local std::string g_err;  // shared with the network runtime
 
 static kfp_status fail(kfp_status st, const char *fmt, ...) {
   char buf[512];

@@ -1,0 +1,125 @@
+"""GPU parity of the network kernels against the oracle MLP.
+
+Both sides use BF16-rounded operands for every product; the GPU accumulates
+in FP32, the oracle in FP64, and GELU outputs may round to a neighbouring
+BF16 value, so the bar is relative L2 <= 1e-3 (forward) and <= 2e-3
+(gradients), per array.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1306_4596_amd as kfp  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def build(sizes, seed):
+    rng = np.random.default_rng(seed)
+    params = [(rng.standard_normal((o, i)) / math.sqrt(i), 0.1 * rng.standard_normal(o))
+              for i, o in zip(sizes[:-1], sizes[1:])]
+    net = kfp.MLP(sizes[0], sizes[1], len(sizes) - 2, sizes[-1], seed=1)
+    for l, (W, b) in enumerate(params):
+        net.set(l, "W", torch.from_numpy(W.astype(np.float32)))
+        net.set(l, "b", torch.from_numpy(b.astype(np.float32)))
+    # the oracle sees exactly the FP32 values the device holds
+    params32 = [(W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64))
+                for W, b in params]
+    return net, params32
+
+
+@pytest.mark.parametrize("sizes,B", [([16, 32, 32, 40], 16), ([64, 128, 128, 128, 8192], 24),
+                                     ([8, 136, 200], 8)])
+def test_forward_matches_oracle(sizes, B):
+    print(f"mlp forward sizes={sizes} B={B}", flush=True)
+    net, params = build(sizes, 3)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((B, sizes[0])).astype(np.float32)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref, _ = omlp.MLP(params, bf16=True).forward(x.astype(np.float64))
+    assert rel(y, ref) <= 1e-3
+
+
+@pytest.mark.parametrize("sizes,B", [([16, 32, 32, 40], 16), ([64, 128, 128, 128, 8192], 24)])
+def test_gradients_match_oracle(sizes, B):
+    """The second case has a reduction of length 8192 in the input gradient of
+    the last layer, which takes the split-K path."""
+    print(f"mlp grads sizes={sizes} B={B}", flush=True)
+    net, params = build(sizes, 5)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((B, sizes[0])).astype(np.float32)
+    t = rng.standard_normal((B, sizes[-1])).astype(np.float32)
+    loss = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    rloss, grads = omlp.MLP(params, bf16=True).backward(x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - rloss) <= 1e-4 * rloss
+    for l, (gW, gb) in enumerate(grads):
+        dW = net.get(l, "dW").cpu().numpy()
+        db = net.get(l, "db").cpu().numpy()
+        assert rel(dW, gW) <= 2e-3, (l, rel(dW, gW))
+        assert rel(db, gb) <= 2e-3, (l, rel(db, gb))
+
+
+def test_adam_step_matches_oracle():
+    sizes = [16, 32, 40]
+    net, params = build(sizes, 7)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((16, 16)).astype(np.float32)
+    t = rng.standard_normal((16, 40)).astype(np.float32)
+    X, T = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    state = {}
+    om = omlp.MLP(params, bf16=True)
+    for step in range(3):
+        net.train_step(X, T, lr=1e-2)
+        _, g = om.backward(x.astype(np.float64), t.astype(np.float64))
+        om.params = omlp.adam_step(om.params, g, state, lr=1e-2)
+    for l, (W, b) in enumerate(om.params):
+        assert rel(net.get(l, "W").cpu().numpy(), W) <= 1e-4
+        assert rel(net.get(l, "b").cpu().numpy(), b) <= 1e-3
+
+
+def test_training_fits_a_linear_map_and_checkpoint_round_trip(tmp_path):
+    """A 3 x 64 GELU network learns a random linear map from 16 inputs to 256
+    outputs; a saved and reloaded network predicts the same outputs."""
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal((256, 16)) / 4.0
+    x = rng.standard_normal((512, 16)).astype(np.float32)
+    y = (x @ G.T).astype(np.float32)
+    net = kfp.MLP(16, 64, 3, 256, seed=2)
+    X, Y = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    first = None
+    for epoch in range(60):
+        for b in range(0, 512, 64):
+            loss = net.train_step(X[b:b + 64], Y[b:b + 64], lr=3e-3)
+            first = loss if first is None else first
+    assert loss < 0.02 * first
+    path = tmp_path / "net.bin"
+    net.save(path)
+    net2 = kfp.MLP.load(path)
+    a = net.forward(X[:32])
+    b = net2.forward(X[:32])
+    assert torch.equal(a, b)
+
+
+def test_data_helpers():
+    rng = np.random.default_rng(10)
+    x = (3.0 + 2.0 * rng.standard_normal((100, 24))).astype(np.float32)
+    X = torch.from_numpy(x).cuda()
+    mean, std = kfp.column_stats(X)
+    assert np.allclose(mean.cpu().numpy(), x.mean(axis=0), rtol=1e-5)
+    assert np.allclose(std.cpu().numpy(), x.std(axis=0), rtol=1e-4)
+    Z = X.clone()
+    kfp.standardize(Z, mean, std)
+    back = kfp.destandardize(Z, mean, std)
+    assert np.allclose(back.cpu().numpy(), x, rtol=1e-5, atol=1e-5)
+    d = torch.from_numpy(rng.standard_normal(1000)).cuda()
+    f = torch.empty(1000, dtype=torch.float32, device="cuda")
+    kfp.cast_f64_f32(d, f)
+    assert np.array_equal(f.cpu().numpy(), d.cpu().numpy().astype(np.float32))
