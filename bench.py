@@ -116,7 +116,7 @@ def main():
     # dominant kernel: the multi-step march kernel (steps per launch > 1) or
     # the one-step kernel; its average duration comes from the library's HIP
     # events on the stream the iteration graphs run on
-    if kper > 1:
+    if kper >= 1:
         launches = sum(iters) * (-(-NT // kper))
         kname = "kfp::march_kernel"
     else:

@@ -151,13 +151,14 @@ kfp_status kfp_swr_batch(int32_t n, const kfp_instance *inst, double tol, int32_
  * contiguous segment of a subdomain's unknown rows for 64 x-columns (the
  * segments are coupled through a small reduced tridiagonal system);
  * seg_max = largest segment the kernel holds in registers (0: segments of
- * any length staged through memory); steps = time steps per launch (1: one
- * launch per step, the state streamed through memory; > 1: the multi-step
- * kernel keeps the state on chip for `steps` steps, with a halo of `steps`
- * columns on each side of a tile).  kfp_tune times the candidates on the
- * device for one shape and stores the winner in the tuning cache (file named
- * by $KFP_TUNE_CACHE, default ~/.cache/kfpswr_tune.json); solves look the
- * cache up, else use a built-in choice.  kfp_set_config forces a
+ * any length staged through memory); steps = time steps per launch: 0 is
+ * the general one-step kernel (any segment length, traces of the previous
+ * level fused in), >= 1 the register march kernel, which keeps the state on
+ * chip for `steps` steps with a halo of max(1, steps) columns on each side
+ * of a tile.  kfp_tune times the candidates on the device for one shape
+ * and stores the winner in the tuning cache (file named by $KFP_TUNE_CACHE,
+ * default ~/.cache/kfpswr_tune.json); solves look the cache up, else use a
+ * built-in choice.  kfp_set_config forces a
  * configuration for subsequent calls (waves = 0 returns to automatic
  * choice); KFP_EINVAL if it is not compiled.
  */

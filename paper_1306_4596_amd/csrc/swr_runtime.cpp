@@ -137,16 +137,21 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
 }
 
 // ---------------------------------------------------------- launch config --
+// steps == 0: the general one-step kernel (any segment length, traces fused
+// one level behind); steps >= 1: the register march kernel, `steps` time
+// steps per launch with a halo of max(1, steps) columns per side.
 struct Config {
   int waves = 0;
   int seg = 0;
-  int steps = 1;  // time steps per launch: 1 = step kernel, > 1 = march kernel
+  int steps = 0;
 };
 
 static bool config_supported(const Config &c) {
-  return c.steps == 1 ? step_config_supported(c.waves, c.seg)
-                      : (c.steps >= 2 && c.steps <= 24 && march_config_supported(c.waves, c.seg));
+  return c.steps == 0 ? step_config_supported(c.waves, c.seg)
+                      : (c.steps >= 1 && c.steps <= 24 && march_config_supported(c.waves, c.seg));
 }
+
+static int halo_of(const Config &c) { return c.steps > 1 ? c.steps : 1; }
 
 static const int kWaves[] = {1, 2, 4, 8, 16};
 static const int kSegs[] = {8, 16, 24, 32, 48, 64};
@@ -265,16 +270,16 @@ static std::map<std::string, Config> *g_tune = nullptr;
 static Config choose_config(const Geo &g) {
   if (g_forced.waves > 0) {
     Config c = g_forced;
-    if (c.steps > 1 && !march_fits(g.n_max, c.waves, c.seg)) {
+    if (c.steps >= 1 && !march_fits(g.n_max, c.waves, c.seg)) {
       const int sm = march_seg_for(g.n_max, c.waves);
       if (sm) {
         c.seg = sm;  // widen to the next compiled segment length
       } else {
-        c.steps = 1;  // no register segment holds it: one launch per step
+        c.steps = 0;  // no register segment holds it: the general step kernel
         c.seg = seg_for(g.n_max, c.waves);
       }
     }
-    if (c.steps == 1 && c.seg > 0 && segs_for(g.n_max, c.waves) > c.seg)
+    if (c.steps == 0 && c.seg > 0 && segs_for(g.n_max, c.waves) > c.seg)
       c.seg = seg_for(g.n_max, c.waves);
     return c;
   }
@@ -286,7 +291,7 @@ static Config choose_config(const Geo &g) {
     // multi-step march by default when a segment of at most 24 rows fits
     for (int w : kWaves) {
       const int sm = march_seg_for(g.n_max, w);
-      if (sm && sm <= 24) return Config{w, sm, g.nx >= 128 ? 16 : 8};
+      if (sm && sm <= 24) return Config{w, sm, 8};
     }
   }
   return default_config(g.n_max);
@@ -637,7 +642,7 @@ static void add_instance(const Geo &g, double p, int waves, int inst, HostTables
 
 static void add_instance_cfg(const Geo &g, double p, int waves, int seg, int steps, int inst,
                              HostTables &t) {
-  if (steps == 1) {
+  if (steps == 0) {
     add_instance(g, p, waves, inst, t);
     return;
   }
@@ -649,7 +654,7 @@ static void add_instance_cfg(const Geo &g, double p, int waves, int seg, int ste
 
 // Output tile width of a configuration: 64 lanes, minus the halo of the
 // multi-step kernel on both sides.
-static int tile_width(const Config &c) { return c.steps > 1 ? 64 - 2 * c.steps : 64; }
+static int tile_width(const Config &c) { return c.steps >= 1 ? 64 - 2 * halo_of(c) : 64; }
 
 static void make_items(const Geo &g, int sub_base, int width, std::vector<Item> &items) {
   // subdomain-fastest order: consecutive workgroups (and so the XCDs they are
@@ -824,7 +829,7 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
   HIP_TRY(pl->lam0.alloc(std::max<size_t>(win, 1)));
   HIP_TRY(pl->lam1.alloc(std::max<size_t>(win, 1)));
   HIP_TRY(pl->g.alloc(geo.nt));
-  if (cfg.steps > 1 && geo.J > 1) HIP_TRY(pl->V.alloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx));
+  if (cfg.steps >= 1 && geo.J > 1) HIP_TRY(pl->V.alloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx));
   HIP_TRY(pl->rowmap.alloc(geo.nv + 1));
   HIP_TRY(pl->ab.alloc(std::max(2 * (geo.J - 1), 1)));
   HIP_TRY(pl->res.alloc(1));
@@ -888,20 +893,20 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
 // Number of state ping-pong flips of one window: the parity of U holding the
 // final state is launches & 1.
 static int march_launches(int nt, const Config &cfg) {
-  return cfg.steps > 1 ? (nt + cfg.steps - 1) / cfg.steps : nt;
+  return cfg.steps >= 1 ? (nt + cfg.steps - 1) / cfg.steps : nt;
 }
 
 static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const InstDev *inst,
                                           const Config &cfg, int nt, int par, int grid,
                                           hipStream_t s) {
   HIP_TRY(launch_reset_res(inst, n_inst, s));
-  if (cfg.steps == 1) {
+  if (cfg.steps == 0) {
     for (int n = 0; n <= nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, par, grid, s));
   } else {
     const int L = march_launches(nt, cfg);
     for (int l = 0; l < L; ++l)
-      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, cfg.steps, l & 1, par,
-                           grid, s));
+      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
+                           par, grid, s));
     HIP_TRY(launch_exchange(t, par, nt, s));
   }
   return KFP_OK;
@@ -1058,14 +1063,14 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
   if ((st = sync_in(user, *pl))) return st;
   if ((st = load_instance(*pl, u0, f, s, 0.0))) return st;
   const StepTables t = pl->dt.view();
-  if (cfg.steps == 1) {
+  if (cfg.steps == 0) {
     for (int n = 0; n < geo.nt; ++n)
       HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, 0, t.n_items, pl->cs));
   } else {
     const int L = march_launches(geo.nt, cfg);
     for (int l = 0; l < L; ++l)
-      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, cfg.steps, l & 1, 0,
-                           t.n_items, pl->cs));
+      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
+                           0, t.n_items, pl->cs));
   }
   double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
   HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
@@ -1172,7 +1177,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (in[i].s ? in[i].s[n + 1] : 1.0);
     HIP_TRY(hipMemcpyAsync(b.g, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, cs));
     HIP_TRY(hipStreamSynchronize(cs));
-    if (cfg.steps > 1 && geo.J > 1)
+    if (cfg.steps >= 1 && geo.J > 1)
       HIP_TRY(dalloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx * 8, (void **)&b.V));
     const int sub_base = (int)h.subs.size();
     add_instance_cfg(geo, b.p, cfg.waves, cfg.seg, cfg.steps, i, h);
@@ -1374,11 +1379,11 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
   std::vector<Config> cands;
   for (int w : kWaves) {
     const int s0 = seg_for(geo.n_max, w);
-    if (s0 > 0) cands.push_back(Config{w, s0, 1});
-    cands.push_back(Config{w, 0, 1});
+    if (s0 > 0) cands.push_back(Config{w, s0, 0});
+    cands.push_back(Config{w, 0, 0});
     const int sm = march_seg_for(geo.n_max, w);
     if (sm)
-      for (int k : {4, 8, 12, 16}) cands.push_back(Config{w, sm, k});
+      for (int k : {1, 4, 8, 12, 16}) cands.push_back(Config{w, sm, k});
   }
   {
     for (const Config &c : cands) {
@@ -1390,12 +1395,12 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
       if (geo.J > 1) HIP_TRY(launch_fill(pl->lam0.p, (size_t)2 * (geo.J - 1) * geo.nt * geo.nx, 0.0, pl->cs));
       const StepTables t = pl->dt.view();
       auto run = [&](int nsteps) -> kfp_status {
-        if (c.steps == 1) {
+        if (c.steps == 0) {
           for (int n = 0; n < nsteps; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
         } else {
           for (int n = 0; n < nsteps; n += c.steps)
-            HIP_TRY(launch_march(t, w, sm, n, c.steps, c.steps, (n / c.steps) & 1, 0, t.n_items,
-                                 pl->cs));
+            HIP_TRY(launch_march(t, w, sm, n, c.steps, halo_of(c), (n / c.steps) & 1, 0,
+                                 t.n_items, pl->cs));
         }
         return KFP_OK;
       };
@@ -1406,7 +1411,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
       HIP_TRY(hipStreamSynchronize(pl->cs));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
-      if (c.steps > 1 && geo.J > 1) {
+      if (c.steps >= 1 && geo.J > 1) {
         // the exchange pass runs once per window: charge its share
         float ex_ms = 0.f;
         HIP_TRY(hipEventRecord(pl->ev0, pl->cs));

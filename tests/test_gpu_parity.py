@@ -175,9 +175,10 @@ def test_max_iter_returns_last_iterate():
 
 
 # ------------------------------------------------- launch configurations ----
-CONFIGS = [(1, 0, 1), (1, 64, 1), (2, 0, 1), (2, 48, 1), (4, 16, 1), (4, 32, 1), (8, 8, 1),
-           (8, 0, 1), (16, 8, 1), (16, 0, 1),
-           # multi-step march kernel: (waves, seg_max, steps per launch)
+CONFIGS = [(1, 0, 0), (1, 64, 0), (2, 0, 0), (2, 48, 0), (4, 16, 0), (4, 32, 0), (8, 8, 0),
+           (8, 0, 0), (16, 8, 0), (16, 0, 0),
+           # register march kernel: (waves, seg_max, steps per launch)
+           (4, 24, 1), (8, 10, 1), (16, 6, 1),
            (4, 24, 2), (4, 24, 8), (8, 10, 4), (8, 10, 7), (16, 8, 8), (16, 6, 16),
            (8, 24, 12), (4, 32, 5), (16, 12, 9)]
 
@@ -202,7 +203,7 @@ def test_every_launch_configuration_agrees(waves, seg, steps, tr):
     assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
 
 
-@pytest.mark.parametrize("steps", [1, 8])
+@pytest.mark.parametrize("steps", [0, 1, 8])
 def test_mono_multi_step_and_tiny_grids(steps):
     """The march kernel on grids narrower than its tiles (lanes wrap around
     the periodic x-range) and with a window shorter than one launch."""
@@ -229,7 +230,7 @@ def test_graph_and_direct_launch_agree_and_are_deterministic():
 
 
 # ------------------------------------------------------------------ batch --
-@pytest.mark.parametrize("cfg", [(16, 32, 1), (16, 12, 6)])
+@pytest.mark.parametrize("cfg", [(16, 32, 0), (16, 12, 6), (8, 24, 1)])
 def test_batch_matches_single_solves(cfg):
     specs = [
         (64, 64, 40, 0.2, 2, 2, R, 4.0),
