@@ -202,6 +202,13 @@ typedef struct kfp_mlp kfp_mlp;
  * The handle is owned by the caller (kfp_mlp_destroy). */
 kfp_status kfp_mlp_create(int32_t in, int32_t hidden, int32_t depth, int64_t out, uint64_t seed,
                           kfp_mlp **mlp);
+/* As kfp_mlp_create, with flags: KFP_MLP_SKIP makes the output layer read
+ * the last hidden activations followed by the network input (a GELU trunk
+ * plus a linear map of the input; its W is [out][hidden + in]).  Ignored
+ * for depth 0.  Other bits: KFP_EINVAL. */
+#define KFP_MLP_SKIP 1
+kfp_status kfp_mlp_create_ex(int32_t in, int32_t hidden, int32_t depth, int64_t out,
+                             int32_t flags, uint64_t seed, kfp_mlp **mlp);
 void kfp_mlp_destroy(kfp_mlp *mlp);
 /* Y[B][out] = net(X[B][in]).  Asynchronous. */
 kfp_status kfp_mlp_forward(kfp_mlp *mlp, int32_t B, const float *X, float *Y, void *stream);
@@ -225,16 +232,24 @@ kfp_status kfp_mlp_save(const kfp_mlp *mlp, const char *path);
 kfp_status kfp_mlp_load(const char *path, kfp_mlp **mlp);
 
 /* Data helpers for building training sets from solver output.  All device
- * pointers, asynchronous.  kfp_column_stats: per-column mean and standard
- * deviation (at least floor_) of X[rows][cols]; kfp_standardize: X = (X -
- * mean) / std in place; kfp_destandardize: lam = mean + std * Y (FP64 out). */
-kfp_status kfp_cast_f64_f32(const double *src, float *dst, int64_t n, void *stream);
+ * pointers, asynchronous.  kfp_cast_f64_f32: dst = (float)(src - base), base
+ * NULL for none (a network can learn the correction to a cheaper guess);
+ * kfp_column_stats: per-column mean and standard deviation (at least floor_)
+ * of X[rows][cols]; kfp_standardize: X = (X - mean) / std in place;
+ * kfp_destandardize: lam = base + mean + std * Y in FP64, base [rows][cols]
+ * FP64 or NULL. */
+kfp_status kfp_cast_f64_f32(const double *src, const double *base, float *dst, int64_t n,
+                            void *stream);
+/* y += alpha * x and y *= a (element-wise), n FP32 values: the residual
+ * targets and composed scales of a network fitted in stages. */
+kfp_status kfp_axpy_f32(const float *x, float *y, float alpha, int64_t n, void *stream);
+kfp_status kfp_mul_f32(const float *a, float *y, int64_t n, void *stream);
 kfp_status kfp_column_stats(const float *X, int32_t rows, int64_t cols, float floor_,
                             float *mean, float *stdv, void *stream);
 kfp_status kfp_standardize(float *X, int32_t rows, int64_t cols, const float *mean,
                            const float *stdv, void *stream);
 kfp_status kfp_destandardize(const float *Y, int32_t rows, int64_t cols, const float *mean,
-                             const float *stdv, double *lam, void *stream);
+                             const float *stdv, const double *base, double *lam, void *stream);
 
 /* Frees all cached workspace (plans, graphs, trace windows). */
 void kfp_release_workspace(void);

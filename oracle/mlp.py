@@ -2,9 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain numpy in FP64:
 Linear -> GELU (erf form) repeated, then a final Linear; mean-squared-error
-loss; Adam.  An optional mode rounds every matrix-product operand to bfloat16
-(round to nearest, ties to even) before the product, mirroring a network that
-keeps BF16 weights and BF16 activations and accumulates in higher precision.
+loss; Adam.  With skip=True the final Linear reads the last hidden
+activations followed by the network input (concatenated in that order), so
+the network is a GELU trunk plus a linear map of its input.  An optional
+mode rounds every matrix-product operand to bfloat16 (round to nearest, ties
+to even) before the product, mirroring a network that keeps BF16 weights and
+BF16 activations and accumulates in higher precision.
 
 Weights are stored as W[out][in] (y = x W^T + b).
 """
@@ -41,20 +44,24 @@ def gelu_grad(z):
 class MLP:
     """params: list of (W [out][in], b [out]) in FP64."""
 
-    def __init__(self, params, bf16=False):
+    def __init__(self, params, bf16=False, skip=False):
         self.params = [(np.array(W, dtype=np.float64), np.array(b, dtype=np.float64))
                        for W, b in params]
         self.bf16 = bf16
+        self.skip = skip and len(self.params) > 1
 
     def _r(self, a):
         return bf16_round(a) if self.bf16 else a
 
     def forward(self, x):
         """Returns output y and the cache of (input, pre-activation) per layer."""
-        a = np.asarray(x, dtype=np.float64)
+        x = np.asarray(x, dtype=np.float64)
+        a = x
         cache = []
         L = len(self.params)
         for l, (W, b) in enumerate(self.params):
+            if self.skip and l == L - 1:
+                a = np.concatenate([a, x], axis=1)
             ar = self._r(a)
             z = ar @ self._r(W).T + b
             cache.append((ar, z))
@@ -82,6 +89,8 @@ class MLP:
             grads[l] = (dr.T @ ar, d.sum(axis=0))
             if l > 0:
                 d = dr @ self._r(W)
+                if self.skip and l == len(self.params) - 1:
+                    d = d[:, : self.params[l - 1][0].shape[0]]  # the input part ends here
         return loss, grads
 
 

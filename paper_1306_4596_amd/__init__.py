@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     ROBIN,
     KfpError,
     SWRStats,
+    axpy_f32,
     bw_probe,
     cast_f64_f32,
     column_stats,
@@ -22,6 +23,7 @@ from .binding import (  # noqa: F401
     lib_path,
     load_library,
     mono_solve,
+    mul_f32,
     release_workspace,
     set_config,
     standardize,

@@ -315,6 +315,8 @@ def _mlp_sigs(lib):
     vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     pd = ctypes.POINTER(ctypes.c_double)
     lib.kfp_mlp_create.argtypes = [i32, i32, i32, i64, ctypes.c_uint64, ctypes.POINTER(vp)]
+    lib.kfp_mlp_create_ex.argtypes = [i32, i32, i32, i64, i32, ctypes.c_uint64,
+                                      ctypes.POINTER(vp)]
     lib.kfp_mlp_destroy.argtypes = [vp]
     lib.kfp_mlp_destroy.restype = None
     lib.kfp_mlp_forward.argtypes = [vp, i32, vp, vp, vp]
@@ -325,29 +327,37 @@ def _mlp_sigs(lib):
     lib.kfp_mlp_param.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.kfp_mlp_save.argtypes = [vp, ctypes.c_char_p]
     lib.kfp_mlp_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
-    lib.kfp_cast_f64_f32.argtypes = [vp, vp, i64, vp]
+    lib.kfp_cast_f64_f32.argtypes = [vp, vp, vp, i64, vp]
     lib.kfp_column_stats.argtypes = [vp, i32, i64, f32, vp, vp, vp]
+    lib.kfp_axpy_f32.argtypes = [vp, vp, f32, i64, vp]
+    lib.kfp_mul_f32.argtypes = [vp, vp, i64, vp]
     lib.kfp_standardize.argtypes = [vp, i32, i64, vp, vp, vp]
-    lib.kfp_destandardize.argtypes = [vp, i32, i64, vp, vp, vp, vp]
-    for n in ("kfp_mlp_create", "kfp_mlp_forward", "kfp_mlp_backward", "kfp_mlp_adam",
+    lib.kfp_destandardize.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
+    for n in ("kfp_mlp_create", "kfp_mlp_create_ex", "kfp_mlp_forward", "kfp_mlp_backward", "kfp_mlp_adam",
               "kfp_mlp_train_step", "kfp_mlp_layer_shape", "kfp_mlp_param", "kfp_mlp_save",
               "kfp_mlp_load", "kfp_cast_f64_f32", "kfp_column_stats", "kfp_standardize",
-              "kfp_destandardize"):
+              "kfp_destandardize", "kfp_axpy_f32", "kfp_mul_f32"):
         getattr(lib, n).restype = ctypes.c_int
     lib._mlp_sigs = True
     return lib
 
 
-class MLP:
-    """Handle of the library's network (BF16 weights, FP32 accumulation)."""
+MLP_SKIP = 1
 
-    def __init__(self, n_in=64, hidden=512, depth=3, n_out=786432, seed=0, _handle=None):
+
+class MLP:
+    """Handle of the library's network (BF16 weights, FP32 accumulation).
+    skip=True: the output layer also reads the network input (a GELU trunk
+    plus a linear map of the input)."""
+
+    def __init__(self, n_in=64, hidden=512, depth=3, n_out=786432, seed=0, skip=False,
+                 _handle=None):
         lib = _mlp_sigs(load_library())
         self._lib = lib
         if _handle is None:
             h = ctypes.c_void_p()
-            _check(lib.kfp_mlp_create(int(n_in), int(hidden), int(depth), int(n_out), int(seed),
-                                      ctypes.byref(h)))
+            _check(lib.kfp_mlp_create_ex(int(n_in), int(hidden), int(depth), int(n_out),
+                                         MLP_SKIP if skip else 0, int(seed), ctypes.byref(h)))
             _handle = h
         self._h = _handle
         self.depth = self.layers() - 1
@@ -436,9 +446,39 @@ class MLP:
         torch.cuda.current_stream().synchronize()
 
 
-def cast_f64_f32(src, dst, stream=None):
+def cast_f64_f32(src, dst, base=None, stream=None):
+    """dst = (float)(src - base); base None for none."""
+    import torch
+
     lib = _mlp_sigs(load_library())
-    _check(lib.kfp_cast_f64_f32(_fptr(src), _fptr(dst), int(src.numel()), _stream(stream)))
+    n = int(src.numel())
+    if dst.numel() != n or (base is not None and base.numel() != n):
+        raise KfpError(KFP_EINVAL, f"cast_f64_f32: sizes differ ({n}, {dst.numel()})")
+    bp = None if base is None else _fptr(base, torch.float64)
+    _check(lib.kfp_cast_f64_f32(_fptr(src, torch.float64), bp, _fptr(dst, torch.float32), n,
+                                _stream(stream)))
+
+
+def axpy_f32(x, y, alpha, stream=None):
+    """y += alpha * x (FP32, same size, in place)."""
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    if x.numel() != y.numel():
+        raise KfpError(KFP_EINVAL, "axpy_f32: sizes differ")
+    _check(lib.kfp_axpy_f32(_fptr(x, torch.float32), _fptr(y, torch.float32), float(alpha),
+                            int(y.numel()), _stream(stream)))
+
+
+def mul_f32(a, y, stream=None):
+    """y *= a element-wise (FP32, same size, in place)."""
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    if a.numel() != y.numel():
+        raise KfpError(KFP_EINVAL, "mul_f32: sizes differ")
+    _check(lib.kfp_mul_f32(_fptr(a, torch.float32), _fptr(y, torch.float32), int(y.numel()),
+                           _stream(stream)))
 
 
 def column_stats(X, floor=1e-6, stream=None):
@@ -462,12 +502,16 @@ def standardize(X, mean, std, stream=None):
                                _fptr(std), _stream(stream)))
 
 
-def destandardize(Y, mean, std, out=None, stream=None):
+def destandardize(Y, mean, std, out=None, base=None, stream=None):
+    """lam = base + mean + std * Y in FP64 (base [rows][cols] FP64 or None)."""
     import torch
 
     lib = _mlp_sigs(load_library())
     rows, cols = Y.shape
     lam = out if out is not None else torch.empty((rows, cols), dtype=torch.float64, device=Y.device)
+    if base is not None and base.numel() != rows * cols:
+        raise KfpError(KFP_EINVAL, "destandardize: base has the wrong size")
+    bp = None if base is None else _fptr(base, torch.float64)
     _check(lib.kfp_destandardize(_fptr(Y, torch.float32), int(rows), int(cols), _fptr(mean),
-                                 _fptr(std), _fptr(lam, torch.float64), _stream(stream)))
+                                 _fptr(std), bp, _fptr(lam, torch.float64), _stream(stream)))
     return lam

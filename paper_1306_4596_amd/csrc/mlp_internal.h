@@ -25,7 +25,10 @@ struct GemmArgs {
 
 hipError_t launch_gemm_nt(const GemmArgs &g, int splits, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float *s_, __bf16 *d, size_t n, hipStream_t s);
-hipError_t launch_f64_to_f32(const double *s_, float *d, size_t n, hipStream_t s);
+hipError_t launch_f32_to_bf16_cols(const float *s_, int rows, int cols, __bf16 *d, long ldd,
+                                   hipStream_t s);
+hipError_t launch_f64_to_f32(const double *s_, const double *base, float *d, size_t n,
+                             hipStream_t s);
 hipError_t launch_mse_grad(const float *Y, const float *T, float *d32, __bf16 *db, size_t n,
                            float scale, double *loss, hipStream_t s);
 hipError_t launch_gelu_back(const float *dA, const float *Z, float *d32, __bf16 *db, size_t n,
@@ -34,8 +37,11 @@ hipError_t launch_colsum(const float *X, int R, int C, float *out, hipStream_t s
 hipError_t launch_transpose_bf16(const __bf16 *src, __bf16 *dst, int R, int C, hipStream_t s);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, size_t n,
                        float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_destandardize(const float *y, const float *mean, const float *stdv, size_t per,
-                                size_t n, double *lam, hipStream_t s);
+hipError_t launch_destandardize(const float *y, const float *mean, const float *stdv,
+                                const double *base, size_t per, size_t n, double *lam,
+                                hipStream_t s);
+hipError_t launch_axpy(const float *x, float *y, float alpha, size_t n, hipStream_t s);
+hipError_t launch_mul(const float *a, float *y, size_t n, hipStream_t s);
 hipError_t launch_colstats(const float *X, int R, size_t C, float *mean, float *stdv, float floor_,
                            hipStream_t s);
 hipError_t launch_standardize(float *X, size_t per, size_t n, const float *mean, const float *stdv,

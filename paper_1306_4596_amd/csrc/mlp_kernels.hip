@@ -133,8 +133,22 @@ __global__ void f32_to_bf16_kernel(const float *__restrict__ s, __bf16 *__restri
   GRID_STRIDE(e, n) d[e] = (__bf16)s[e];
 }
 
-__global__ void f64_to_f32_kernel(const double *__restrict__ s, float *__restrict__ d, size_t n) {
-  GRID_STRIDE(e, n) d[e] = (float)s[e];
+// [rows][cols] FP32 into the columns of a wider BF16 matrix (row stride ldd)
+__global__ void f32_to_bf16_cols_kernel(const float *__restrict__ s, int cols,
+                                        __bf16 *__restrict__ d, long ldd, size_t n) {
+  GRID_STRIDE(e, n) {
+    const size_t r = e / cols, c = e % cols;
+    d[r * ldd + c] = (__bf16)s[e];
+  }
+}
+
+__global__ void f64_to_f32_kernel(const double *__restrict__ s, const double *__restrict__ base,
+                                  float *__restrict__ d, size_t n) {
+  if (base) {
+    GRID_STRIDE(e, n) d[e] = (float)(s[e] - base[e]);
+  } else {
+    GRID_STRIDE(e, n) d[e] = (float)s[e];
+  }
 }
 
 // dY = 2 (Y - T) / (B out): FP32 copy (bias gradient) and BF16 copy (products);
@@ -217,11 +231,13 @@ __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g,
 
 // lambda = mean + std * y, FP32 -> FP64 (de-standardised network output)
 __global__ void destandardize_kernel(const float *__restrict__ y, const float *__restrict__ mean,
-                                     const float *__restrict__ stdv, size_t per, size_t n,
+                                     const float *__restrict__ stdv,
+                                     const double *__restrict__ base, size_t per, size_t n,
                                      double *__restrict__ lam) {
   GRID_STRIDE(e, n) {
     const size_t j = e % per;
-    lam[e] = (double)mean[j] + (double)stdv[j] * (double)y[e];
+    const double v = (double)mean[j] + (double)stdv[j] * (double)y[e];
+    lam[e] = base ? base[e] + v : v;
   }
 }
 
@@ -243,6 +259,15 @@ __global__ __launch_bounds__(256) void colstats_kernel(const float *__restrict__
   double sd = sqrt(var);
   mean[c] = (float)mu;
   stdv[c] = (float)(sd > floor_ ? sd : floor_);
+}
+
+__global__ void axpy_kernel(const float *__restrict__ x, float *__restrict__ y, float alpha,
+                            size_t n) {
+  GRID_STRIDE(e, n) y[e] = fmaf(alpha, x[e], y[e]);
+}
+
+__global__ void mul_kernel(const float *__restrict__ a, float *__restrict__ y, size_t n) {
+  GRID_STRIDE(e, n) y[e] *= a[e];
 }
 
 __global__ void standardize_kernel(float *__restrict__ X, size_t per, size_t n,
@@ -272,9 +297,19 @@ hipError_t launch_f32_to_bf16(const float *s_, __bf16 *d, size_t n, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_f64_to_f32(const double *s_, float *d, size_t n, hipStream_t s) {
+hipError_t launch_f32_to_bf16_cols(const float *s_, int rows, int cols, __bf16 *d, long ldd,
+                                   hipStream_t s) {
+  const size_t n = (size_t)rows * cols;
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(egrid(n)), dim3(256), 0, s, s_, d, n);
+  hipLaunchKernelGGL(f32_to_bf16_cols_kernel, dim3(egrid(n)), dim3(256), 0, s, s_, cols, d, ldd,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double *s_, const double *base, float *d, size_t n,
+                             hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(egrid(n)), dim3(256), 0, s, s_, base, d, n);
   return hipGetLastError();
 }
 
@@ -310,10 +345,24 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb,
   return hipGetLastError();
 }
 
-hipError_t launch_destandardize(const float *y, const float *mean, const float *stdv, size_t per,
-                                size_t n, double *lam, hipStream_t s) {
-  hipLaunchKernelGGL(destandardize_kernel, dim3(egrid(n)), dim3(256), 0, s, y, mean, stdv, per, n,
-                     lam);
+hipError_t launch_destandardize(const float *y, const float *mean, const float *stdv,
+                                const double *base, size_t per, size_t n, double *lam,
+                                hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(destandardize_kernel, dim3(egrid(n)), dim3(256), 0, s, y, mean, stdv, base,
+                     per, n, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(const float *x, float *y, float alpha, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(axpy_kernel, dim3(egrid(n)), dim3(256), 0, s, x, y, alpha, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul(const float *a, float *y, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(mul_kernel, dim3(egrid(n)), dim3(256), 0, s, a, y, n);
   return hipGetLastError();
 }
 

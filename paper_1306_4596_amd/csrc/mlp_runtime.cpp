@@ -75,6 +75,7 @@ struct Acts {
 
 struct kfp_mlp {
   int in = 0, hidden = 0, depth = 0;
+  int skip = 0;  // the output layer also reads the network input (depth >= 1)
   long out = 0;
   long long step = 0;
   std::vector<kfp::Layer> L;
@@ -127,9 +128,11 @@ static kfp_status ensure_acts(kfp_mlp *m, int B) {
   a.Ab.assign(nh, nullptr);
   a.At.assign(nh, nullptr);
   for (int l = 0; l < nh; ++l) {
+    // the last hidden activations sit beside a copy of the input with skip
+    const size_t w = (size_t)m->hidden + ((m->skip && l == nh - 1) ? m->in : 0);
     MHIP(dmalloc(&a.Z[l], (size_t)B * m->hidden));
-    MHIP(dmalloc(&a.Ab[l], (size_t)B * m->hidden));
-    MHIP(dmalloc(&a.At[l], (size_t)B * m->hidden));
+    MHIP(dmalloc(&a.Ab[l], (size_t)B * w));
+    MHIP(dmalloc(&a.At[l], (size_t)B * w));
   }
   MHIP(dmalloc(&a.Y, (size_t)B * m->out));
   MHIP(dmalloc(&a.d32, (size_t)B * m->out));
@@ -201,20 +204,23 @@ static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream
     Layer &L = m->L[l];
     GemmArgs g = gargs(B, (int)L.out, L.in, cur, cur_w, L.Wb, L.in);
     g.bias = L.b;
+    const bool concat = m->skip && l == nl - 2;
+    const long wcat = concat ? L.out + m->in : L.out;
     if (l < nl - 1) {
       g.C = a.Z[l];
       g.ldc = L.out;
       g.Cb = a.Ab[l];
-      g.ldcb = L.out;
+      g.ldcb = wcat;
       g.gelu = 1;
     } else {
       g.C = Y;
       g.ldc = L.out;
     }
     if ((st = gemm(m, g, s))) return st;
+    if (concat) MHIP(launch_f32_to_bf16_cols(X, B, m->in, a.Ab[l] + L.out, wcat, s));
     if (l < nl - 1) {
       cur = a.Ab[l];
-      cur_w = (int)L.out;
+      cur_w = (int)wcat;
     }
   }
   return KFP_OK;
@@ -248,12 +254,14 @@ static kfp_status backward(kfp_mlp *m, int B, const float *X, const float *T, do
     gw.ldc = L.in;
     if ((st = gemm(m, gw, s))) return st;
     if (l == 0) break;
-    // input gradient: dA[b][i] = sum_o d[b][o] W^T[i][o]
-    GemmArgs gx = gargs(B, L.in, outw, dbf, outw, L.Wt, outw);
+    // input gradient: dA[b][i] = sum_o d[b][o] W^T[i][o], over the hidden
+    // inputs only (the input columns of a skip layer end there)
+    const int hin = (m->skip && l == nl - 1) ? m->hidden : L.in;
+    GemmArgs gx = gargs(B, hin, outw, dbf, outw, L.Wt, outw);
     gx.C = a.dA;
-    gx.ldc = L.in;
+    gx.ldc = hin;
     if ((st = gemm(m, gx, s))) return st;
-    MHIP(launch_gelu_back(a.dA, a.Z[l - 1], a.dZ32, a.dZb, (size_t)B * L.in, s));
+    MHIP(launch_gelu_back(a.dA, a.Z[l - 1], a.dZ32, a.dZb, (size_t)B * hin, s));
     d32 = a.dZ32;
     dbf = a.dZb;
     dtr = a.dZt;
@@ -290,22 +298,25 @@ static kfp_status refresh_copies(kfp_mlp *m, hipStream_t s) {
   return KFP_OK;
 }
 
-static kfp_status create(int in, int hidden, int depth, long out, unsigned long long seed,
-                         bool init, kfp_mlp **res) {
+static kfp_status create(int in, int hidden, int depth, long out, int flags,
+                         unsigned long long seed, bool init, kfp_mlp **res) {
   if (in < 8 || in % 8 || hidden < 8 || hidden % 8 || depth < 0 || depth > 16 || out < 1 ||
       out % 8)
     return mfail(KFP_EINVAL,
                  "network shape: in, hidden and out must be positive multiples of 8, depth 0..16");
+  if (flags & ~KFP_MLP_SKIP) return mfail(KFP_EINVAL, "unknown network flags %d", flags);
   std::unique_ptr<kfp_mlp> m(new kfp_mlp());
   m->in = in;
   m->hidden = hidden;
   m->depth = depth;
   m->out = out;
+  m->skip = (flags & KFP_MLP_SKIP) && depth >= 1;
   const int nl = depth + 1;
   m->L.resize(nl);
   for (int l = 0; l < nl; ++l) {
     Layer &L = m->L[l];
     L.in = (l == 0) ? in : hidden;
+    if (m->skip && l == nl - 1) L.in += in;
     L.out = (l == nl - 1) ? out : hidden;
     const size_t nw = (size_t)L.out * L.in;
     auto bad = [&](hipError_t e) {
@@ -360,7 +371,15 @@ kfp_status kfp_mlp_create(int32_t in, int32_t hidden, int32_t depth, int64_t out
   std::lock_guard<std::recursive_mutex> lk(m_mu);
   m_err.clear();
   if (!mlp) return mfail(KFP_EINVAL, "mlp is NULL");
-  return create(in, hidden, depth, (long)out, seed, true, mlp);
+  return create(in, hidden, depth, (long)out, 0, seed, true, mlp);
+}
+
+kfp_status kfp_mlp_create_ex(int32_t in, int32_t hidden, int32_t depth, int64_t out,
+                             int32_t flags, uint64_t seed, kfp_mlp **mlp) {
+  std::lock_guard<std::recursive_mutex> lk(m_mu);
+  m_err.clear();
+  if (!mlp) return mfail(KFP_EINVAL, "mlp is NULL");
+  return create(in, hidden, depth, (long)out, flags, seed, true, mlp);
 }
 
 void kfp_mlp_destroy(kfp_mlp *m) {
@@ -442,8 +461,8 @@ kfp_status kfp_mlp_save(const kfp_mlp *m, const char *path) {
   if (!m || !path) return mfail(KFP_EINVAL, "save: bad arguments");
   FILE *fp = fopen(path, "wb");
   if (!fp) return mfail(KFP_EINVAL, "save: cannot open %s", path);
-  const char magic[8] = {'K', 'F', 'P', 'M', 'L', 'P', '1', 0};
-  long long hdr[5] = {m->in, m->hidden, m->depth, m->out, m->step};
+  const char magic[8] = {'K', 'F', 'P', 'M', 'L', 'P', '2', 0};
+  long long hdr[6] = {m->in, m->hidden, m->depth, m->out, m->step, m->skip ? KFP_MLP_SKIP : 0};
   bool ok = fwrite(magic, 1, 8, fp) == 8 && fwrite(hdr, sizeof hdr, 1, fp) == 1;
   std::vector<float> h;
   for (const auto &L : m->L) {
@@ -469,14 +488,18 @@ kfp_status kfp_mlp_load(const char *path, kfp_mlp **res) {
   FILE *fp = fopen(path, "rb");
   if (!fp) return mfail(KFP_EINVAL, "load: cannot open %s", path);
   char magic[8];
-  long long hdr[5];
-  if (fread(magic, 1, 8, fp) != 8 || memcmp(magic, "KFPMLP1", 8) != 0 ||
-      fread(hdr, sizeof hdr, 1, fp) != 1) {
+  long long hdr[6] = {0, 0, 0, 0, 0, 0};
+  // version 1 headers have no flags word
+  const bool ok_magic = fread(magic, 1, 8, fp) == 8 &&
+                        (memcmp(magic, "KFPMLP1", 8) == 0 || memcmp(magic, "KFPMLP2", 8) == 0);
+  const size_t nh = (ok_magic && magic[6] == '2') ? 6 : 5;
+  if (!ok_magic || fread(hdr, sizeof(long long), nh, fp) != nh) {
     fclose(fp);
     return mfail(KFP_EINVAL, "load: %s is not a network checkpoint", path);
   }
   kfp_mlp *m = nullptr;
-  kfp_status st = create((int)hdr[0], (int)hdr[1], (int)hdr[2], (long)hdr[3], 0, false, &m);
+  kfp_status st =
+      create((int)hdr[0], (int)hdr[1], (int)hdr[2], (long)hdr[3], (int)hdr[5], 0, false, &m);
   if (st) {
     fclose(fp);
     return st;
@@ -506,10 +529,26 @@ kfp_status kfp_mlp_load(const char *path, kfp_mlp **res) {
   return KFP_OK;
 }
 
-kfp_status kfp_cast_f64_f32(const double *src, float *dst, int64_t n, void *stream) {
+kfp_status kfp_cast_f64_f32(const double *src, const double *base, float *dst, int64_t n,
+                            void *stream) {
   m_err.clear();
+  if (n < 0) return mfail(KFP_EINVAL, "cast: negative size");
   if ((!src || !dst) && n > 0) return mfail(KFP_EINVAL, "cast: NULL pointer");
-  MHIP(launch_f64_to_f32(src, dst, (size_t)n, (hipStream_t)stream));
+  MHIP(launch_f64_to_f32(src, base, dst, (size_t)n, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_axpy_f32(const float *x, float *y, float alpha, int64_t n, void *stream) {
+  m_err.clear();
+  if (n < 0 || ((!x || !y) && n > 0)) return mfail(KFP_EINVAL, "axpy: bad arguments");
+  MHIP(launch_axpy(x, y, alpha, (size_t)n, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_mul_f32(const float *a, float *y, int64_t n, void *stream) {
+  m_err.clear();
+  if (n < 0 || ((!a || !y) && n > 0)) return mfail(KFP_EINVAL, "mul: bad arguments");
+  MHIP(launch_mul(a, y, (size_t)n, (hipStream_t)stream));
   return KFP_OK;
 }
 
@@ -530,11 +569,11 @@ kfp_status kfp_standardize(float *X, int32_t rows, int64_t cols, const float *me
 }
 
 kfp_status kfp_destandardize(const float *Y, int32_t rows, int64_t cols, const float *mean,
-                             const float *stdv, double *lam, void *stream) {
+                             const float *stdv, const double *base, double *lam, void *stream) {
   m_err.clear();
   if (!Y || !mean || !stdv || !lam || rows < 1 || cols < 1)
     return mfail(KFP_EINVAL, "destandardize: bad args");
-  MHIP(launch_destandardize(Y, mean, stdv, (size_t)cols, (size_t)rows * cols, lam,
+  MHIP(launch_destandardize(Y, mean, stdv, base, (size_t)cols, (size_t)rows * cols, lam,
                             (hipStream_t)stream));
   return KFP_OK;
 }

@@ -24,19 +24,77 @@
 
 namespace kfp {
 
+template <class T>
+using KConst = __attribute__((address_space(4))) const T;
+template <class T>
+__device__ __forceinline__ KConst<T> *as_const(const T *p) {
+  return (KConst<T> *)p;
+}
+
+template <class T>
+using KGlob = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ KGlob<T> *as_glob(T *p) {
+  return (KGlob<T> *)p;
+}
+
+// Copy of a descriptor from the constant address space (scalar loads), in
+// words as wide as its alignment so that pointers stay whole.
+template <class W, int N>
+struct Words {
+  W w[N];
+};
+template <class T>
+__device__ __forceinline__ T load_const(KConst<T> *p) {
+  using W = typename std::conditional<alignof(T) >= 8 && sizeof(T) % 8 == 0,
+                                      unsigned long long, unsigned>::type;
+  static_assert(sizeof(T) % sizeof(W) == 0, "descriptor size");
+  constexpr int N = sizeof(T) / sizeof(W);
+  Words<W, N> v;
+  KConst<W> *q = reinterpret_cast<KConst<W> *>(p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v.w[i] = q[i];
+  return __builtin_bit_cast(T, v);
+}
+
+// The instance descriptor holds pointers: copy it field by field, so that
+// every pointer is loaded with its own type and the copy stays in registers.
+__device__ __forceinline__ InstDev load_inst(KConst<InstDev> *p) {
+  InstDev I;
+  I.U[0] = p->U[0];
+  I.U[1] = p->U[1];
+  I.u0 = p->u0;
+  I.f = p->f;
+  I.g = p->g;
+  I.lam[0] = p->lam[0];
+  I.lam[1] = p->lam[1];
+  I.res = p->res;
+  I.V = p->V;
+  I.r = p->r;
+  I.p = p->p;
+  I.q = p->q;
+  I.hv = p->hv;
+  I.nx = p->nx;
+  I.nv = p->nv;
+  I.nt = p->nt;
+  I.tr = p->tr;
+  I.active = p->active;
+  I.pad_ = 0;
+  return I;
+}
+
 // ---------------------------------------------------------------------------
 // interface traces and residual of time level n (1 <= n <= nt), from U^n
 // ---------------------------------------------------------------------------
+// S: state U^n of the instance; lin / lout: trace windows read / written.
 __device__ __forceinline__ void traces_and_residual(const StepTables &t, const SubDev &sd,
-                                                    const InstDev &I, int n, int par, int lane,
-                                                    int m, int mc, bool valid) {
+                                                    const InstDev &I, const double *S,
+                                                    const double *lin, double *lout, int n,
+                                                    int lane, int m, int mc, bool valid) {
   const int nx = I.nx;
   const size_t plane = (size_t)I.nt * nx;
   const size_t lvl = (size_t)(n - 1) * nx;
-  const double *S = I.U[n & 1];
   const double *self = S + (size_t)sd.row_off * nx;
-  double *lout = I.lam[par ^ 1];
-  const double *lin = I.lam[par];
   const bool robin = I.tr == 1;
   if (sd.out_hi_plane >= 0) {  // Q_2 u_j at a_{j+1}, eq. (6.9)
     const double ua = self[(size_t)sd.out_hi_row * nx + mc];
@@ -57,7 +115,7 @@ __device__ __forceinline__ void traces_and_residual(const StepTables &t, const S
     if (valid) lout[(size_t)sd.out_lo_plane * plane + lvl + m] = v;
   }
   if (sd.res_nb >= 0) {  // (6.12) at the two end nodes of the overlap
-    const SubDev nb = t.subs[sd.res_nb];
+    const SubDev nb = load_const(as_const(t.subs) + sd.res_nb);
     const double *oth = S + (size_t)nb.row_off * nx;
     const double sa = self[(size_t)sd.out_hi_row * nx + mc];
     const double na = sd.res_row_a_nb >= 0 ? oth[(size_t)sd.res_row_a_nb * nx + mc]
@@ -80,9 +138,9 @@ __device__ __forceinline__ void traces_and_residual(const StepTables &t, const S
 
 // Right-hand side of local row i for step n -> n+1.
 __device__ __forceinline__ double row_rhs(const SubDev &sd, const InstDev &I, const RowCoef &c,
-                                          int i, const double *src, const double *fr,
-                                          const double *lin, size_t plane, int n, int mc,
-                                          double gn) {
+                                          int i, KGlob<const double> *src,
+                                          KGlob<const double> *fr, KGlob<const double> *lin,
+                                          size_t plane, int n, int mc, double gn) {
   const int nx = I.nx;
   if (i == 0 && sd.lo_kind == END_ROBIN)
     return lin[(size_t)sd.lam_lo * plane + (size_t)n * nx + mc];
@@ -153,30 +211,39 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int it = blockIdx.x; it < t.n_items; it += gridDim.x) {
-    const Item item = t.items[it];
-    const SubDev sd = t.subs[item.sub];
-    const InstDev &I = t.inst[sd.inst];
+    const Item item = load_const(as_const(t.items) + it);
+    const SubDev sd = load_const(as_const(t.subs) + item.sub);
+    KConst<InstDev> *ip = as_const(t.inst) + sd.inst;
+    const InstDev I = load_inst(ip);
     if (!I.active) continue;
+    // ping-pong buffers picked in constant memory (n and par are uniform)
+    const double *Ucur = ip->U[n & 1];
+    double *Unext = ip->U[(n + 1) & 1];
+    const double *lam_in = ip->lam[par];
+    double *lam_out = ip->lam[par ^ 1];
     const int nx = I.nx;
     const int nt = I.nt;
     const int m = item.x0 + lane;
     const bool valid = m < nx;
     const int mc = valid ? m : nx - 1;
-    if (w == 0 && n >= 1 && n <= nt) traces_and_residual(t, sd, I, n, par, lane, m, mc, valid);
+    if (w == 0 && n >= 1 && n <= nt)
+      traces_and_residual(t, sd, I, Ucur, lam_in, lam_out, n, lane, m, mc, valid);
     if (n >= nt) continue;
 
     const size_t plane = (size_t)nt * nx;
-    const double *src = (n == 0) ? I.u0 + (size_t)sd.g_lo * nx : I.U[n & 1] + (size_t)sd.row_off * nx;
-    double *dst = I.U[(n + 1) & 1] + (size_t)sd.row_off * nx;
-    const double *fr = I.f + (size_t)sd.g_lo * nx;
-    const double *lin = I.lam[par];
-    const double gn = I.g[n];
-    const RowCoef *__restrict__ rows = t.rows + sd.tab;
+    KGlob<const double> *src = as_glob((n == 0) ? I.u0 + (size_t)sd.g_lo * nx
+                                                : Ucur + (size_t)sd.row_off * nx);
+    KGlob<double> *dst = as_glob(Unext + (size_t)sd.row_off * nx);
+    KGlob<const double> *fr = as_glob(I.f + (size_t)sd.g_lo * nx);
+    KGlob<const double> *lin = as_glob(lam_in);
+    const double gn = as_glob(I.g)[n];
+    KConst<RowCoef> *rows = as_const(t.rows) + sd.tab;
+    KConst<int> *segs = as_const(t.segs);
     const int P = sd.P;
     int s0 = 0, len = 0, blk = 0;
     if (w < P) {
-      s0 = t.segs[sd.seg + w];
-      len = t.segs[sd.seg + w + 1] - s0;
+      s0 = segs[sd.seg + w];
+      len = segs[sd.seg + w + 1] - s0;
       blk = (w < P - 1) ? len - 1 : len;
     }
     double xlo = 0.0, xhi = 0.0;
@@ -211,7 +278,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
 #pragma unroll
         for (int k = 0; k < SEGMAX; ++k) {
           if (k < blk) {
-            const RowCoef c = rows[s0 + k];
+            const RowCoef c = load_const(rows + s0 + k);
             y = (k == 0) ? d[k] * c.fa : fma(c.fb, y, d[k] * c.fa);
             d[k] = y;
           }
@@ -245,7 +312,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
 #pragma unroll
         for (int k = 0; k < SEGMAX; ++k) {
           if (k < blk) {
-            const RowCoef c = rows[s0 + k];
+            const RowCoef c = load_const(rows + s0 + k);
             const double v = fma(-c.sl, xlo, fma(-c.sr, xhi, d[k]));
             dst[(size_t)(s0 + k) * nx + m] = v;
           }
@@ -257,7 +324,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
       if (w < P) {
         double y = 0.0, sep = 0.0;
         for (int k = 0; k < len; ++k) {
-          const RowCoef c = rows[s0 + k];
+          const RowCoef c = load_const(rows + s0 + k);
           const double dk = row_rhs(sd, I, c, s0 + k, src, fr, lin, plane, n, mc, gn);
           if (k < blk) {
             y = (k == 0) ? dk * c.fa : fma(c.fb, y, dk * c.fa);
@@ -285,7 +352,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
         if (w < P) {
           reduced_solve<NW>(t.reds + sd.red, P, w, lane, sh_first, sh_last, sh_sep, xlo, xhi);
           for (int k = 0; k < blk; ++k) {
-            const RowCoef c = rows[s0 + k];
+            const RowCoef c = load_const(rows + s0 + k);
             const size_t o = (size_t)(s0 + k) * nx + mc;
             dst[o] = fma(-c.sl, xlo, fma(-c.sr, xhi, dst[o]));
           }
@@ -309,13 +376,6 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
 // Interface-node values of every level go to value planes; the exchange
 // pass turns them into traces and the residual.
 // ---------------------------------------------------------------------------
-template <class T>
-using KConst = __attribute__((address_space(4))) const T;
-template <class T>
-__device__ __forceinline__ KConst<T> *as_const(const T *p) {
-  return (KConst<T> *)p;
-}
-
 // Upwind neighbour of every lane: lane i receives lane i-1 (v > 0, the cell
 // at m-1) or lane i+1 (v < 0, the cell at m+1) through a wave-wide DPP shift;
 // the edge lane keeps its own value (it is halo and becomes invalid anyway).
@@ -334,34 +394,37 @@ __device__ __forceinline__ double from_upper_lane(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// A wave's column segment of SEG <= 32 rows held in registers.  Two vectors
-// of at most 16 doubles, so that a wave-uniform run-time index compiles to
-// relative register addressing (longer vectors would be spilled to scratch).
+// A wave's column segment of SEG <= 48 rows held in registers.  Up to three
+// vectors of at most 16 doubles, so that a wave-uniform run-time index
+// compiles to relative register addressing (longer vectors would be spilled
+// to scratch).
 template <int SEG>
 struct SegRegs {
   static constexpr int NA = SEG < 16 ? SEG : 16;
-  static constexpr int NB = SEG > 16 ? SEG - 16 : 1;
+  static constexpr int NB = SEG > 32 ? 16 : (SEG > 16 ? SEG - 16 : 1);
+  static constexpr int NC = SEG > 32 ? SEG - 32 : 1;
   typedef double va __attribute__((ext_vector_type(NA)));
   typedef double vb __attribute__((ext_vector_type(NB)));
+  typedef double vc __attribute__((ext_vector_type(NC)));
   va a;
   vb b;
+  vc c;
   template <int K>
   __device__ __forceinline__ double ld() const {
     if constexpr (K < 16) return a[K];
-    else return b[K - 16];
+    else if constexpr (K < 32) return b[K - 16];
+    else return c[K - 32];
   }
   template <int K>
   __device__ __forceinline__ void st(double v) {
     if constexpr (K < 16) a[K] = v;
-    else b[K - 16] = v;
+    else if constexpr (K < 32) b[K - 16] = v;
+    else c[K - 32] = v;
   }
   __device__ __forceinline__ double get(int k) const {
     if (SEG <= 16 || k < 16) return a[k];
-    return b[k - 16];
-  }
-  __device__ __forceinline__ void set(int k, double v) {
-    if (SEG <= 16 || k < 16) a[k] = v;
-    else b[k - 16] = v;
+    if (SEG <= 32 || k < 32) return b[k - 16];
+    return c[k - 32];
   }
 };
 
@@ -373,21 +436,20 @@ __device__ __forceinline__ void static_for(F &&f) {
   }
 }
 
-template <class T>
-using KGlob = __attribute__((address_space(1))) T;
-template <class T>
-__device__ __forceinline__ KGlob<T> *as_glob(T *p) {
-  return (KGlob<T> *)p;
-}
-
 // Upwind direction of a wave's rows: all v < 0 (neighbour at m+1), all
 // v >= 0 (neighbour at m-1), or mixed (the wave holding v = 0).
 enum Dir : int { DIR_UP = 0, DIR_LO = 1, DIR_MIX = 2 };
 
+// Segments longer than this keep only the state in registers and re-read
+// the (cache-resident) source rows every step.
+constexpr int kFRegMax = 24;
+
 template <int SEG, int NW, int DIR>
 __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG> &fs,
                                               KConst<MarchCoef> *mc, double gn, int k0,
-                                              double blo, double bhi, int vsplit) {
+                                              double blo, double bhi, int vsplit,
+                                              KGlob<const double> *fr, int base, int nx,
+                                              int col) {
   double y = 0.0;
   double na = mc[0].alpha, nbt = mc[0].beta, nf = mc[0].fb;
   static_for<0, SEG>([&](auto kc) {
@@ -408,7 +470,13 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
       const double a = from_lower_lane(u), c = from_upper_lane(u);
       nb = (k >= vsplit) ? a : c;
     }
-    double tk = fma(al, u, fma(be, nb, gn * fs.template ld<k>()));
+    double fk;
+    if constexpr (SEG <= kFRegMax) {
+      fk = fs.template ld<k>();
+    } else {
+      fk = mc[k].fa * fr[(size_t)max(base + k, 0) * nx + col];
+    }
+    double tk = fma(al, u, fma(be, nb, gn * fk));
     if (k == k0) tk += blo;
     if constexpr (k == SEG - 1) tk += bhi;
     y = fma(fbk, y, tk);
@@ -477,7 +545,7 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
         constexpr int k = decltype(kc)::value;
         const int r = max(base + k, 0);
         d.template st<k>(src[(size_t)r * nx + col]);
-        fs.template st<k>(mc0[k].fa * fr[(size_t)r * nx + col]);
+        if constexpr (SEG <= kFRegMax) fs.template st<k>(mc0[k].fa * fr[(size_t)r * nx + col]);
       });
     }
     // end rows taking boundary data: row 0 in wave 0, row n-1 in the last wave
@@ -509,11 +577,11 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
         }
         // transport + source + forward elimination, one pass
         if (dir == DIR_LO)
-          march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, k0, blo, bhi, vsplit);
+          march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, k0, blo, bhi, vsplit, fr, base, nx, col);
         else if (dir == DIR_UP)
-          march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, k0, blo, bhi, vsplit);
+          march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, k0, blo, bhi, vsplit, fr, base, nx, col);
         else
-          march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, k0, blo, bhi, vsplit);
+          march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, k0, blo, bhi, vsplit, fr, base, nx, col);
         // back substitution
         double x = d.template ld<SEG - 1>();
         double nbc = mc[SEG - 2 >= 0 ? SEG - 2 : 0].bc;
@@ -612,14 +680,14 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
 // at b_j, and max |u_j - u_{j+1}| at the two end nodes of the overlap.
 __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par) {
   __shared__ unsigned long long red[4];
-  const ExItem ex = t.ex[blockIdx.y];
-  const InstDev &I = t.inst[ex.inst];
+  const ExItem ex = load_const(as_const(t.ex) + blockIdx.y);
+  const InstDev I = load_inst(as_const(t.inst) + ex.inst);
   if (!I.active) return;
   const size_t plane = (size_t)I.nt * I.nx;
   const int j = ex.j;
   const double *V = I.V + (size_t)j * 6 * plane;
-  const double *lin = I.lam[par];
-  double *lout = I.lam[par ^ 1];
+  const double *lin = par ? I.lam[1] : I.lam[0];
+  double *lout = par ? I.lam[0] : I.lam[1];
   const bool robin = I.tr == 1;
   unsigned long long r = 0ull;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
@@ -812,7 +880,7 @@ bool step_config_supported(int waves, int seg_max) {
   X(2, 4) X(2, 8) X(2, 12) X(2, 16) X(2, 24) X(2, 32) \
   X(4, 4) X(4, 6) X(4, 8) X(4, 12) X(4, 16) X(4, 20) X(4, 24) X(4, 32) \
   X(8, 4) X(8, 6) X(8, 8) X(8, 10) X(8, 12) X(8, 14) X(8, 17) X(8, 20) X(8, 24) \
-  X(16, 4) X(16, 6) X(16, 8) X(16, 9) X(16, 10) X(16, 12)
+  X(16, 4) X(16, 6) X(16, 8) X(16, 9) X(16, 10) X(16, 12) X(8, 33) X(8, 40)
 
 bool march_config_supported(int waves, int seg_max) {
 #define KFP_CHECK(W, S) \

@@ -194,6 +194,17 @@ static Config default_config(int n_max) {
   return c;
 }
 
+// Register march kernel by default: the fewest wavefronts (at most 8, where
+// the registers hold a segment without spilling) whose segment fits.
+static Config default_march(int n_max) {
+  for (int w : kWaves) {
+    if (w > 8) break;
+    const int sm = march_seg_for(n_max, w);
+    if (sm && (sm <= 24 || w == 8)) return Config{w, sm, 8};
+  }
+  return Config{};
+}
+
 static Config g_forced;  // waves == 0: automatic
 
 // Tuning cache: a flat JSON object {"key": [waves, seg], ...}.
@@ -288,11 +299,8 @@ static Config choose_config(const Geo &g) {
   if (it != g_tune->end() && (it->second.seg == 0 || segs_for(g.n_max, it->second.waves) <= it->second.seg))
     return it->second;
   if (g.J > 0 && g.nx > 0) {
-    // multi-step march by default when a segment of at most 24 rows fits
-    for (int w : kWaves) {
-      const int sm = march_seg_for(g.n_max, w);
-      if (sm && sm <= 24) return Config{w, sm, 8};
-    }
+    const Config c = default_march(g.n_max);
+    if (c.waves) return c;
   }
   return default_config(g.n_max);
 }
@@ -812,6 +820,9 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
   if (it != g_plans.end()) {
     g_plan_lru.erase(std::find(g_plan_lru.begin(), g_plan_lru.end(), key));
     g_plan_lru.push_back(key);
+    // the key leaves out T (buffers and partition do not depend on it); the
+    // coefficient tables built from the plan's geometry must see this call's
+    it->second->geo = geo;
     *out = it->second.get();
     return KFP_OK;
   }
@@ -1081,10 +1092,41 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
 struct BatchInst {
   Geo geo;
   double p;
-  double *U0, *U1, *lam0, *lam1, *g, *V = nullptr;
-  int *rowmap;
-  size_t win;
+  double *U0 = nullptr, *U1 = nullptr, *lam0 = nullptr, *lam1 = nullptr, *g = nullptr,
+         *V = nullptr;
+  int *rowmap = nullptr;
+  size_t win = 0;
+  int cls = 0;  // launch class
 };
+
+// Instances whose tallest subdomain needs the same launch configuration
+// share tables and launches; every class advances in the same iteration.
+struct BatchClass {
+  Config cfg;
+  std::vector<int> members;
+  HostTables h;
+  DevTables dt;
+  int grid = 1;
+  int nt_max = 0;
+};
+
+static Config batch_config(int n_max) {
+  if (g_forced.waves > 0) {
+    Geo probe;
+    probe.nx = 0;
+    probe.n_max = n_max;
+    probe.J = 0;
+    probe.tr = -1;
+    return choose_config(probe);
+  }
+  if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
+  char key[96];
+  snprintf(key, sizeof key, "%s/batch/nmax%d", arch_name().c_str(), n_max);
+  auto it = g_tune->find(key);
+  if (it != g_tune->end()) return it->second;
+  const Config c = default_march(n_max);
+  return c.waves ? c : default_config(n_max);
+}
 
 static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol, int max_iter,
                                  kfp_swr_stats *stats, hipStream_t user) {
@@ -1093,7 +1135,6 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
   if (!(tol > 0.0)) return fail(KFP_EINVAL, "tol must be > 0");
   if (max_iter < 1) return fail(KFP_EINVAL, "max_iter must be >= 1");
   std::vector<BatchInst> bi(n_inst);
-  int n_max = 0, nt_max = 0;
   for (int i = 0; i < n_inst; ++i) {
     kfp_status st = make_geo(&in[i].g, in[i].J, in[i].overlap, in[i].tr, in[i].p, bi[i].geo);
     if (st) return fail(st, "instance %d: %s", i, g_err.c_str());
@@ -1103,44 +1144,39 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       for (int n = 0; n <= in[i].g.nt; ++n)
         if (!std::isfinite(in[i].s[n])) return fail(KFP_EINVAL, "instance %d: s not finite", i);
     bi[i].p = in[i].p;
-    n_max = std::max(n_max, bi[i].geo.n_max);
-    nt_max = std::max(nt_max, in[i].g.nt);
   }
-  Geo probe;
-  probe.nx = 0;
-  probe.n_max = n_max;
-  probe.J = 0;
-  probe.tr = -1;
-  Config cfg = g_forced.waves > 0 ? choose_config(probe) : default_config(n_max);
-  if (g_forced.waves == 0) {
-    for (int w : kWaves) {
-      const int sm = march_seg_for(n_max, w);
-      if (sm && sm <= 24) {
-        cfg = Config{w, sm, 8};
+  // launch classes
+  std::vector<BatchClass> cls;
+  for (int i = 0; i < n_inst; ++i) {
+    const Config c = batch_config(bi[i].geo.n_max);
+    int k = 0;
+    for (; k < (int)cls.size(); ++k)
+      if (cls[k].cfg.waves == c.waves && cls[k].cfg.seg == c.seg && cls[k].cfg.steps == c.steps)
         break;
-      }
+    if (k == (int)cls.size()) {
+      cls.emplace_back();
+      cls.back().cfg = c;
     }
+    cls[k].members.push_back(i);
+    cls[k].nt_max = std::max(cls[k].nt_max, bi[i].geo.nt);
+    bi[i].cls = k;
   }
-  if (g_forced.waves == 0) {
-    if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
-    char key[96];
-    snprintf(key, sizeof key, "%s/batch/nmax%d", arch_name().c_str(), n_max);
-    auto it = g_tune->find(key);
-    if (it != g_tune->end()) cfg = it->second;
-  }
+
   hipStream_t cs;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   struct Guard {
     std::vector<void *> ptrs;
     hipStream_t s;
     std::vector<hipGraphExec_t> ge;
+    std::vector<BatchClass> *cls;
     ~Guard() {
       for (auto g : ge)
         if (g) (void)hipGraphExecDestroy(g);
+      for (auto &c : *cls) c.dt.release();
       for (void *p : ptrs) (void)hipFree(p);
       (void)hipStreamDestroy(s);
     }
-  } guard{{}, cs, {nullptr, nullptr}};
+  } guard{{}, cs, {nullptr, nullptr}, &cls};
   auto dalloc = [&](size_t bytes, void **p) -> hipError_t {
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
     if (e == hipSuccess) guard.ptrs.push_back(*p);
@@ -1152,16 +1188,15 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
   HIP_TRY(hipStreamWaitEvent(cs, ev, 0));
   HIP_TRY(hipEventDestroy(ev));
 
-  // workspace and tables; items sorted largest-first (LPT) for the
-  // persistent grid
-  HostTables h;
   std::vector<InstDev> idev(n_inst);
   unsigned long long *res = nullptr;
+  InstDev *d_inst = nullptr;
   HIP_TRY(dalloc(sizeof(unsigned long long) * n_inst, (void **)&res));
-  std::vector<std::pair<int, Item>> weighted;
+  HIP_TRY(dalloc(sizeof(InstDev) * n_inst, (void **)&d_inst));
   for (int i = 0; i < n_inst; ++i) {
     BatchInst &b = bi[i];
     const Geo &geo = b.geo;
+    const Config &cfg = cls[b.cls].cfg;
     const size_t state = (size_t)geo.rows * geo.nx;
     b.win = (size_t)2 * (geo.J - 1) * geo.nt * geo.nx;
     HIP_TRY(dalloc(state * 8, (void **)&b.U0));
@@ -1170,6 +1205,8 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     HIP_TRY(dalloc(b.win * 8, (void **)&b.lam1));
     HIP_TRY(dalloc(geo.nt * 8, (void **)&b.g));
     HIP_TRY(dalloc((geo.nv + 1) * sizeof(int), (void **)&b.rowmap));
+    if (cfg.steps >= 1 && geo.J > 1)
+      HIP_TRY(dalloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx * 8, (void **)&b.V));
     HIP_TRY(hipMemcpyAsync(b.rowmap, geo.rowmap.data(), (geo.nv + 1) * sizeof(int),
                            hipMemcpyHostToDevice, cs));
     std::vector<double> gv(geo.nt);
@@ -1177,14 +1214,6 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (in[i].s ? in[i].s[n + 1] : 1.0);
     HIP_TRY(hipMemcpyAsync(b.g, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, cs));
     HIP_TRY(hipStreamSynchronize(cs));
-    if (cfg.steps >= 1 && geo.J > 1)
-      HIP_TRY(dalloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx * 8, (void **)&b.V));
-    const int sub_base = (int)h.subs.size();
-    add_instance_cfg(geo, b.p, cfg.waves, cfg.seg, cfg.steps, i, h);
-    make_ex(geo, i, h.ex);
-    std::vector<Item> it;
-    make_items(geo, sub_base, tile_width(cfg), it);
-    for (const Item &x : it) weighted.push_back({h.subs[x.sub].n * geo.nt, x});
     InstDev &d = idev[i];
     d.U[0] = b.U0;
     d.U[1] = b.U1;
@@ -1212,24 +1241,38 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       }
     }
   }
-  std::stable_sort(weighted.begin(), weighted.end(),
-                   [](const std::pair<int, Item> &x, const std::pair<int, Item> &y) {
-                     return x.first > y.first;
-                   });
-  for (auto &w : weighted) h.items.push_back(w.second);
-  DevTables dt;
-  struct DtGuard {
-    DevTables *d;
-    ~DtGuard() { d->release(); }
-  } dtg{&dt};
-  HIP_TRY(dt.upload(h, idev, cs));
-  const StepTables t = dt.view();
-  int dev_count = 0, cus = 256;
-  if (hipGetDevice(&dev_count) == hipSuccess) {
+  HIP_TRY(hipMemcpyAsync(d_inst, idev.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice, cs));
+  int dev_id = 0, cus = 256;
+  if (hipGetDevice(&dev_id) == hipSuccess) {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev_count) == hipSuccess) cus = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, dev_id) == hipSuccess) cus = prop.multiProcessorCount;
   }
-  const int grid = std::max(1, std::min<int>((int)h.items.size(), cus * std::max(1, 32 / cfg.waves)));
+  // per class: tables, items sorted largest first (LPT) for the persistent grid
+  for (auto &c : cls) {
+    std::vector<std::pair<long, Item>> weighted;
+    for (int i : c.members) {
+      const Geo &geo = bi[i].geo;
+      const int sub_base = (int)c.h.subs.size();
+      add_instance_cfg(geo, bi[i].p, c.cfg.waves, c.cfg.seg, c.cfg.steps, i, c.h);
+      make_ex(geo, i, c.h.ex);
+      std::vector<Item> it;
+      make_items(geo, sub_base, tile_width(c.cfg), it);
+      for (const Item &x : it) weighted.push_back({(long)c.h.subs[x.sub].n * geo.nt, x});
+    }
+    std::stable_sort(weighted.begin(), weighted.end(),
+                     [](const std::pair<long, Item> &x, const std::pair<long, Item> &y) {
+                       return x.first > y.first;
+                     });
+    for (auto &w : weighted) c.h.items.push_back(w.second);
+    HIP_TRY(c.dt.upload(c.h, {}, cs));
+    c.grid = std::max(1, std::min<int>((int)c.h.items.size(),
+                                       cus * std::max(1, 32 / c.cfg.waves)));
+  }
+  auto view = [&](BatchClass &c) {
+    StepTables t = c.dt.view();
+    t.inst = d_inst;
+    return t;
+  };
 
   // non-finite guesses fall back to zero
   std::vector<int> restarted(n_inst, 0);
@@ -1249,12 +1292,30 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       }
   }
 
+  auto iteration = [&](int par) -> kfp_status {
+    HIP_TRY(launch_reset_res(d_inst, n_inst, cs));
+    for (auto &c : cls) {
+      const StepTables t = view(c);
+      if (c.cfg.steps == 0) {
+        for (int n = 0; n <= c.nt_max; ++n)
+          HIP_TRY(launch_step(t, c.cfg.waves, c.cfg.seg, n, par, c.grid, cs));
+      } else {
+        const int L = march_launches(c.nt_max, c.cfg);
+        for (int l = 0; l < L; ++l)
+          HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.seg, l * c.cfg.steps, c.cfg.steps,
+                               halo_of(c.cfg), l & 1, par, c.grid, cs));
+        HIP_TRY(launch_exchange(t, par, c.nt_max, cs));
+      }
+    }
+    return KFP_OK;
+  };
+
   const bool graphs = use_graphs();
   if (graphs) {
     for (int par = 0; par < 2; ++par) {
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      kfp_status st = launch_iteration_direct(t, n_inst, dt.inst.p, cfg, nt_max, par, grid, cs);
+      kfp_status st = iteration(par);
       hipError_t e = hipStreamEndCapture(cs, &graph);
       if (st) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -1292,7 +1353,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     if (graphs) {
       HIP_TRY(hipGraphLaunch(guard.ge[par], cs));
     } else {
-      kfp_status st = launch_iteration_direct(t, n_inst, dt.inst.p, cfg, nt_max, par, grid, cs);
+      kfp_status st = iteration(par);
       if (st) return st;
     }
     HIP_TRY(hipEventRecord(e1, cs));
@@ -1317,15 +1378,15 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       }
     }
     if (changed) {
-      HIP_TRY(hipMemcpyAsync(dt.inst.p, idev.data(), sizeof(InstDev) * n_inst,
-                             hipMemcpyHostToDevice, cs));
+      HIP_TRY(hipMemcpyAsync(d_inst, idev.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice,
+                             cs));
       HIP_TRY(hipStreamSynchronize(cs));
     }
   }
   for (int i = 0; i < n_inst; ++i) {
     const BatchInst &b = bi[i];
     const Geo &geo = b.geo;
-    double *Ufin = (march_launches(geo.nt, cfg) & 1) ? b.U1 : b.U0;
+    double *Ufin = (march_launches(geo.nt, cls[b.cls].cfg) & 1) ? b.U1 : b.U0;
     HIP_TRY(launch_assemble(Ufin, b.rowmap, in[i].uT, geo.nv, geo.nx, cs));
     if (in[i].lambda_out && b.win)
       HIP_TRY(launch_copy((iters[i] & 1) ? b.lam1 : b.lam0, in[i].lambda_out, b.win, cs));

@@ -7,6 +7,19 @@ backward and Adam kernels.  At solve time its prediction is the initial guess
 lambda^0; the SWR iteration still runs to the same tolerance, so it is both
 the fallback and the judge of the network's error.
 
+The map from coefficients to converged traces is linear (the equation and
+the discretisation are linear, and the fields are linear in the
+coefficients), so by default the output layer also reads the input: the GELU
+trunk plus a linear map of the coefficients, whose accuracy is then bounded
+by the BF16 rounding of weights and inputs rather than by how well GELU units
+imitate a linear function away from the training data.
+
+By default the network learns the correction to the u0-extension guess
+(Q(u0) at every time level): lambda^0 = Q(u0) + net(coefficients).  The
+correction is a small fraction of the traces, so the same relative error of a
+BF16 network leaves a much smaller absolute error in lambda^0.  base="zero"
+learns the traces themselves.
+
     python -m paper_1306_4596_amd.learned --train 20000 --eval 2000 --out results.json
 """
 from __future__ import annotations
@@ -47,6 +60,21 @@ def coef_matrix(seeds):
     return np.stack([inputs.coefficients(int(s)) for s in seeds]).astype(np.float64)
 
 
+N_FEAT = 2 * inputs.N_COEF
+
+
+def features(C):
+    """Network input of coefficient rows: each coefficient as a BF16 value
+    plus its remainder scaled by 2^8, so that a BF16 operand path still sees
+    the coefficient to about 16 significant bits ([N][128] FP32)."""
+    import torch
+
+    c = torch.as_tensor(np.asarray(C, dtype=np.float64)).reshape(-1, inputs.N_COEF).float()
+    hi = c.to(torch.bfloat16).float()
+    lo = (c - hi) * 256.0
+    return torch.cat([hi, lo], dim=1).contiguous()
+
+
 class FieldMaker:
     """Fields of many seeds at once: (u0, f) = coefficients x mode basis."""
 
@@ -69,15 +97,25 @@ class FieldMaker:
         return np.ascontiguousarray(u0), np.ascontiguousarray(f)
 
 
-def generate(shape: Shape, seeds, batch=128, tol=1e-10, max_iter=500, log=None):
-    """Converged traces of every seed (FP32, [N][n_out]) and their coefficients
-    ([N][64] FP32), both on the GPU; plus the iteration counts."""
+def base_guess(shape: Shape, u0, base):
+    """The guess a network corrects: None (zero) or Q(u0) extended in time."""
+    if base == "zero":
+        return None
+    if base == "u0":
+        return kb.u0_guess(u0, shape.nt, shape.J, shape.overlap, shape.tr, shape.p)
+    raise ValueError(f"unknown base guess {base!r}")
+
+
+def generate(shape: Shape, seeds, batch=128, tol=1e-10, max_iter=500, log=None, base="u0"):
+    """Training targets of every seed: converged traces minus the base guess
+    (FP32, [N][n_out]) and the network inputs (features(), [N][128] FP32),
+    both on the GPU; plus the iteration counts."""
     import torch
 
     seeds = list(seeds)
     N = len(seeds)
     C = coef_matrix(seeds)
-    X = torch.from_numpy(C.astype(np.float32)).cuda()
+    X = features(C).cuda()
     Y = torch.empty((N, shape.n_out), dtype=torch.float32, device="cuda")
     iters = np.zeros(N, dtype=np.int32)
     fm = FieldMaker(shape)
@@ -93,7 +131,8 @@ def generate(shape: Shape, seeds, batch=128, tol=1e-10, max_iter=500, log=None):
         if rc != 0:
             raise RuntimeError("training solve did not converge")
         for i, (_, lam, st) in enumerate(res):
-            kb.cast_f64_f32(lam.reshape(-1), Y[b0 + i])
+            b = base_guess(shape, U0[i], base)
+            kb.cast_f64_f32(lam.reshape(-1), Y[b0 + i], base=None if b is None else b.reshape(-1))
             iters[b0 + i] = st.iters
         if log:
             log(f"generated {b1}/{N} traces ({time.time() - t0:.1f} s, "
@@ -103,26 +142,31 @@ def generate(shape: Shape, seeds, batch=128, tol=1e-10, max_iter=500, log=None):
 
 
 class LearnedGuess:
-    """Network + per-output standardisation of one problem shape."""
+    """Networks + per-output scales of one problem shape.
 
-    def __init__(self, shape: Shape, hidden=512, depth=3, seed=0, net=None):
+    Stage 1 is the network (depth x hidden, GELU, optionally with the input
+    skip); each further stage is a linear network (depth 0) fitted to what
+    the stages before it leave over, in its own standardised units.  Two
+    BF16 stages reach far below the ~2^-9 relative rounding floor of one.
+    lambda^0 = base + sum over stages of (mean_k + std_k * net_k(x))."""
+
+    def __init__(self, shape: Shape, hidden=512, depth=3, seed=0, base="u0", skip=True,
+                 refine=0, nets=None):
         self.shape = shape
-        self.net = net if net is not None else kb.MLP(inputs.N_COEF, hidden, depth, shape.n_out,
-                                                      seed=seed)
-        self.mean = None
-        self.std = None
+        self.base = base
+        if nets is None:
+            nets = [kb.MLP(N_FEAT, hidden, depth, shape.n_out, seed=seed, skip=skip)]
+            nets += [kb.MLP(N_FEAT, 8, 0, shape.n_out, seed=seed + 1 + k) for k in range(refine)]
+        self.nets = nets
+        self.means = []
+        self.stds = []
 
-    def fit(self, X, Y, epochs=30, batch=256, lr=1e-3, lr_min=1e-5, log=None, seed=0):
-        """Standardises Y in place (per output) and trains with Adam on a
-        cosine learning-rate schedule.  Returns the epoch losses."""
+    def _train(self, net, X, Y, epochs, batch, lr, lr_min, rng, log, tag):
         import torch
 
-        self.mean, self.std = kb.column_stats(Y, floor=1e-6)
-        kb.standardize(Y, self.mean, self.std)
         N = X.shape[0]
         nb = max(1, N // batch)
         steps = epochs * nb
-        rng = np.random.default_rng(seed)
         hist = []
         k = 0
         for ep in range(epochs):
@@ -133,28 +177,68 @@ class LearnedGuess:
                 xb = X.index_select(0, idx).contiguous()
                 yb = Y.index_select(0, idx).contiguous()
                 cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * k / max(1, steps - 1)))
-                tot += self.net.train_step(xb, yb, cur)
+                tot += net.train_step(xb, yb, cur)
                 k += 1
             hist.append(tot / nb)
             if log:
-                log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.4e}")
+                log(f"{tag} epoch {ep + 1}/{epochs}: loss {hist[-1]:.4e}")
         return hist
 
-    def predict(self, coef):
-        """Initial traces lambda^0 (FP64 [B][2(J-1)][nt][nx]) for coefficient rows."""
+    def fit(self, X, Y, epochs=30, batch=256, lr=1e-3, lr_min=1e-5, log=None, seed=0,
+            refine_epochs=None, refine_lr=None):
+        """Trains every stage; Y (targets, FP32 [N][n_out]) is overwritten
+        (standardised, then replaced by each stage's remainder).  Returns the
+        epoch losses of all stages, in order."""
+        rng = np.random.default_rng(seed)
+        self.means, self.stds = [], []
+        hist = []
+        scale = None
+        for k, net in enumerate(self.nets):
+            mean, std = kb.column_stats(Y, floor=1e-6 if k == 0 else 1e-9)
+            kb.standardize(Y, mean, std)
+            if scale is not None:  # back to the units of lambda
+                kb.mul_f32(scale, mean)
+                kb.mul_f32(scale, std)
+            self.means.append(mean)
+            self.stds.append(std)
+            ep = epochs if k == 0 else (refine_epochs or epochs)
+            rate = lr if k == 0 else (refine_lr or lr)
+            hist += self._train(net, X, Y, ep, batch, rate, lr_min, rng, log, f"stage {k + 1}")
+            if k + 1 < len(self.nets):
+                for b0 in range(0, X.shape[0], batch):
+                    P = net.forward(X[b0:b0 + batch].contiguous())
+                    kb.axpy_f32(P, Y[b0:b0 + batch], -1.0)
+            scale = std
+        return hist
+
+    def predict(self, coef, u0=None):
+        """Initial traces lambda^0 (FP64 [B][2(J-1)][nt][nx]) for coefficient
+        rows; u0 ([B][nv+1][nx] or [nv+1][nx], FP64 on the GPU) is needed when
+        the networks correct the u0-extension guess."""
         import torch
 
-        X = torch.as_tensor(np.asarray(coef, dtype=np.float32)).reshape(-1, inputs.N_COEF).cuda()
-        Yp = self.net.forward(X)
-        lam = kb.destandardize(Yp, self.mean, self.std)
+        X = features(coef).cuda()
         s = self.shape
+        lam = None
+        if self.base != "zero":
+            if u0 is None:
+                raise ValueError("this guess corrects the u0 guess: pass u0")
+            u0 = u0.reshape(-1, s.nv + 1, s.nx)
+            if u0.shape[0] != X.shape[0]:
+                raise ValueError("one u0 per coefficient row")
+            lam = torch.stack([base_guess(s, u0[i], self.base) for i in range(u0.shape[0])])
+            lam = lam.reshape(X.shape[0], -1)
+        for net, mean, std in zip(self.nets, self.means, self.stds):
+            lam = kb.destandardize(net.forward(X), mean, std, base=lam)
         return lam.reshape(-1, 2 * (s.J - 1), s.nt, s.nx)
 
     def save(self, prefix):
         import torch
 
-        self.net.save(prefix + ".net")
-        torch.save({"mean": self.mean.cpu(), "std": self.std.cpu(), "shape": asdict(self.shape)},
+        for k, net in enumerate(self.nets):
+            net.save(f"{prefix}.net{k}")
+        torch.save({"means": [m.cpu() for m in self.means], "stds": [d.cpu() for d in self.stds],
+                    "shape": asdict(self.shape), "base": self.base, "stages": len(self.nets)},
                    prefix + ".std.pt")
 
     @classmethod
@@ -162,47 +246,58 @@ class LearnedGuess:
         import torch
 
         d = torch.load(prefix + ".std.pt", weights_only=True)
-        g = cls(Shape(**d["shape"]), net=kb.MLP.load(prefix + ".net"))
-        g.mean = d["mean"].cuda()
-        g.std = d["std"].cuda()
+        nets = [kb.MLP.load(f"{prefix}.net{k}") for k in range(d["stages"])]
+        g = cls(Shape(**d["shape"]), base=d["base"], nets=nets)
+        g.means = [m.cuda() for m in d["means"]]
+        g.stds = [x.cuda() for x in d["stds"]]
         return g
 
 
-def evaluate(shape: Shape, seeds, guess: LearnedGuess | None, tol=1e-10, max_iter=500, log=None):
+def evaluate(shape: Shape, seeds, guess=None, tol=1e-10, max_iter=500, log=None):
     """Iterations and wall time to tolerance for zero, u0-extension and
-    learned initial traces on each seed (single solves, synchronised)."""
+    learned initial traces on each seed (single solves, synchronised; the
+    time of a learned run includes its inference), and the error of each
+    initial guess against the converged traces (max-norm, relative to the
+    traces' max-norm).  guess: one LearnedGuess (reported as "learned") or a
+    dict name -> LearnedGuess."""
     import torch
 
+    guesses = {} if guess is None else (guess if isinstance(guess, dict) else {"learned": guess})
     fm = FieldMaker(shape)
-    out = {"zero": [], "u0": [], "learned": []}
+    out = {"zero": [], "u0": []}
+    out.update({k: [] for k in guesses})
     C = coef_matrix(seeds)
     for i, s in enumerate(seeds):
         u0s, fs = fm.make(C[i:i + 1])
         U0 = torch.from_numpy(u0s[0]).cuda()
         F = torch.from_numpy(fs[0]).cuda()
-        runs = [("zero", None), ("u0", "u0")]
-        if guess is not None:
-            runs.append(("learned", "learned"))
+        runs = [("zero", None), ("u0", "u0")] + [(k, g) for k, g in guesses.items()]
         ref = None
+        lam_star = None
         for name, kind in runs:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             lam0 = None
             if kind == "u0":
                 lam0 = kb.u0_guess(U0, shape.nt, shape.J, shape.overlap, shape.tr, shape.p)
-            elif kind == "learned":
-                lam0 = guess.predict(C[i])[0].contiguous()
-            uT, _, st = kb.swr_solve(U0, F, shape.T, shape.nt, shape.J, shape.overlap, shape.tr,
-                                     p=shape.p, tol=tol, max_iter=max_iter, lambda_init=lam0,
-                                     history=False)
+            elif kind is not None:
+                lam0 = kind.predict(C[i], U0)[0].contiguous()
+            uT, lam, st = kb.swr_solve(U0, F, shape.T, shape.nt, shape.J, shape.overlap,
+                                       shape.tr, p=shape.p, tol=tol, max_iter=max_iter,
+                                       lambda_init=lam0, history=False,
+                                       want_lambda=lam_star is None)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+            if lam_star is None:
+                lam_star = lam
+            scale = float(lam_star.abs().max())
+            gerr = float((lam_star if lam0 is None else (lam0 - lam_star)).abs().max()) / scale
             if ref is None:
                 ref = uT
                 err = 0.0
             else:
                 err = float((uT - ref).norm() / ref.norm())
-            out[name].append({"seed": int(s), "iters": st.iters, "seconds": dt,
+            out[name].append({"seed": int(s), "iters": st.iters, "seconds": dt, "guess_err": gerr,
                               "residual": st.residual, "rel_l2_vs_zero_guess": err,
                               "restarted": st.restarted})
         if log and (i + 1) % max(1, len(seeds) // 10) == 0:
@@ -221,8 +316,18 @@ def summarize(ev):
                   "iters_p90": float(np.percentile(it, 90)), "seconds_mean": float(sec.mean()),
                   "seconds_median": float(np.median(sec)),
                   "seconds_p90": float(np.percentile(sec, 90)),
+                  "guess_err_median": float(np.median([r["guess_err"] for r in v])),
                   "max_rel_l2_vs_zero_guess": float(max(r["rel_l2_vs_zero_guess"] for r in v))}
     return res
+
+
+VARIANTS = {
+    # name: (depth, hidden, skip, refine)
+    "mlp": (3, 512, False, 0),        # 3 x 512 GELU
+    "mlp_skip": (3, 512, True, 0),    # 3 x 512 GELU + linear input skip
+    "linear": (0, 8, False, 0),       # one BF16 linear layer
+    "linear_x3": (0, 8, False, 2),    # linear + two refinement stages
+}
 
 
 def main():
@@ -232,30 +337,48 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--hidden", type=int, default=512)
+    ap.add_argument("--refine-lr", type=float, default=3e-3)
     ap.add_argument("--out", default="learned_results.json")
-    ap.add_argument("--save", default=None)
+    ap.add_argument("--save", default=None, help="checkpoint prefix (one per variant)")
+    ap.add_argument("--base", default="u0", choices=["u0", "zero"])
+    ap.add_argument("--variants", default="mlp,linear_x3",
+                    help="comma-separated from " + ",".join(VARIANTS))
     args = ap.parse_args()
 
     def log(msg):
         print(msg, flush=True)
 
+    import torch
+
     shape = SHAPE_256
     t0 = time.time()
-    X, Y, iters = generate(shape, range(args.train), log=log)
+    X, Y0, iters = generate(shape, range(args.train), log=log, base=args.base)
     t_gen = time.time() - t0
-    guess = LearnedGuess(shape, hidden=args.hidden)
-    t0 = time.time()
-    hist = guess.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
-    t_train = time.time() - t0
-    del X, Y
-    if args.save:
-        guess.save(args.save)
-    ev = evaluate(shape, range(20000, 20000 + args.eval), guess, log=log)
-    res = {"shape": asdict(shape), "train_seeds": args.train, "eval_seeds": args.eval,
-           "epochs": args.epochs, "generate_seconds": t_gen, "train_seconds": t_train,
-           "train_iters_mean": float(iters.mean()), "loss_history": hist,
-           "summary": summarize(ev)}
+    guesses, train = {}, {}
+    names = [v for v in args.variants.split(",") if v]
+    for k, name in enumerate(names):
+        depth, hidden, skip, refine = VARIANTS[name]
+        Y = Y0 if k == len(names) - 1 else Y0.clone()
+        g = LearnedGuess(shape, hidden=hidden, depth=depth, base=args.base, skip=skip,
+                         refine=refine)
+        t0 = time.time()
+        hist = g.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
+                     refine_lr=args.refine_lr)
+        torch.cuda.synchronize()
+        train[name] = {"seconds": time.time() - t0, "loss_history": hist,
+                       "depth": depth, "hidden": hidden, "skip": skip, "refine": refine}
+        del Y
+        if args.save:
+            g.save(f"{args.save}.{name}")
+        guesses[name] = g
+        log(f"trained {name} in {train[name]['seconds']:.1f} s")
+    del X, Y0
+    torch.cuda.empty_cache()
+    ev = evaluate(shape, range(20000, 20000 + args.eval), guesses, log=log)
+    res = {"shape": asdict(shape), "base": args.base, "train_seeds": args.train,
+           "eval_seeds": args.eval, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+           "generate_seconds": t_gen, "train_iters_mean": float(iters.mean()),
+           "train": train, "summary": summarize(ev)}
     with open(args.out, "w") as fp:
         json.dump(res, fp, indent=1)
     log(json.dumps(res["summary"]))

@@ -1,7 +1,8 @@
 """The learned initial traces, end to end on a reduced shape: solves of the
-method generate the training set, the library's kernels train the network,
-and on held-out seeds the learned guess reaches the same tolerance and the
-same solution in fewer SWR iterations than the zero guess."""
+method generate the training set, the library's kernels train the networks,
+and on held-out seeds the learned guesses reach the same tolerance and the
+same solution in fewer SWR iterations than the zero and u0-extension
+guesses."""
 import numpy as np
 import pytest
 
@@ -13,22 +14,37 @@ from paper_1306_4596_amd import learned  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_guess_saves_iterations():
+def test_learned_guess_saves_iterations(tmp_path):
     shape = learned.Shape(64, 64, 64, 0.25, 4, 2, kfp.ROBIN, 4.0)
     print("generating", flush=True)
     X, Y, iters = learned.generate(shape, range(512), batch=128, tol=1e-10)
     assert np.all(iters > 0)
-    guess = learned.LearnedGuess(shape, hidden=256, depth=3, seed=1)
-    print("training", flush=True)
-    hist = guess.fit(X, Y, epochs=300, batch=32, lr=2e-3, lr_min=1e-6)
-    print("loss", hist[0], hist[-1], flush=True)
-    assert hist[-1] < 0.01 * hist[0]
-    ev = learned.evaluate(shape, range(10000, 10012), guess, tol=1e-10)
-    z = np.array([r["iters"] for r in ev["zero"]])
-    l_ = np.array([r["iters"] for r in ev["learned"]])
-    print("zero", z, "learned", l_, "u0", [r["iters"] for r in ev["u0"]], flush=True)
-    assert all(r["residual"] < 1e-10 for r in ev["learned"])
-    # both runs stop at an absolute residual of 1e-10: the same discrete solution
-    assert max(r["rel_l2_vs_zero_guess"] for r in ev["learned"]) < 1e-8
-    assert l_.mean() < z.mean() - 2
-    assert not any(r["restarted"] for r in ev["learned"])
+    # one BF16 linear stage and two refinement stages
+    lin = learned.LearnedGuess(shape, depth=0, refine=2, seed=1)
+    print("training linear stages", flush=True)
+    h1 = lin.fit(X, Y.clone(), epochs=200, batch=32, lr=3e-3, lr_min=1e-6)
+    assert h1[199] < 1e-3 * h1[0]
+    # the 3-layer GELU network with the input skip
+    mlp = learned.LearnedGuess(shape, hidden=256, depth=3, skip=True, seed=1)
+    print("training GELU network", flush=True)
+    h2 = mlp.fit(X, Y, epochs=100, batch=32, lr=2e-3, lr_min=1e-6)
+    assert h2[-1] < 0.01 * h2[0]
+    ev = learned.evaluate(shape, range(10000, 10012), {"lin": lin, "mlp": mlp}, tol=1e-10)
+    it = {k: np.array([r["iters"] for r in v]) for k, v in ev.items()}
+    print({k: v.tolist() for k, v in it.items()}, flush=True)
+    for k in ("lin", "mlp"):
+        assert all(r["residual"] < 1e-10 for r in ev[k])
+        # every run stops at an absolute residual of 1e-10: the same solution
+        assert max(r["rel_l2_vs_zero_guess"] for r in ev[k]) < 1e-8
+        assert not any(r["restarted"] for r in ev[k])
+    assert np.median([r["guess_err"] for r in ev["lin"]]) < 1e-4
+    assert it["lin"].mean() < 0.6 * it["zero"].mean()
+    assert it["lin"].mean() < it["u0"].mean() - 5
+    assert it["mlp"].mean() < it["zero"].mean()
+    # a saved guess predicts the same traces
+    lin.save(str(tmp_path / "g"))
+    back = learned.LearnedGuess.load(str(tmp_path / "g"))
+    u0s, _ = learned.FieldMaker(shape).make(learned.coef_matrix([10000]))
+    U0 = torch.from_numpy(u0s[0]).cuda()
+    c = learned.coef_matrix([10000])[0]
+    assert torch.equal(lin.predict(c, U0), back.predict(c, U0))

@@ -22,11 +22,15 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def build(sizes, seed):
+def build(sizes, seed, skip=False):
     rng = np.random.default_rng(seed)
     params = [(rng.standard_normal((o, i)) / math.sqrt(i), 0.1 * rng.standard_normal(o))
               for i, o in zip(sizes[:-1], sizes[1:])]
-    net = kfp.MLP(sizes[0], sizes[1], len(sizes) - 2, sizes[-1], seed=1)
+    if skip:  # the output layer also reads the input
+        W, b = params[-1]
+        params[-1] = (np.concatenate([W, rng.standard_normal((W.shape[0], sizes[0])) / 4.0],
+                                     axis=1), b)
+    net = kfp.MLP(sizes[0], sizes[1], len(sizes) - 2, sizes[-1], seed=1, skip=skip)
     for l, (W, b) in enumerate(params):
         net.set(l, "W", torch.from_numpy(W.astype(np.float32)))
         net.set(l, "b", torch.from_numpy(b.astype(np.float32)))
@@ -36,29 +40,32 @@ def build(sizes, seed):
     return net, params32
 
 
+@pytest.mark.parametrize("skip", [False, True])
 @pytest.mark.parametrize("sizes,B", [([16, 32, 32, 40], 16), ([64, 128, 128, 128, 8192], 24),
                                      ([8, 136, 200], 8)])
-def test_forward_matches_oracle(sizes, B):
-    print(f"mlp forward sizes={sizes} B={B}", flush=True)
-    net, params = build(sizes, 3)
+def test_forward_matches_oracle(sizes, B, skip):
+    print(f"mlp forward sizes={sizes} B={B} skip={skip}", flush=True)
+    net, params = build(sizes, 3, skip)
     rng = np.random.default_rng(4)
     x = rng.standard_normal((B, sizes[0])).astype(np.float32)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
-    ref, _ = omlp.MLP(params, bf16=True).forward(x.astype(np.float64))
+    ref, _ = omlp.MLP(params, bf16=True, skip=skip).forward(x.astype(np.float64))
     assert rel(y, ref) <= 1e-3
 
 
+@pytest.mark.parametrize("skip", [False, True])
 @pytest.mark.parametrize("sizes,B", [([16, 32, 32, 40], 16), ([64, 128, 128, 128, 8192], 24)])
-def test_gradients_match_oracle(sizes, B):
+def test_gradients_match_oracle(sizes, B, skip):
     """The second case has a reduction of length 8192 in the input gradient of
     the last layer, which takes the split-K path."""
-    print(f"mlp grads sizes={sizes} B={B}", flush=True)
-    net, params = build(sizes, 5)
+    print(f"mlp grads sizes={sizes} B={B} skip={skip}", flush=True)
+    net, params = build(sizes, 5, skip)
     rng = np.random.default_rng(6)
     x = rng.standard_normal((B, sizes[0])).astype(np.float32)
     t = rng.standard_normal((B, sizes[-1])).astype(np.float32)
     loss = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
-    rloss, grads = omlp.MLP(params, bf16=True).backward(x.astype(np.float64), t.astype(np.float64))
+    rloss, grads = omlp.MLP(params, bf16=True, skip=skip).backward(x.astype(np.float64),
+                                                                  t.astype(np.float64))
     assert abs(loss - rloss) <= 1e-4 * rloss
     for l, (gW, gb) in enumerate(grads):
         dW = net.get(l, "dW").cpu().numpy()
@@ -93,6 +100,7 @@ def test_training_fits_a_linear_map_and_checkpoint_round_trip(tmp_path):
     x = rng.standard_normal((512, 16)).astype(np.float32)
     y = (x @ G.T).astype(np.float32)
     net = kfp.MLP(16, 64, 3, 256, seed=2)
+    net_s = kfp.MLP(16, 64, 3, 256, seed=2, skip=True)
     X, Y = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
     first = None
     for epoch in range(60):
@@ -100,12 +108,19 @@ def test_training_fits_a_linear_map_and_checkpoint_round_trip(tmp_path):
             loss = net.train_step(X[b:b + 64], Y[b:b + 64], lr=3e-3)
             first = loss if first is None else first
     assert loss < 0.02 * first
-    path = tmp_path / "net.bin"
-    net.save(path)
-    net2 = kfp.MLP.load(path)
-    a = net.forward(X[:32])
-    b = net2.forward(X[:32])
-    assert torch.equal(a, b)
+    # with the input skip the linear map is inside the model class
+    first_s = None
+    for epoch in range(60):
+        for b in range(0, 512, 64):
+            loss_s = net_s.train_step(X[b:b + 64], Y[b:b + 64], lr=3e-3)
+            first_s = loss_s if first_s is None else first_s
+    assert loss_s < 0.02 * first_s and loss_s < loss
+    for n in (net, net_s):
+        path = tmp_path / "net.bin"
+        n.save(path)
+        n2 = kfp.MLP.load(path)
+        assert n2.layers() == n.layers() and n2.shape(n.depth) == n.shape(n.depth)
+        assert torch.equal(n.forward(X[:32]), n2.forward(X[:32]))
 
 
 def test_data_helpers():
@@ -119,7 +134,15 @@ def test_data_helpers():
     kfp.standardize(Z, mean, std)
     back = kfp.destandardize(Z, mean, std)
     assert np.allclose(back.cpu().numpy(), x, rtol=1e-5, atol=1e-5)
+    base = torch.from_numpy(rng.standard_normal((100, 24))).cuda()
+    back = kfp.destandardize(Z, mean, std, base=base)
+    ref = base.cpu().numpy() + (mean.cpu().numpy().astype(np.float64)
+                                + std.cpu().numpy().astype(np.float64) * Z.cpu().numpy())
+    assert np.allclose(back.cpu().numpy(), ref, rtol=1e-12, atol=1e-12)
     d = torch.from_numpy(rng.standard_normal(1000)).cuda()
     f = torch.empty(1000, dtype=torch.float32, device="cuda")
     kfp.cast_f64_f32(d, f)
     assert np.array_equal(f.cpu().numpy(), d.cpu().numpy().astype(np.float32))
+    b = torch.from_numpy(rng.standard_normal(1000)).cuda()
+    kfp.cast_f64_f32(d, f, base=b)
+    assert np.array_equal(f.cpu().numpy(), (d - b).cpu().numpy().astype(np.float32))

@@ -163,6 +163,20 @@ def test_resume_from_returned_traces():
     assert torch.equal(a, b2) and torch.equal(la, lb2)
 
 
+def test_cached_plan_takes_each_calls_time_step():
+    """Solves of one shape with different T share the cached buffers; each
+    must still use its own dt (also after u0_guess, which takes any valid T)."""
+    nx, nv, nt, J, o = 64, 64, 40, 4, 2
+    u0, f = inputs.random_fields(13, nx, nv)
+    kfp.u0_guess(dev(u0), nt, J, o, R, p=4.0)
+    for T in (0.2, 0.05, 0.2):
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, R, p=4.0, tol=1e-300, max_iter=3)
+        uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, R, p=4.0, tol=1e-300,
+                                    max_iter=3, want_lambda=True)
+        assert rel(host(uT), ref.uT) <= 1e-12, T
+        assert rel(host(lam), ref.lam) <= 1e-12, T
+
+
 def test_max_iter_returns_last_iterate():
     nx, nv, nt, T = 64, 64, 30, 0.2
     u0, f = inputs.random_fields(6, nx, nv)
@@ -196,6 +210,30 @@ def test_every_launch_configuration_agrees(waves, seg, steps, tr):
     # a forced register segment too short for the subdomain is widened to the
     # next compiled size (or the memory-staged variant)
     assert got[0] == waves and got[2] == steps and (got[1] == 0 or got[1] >= seg)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3,
+                                want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+# J = 4 on 64 v-cells: about 19 rows per subdomain, interior subdomains with
+# transmission rows at both ends; single- and two-wave register segments
+CONFIGS_J4 = [(1, 0, 0), (2, 0, 0), (4, 8, 0), (1, 24, 1), (1, 24, 8), (1, 32, 3), (2, 12, 4),
+              (2, 16, 8), (4, 6, 2), (4, 8, 8), (8, 4, 1), (8, 4, 8)]
+
+
+@pytest.mark.parametrize("waves,seg,steps", CONFIGS_J4)
+@pytest.mark.parametrize("tr", [D, R])
+def test_launch_configurations_interior_subdomains(waves, seg, steps, tr):
+    nx, nv, nt, T, J, o = 80, 64, 20, 0.2, 4, 2
+    print(f"config J=4 waves={waves} seg={seg} steps={steps} tr={tr}", flush=True)
+    u0, f = inputs.random_fields(14, nx, nv)
+    p = 4.0 if tr == R else 0.0
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3)
+    kfp.set_config(waves, seg, steps)
+    got = kfp.get_config(nx, nv, nt, T, J, o, tr)
+    assert got[0] == waves and got[2] == steps
     uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3,
                                 want_lambda=True)
     assert rel(host(uT), ref.uT) <= 1e-12

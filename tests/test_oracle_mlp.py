@@ -36,10 +36,19 @@ def make_params(rng, sizes):
             for i, o in zip(sizes[:-1], sizes[1:])]
 
 
-def test_backward_matches_central_differences():
+def skip_params(rng, sizes):
+    """Parameters of a skip network: the last layer reads hidden + input."""
+    p = make_params(rng, sizes)
+    W, b = p[-1]
+    p[-1] = (np.concatenate([W, rng.standard_normal((W.shape[0], sizes[0])) / 3.0], axis=1), b)
+    return p
+
+
+@pytest.mark.parametrize("skip", [False, True])
+def test_backward_matches_central_differences(skip):
     rng = np.random.default_rng(0)
     sizes = [5, 7, 6, 4]
-    net = mlp.MLP(make_params(rng, sizes))
+    net = mlp.MLP(skip_params(rng, sizes) if skip else make_params(rng, sizes), skip=skip)
     x = rng.standard_normal((3, 5))
     t = rng.standard_normal((3, 4))
     loss, grads = net.backward(x, t)
@@ -92,3 +101,20 @@ def test_bf16_mode_rounds_operands():
     W, b = params[0]
     ref = mlp.bf16_round(x) @ mlp.bf16_round(W).T + b
     assert np.array_equal(y16, ref)
+
+
+def test_skip_network_with_silent_trunk_is_the_linear_map():
+    """Zero weights on the hidden part of the last layer leave y = x S^T + b,
+    with S the input block of that layer: the order of the concatenation."""
+    rng = np.random.default_rng(3)
+    sizes = [6, 8, 8, 5]
+    p = skip_params(rng, sizes)
+    W, b = p[-1]
+    W[:, :8] = 0.0
+    net = mlp.MLP(p, skip=True)
+    x = rng.standard_normal((4, 6))
+    y, _ = net.forward(x)
+    assert np.allclose(y, x @ W[:, 8:].T + b, rtol=0, atol=1e-14)
+    # and its gradient reaches only the last layer
+    _, g = net.backward(x, np.zeros((4, 5)))
+    assert all(np.all(gW == 0) and np.all(gb == 0) for gW, gb in g[:-1])
