@@ -72,6 +72,8 @@ typedef struct {
   double residual;      /* r^k of the last iteration (eq. (6.12))            */
   double seconds;       /* wall time of the call                             */
   double device_seconds;/* device time of the iteration graphs (HIP events)  */
+  double step_seconds;  /* the part of it in the time-step kernels (batch:   */
+                        /* the whole iteration)                              */
   double cell_steps;    /* subdomain cell-steps executed (all iterations)    */
   double alg_bytes;     /* algorithmic HBM bytes of those cell-steps         */
   double *res_history;  /* [host] optional, length max_iter: r^1..r^iters   */

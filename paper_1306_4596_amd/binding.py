@@ -28,7 +28,8 @@ class Grid(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarted", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("device_seconds", ctypes.c_double), ("cell_steps", ctypes.c_double),
+                ("device_seconds", ctypes.c_double), ("step_seconds", ctypes.c_double),
+                ("cell_steps", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("res_history", ctypes.POINTER(ctypes.c_double))]
 
 
@@ -49,6 +50,7 @@ class SWRStats:
         self.residual = st.residual
         self.seconds = st.seconds
         self.device_seconds = st.device_seconds
+        self.step_seconds = st.step_seconds
         self.cell_steps = st.cell_steps
         self.alg_bytes = st.alg_bytes
         self.res_history = history

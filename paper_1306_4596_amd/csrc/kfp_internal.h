@@ -55,6 +55,7 @@ struct SubDev {
   int res_plane_a, res_plane_b;  // planes holding the fixed-node values (Dirichlet)
   int pad;            // multi-step layout: leading identity rows of the last segment
   int vsplit;         // first local row with v >= 0 (upwind neighbour at m-1)
+  int rinv;           // multi-step layout: first entry of the reduced-system inverse
 };
 
 // Per unknown row: transport weight and the factors of the local (segment)
@@ -114,6 +115,7 @@ struct StepTables {
   const int *segs;
   const ExItem *ex;
   const MarchCoef *mrows;
+  const double *rinv;  // per multi-step subdomain: (P-1) x (P-1) inverse, row-major
   int n_items;
   int n_ex;
 };

@@ -236,7 +236,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
     KGlob<double> *dst = as_glob(Unext + (size_t)sd.row_off * nx);
     KGlob<const double> *fr = as_glob(I.f + (size_t)sd.g_lo * nx);
     KGlob<const double> *lin = as_glob(lam_in);
-    const double gn = as_glob(I.g)[n];
+    const double gn = as_const(I.g)[n];  // scalar load: no vector-memory wait
     KConst<RowCoef> *rows = as_const(t.rows) + sd.tab;
     KConst<int> *segs = as_const(t.segs);
     const int P = sd.P;
@@ -378,19 +378,15 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
 // ---------------------------------------------------------------------------
 // Upwind neighbour of every lane: lane i receives lane i-1 (v > 0, the cell
 // at m-1) or lane i+1 (v < 0, the cell at m+1) through a wave-wide DPP shift;
-// the edge lane keeps its own value (it is halo and becomes invalid anyway).
+// the edge lane, which has no neighbour in the wave, reads 0 (it is halo).
 __device__ __forceinline__ double from_lower_lane(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), 0x138, 0xf,
-                                             0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), 0x138, 0xf,
-                                             0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_upper_lane(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), 0x130, 0xf,
-                                             0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), 0x130, 0xf,
-                                             0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -444,22 +440,24 @@ enum Dir : int { DIR_UP = 0, DIR_LO = 1, DIR_MIX = 2 };
 // the (cache-resident) source rows every step.
 constexpr int kFRegMax = 24;
 
+// Upper bound of the steps one multi-step launch takes (checked by the host).
+constexpr int kMaxStepsPerLaunch = 24;
+
+// Transport, source and forward elimination of one step.  The elimination
+// starts from y = blo, the boundary data of row 0 of the subdomain (zero in
+// every other wave): the first real row of each segment has multiplier 1,
+// and the padding rows in front of it pass y on unchanged, so the data
+// lands on that row without a per-row test.  mc: the wave's coefficient
+// rows in LDS (wave-uniform addresses: broadcast reads).
 template <int SEG, int NW, int DIR>
 __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG> &fs,
-                                              KConst<MarchCoef> *mc, double gn, int k0,
-                                              double blo, double bhi, int vsplit,
+                                              const MarchCoef *mc, double gn, double blo,
+                                              double bhi, int vsplit,
                                               KGlob<const double> *fr, int base, int nx,
                                               int col) {
-  double y = 0.0;
-  double na = mc[0].alpha, nbt = mc[0].beta, nf = mc[0].fb;
+  double y = blo;
   static_for<0, SEG>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    const double al = na, be = nbt, fbk = nf;
-    if constexpr (k + 1 < SEG) {
-      na = mc[k + 1].alpha;
-      nbt = mc[k + 1].beta;
-      nf = mc[k + 1].fb;
-    }
     const double u = d.template ld<k>();
     double nb;
     if constexpr (DIR == DIR_LO) {
@@ -476,12 +474,10 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
     } else {
       fk = mc[k].fa * fr[(size_t)max(base + k, 0) * nx + col];
     }
-    double tk = fma(al, u, fma(be, nb, gn * fk));
-    if (k == k0) tk += blo;
+    double tk = fma(mc[k].alpha, u, fma(mc[k].beta, nb, gn * fk));
     if constexpr (k == SEG - 1) tk += bhi;
-    y = fma(fbk, y, tk);
+    y = fma(mc[k].fb, y, tk);
     d.template st<k>(y);
-    __builtin_amdgcn_sched_barrier(0);
   });
 }
 
@@ -491,6 +487,18 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
   __shared__ double sh_first[NW][64];
   __shared__ double sh_last[NW][64];
   __shared__ double sh_sep[NW][64];
+  // boundary data of the launch's steps (low end, high end), staged once so
+  // that the step loop issues no vector loads: its stores then never hold a
+  // step up, since nothing in the loop waits on vector memory
+  __shared__ double sh_bd[2][kMaxStepsPerLaunch][64];
+  // the work item's coefficient rows (per wave), reduced system and source
+  // factors, staged once per item: the step loop then issues no scalar
+  // loads either, and LDS reads (returned in order) can be waited on one by
+  // one, so they are issued well ahead of their use
+  __shared__ MarchCoef sh_mc[NW][SEG];
+  __shared__ RedCoef sh_rc[NW];
+  __shared__ double sh_rinv[(NW - 1) * (NW - 1) + 1];
+  __shared__ double sh_g[NW][kMaxStepsPerLaunch];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   KConst<Item> *items = as_const(t.items);
@@ -505,7 +513,7 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
     const int nx = I->nx;
     const int nt = I->nt;
     if (n0 >= nt) continue;
-    const int steps = min(S, nt - n0);
+    const int steps = min(min(S, kMaxStepsPerLaunch), nt - n0);  // S is checked by the host
     const int rel = lane - H;
     int col = (x0 + rel) % nx;
     if (col < 0) col += nx;
@@ -519,7 +527,6 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
     KGlob<double> *dst = as_glob(I->U[src_par ^ 1] + (size_t)row_off * nx);
     KGlob<const double> *fr = as_glob(I->f + (size_t)g_lo * nx);
     KGlob<const double> *lin = as_glob((const double *)I->lam[par]);
-    KGlob<const double> *gtab = as_glob(I->g);
     KGlob<double> *Vbase = as_glob(I->V);
     const double rr = I->r;
     const bool robin = I->tr == 1;
@@ -531,112 +538,113 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
     // rows with local index >= vsplit have v >= 0: upwind neighbour at m-1
     const int vsplit = sd->vsplit - base;
     const int dir = vsplit <= 0 ? DIR_LO : (vsplit >= SEG ? DIR_UP : DIR_MIX);
-    // coefficient tables are read through the constant address space, so
-    // every (wave-uniform) access is a scalar load
-    KConst<MarchCoef> *mc0 = as_const(t.mrows) + sd->tab + w * SEG;
-    KConst<RedCoef> *rc0 = as_const(t.reds) + sd->red;
     const int lo_kind = sd->lo_kind, hi_kind = sd->hi_kind;
     const int lam_lo = sd->lam_lo, lam_hi = sd->lam_hi;
     const int out_hi_plane = sd->out_hi_plane, out_hi_row = sd->out_hi_row;
     const int out_lo_plane = sd->out_lo_plane, out_lo_row = sd->out_lo_row;
+    // end rows taking boundary data: row 0 in wave 0, row n-1 in the last wave
+    const bool lo_end = active && w == 0 && lo_kind != END_PHYS;
+    const bool hi_end = active && last && hi_kind != END_PHYS;
+    KGlob<const double> *lin_lo = lin + (size_t)(lam_lo > 0 ? lam_lo : 0) * plane + col;
+    KGlob<const double> *lin_hi = lin + (size_t)(lam_hi > 0 ? lam_hi : 0) * plane + col;
+    // staging: each wave copies its own rows, factors and boundary data
+    // (written and read by the same wave: no barrier); the reduced system is
+    // copied by wave 0 and first read after the step's first barrier (the
+    // previous item's last reads ended at its last step's second barrier)
+    const MarchCoef *mc = sh_mc[w];
+    if (active) {
+      KGlob<const double> *ct = as_glob((const double *)(t.mrows + sd->tab + w * SEG));
+      double *cs = reinterpret_cast<double *>(sh_mc[w]);
+      constexpr int NCW = SEG * (int)(sizeof(MarchCoef) / sizeof(double));
+#pragma unroll
+      for (int e0 = 0; e0 < NCW; e0 += 64)
+        if (e0 + lane < NCW) cs[e0 + lane] = ct[e0 + lane];
+      KGlob<const double> *gt = as_glob(I->g);
+      if (lane < steps) sh_g[w][lane] = gt[n0 + lane];
+      if (w == 0 && P > 1) {
+        constexpr int NRW = (int)(sizeof(RedCoef) / sizeof(double));
+        KGlob<const double> *rt = as_glob((const double *)(t.reds + sd->red));
+        double *rs = reinterpret_cast<double *>(sh_rc);
+        for (int e = lane; e < (P - 1) * NRW; e += 64) rs[e] = rt[e];
+        KGlob<const double> *rv = as_glob(t.rinv + sd->rinv);
+        for (int e = lane; e < (P - 1) * (P - 1); e += 64) sh_rinv[e] = rv[e];
+      }
+      if (lo_end)
+        for (int s = 0; s < steps; ++s) sh_bd[0][s][lane] = lin_lo[(size_t)(n0 + s) * nx];
+      if (hi_end)
+        for (int s = 0; s < steps; ++s) sh_bd[1][s][lane] = lin_hi[(size_t)(n0 + s) * nx];
+    }
     SegRegs<SEG> d, fs;
     if (active) {
       static_for<0, SEG>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         const int r = max(base + k, 0);
         d.template st<k>(src[(size_t)r * nx + col]);
-        if constexpr (SEG <= kFRegMax) fs.template st<k>(mc0[k].fa * fr[(size_t)r * nx + col]);
+        if constexpr (SEG <= kFRegMax) fs.template st<k>(mc[k].fa * fr[(size_t)r * nx + col]);
       });
     }
-    // end rows taking boundary data: row 0 in wave 0, row n-1 in the last wave
-    const bool lo_end = active && w == 0 && lo_kind != END_PHYS;
-    const bool hi_end = active && last && hi_kind != END_PHYS;
-    const double lo_scale = lo_end ? mc0[k0].fab * (lo_kind == END_ROBIN ? 1.0 : rr) : 0.0;
-    const double hi_scale = hi_end ? mc0[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : rr) : 0.0;
-    KGlob<const double> *lin_lo = lin + (size_t)(lam_lo > 0 ? lam_lo : 0) * plane + col;
-    KGlob<const double> *lin_hi = lin + (size_t)(lam_hi > 0 ? lam_hi : 0) * plane + col;
-    // boundary data of the first step, then prefetched one step ahead
-    double nlo = lo_end ? lin_lo[(size_t)n0 * nx] : 0.0;
-    double nhi = hi_end ? lin_hi[(size_t)n0 * nx] : 0.0;
+    const double lo_scale = lo_end ? mc[k0].fab * (lo_kind == END_ROBIN ? 1.0 : rr) : 0.0;
+    const double hi_scale = hi_end ? mc[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : rr) : 0.0;
     for (int s = 0; s < steps; ++s) {
       const int n = n0 + s;
       double xlo = 0.0, xhi = 0.0;
-      // loop-variant table pointers: the tables are re-read row by row
-      // through the scalar cache instead of being pinned in registers
-      int zoff = 0;
-      asm volatile("" : "+s"(zoff));
-      KConst<MarchCoef> *mc = mc0 + zoff;
-      KConst<RedCoef> *rcs = rc0 + zoff;
+      // the direction split, segment count and wave index are re-derived
+      // each step, so that tests built on them are not kept as per-row
+      // masks across the loop (they would not fit in scalar registers)
+      int vs = vsplit, Pq = P, wq = w;
+      asm volatile("" : "+s"(vs), "+s"(Pq), "+s"(wq));
       if (active) {
-        const double gn = gtab[n];
-        const double blo = lo_scale * nlo;
-        const double bhi = hi_scale * nhi;
-        if (s + 1 < steps) {
-          if (lo_end) nlo = lin_lo[(size_t)(n + 1) * nx];
-          if (hi_end) nhi = lin_hi[(size_t)(n + 1) * nx];
-        }
+        const double gn = sh_g[w][s];
+        const double blo = lo_end ? lo_scale * sh_bd[0][s][lane] : 0.0;
+        const double bhi = hi_end ? hi_scale * sh_bd[1][s][lane] : 0.0;
         // transport + source + forward elimination, one pass
         if (dir == DIR_LO)
-          march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, k0, blo, bhi, vsplit, fr, base, nx, col);
+          march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
         else if (dir == DIR_UP)
-          march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, k0, blo, bhi, vsplit, fr, base, nx, col);
+          march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
         else
-          march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, k0, blo, bhi, vsplit, fr, base, nx, col);
+          march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
         // back substitution
         double x = d.template ld<SEG - 1>();
-        double nbc = mc[SEG - 2 >= 0 ? SEG - 2 : 0].bc;
         static_for<0, SEG - 1>([&](auto kc) {
           constexpr int k = SEG - 2 - decltype(kc)::value;
-          const double bck = nbc;
-          if constexpr (k - 1 >= 0) nbc = mc[k - 1].bc;
-          x = fma(bck, x, d.template ld<k>());
+          x = fma(mc[k].bc, x, d.template ld<k>());
           d.template st<k>(x);
-          __builtin_amdgcn_sched_barrier(0);
         });
-        if (P > 1) {
+        if (Pq > 1) {
           sh_first[w][lane] = d.get(k0);
           sh_last[w][lane] = d.template ld<SEG - 2>();
           sh_sep[w][lane] = d.template ld<SEG - 1>();
         }
       }
-      if (P > 1) {
+      if (Pq > 1) {
         __syncthreads();
         if (active) {
-          // reduced separator system, per column, from LDS
-          double z[NW > 1 ? NW - 1 : 1];
-          double prev = 0.0;
+          // reduced separator system, per column: right-hand sides D_r from
+          // LDS, then the two separators this wave borders (r = w-1, w) as
+          // dot products with rows of the precomputed inverse
+          const int m = Pq - 1;
+          const double *Rl = sh_rinv + (wq > 0 ? wq - 1 : 0) * m;
+          const double *Rh = sh_rinv + (wq < m ? wq : 0) * m;
+          double xl = 0.0, xh = 0.0;
 #pragma unroll
           for (int q = 0; q < NW - 1; ++q) {
-            if (q < P - 1) {
-              const double D = sh_sep[q][lane] - rcs[q].ra * sh_last[q][lane] -
-                               rcs[q].rc * sh_first[q + 1][lane];
-              prev = (q == 0) ? D * rcs[q].g1 : fma(rcs[q].g2, prev, D * rcs[q].g1);
-              z[q] = prev;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          double nxt = 0.0;
-#pragma unroll
-          for (int q = NW - 2; q >= 0; --q) {
-            if (q < P - 1) {
-              nxt = (q == P - 2) ? z[q] : fma(rcs[q].h, nxt, z[q]);
-              if (q == w - 1) xlo = nxt;
-              if (q == w) xhi = nxt;
+            if (q < m) {
+              const RedCoef &rq = sh_rc[q];
+              const double D = sh_sep[q][lane] - rq.ra * sh_last[q][lane] -
+                               rq.rc * sh_first[q + 1][lane];
+              xl = fma(Rl[q], D, xl);
+              xh = fma(Rh[q], D, xh);
             }
           }
+          xlo = wq > 0 ? xl : 0.0;
+          xhi = wq < m ? xh : 0.0;
         }
       }
       if (active) {
-        double nsl = mc[0].sl, nsr = mc[0].sr;
         static_for<0, SEG>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          const double slk = nsl, srk = nsr;
-          if constexpr (k + 1 < SEG) {
-            nsl = mc[k + 1].sl;
-            nsr = mc[k + 1].sr;
-          }
-          d.template st<k>(fma(-slk, xlo, fma(-srk, xhi, d.template ld<k>())));
-          __builtin_amdgcn_sched_barrier(0);
+          d.template st<k>(fma(-mc[k].sl, xlo, fma(-mc[k].sr, xhi, d.template ld<k>())));
         });
         if (!last) d.template st<SEG - 1>(xhi);
         // interface-node values of level n+1
@@ -664,7 +672,7 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
           }
         }
       }
-      if (P > 1) __syncthreads();  // the next step rewrites the LDS slots
+      if (Pq > 1) __syncthreads();  // the next step rewrites the LDS slots
     }
     if (active && out) {
       static_for<0, SEG>([&](auto kc) {
@@ -892,6 +900,7 @@ bool march_config_supported(int waves, int seg_max) {
 
 hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int S, int H,
                         int src, int par, int grid, hipStream_t s) {
+  if (S < 1 || S > kMaxStepsPerLaunch || H < 1 || 2 * H >= 64) return hipErrorInvalidValue;
 #define KFP_LAUNCH(W, SM)                                                                   \
   if (waves == W && seg_max == SM) {                                                       \
     hipLaunchKernelGGL((march_kernel<SM, W>), dim3(grid), dim3(W * 64), 0, s, t, n0, S, H, \

@@ -200,7 +200,7 @@ static Config default_march(int n_max) {
   for (int w : kWaves) {
     if (w > 8) break;
     const int sm = march_seg_for(n_max, w);
-    if (sm && (sm <= 24 || w == 8)) return Config{w, sm, 8};
+    if (sm && (sm <= 24 || w == 8)) return Config{w, sm, 16};
   }
   return Config{};
 }
@@ -310,6 +310,7 @@ struct HostTables {
   std::vector<SubDev> subs;
   std::vector<RowCoef> rows;
   std::vector<MarchCoef> mrows;
+  std::vector<double> rinv;
   std::vector<RedCoef> reds;
   std::vector<int> segs;
   std::vector<Item> items;
@@ -555,6 +556,31 @@ static SubDev sub_descriptor(const Geo &g, int j, int inst, int sub_base) {
 // Tables of one subdomain in the multi-step layout: P = ceil(n / SEG)
 // segments of exactly SEG rows; a non-final segment ends with its separator;
 // the final one starts with pad = P SEG - n identity rows.
+// Inverse of the m x m tridiagonal matrix with sub-diagonal al[1..m-1],
+// diagonal be and super-diagonal ga[0..m-2] (row-major into inv), column by
+// column with the Thomas factorisation (the reduced matrix of a diagonally
+// dominant system is diagonally dominant: no pivoting needed).
+static void tridiag_inverse(const std::vector<double> &al, const std::vector<double> &be,
+                            const std::vector<double> &ga, std::vector<double> &inv) {
+  const int m = (int)be.size();
+  inv.assign((size_t)m * m, 0.0);
+  std::vector<double> cp(m), piv(m), z(m);
+  for (int i = 0; i < m; ++i) {
+    piv[i] = (i == 0) ? be[0] : be[i] - al[i] * cp[i - 1];
+    cp[i] = (i < m - 1) ? ga[i] / piv[i] : 0.0;
+  }
+  for (int col = 0; col < m; ++col) {
+    for (int i = 0; i < m; ++i) {
+      const double rhs = (i == col) ? 1.0 : 0.0;
+      z[i] = (i == 0) ? rhs / piv[0] : (rhs - al[i] * z[i - 1]) / piv[i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      const double x = (i == m - 1) ? z[i] : z[i] - cp[i] * inv[(size_t)(i + 1) * m + col];
+      inv[(size_t)i * m + col] = x;
+    }
+  }
+}
+
 static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst, int sub_base,
                                 HostTables &t) {
   const SubGeo &s = g.sub[j];
@@ -568,6 +594,7 @@ static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst
   d.tab = (int)t.mrows.size();
   d.seg = -1;
   d.red = (int)t.reds.size();
+  d.rinv = (int)t.rinv.size();
   d.P = P;
   d.pad = pad;
   t.subs.push_back(d);
@@ -589,6 +616,9 @@ static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst
   };
   for (int w = 0; w < P; ++w) {
     const int k0 = (w == P - 1) ? pad : 0;
+    // padding rows: no transport, no source, multiplier 1 (they pass the
+    // elimination's starting value, the low boundary data, to row k0)
+    for (int k = 0; k < k0; ++k) mc[(size_t)w * seg + k].fb = 1.0;
     for (int k = k0; k < seg; ++k) {
       const int i = w * seg + k - k0;  // local row
       MarchCoef &c = mc[(size_t)w * seg + k];
@@ -608,7 +638,9 @@ static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst
       c.alpha = rob ? 0.0 : fa * (1.0 - wgt);
       c.beta = rob ? 0.0 : fa * wgt;
       c.fa = rob ? 0.0 : fa;
-      c.fb = (kb == 0) ? 0.0 : -lo[i] * fa;
+      // the first row of a segment adds the incoming value once (it is the
+      // low boundary data in the segment holding row 0, zero elsewhere)
+      c.fb = (kb == 0) ? 1.0 : -lo[i] * fa;
       c.bc = (i < b1[w]) ? -bf[w].cp[kb] : 0.0;
       c.sl = bf[w].gL[kb];
       c.sr = bf[w].gR[kb];
@@ -640,6 +672,12 @@ static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst
       c.h = -cpk;
       cprev = cpk;
     }
+    // the multi-step kernel applies the explicit inverse of the reduced
+    // system (at most 15 x 15): every separator value is then an independent
+    // dot product instead of a link in a serial chain
+    std::vector<double> inv;
+    tridiag_inverse(al, be, ga, inv);
+    t.rinv.insert(t.rinv.end(), inv.begin(), inv.end());
   }
 }
 
@@ -707,6 +745,7 @@ struct DevTables {
   DevBuf<int> segs;
   DevBuf<ExItem> ex;
   DevBuf<MarchCoef> mrows;
+  DevBuf<double> rinv;
   StepTables view() const {
     StepTables t;
     t.inst = inst.p;
@@ -717,6 +756,7 @@ struct DevTables {
     t.segs = segs.p;
     t.ex = ex.p;
     t.mrows = mrows.p;
+    t.rinv = rinv.p;
     t.n_items = (int)items.n;
     t.n_ex = (int)ex.n;
     return t;
@@ -731,6 +771,7 @@ struct DevTables {
     if ((e = segs.alloc(h.segs.size())) != hipSuccess) return e;
     if ((e = ex.alloc(std::max<size_t>(h.ex.size(), 1))) != hipSuccess) return e;
     if ((e = mrows.alloc(std::max<size_t>(h.mrows.size(), 1))) != hipSuccess) return e;
+    if ((e = rinv.alloc(std::max<size_t>(h.rinv.size(), 1))) != hipSuccess) return e;
     items.n = h.items.size();
     ex.n = h.ex.size();
     auto cp = [&](void *d, const void *src, size_t bytes) {
@@ -745,6 +786,7 @@ struct DevTables {
     if ((e = cp(ex.p, h.ex.data(), h.ex.size() * sizeof(ExItem))) != hipSuccess) return e;
     if ((e = cp(mrows.p, h.mrows.data(), h.mrows.size() * sizeof(MarchCoef))) != hipSuccess)
       return e;
+    if ((e = cp(rinv.p, h.rinv.data(), h.rinv.size() * sizeof(double))) != hipSuccess) return e;
     return hipStreamSynchronize(s);  // host vectors may go out of scope
   }
   void release() {
@@ -755,6 +797,7 @@ struct DevTables {
     reds.release();
     segs.release();
     ex.release();
+    rinv.release();
     mrows.release();
   }
 };
@@ -777,10 +820,14 @@ struct Plan {
   DevBuf<unsigned int> cnt;
   unsigned long long *h_res = nullptr;  // pinned
   hipStream_t cs = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev0 = nullptr, ev1 = nullptr, evm = nullptr;
+  // per parity: the time steps of an iteration, then its exchange (if any)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t gexch[2] = {nullptr, nullptr};
   bool captured = false;
   ~Plan() {
+    for (auto &ge : gexch)
+      if (ge) (void)hipGraphExecDestroy(ge);
     for (auto &ge : gexec)
       if (ge) (void)hipGraphExecDestroy(ge);
     dt.release();
@@ -800,6 +847,7 @@ struct Plan {
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (evm) (void)hipEventDestroy(evm);
   }
 };
 
@@ -851,6 +899,7 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
   HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
   HIP_TRY(hipEventCreate(&pl->ev0));
   HIP_TRY(hipEventCreate(&pl->ev1));
+  HIP_TRY(hipEventCreate(&pl->evm));
   HIP_TRY(hipMemcpy(pl->rowmap.p, geo.rowmap.data(), sizeof(int) * (geo.nv + 1),
                     hipMemcpyHostToDevice));
   std::vector<int> ab;
@@ -907,40 +956,47 @@ static int march_launches(int nt, const Config &cfg) {
   return cfg.steps >= 1 ? (nt + cfg.steps - 1) / cfg.steps : nt;
 }
 
+// One iteration's launches: part 1 = the time steps (with the residual
+// reset), part 2 = the exchange of the multi-step path, 0 = both.
 static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const InstDev *inst,
                                           const Config &cfg, int nt, int par, int grid,
-                                          hipStream_t s) {
-  HIP_TRY(launch_reset_res(inst, n_inst, s));
-  if (cfg.steps == 0) {
-    for (int n = 0; n <= nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, par, grid, s));
-  } else {
-    const int L = march_launches(nt, cfg);
-    for (int l = 0; l < L; ++l)
-      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
-                           par, grid, s));
-    HIP_TRY(launch_exchange(t, par, nt, s));
+                                          hipStream_t s, int part = 0) {
+  if (part != 2) {
+    HIP_TRY(launch_reset_res(inst, n_inst, s));
+    if (cfg.steps == 0) {
+      for (int n = 0; n <= nt; ++n) HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, par, grid, s));
+    } else {
+      const int L = march_launches(nt, cfg);
+      for (int l = 0; l < L; ++l)
+        HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg),
+                             l & 1, par, grid, s));
+    }
   }
+  if (part != 1 && cfg.steps != 0) HIP_TRY(launch_exchange(t, par, nt, s));
   return KFP_OK;
 }
 
 static kfp_status capture_graphs(Plan &pl) {
   if (pl.captured) return KFP_OK;
   const StepTables t = pl.dt.view();
-  for (int par = 0; par < 2; ++par) {
-    hipGraph_t graph = nullptr;
-    HIP_TRY(hipStreamBeginCapture(pl.cs, hipStreamCaptureModeThreadLocal));
-    kfp_status st = launch_iteration_direct(t, 1, pl.dt.inst.p, pl.cfg, pl.geo.nt, par,
-                                            t.n_items, pl.cs);
-    hipError_t e = hipStreamEndCapture(pl.cs, &graph);
-    if (st) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return st;
+  const int parts = pl.cfg.steps != 0 ? 2 : 1;
+  for (int par = 0; par < 2; ++par)
+    for (int part = 1; part <= parts; ++part) {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(pl.cs, hipStreamCaptureModeThreadLocal));
+      kfp_status st = launch_iteration_direct(t, 1, pl.dt.inst.p, pl.cfg, pl.geo.nt, par,
+                                              t.n_items, pl.cs, part);
+      hipError_t e = hipStreamEndCapture(pl.cs, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      HIP_TRY(e);
+      e = hipGraphInstantiate(part == 1 ? &pl.gexec[par] : &pl.gexch[par], graph, nullptr,
+                              nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIP_TRY(e);
     }
-    HIP_TRY(e);
-    e = hipGraphInstantiate(&pl.gexec[par], graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HIP_TRY(e);
-  }
   pl.captured = true;
   return KFP_OK;
 }
@@ -1008,7 +1064,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   const bool graphs = use_graphs();
   if (graphs && (st = capture_graphs(*pl))) return st;
   const StepTables t = pl->dt.view();
-  double dev_ms = 0.0, r = INFINITY;
+  double dev_ms = 0.0, step_ms = 0.0, r = INFINITY;
   int k = 0;
   for (k = 1; k <= max_iter; ++k) {
     const int par = (k - 1) & 1;
@@ -1016,16 +1072,27 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     if (graphs) {
       HIP_TRY(hipGraphLaunch(pl->gexec[par], pl->cs));
     } else if ((st = launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt, par, t.n_items,
-                                             pl->cs))) {
+                                             pl->cs, 1))) {
       return st;
+    }
+    HIP_TRY(hipEventRecord(pl->evm, pl->cs));
+    if (cfg.steps != 0) {
+      if (graphs) {
+        HIP_TRY(hipGraphLaunch(pl->gexch[par], pl->cs));
+      } else if ((st = launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt, par, t.n_items,
+                                               pl->cs, 2))) {
+        return st;
+      }
     }
     HIP_TRY(hipEventRecord(pl->ev1, pl->cs));
     HIP_TRY(hipMemcpyAsync(pl->h_res, pl->res.p, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            pl->cs));
     HIP_TRY(hipStreamSynchronize(pl->cs));
-    float ms = 0.f;
+    float ms = 0.f, ms_step = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+    HIP_TRY(hipEventElapsedTime(&ms_step, pl->ev0, pl->evm));
     dev_ms += ms;
+    step_ms += ms_step;
     r = bits_to_double(*pl->h_res);
     if (J == 1) r = 0.0;
     if (stats && stats->res_history) stats->res_history[k - 1] = r;
@@ -1051,6 +1118,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     stats->restarted = restarted;
     stats->residual = r;
     stats->device_seconds = dev_ms * 1e-3;
+    stats->step_seconds = step_ms * 1e-3;
     stats->cell_steps = (double)k * geo.nt * geo.nx * geo.rows;
     stats->alg_bytes = 24.0 * stats->cell_steps;
     stats->seconds = now_s() - t_start;
@@ -1405,6 +1473,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       stats[i].residual = resid[i];
       stats[i].seconds = secs;
       stats[i].device_seconds = dev_ms * 1e-3;
+      stats[i].step_seconds = dev_ms * 1e-3;  // batch iterations are not split
       stats[i].cell_steps = (double)iters[i] * geo.nt * geo.nx * geo.rows;
       stats[i].alg_bytes = 24.0 * stats[i].cell_steps;
     }
