@@ -76,6 +76,10 @@ def load_library():
         raise RuntimeError(
             f"libkfpswr is not built ({_LIB_PATH} missing); run "
             "`python -m paper_1306_4596_amd.build` (needs hipcc for gfx950)")
+    # torch first: its HIP runtime then also serves the library (same soname);
+    # loading the library first would bring a second runtime into the process
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     G = ctypes.POINTER(Grid)

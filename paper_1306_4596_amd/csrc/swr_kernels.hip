@@ -484,9 +484,12 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
 template <int SEG, int NW>
 __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, int S, int H,
                                                         int src_par, int par) {
-  __shared__ double sh_first[NW][64];
-  __shared__ double sh_last[NW][64];
-  __shared__ double sh_sep[NW][64];
+  // segment end values for the reduced system, double-buffered by step
+  // parity: a step's writes never meet the previous step's reads, so one
+  // barrier per step suffices
+  __shared__ double sh_first[2][NW][64];
+  __shared__ double sh_last[2][NW][64];
+  __shared__ double sh_sep[2][NW][64];
   // boundary data of the launch's steps (low end, high end), staged once so
   // that the step loop issues no vector loads: its stores then never hold a
   // step up, since nothing in the loop waits on vector memory
@@ -612,9 +615,9 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
           d.template st<k>(x);
         });
         if (Pq > 1) {
-          sh_first[w][lane] = d.get(k0);
-          sh_last[w][lane] = d.template ld<SEG - 2>();
-          sh_sep[w][lane] = d.template ld<SEG - 1>();
+          sh_first[s & 1][w][lane] = d.get(k0);
+          sh_last[s & 1][w][lane] = d.template ld<SEG - 2>();
+          sh_sep[s & 1][w][lane] = d.template ld<SEG - 1>();
         }
       }
       if (Pq > 1) {
@@ -631,8 +634,8 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
           for (int q = 0; q < NW - 1; ++q) {
             if (q < m) {
               const RedCoef &rq = sh_rc[q];
-              const double D = sh_sep[q][lane] - rq.ra * sh_last[q][lane] -
-                               rq.rc * sh_first[q + 1][lane];
+              const double D = sh_sep[s & 1][q][lane] - rq.ra * sh_last[s & 1][q][lane] -
+                               rq.rc * sh_first[s & 1][q + 1][lane];
               xl = fma(Rl[q], D, xl);
               xh = fma(Rh[q], D, xh);
             }
@@ -672,8 +675,9 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
           }
         }
       }
-      if (Pq > 1) __syncthreads();  // the next step rewrites the LDS slots
     }
+    // the next item restages the reduced system and reuses the slots
+    if (P > 1) __syncthreads();
     if (active && out) {
       static_for<0, SEG>([&](auto kc) {
         constexpr int k = decltype(kc)::value;

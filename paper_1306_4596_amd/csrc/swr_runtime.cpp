@@ -196,11 +196,16 @@ static Config default_config(int n_max) {
 
 // Register march kernel by default: the fewest wavefronts (at most 8, where
 // the registers hold a segment without spilling) whose segment fits.
-static Config default_march(int n_max) {
+// Default multi-step configuration: the fewest waves (at most 8) whose
+// register segment holds the subdomain, and 16 steps per launch (a 32-column
+// tile) unless the 48-column tiles of 8 steps already give every compute
+// unit two workgroups: then the smaller halo wins.  `items8`: work items of
+// the whole launch set at 8 steps per launch (0: unknown).
+static Config default_march(int n_max, long items8 = 0) {
   for (int w : kWaves) {
     if (w > 8) break;
     const int sm = march_seg_for(n_max, w);
-    if (sm && (sm <= 24 || w == 8)) return Config{w, sm, 16};
+    if (sm && (sm <= 24 || w == 8)) return Config{w, sm, items8 >= 2L * 256 ? 8 : 16};
   }
   return Config{};
 }
@@ -299,7 +304,7 @@ static Config choose_config(const Geo &g) {
   if (it != g_tune->end() && (it->second.seg == 0 || segs_for(g.n_max, it->second.waves) <= it->second.seg))
     return it->second;
   if (g.J > 0 && g.nx > 0) {
-    const Config c = default_march(g.n_max);
+    const Config c = default_march(g.n_max, (long)g.J * ((g.nx + 47) / 48));
     if (c.waves) return c;
   }
   return default_config(g.n_max);
@@ -1192,7 +1197,8 @@ static Config batch_config(int n_max) {
   snprintf(key, sizeof key, "%s/batch/nmax%d", arch_name().c_str(), n_max);
   auto it = g_tune->find(key);
   if (it != g_tune->end()) return it->second;
-  const Config c = default_march(n_max);
+  // a batch has many work items: the 8-step layout
+  const Config c = default_march(n_max, 1L << 20);
   return c.waves ? c : default_config(n_max);
 }
 

@@ -1,0 +1,96 @@
+"""Throughput of the SWR path on the workloads beside the benchmark one.
+
+    python -m paper_1306_4596_amd.workloads batch [--n 256]
+    python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8]
+
+`batch`: uneven instances (Nx, Nv from {128, 256, 512, 1024}, J from
+{2, 4, 8, 16}, Nt = 512, T = 0.25, overlap 2, Robin p = 4) solved together
+by kfp_swr_batch to 1e-10.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J = 32,
+overlap 2, Robin p = 8, a fixed number of SWR iterations (a full solve takes
+minutes), once per launch configuration.  Each prints one JSON line per
+measurement.  Inputs are seeded and synthetic (inputs.py).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import binding as kb
+from . import inputs
+
+
+def run_batch(n: int, reps: int = 2):
+    import torch
+
+    specs = inputs.batch_specs(n)
+    insts = []
+    for sp in specs:
+        u0, f = inputs.fields_from_coefficients(sp["coef"], sp["nx"], sp["nv"])
+        insts.append(dict(u0=torch.from_numpy(u0).cuda(), f=torch.from_numpy(f).cuda(),
+                          T=sp["T"], nt=sp["nt"], J=sp["J"], overlap=sp["overlap"], tr=kb.ROBIN,
+                          p=sp["p"]))
+    for rep in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, rc = kb.swr_batch(insts, tol=1e-10, max_iter=400)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cells = sum(r[2].cell_steps for r in res)
+        its = [r[2].iters for r in res]
+        print(json.dumps({"workload": f"batch of {n} uneven SWR instances", "rep": rep, "status": rc,
+                          "wall_s": wall, "device_s": res[0][2].device_seconds,
+                          "cell_steps": cells, "cell_steps_per_s": cells / wall,
+                          "iters_min": min(its), "iters_mean": float(np.mean(its)),
+                          "iters_max": max(its)}), flush=True)
+
+
+def run_large(iters: int, configs):
+    import torch
+
+    nx = nv = 4096
+    nt, T, J, o, p = 8192, 1.0, 32, 2, 8.0
+    u0, f = inputs.random_fields(0, nx, nv)
+    U0 = torch.from_numpy(u0).cuda()
+    F = torch.from_numpy(f).cuda()
+    del u0, f
+    rows = kb.subdomain_rows(nx, nv, nt, T, J, o, kb.ROBIN)
+    for cfg in configs:
+        if cfg is not None:
+            kb.set_config(*cfg)
+        used = kb.get_config(nx, nv, nt, T, J, o, kb.ROBIN)
+        t0 = time.perf_counter()
+        _, _, st = kb.swr_solve(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-300, max_iter=iters)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(json.dumps({"workload": "4096x4096 Nt=8192 T=1 J=32 overlap=2 Robin p=8",
+                          "iterations": st.iters, "config": used, "rows": rows,
+                          "wall_s_incl_setup": wall, "device_s": st.device_seconds,
+                          "step_kernel_s": st.step_seconds,
+                          "cell_steps_per_s": st.cell_steps / st.device_seconds,
+                          "streaming_equivalent_GBps": 24.0 * st.cell_steps / st.step_seconds / 1e9}),
+              flush=True)
+        kb.release_workspace()
+    kb.set_config(0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["batch", "large"])
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--iters", type=int, default=1)
+    ap.add_argument("--configs", nargs="*", default=[],
+                    help="launch configurations waves,seg,steps (default: the library's choice)")
+    a = ap.parse_args()
+    kb.load_library()
+    if a.which == "batch":
+        run_batch(a.n)
+    else:
+        cfgs = [tuple(int(x) for x in c.split(",")) for c in a.configs] or [None]
+        run_large(a.iters, cfgs)
+
+
+if __name__ == "__main__":
+    main()
