@@ -74,6 +74,7 @@ typedef struct {
   double device_seconds;/* device time of the iteration graphs (HIP events)  */
   double step_seconds;  /* the part of it in the time-step kernels (batch:   */
                         /* the whole iteration)                              */
+  double step_launches; /* launches of the time-step kernel (0: batch)      */
   double cell_steps;    /* subdomain cell-steps executed (all iterations)    */
   double alg_bytes;     /* algorithmic HBM bytes of those cell-steps         */
   double *res_history;  /* [host] optional, length max_iter: r^1..r^iters   */
@@ -167,6 +168,27 @@ kfp_status kfp_swr_batch(int32_t n, const kfp_instance *inst, double tol, int32_
 kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, double p,
                     int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out, void *stream);
 kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps);
+
+/*
+ * kfp_set_pipeline -- overlap SWR iterations in time.  Iteration k at a
+ * time block needs only iteration k-1's traces of that block (the method is
+ * causal in time), so iteration k+1 can march d blocks behind iteration k;
+ * kfp_swr_solve then keeps `inflight` iterations in flight on its own state
+ * and trace window, stops at the first iteration below the tolerance and
+ * returns exactly the iterate, traces, count and history of the
+ * non-overlapped iteration.  inflight: -1 automatic (when one iteration's
+ * launches hold fewer than 512 work items; the default), 0 off, >= 2 forced.
+ * Applies to multi-step configurations with J >= 2; KFP_EINVAL otherwise.
+ */
+kfp_status kfp_set_pipeline(int32_t inflight);
+
+/*
+ * kfp_set_kernel_timing -- with on != 0, overlapped-iteration solves launch
+ * their kernels directly (not from a replayed graph) with HIP events around
+ * every time-step kernel launch, so that kfp_swr_stats.step_seconds holds
+ * those kernels' time alone.  Off by default.
+ */
+kfp_status kfp_set_kernel_timing(int32_t on);
 kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
                           int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out);
 

@@ -26,6 +26,8 @@ from .binding import (  # noqa: F401
     mul_f32,
     release_workspace,
     set_config,
+    set_kernel_timing,
+    set_pipeline,
     standardize,
     subdomain_rows,
     swr_batch,

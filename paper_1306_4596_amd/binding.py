@@ -29,6 +29,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarted", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("device_seconds", ctypes.c_double), ("step_seconds", ctypes.c_double),
+                ("step_launches", ctypes.c_double),
                 ("cell_steps", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("res_history", ctypes.POINTER(ctypes.c_double))]
 
@@ -51,6 +52,7 @@ class SWRStats:
         self.seconds = st.seconds
         self.device_seconds = st.device_seconds
         self.step_seconds = st.step_seconds
+        self.step_launches = st.step_launches
         self.cell_steps = st.cell_steps
         self.alg_bytes = st.alg_bytes
         self.res_history = history
@@ -93,6 +95,8 @@ def load_library():
     pi = ctypes.POINTER(i32)
     lib.kfp_tune.argtypes = [G, i32, i32, i32, f64, pi, pi, pi, vp]
     lib.kfp_set_config.argtypes = [i32, i32, i32]
+    lib.kfp_set_pipeline.argtypes = [i32]
+    lib.kfp_set_kernel_timing.argtypes = [i32]
     lib.kfp_get_config.argtypes = [G, i32, i32, i32, pi, pi, pi]
     lib.kfp_subdomain_rows.argtypes = [G, i32, i32, i32, ctypes.POINTER(ctypes.c_int64)]
     lib.kfp_bw_probe.argtypes = [vp, vp, ctypes.c_int64, vp]
@@ -100,7 +104,7 @@ def load_library():
     lib.kfp_last_error.argtypes = []
     lib.kfp_release_workspace.restype = None
     for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_u0_guess", "kfp_swr_batch", "kfp_tune",
-                 "kfp_set_config", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
+                 "kfp_set_config", "kfp_set_pipeline", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -298,6 +302,16 @@ def bw_probe(src, dst, stream=None):
                                        ctypes.c_void_p(dst.data_ptr()), int(nbytes),
                                        _stream(stream)))
     return nbytes
+
+
+def set_pipeline(inflight=-1):
+    """Overlapped SWR iterations: -1 automatic (default), 0 off, >= 2 in flight."""
+    _check(load_library().kfp_set_pipeline(int(inflight)))
+
+
+def set_kernel_timing(on=True):
+    """HIP events around every time-step kernel launch of overlapped solves."""
+    _check(load_library().kfp_set_kernel_timing(1 if on else 0))
 
 
 def release_workspace():

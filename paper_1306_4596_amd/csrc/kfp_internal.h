@@ -116,8 +116,26 @@ struct StepTables {
   const ExItem *ex;
   const MarchCoef *mrows;
   const double *rinv;  // per multi-step subdomain: (P-1) x (P-1) inverse, row-major
+  const int *blk;      // pipelined iterations: time block of each instance this launch
+                       // (-1: idle), or nullptr
   int n_items;
   int n_ex;
+};
+
+// Pipelined iterations.  Waveform relaxation is causal in time: iteration k
+// at time block b needs only iteration k-1's traces of block b.  Instance
+// (slot) i holds iteration k with k mod M = i and marches block
+// b = t - d (k-1) at launch t; a one-thread kernel after each launch records
+// finished iterations, stops at convergence and schedules the next launch.
+struct PipeCtl {
+  int t;         // index of the launch scheduled last
+  int stop;      // 0 running; k > 0 last iteration (converged or kmax); -1 non-finite r^1
+  int done;      // iterations completed
+  int kmax;      // iterations allowed
+  int M, d, L;   // slots, lag between iterations (launches), launches per window
+  int restart_on_nonfinite;
+  int last_busy; // last launch index with any slot scheduled
+  double tol;
 };
 
 // Slots of the interface-node value planes written by the multi-step kernel:
@@ -139,7 +157,11 @@ hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int
 bool march_config_supported(int waves, int seg_max);
 // Exchange pass of the multi-step path: traces (6.9)/(6.11) of every level
 // and the residual (6.12) from the interface-node value planes.
-hipError_t launch_exchange(const StepTables &t, int par, int nt_max, hipStream_t s);
+// S: steps per launch (pipelined tables: the exchange covers the levels of
+// each instance's current block only).
+hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s);
+hipError_t launch_pipe_tick(PipeCtl *c, int *blk, int *iter, unsigned long long *res,
+                            double *hist, hipStream_t s);
 hipError_t launch_reset_res(const InstDev *inst, int n_inst, hipStream_t s);
 hipError_t launch_assemble(const double *Ufinal, const int *rowmap, double *uT, int nv, int nx,
                            hipStream_t s);

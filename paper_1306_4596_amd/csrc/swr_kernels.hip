@@ -18,6 +18,7 @@
 // 64 lanes read 512 contiguous bytes per row.  All arithmetic is FP64.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <type_traits>
 
 #include "kfp_internal.h"
@@ -482,8 +483,8 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
 }
 
 template <int SEG, int NW>
-__global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, int S, int H,
-                                                        int src_par, int par) {
+__global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in, int S, int H,
+                                                        int src_in, int par) {
   // segment end values for the reduced system, double-buffered by step
   // parity: a step's writes never meet the previous step's reads, so one
   // barrier per step suffices
@@ -513,6 +514,13 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
     KConst<SubDev> *sd = subs + sub;
     KConst<InstDev> *I = insts + sd->inst;
     if (!I->active) continue;
+    int n0 = n0_in, src_par = src_in;
+    if (t.blk) {  // pipelined iterations: this instance's block of this launch
+      const int b = as_const(t.blk)[sd->inst];
+      if (b < 0) continue;
+      n0 = b * S;
+      src_par = b & 1;
+    }
     const int nx = I->nx;
     const int nt = I->nt;
     if (n0 >= nt) continue;
@@ -690,19 +698,29 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0, in
 // Traces of every level and the residual of one interface, from the value
 // planes: lambda_{j->j+1} = Q_2 u_j at a_{j+1}, lambda_{j+1->j} = Q_1 u_{j+1}
 // at b_j, and max |u_j - u_{j+1}| at the two end nodes of the overlap.
-__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par) {
+__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, int S) {
   __shared__ unsigned long long red[4];
   const ExItem ex = load_const(as_const(t.ex) + blockIdx.y);
   const InstDev I = load_inst(as_const(t.inst) + ex.inst);
   if (!I.active) return;
   const size_t plane = (size_t)I.nt * I.nx;
+  // levels covered: the whole window, or (pipelined) the instance's block
+  size_t e_begin = 0, e_end = plane;
+  if (t.blk) {
+    const int b = as_const(t.blk)[ex.inst];
+    if (b < 0) return;
+    const int n0 = b * S;
+    if (n0 >= I.nt) return;
+    e_begin = (size_t)n0 * I.nx;
+    e_end = (size_t)min(n0 + S, I.nt) * I.nx;
+  }
   const int j = ex.j;
   const double *V = I.V + (size_t)j * 6 * plane;
   const double *lin = par ? I.lam[1] : I.lam[0];
   double *lout = par ? I.lam[0] : I.lam[1];
   const bool robin = I.tr == 1;
   unsigned long long r = 0ull;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
+  for (size_t e = e_begin + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < e_end;
        e += (size_t)gridDim.x * blockDim.x) {
     const double ua = V[V_A_LO * plane + e];
     const double ubh = V[V_B_HI * plane + e];
@@ -737,6 +755,49 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par) {
     for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
     if (m) atomicMax(I.res, m);
   }
+}
+
+// Scheduler of pipelined iterations, run by one lane after every launch:
+// records the iterations whose last block just ran (residual history,
+// convergence, the first non-finite residual), then assigns each slot its
+// block of the next launch (slot i: the iteration k = i mod M, if any, with
+// 0 <= t - d (k-1) < L), clearing the residual of iterations that start.
+__global__ void pipe_tick_kernel(PipeCtl *c, int *blk, int *iter, unsigned long long *res,
+                                 double *hist) {
+  if (threadIdx.x != 0) return;
+  const int M = c->M, d = c->d, L = c->L;
+  for (int i = 0; i < M; ++i) {
+    if (blk[i] != L - 1) continue;
+    const int k = iter[i];
+    const double r = __longlong_as_double((long long)res[i]);
+    hist[k - 1] = r;
+    c->done = k;
+    if (c->stop == 0) {
+      if (k == 1 && c->restart_on_nonfinite && !(r <= DBL_MAX))
+        c->stop = -1;
+      else if (r < c->tol || k >= c->kmax)
+        c->stop = k;
+    }
+  }
+  const int t1 = c->t + 1;
+  c->t = t1;
+  const int khi = t1 / d + 1;
+  bool any = false;
+  for (int i = 0; i < M; ++i) {
+    int b = -1;
+    const int k = khi - (((khi - i) % M) + M) % M;
+    if (c->stop == 0 && k >= 1 && k <= c->kmax) {
+      const int bb = t1 - d * (k - 1);
+      if (bb >= 0 && bb < L) b = bb;
+    }
+    if (b == 0) res[i] = 0ull;
+    if (b >= 0) {
+      iter[i] = k;
+      any = true;
+    }
+    blk[i] = b;
+  }
+  if (any) c->last_busy = t1;
 }
 
 // ---------------------------------------------------------------------------
@@ -916,10 +977,17 @@ hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_exchange(const StepTables &t, int par, int nt_max, hipStream_t s) {
-  (void)nt_max;
+hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s) {
   if (t.n_ex == 0) return hipSuccess;
-  hipLaunchKernelGGL(exchange_kernel, dim3(256, t.n_ex), dim3(256), 0, s, t, par);
+  // a block of S levels is S * nx nodes per interface: fewer workgroups then
+  const unsigned gx = t.blk ? 32u : 256u;
+  hipLaunchKernelGGL(exchange_kernel, dim3(gx, t.n_ex), dim3(256), 0, s, t, par, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_pipe_tick(PipeCtl *c, int *blk, int *iter, unsigned long long *res,
+                            double *hist, hipStream_t s) {
+  hipLaunchKernelGGL(pipe_tick_kernel, dim3(1), dim3(64), 0, s, c, blk, iter, res, hist);
   return hipGetLastError();
 }
 

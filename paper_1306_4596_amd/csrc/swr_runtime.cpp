@@ -211,6 +211,14 @@ static Config default_march(int n_max, long items8 = 0) {
 }
 
 static Config g_forced;  // waves == 0: automatic
+static int g_pipe = -1;  // pipelined iterations: -1 automatic, 0 off, F >= 2 in flight
+// Automatic overlap below this many work items per launch (half the compute
+// units: one 8-wave workgroup per CU runs at a time), aiming at this many
+// items per overlapped launch (several rounds, so the last round's tail is
+// a small share).
+static const long kPipeItems = 128;
+static const long kPipeTarget = 1024;
+static bool g_ktime = false;  // time every step-kernel launch with HIP events
 
 // Tuning cache: a flat JSON object {"key": [waves, seg], ...}.
 static std::string tune_path() {
@@ -304,7 +312,11 @@ static Config choose_config(const Geo &g) {
   if (it != g_tune->end() && (it->second.seg == 0 || segs_for(g.n_max, it->second.waves) <= it->second.seg))
     return it->second;
   if (g.J > 0 && g.nx > 0) {
-    const Config c = default_march(g.n_max, (long)g.J * ((g.nx + 47) / 48));
+    // overlapped iterations (see pipe_params) supply work items to spare:
+    // then the smaller halo of 8 steps per launch
+    const long items8 = (long)g.J * ((g.nx + 47) / 48);
+    const bool piped = g_pipe != 0 && g.J > 1 && (g_pipe > 0 || items8 < kPipeItems);
+    const Config c = default_march(g.n_max, piped ? (1L << 20) : items8);
     if (c.waves) return c;
   }
   return default_config(g.n_max);
@@ -762,6 +774,7 @@ struct DevTables {
     t.ex = ex.p;
     t.mrows = mrows.p;
     t.rinv = rinv.p;
+    t.blk = nullptr;
     t.n_items = (int)items.n;
     t.n_ex = (int)ex.n;
     return t;
@@ -830,7 +843,29 @@ struct Plan {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphExec_t gexch[2] = {nullptr, nullptr};
   bool captured = false;
+  // pipelined iterations (M > 0): M slot instances with their own state and
+  // trace window; slot i writes window i and reads window i-1 (mod M)
+  int M = 0, d = 0, L = 0, G = 0;
+  DevBuf<double> slotU, W, hist;
+  DevBuf<unsigned long long> pres;
+  DevBuf<int> blk, iter;
+  DevBuf<PipeCtl> ctl;
+  PipeCtl *h_ctl = nullptr;  // pinned
+  hipGraphExec_t gpipe = nullptr;
+  const double *gpipe_hist = nullptr;  // history buffer the chunk graph was captured with
+  std::vector<hipEvent_t> tev;  // around each march launch of the chunk graph
   ~Plan() {
+    if (gpipe) (void)hipGraphExecDestroy(gpipe);
+    for (auto e : tev)
+      if (e) (void)hipEventDestroy(e);
+    slotU.release();
+    W.release();
+    hist.release();
+    pres.release();
+    blk.release();
+    iter.release();
+    ctl.release();
+    if (h_ctl) (void)hipHostFree(h_ctl);
     for (auto &ge : gexch)
       if (ge) (void)hipGraphExecDestroy(ge);
     for (auto &ge : gexec)
@@ -860,15 +895,49 @@ static std::map<std::string, std::unique_ptr<Plan>> g_plans;
 static std::vector<std::string> g_plan_lru;
 static const size_t kMaxPlans = 3;
 
-static std::string plan_key(const Geo &g, const Config &c) {
+struct PipeParams {
+  int M = 0, d = 0;
+};
+
+// Pipelined iterations when one iteration's launches leave the GPU short of
+// work: F iterations in flight (d = L / F launches apart) so that a launch
+// holds about kPipeTarget work items; M = ceil(L/d) + 1 slots, each with a
+// state and a trace window, within a memory budget.
+static PipeParams pipe_params(const Geo &g, const Config &c) {
+  PipeParams pp;
+  if (g_pipe == 0 || c.steps < 1 || g.J < 2) return pp;
+  const int L = (g.nt + c.steps - 1) / c.steps;
+  const long items = (long)g.J * ((g.nx + tile_width(c) - 1) / tile_width(c));
+  if (g_pipe < 0 && items >= kPipeItems) return pp;
+  long F = g_pipe > 0 ? g_pipe : (kPipeTarget + items - 1) / items;
+  F = std::min<long>(F, L);
+  if (F < 2) return pp;
+  int d = std::max(1, (int)(L / F));
+  const double per_slot = 8.0 * ((double)2 * (g.J - 1) * g.nt * g.nx + 2.0 * g.rows * g.nx);
+  const double budget = 24e9;
+  for (;;) {
+    const int M = (L + d - 1) / d + 1;
+    if (M * per_slot <= budget || d >= L) {
+      if (M >= 3) {
+        pp.M = M;
+        pp.d = d;
+      }
+      return pp;
+    }
+    d *= 2;
+  }
+}
+
+static std::string plan_key(const Geo &g, const Config &c, int M) {
   char buf[200];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/s%d/k%d", g.nx, g.nv, g.nt, g.J, g.o, g.tr,
-           c.waves, c.seg, c.steps);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/s%d/k%d/M%d", g.nx, g.nv, g.nt, g.J, g.o, g.tr,
+           c.waves, c.seg, c.steps, M);
   return buf;
 }
 
-static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
-  const std::string key = plan_key(geo, cfg);
+static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out,
+                           PipeParams pp = PipeParams()) {
+  const std::string key = plan_key(geo, cfg, pp.M);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     g_plan_lru.erase(std::find(g_plan_lru.begin(), g_plan_lru.end(), key));
@@ -914,6 +983,21 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out) {
   }
   if (!ab.empty())
     HIP_TRY(hipMemcpy(pl->ab.p, ab.data(), sizeof(int) * ab.size(), hipMemcpyHostToDevice));
+  if (pp.M > 0) {
+    pl->M = pp.M;
+    pl->d = pp.d;
+    pl->L = (geo.nt + cfg.steps - 1) / cfg.steps;
+    pl->G = std::min(16, pl->L);
+    HIP_TRY(pl->slotU.alloc((size_t)pp.M * 2 * state));
+    HIP_TRY(pl->W.alloc((size_t)pp.M * win));
+    HIP_TRY(pl->pres.alloc(pp.M));
+    HIP_TRY(pl->blk.alloc(pp.M));
+    HIP_TRY(pl->iter.alloc(pp.M));
+    HIP_TRY(pl->ctl.alloc(1));
+    HIP_TRY(hipHostMalloc((void **)&pl->h_ctl, sizeof(PipeCtl)));
+    pl->tev.assign(2 * pl->G, nullptr);
+    for (auto &e : pl->tev) HIP_TRY(hipEventCreate(&e));
+  }
   *out = pl.get();
   g_plans[key] = std::move(pl);
   g_plan_lru.push_back(key);
@@ -925,9 +1009,13 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
                                 double p) {
   const Geo &geo = pl.geo;
   HostTables h;
-  add_instance_cfg(geo, p, pl.cfg.waves, pl.cfg.seg, pl.cfg.steps, 0, h);
-  make_items(geo, 0, tile_width(pl.cfg), h.items);
-  make_ex(geo, 0, h.ex);
+  const int n_inst = pl.M > 0 ? pl.M : 1;
+  for (int i = 0; i < n_inst; ++i) {
+    const int sub_base = (int)h.subs.size();
+    add_instance_cfg(geo, p, pl.cfg.waves, pl.cfg.seg, pl.cfg.steps, i, h);
+    make_items(geo, sub_base, tile_width(pl.cfg), h.items);
+    make_ex(geo, i, h.ex);
+  }
   InstDev in{};
   in.U[0] = pl.U0.p;
   in.U[1] = pl.U1.p;
@@ -951,7 +1039,19 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   std::vector<double> gv(geo.nt);
   for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
   HIP_TRY(hipMemcpyAsync(pl.g.p, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, pl.cs));
-  HIP_TRY(pl.dt.upload(h, {in}, pl.cs));
+  std::vector<InstDev> ins(n_inst, in);
+  if (pl.M > 0) {
+    const size_t state = (size_t)geo.rows * geo.nx;
+    const size_t win = (size_t)2 * (geo.J - 1) * geo.nt * geo.nx;
+    for (int i = 0; i < pl.M; ++i) {
+      ins[i].U[0] = pl.slotU.p + (size_t)i * 2 * state;
+      ins[i].U[1] = ins[i].U[0] + state;
+      ins[i].lam[0] = pl.W.p + (size_t)((i + pl.M - 1) % pl.M) * win;  // read: iteration k-1
+      ins[i].lam[1] = pl.W.p + (size_t)i * win;                        // written: iteration k
+      ins[i].res = pl.pres.p + i;
+    }
+  }
+  HIP_TRY(pl.dt.upload(h, ins, pl.cs));
   return KFP_OK;
 }
 
@@ -977,7 +1077,7 @@ static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const
                              l & 1, par, grid, s));
     }
   }
-  if (part != 1 && cfg.steps != 0) HIP_TRY(launch_exchange(t, par, nt, s));
+  if (part != 1 && cfg.steps != 0) HIP_TRY(launch_exchange(t, par, cfg.steps, s));
   return KFP_OK;
 }
 
@@ -1028,6 +1128,149 @@ static kfp_status sync_out(hipStream_t user, Plan &pl) {
   return KFP_OK;
 }
 
+// ------------------------------------------------------- pipelined solve --
+// One chunk: G launches, each the march of every slot's current block, the
+// exchange of those blocks, and the scheduler.  Captured once as a graph and
+// replayed until the scheduler stops; with kernel timing on, launched
+// directly with HIP events around each march launch instead.
+static kfp_status launch_pipe_chunk(Plan &pl, bool timed) {
+  StepTables t = pl.dt.view();
+  t.blk = pl.blk.p;
+  const Config &c = pl.cfg;
+  for (int l = 0; l < pl.G; ++l) {
+    if (timed) HIP_TRY(hipEventRecord(pl.tev[2 * l], pl.cs));
+    HIP_TRY(launch_march(t, c.waves, c.seg, 0, c.steps, halo_of(c), 0, 0, t.n_items, pl.cs));
+    if (timed) HIP_TRY(hipEventRecord(pl.tev[2 * l + 1], pl.cs));
+    HIP_TRY(launch_exchange(t, 0, c.steps, pl.cs));
+    HIP_TRY(launch_pipe_tick(pl.ctl.p, pl.blk.p, pl.iter.p, pl.pres.p, pl.hist.p, pl.cs));
+  }
+  return KFP_OK;
+}
+
+static kfp_status capture_pipe_graph(Plan &pl) {
+  if (pl.gpipe) return KFP_OK;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(pl.cs, hipStreamCaptureModeThreadLocal));
+  kfp_status st = launch_pipe_chunk(pl, false);
+  hipError_t e = hipStreamEndCapture(pl.cs, &graph);
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  HIP_TRY(e);
+  e = hipGraphInstantiate(&pl.gpipe, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_TRY(e);
+  return KFP_OK;
+}
+
+static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double tol,
+                             int max_iter, bool had_guess, int restarted, double *uT,
+                             double *lambda_out, kfp_swr_stats *stats, hipStream_t user,
+                             double t_start) {
+  const size_t win = (size_t)2 * (geo.J - 1) * geo.nt * geo.nx;
+  const size_t state = (size_t)geo.rows * geo.nx;
+  HIP_TRY(pl.hist.alloc(max_iter));
+  if (pl.gpipe && pl.gpipe_hist != pl.hist.p) {
+    // the chunk graph holds the history pointer: capture again after a resize
+    (void)hipGraphExecDestroy(pl.gpipe);
+    pl.gpipe = nullptr;
+  }
+  const bool timed = g_ktime || !use_graphs();
+  if (!timed) {
+    kfp_status st = capture_pipe_graph(pl);
+    if (st) return st;
+    pl.gpipe_hist = pl.hist.p;
+  }
+  const long max_launches = (long)pl.L + (long)pl.d * (max_iter - 1) + pl.G;
+  double dev_ms = 0.0, step_ms = 0.0;
+  long launches = 0;
+  for (;;) {
+    PipeCtl c{};
+    c.t = -1;
+    c.kmax = max_iter;
+    c.M = pl.M;
+    c.d = pl.d;
+    c.L = pl.L;
+    c.restart_on_nonfinite = (had_guess && !restarted) ? 1 : 0;
+    c.last_busy = -1;
+    c.tol = tol;
+    HIP_TRY(hipMemcpyAsync(pl.ctl.p, &c, sizeof c, hipMemcpyHostToDevice, pl.cs));
+    HIP_TRY(hipMemsetAsync(pl.blk.p, 0xff, sizeof(int) * pl.M, pl.cs));  // all idle
+    HIP_TRY(launch_pipe_tick(pl.ctl.p, pl.blk.p, pl.iter.p, pl.pres.p, pl.hist.p, pl.cs));
+    long chunks = 0;
+    for (;;) {
+      HIP_TRY(hipEventRecord(pl.ev0, pl.cs));
+      if (timed) {
+        kfp_status st = launch_pipe_chunk(pl, true);
+        if (st) return st;
+      } else {
+        HIP_TRY(hipGraphLaunch(pl.gpipe, pl.cs));
+      }
+      HIP_TRY(hipEventRecord(pl.ev1, pl.cs));
+      HIP_TRY(hipMemcpyAsync(pl.h_ctl, pl.ctl.p, sizeof(PipeCtl), hipMemcpyDeviceToHost, pl.cs));
+      HIP_TRY(hipStreamSynchronize(pl.cs));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, pl.ev0, pl.ev1));
+      dev_ms += ms;
+      // march launches that had work (the chunk's tail after the stop idles)
+      for (int l = 0; l < pl.G; ++l) {
+        if (chunks * pl.G + l > pl.h_ctl->last_busy) break;
+        if (timed) {
+          float m = 0.f;
+          HIP_TRY(hipEventElapsedTime(&m, pl.tev[2 * l], pl.tev[2 * l + 1]));
+          step_ms += m;
+        }
+        ++launches;
+      }
+      ++chunks;
+      if (pl.h_ctl->stop != 0 || pl.h_ctl->done >= max_iter) break;
+      if (chunks * pl.G > max_launches)
+        return fail(KFP_EDEVICE, "pipelined iterations did not finish (%d done)",
+                    pl.h_ctl->done);
+    }
+    if (pl.h_ctl->stop == -1) {
+      // a finite-looking guess that still produced a non-finite mismatch:
+      // restart once from zero traces
+      HIP_TRY(launch_fill(pl.W.p, win, 0.0, pl.cs));
+      restarted = 1;
+      continue;
+    }
+    break;
+  }
+  const int k = pl.h_ctl->stop > 0 ? pl.h_ctl->stop : pl.h_ctl->done;
+  std::vector<double> hist(k);
+  HIP_TRY(hipMemcpyAsync(hist.data(), pl.hist.p, sizeof(double) * k, hipMemcpyDeviceToHost,
+                         pl.cs));
+  HIP_TRY(hipStreamSynchronize(pl.cs));
+  const double r = hist[k - 1];
+  const int slot = k % pl.M;
+  const double *U = pl.slotU.p + (size_t)slot * 2 * state + ((pl.L & 1) ? state : 0);
+  HIP_TRY(launch_assemble(U, pl.rowmap.p, uT, geo.nv, geo.nx, pl.cs));
+  if (lambda_out && win)
+    HIP_TRY(launch_copy(pl.W.p + (size_t)slot * win, lambda_out, win, pl.cs));
+  kfp_status st2 = sync_out(user, pl);
+  if (st2) return st2;
+  HIP_TRY(hipStreamSynchronize(pl.cs));
+  const bool converged = r < tol;
+  if (stats) {
+    stats->iters = k;
+    stats->restarted = restarted;
+    stats->residual = r;
+    stats->device_seconds = dev_ms * 1e-3;
+    stats->step_seconds = (timed ? step_ms : dev_ms) * 1e-3;
+    stats->step_launches = (double)launches;
+    stats->cell_steps = (double)k * geo.nt * geo.nx * geo.rows;
+    stats->alg_bytes = 24.0 * stats->cell_steps;
+    stats->seconds = now_s() - t_start;
+    if (stats->res_history)
+      for (int i = 0; i < k; ++i) stats->res_history[i] = hist[i];
+  }
+  (void)cfg;
+  if (!converged) return fail(KFP_ENOCONV, "no convergence after %d iterations (r = %g)", k, r);
+  return KFP_OK;
+}
+
 // ------------------------------------------------------------------ solves --
 static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const double *f,
                                  const double *s, int J, int o, int tr, double p, double tol,
@@ -1044,28 +1287,34 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     for (int n = 0; n <= g->nt; ++n)
       if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
   const Config cfg = choose_config(geo);
+  const PipeParams pp = pipe_params(geo, cfg);
   Plan *pl = nullptr;
-  if ((st = get_plan(geo, cfg, &pl))) return st;
+  if ((st = get_plan(geo, cfg, &pl, pp))) return st;
   if ((st = sync_in(user, *pl))) return st;
   if ((st = load_instance(*pl, u0, f, s, p))) return st;
   const size_t win = (size_t)2 * (J - 1) * geo.nt * geo.nx;
   int restarted = 0;
+  // lambda^0 goes to window 0 (pipelined: read by the slot of iteration 1)
+  double *lam_first = pl->M > 0 ? pl->W.p : pl->lam0.p;
   if (win) {
     if (lambda_init) {
-      HIP_TRY(launch_copy(lambda_init, pl->lam0.p, win, pl->cs));
+      HIP_TRY(launch_copy(lambda_init, lam_first, win, pl->cs));
       HIP_TRY(hipMemsetAsync(pl->cnt.p, 0, sizeof(unsigned int), pl->cs));
-      HIP_TRY(launch_count_nonfinite(pl->lam0.p, win, pl->cnt.p, pl->cs));
+      HIP_TRY(launch_count_nonfinite(lam_first, win, pl->cnt.p, pl->cs));
       unsigned int bad = 0;
       HIP_TRY(hipMemcpyAsync(&bad, pl->cnt.p, sizeof bad, hipMemcpyDeviceToHost, pl->cs));
       HIP_TRY(hipStreamSynchronize(pl->cs));
       if (bad) {
-        HIP_TRY(launch_fill(pl->lam0.p, win, 0.0, pl->cs));
+        HIP_TRY(launch_fill(lam_first, win, 0.0, pl->cs));
         restarted = 1;
       }
     } else {
-      HIP_TRY(launch_fill(pl->lam0.p, win, 0.0, pl->cs));
+      HIP_TRY(launch_fill(lam_first, win, 0.0, pl->cs));
     }
   }
+  if (pl->M > 0)
+    return pipe_solve(*pl, geo, cfg, tol, max_iter, lambda_init != nullptr, restarted, uT,
+                      lambda_out, stats, user, t_start);
   const bool graphs = use_graphs();
   if (graphs && (st = capture_graphs(*pl))) return st;
   const StepTables t = pl->dt.view();
@@ -1124,6 +1373,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     stats->residual = r;
     stats->device_seconds = dev_ms * 1e-3;
     stats->step_seconds = step_ms * 1e-3;
+    stats->step_launches = (double)k * march_launches(geo.nt, cfg);
     stats->cell_steps = (double)k * geo.nt * geo.nx * geo.rows;
     stats->alg_bytes = 24.0 * stats->cell_steps;
     stats->seconds = now_s() - t_start;
@@ -1378,7 +1628,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
         for (int l = 0; l < L; ++l)
           HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.seg, l * c.cfg.steps, c.cfg.steps,
                                halo_of(c.cfg), l & 1, par, c.grid, cs));
-        HIP_TRY(launch_exchange(t, par, c.nt_max, cs));
+        HIP_TRY(launch_exchange(t, par, c.cfg.steps, cs));
       }
     }
     return KFP_OK;
@@ -1480,6 +1730,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       stats[i].seconds = secs;
       stats[i].device_seconds = dev_ms * 1e-3;
       stats[i].step_seconds = dev_ms * 1e-3;  // batch iterations are not split
+      stats[i].step_launches = 0;
       stats[i].cell_steps = (double)iters[i] * geo.nt * geo.nx * geo.rows;
       stats[i].alg_bytes = 24.0 * stats[i].cell_steps;
     }
@@ -1551,7 +1802,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
         // the exchange pass runs once per window: charge its share
         float ex_ms = 0.f;
         HIP_TRY(hipEventRecord(pl->ev0, pl->cs));
-        HIP_TRY(launch_exchange(t, 0, geo.nt, pl->cs));
+        HIP_TRY(launch_exchange(t, 0, c.steps, pl->cs));
         HIP_TRY(hipEventRecord(pl->ev1, pl->cs));
         HIP_TRY(hipStreamSynchronize(pl->cs));
         HIP_TRY(hipEventElapsedTime(&ex_ms, pl->ev0, pl->ev1));
@@ -1626,6 +1877,21 @@ kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, d
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   return tune_impl(g, J, overlap, tr, p, waves_out, seg_max_out, steps_out, (hipStream_t)stream);
+}
+
+kfp_status kfp_set_kernel_timing(int32_t on) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  g_ktime = on != 0;
+  return KFP_OK;
+}
+
+kfp_status kfp_set_pipeline(int32_t inflight) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (inflight < -1 || inflight == 1) return fail(KFP_EINVAL, "inflight must be -1, 0 or >= 2");
+  g_pipe = inflight;
+  return KFP_OK;
 }
 
 kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps) {

@@ -37,8 +37,10 @@ def rel(a, b):
 @pytest.fixture(autouse=True)
 def _auto_config():
     kfp.set_config(0)
+    kfp.set_pipeline(-1)
     yield
     kfp.set_config(0)
+    kfp.set_pipeline(-1)
     os.environ.pop("KFP_NO_GRAPH", None)
 
 
@@ -265,6 +267,67 @@ def test_graph_and_direct_launch_agree_and_are_deterministic():
                              want_lambda=True)
     assert torch.equal(a, b) and torch.equal(la, lb)
     assert torch.equal(a, c) and torch.equal(la, lc)
+
+
+# ------------------------------------------------- overlapped iterations ----
+PIPE_CASES = [
+    # nx, nv, nt, T, J, o, tr, p, (waves, seg, steps) or None
+    (64, 64, 60, 0.3, 4, 2, R, 4.0, None),
+    (64, 64, 200, 0.1, 2, 4, D, 0.0, None),
+    (100, 96, 41, 0.2, 3, 3, R, 2.5, (4, 12, 4)),
+    (70, 120, 30, 0.2, 8, 1, D, 0.0, (2, 12, 3)),
+    (200, 128, 64, 0.25, 4, 5, R, 8.0, (4, 12, 8)),
+]
+
+
+@pytest.mark.parametrize("case", PIPE_CASES)
+@pytest.mark.parametrize("inflight", [2, 3, 7])
+def test_overlapped_iterations_equal_plain_iterations(case, inflight):
+    """Iterations overlapped in time reproduce the plain iteration exactly:
+    iterate, traces, count and residual history, bit for bit."""
+    nx, nv, nt, T, J, o, tr, p, cfg = case
+    print(f"pipeline case={case} inflight={inflight}", flush=True)
+    if cfg:
+        kfp.set_config(*cfg)
+    u0, f = inputs.random_fields(21, nx, nv)
+    runs = []
+    for mode in (0, inflight):
+        kfp.set_pipeline(mode)
+        runs.append(kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-11, max_iter=400,
+                                  want_lambda=True))
+    (a, la, sa), (b, lb, sb) = runs
+    assert sa.iters == sb.iters and sa.residual < 1e-11
+    assert torch.equal(a, b) and torch.equal(la, lb)
+    assert np.array_equal(sa.res_history, sb.res_history)
+    # and the fixed-count form (stops at max_iter, not at the tolerance)
+    kfp.set_pipeline(inflight)
+    c, lc, sc = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=5,
+                              want_lambda=True)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-300, max_iter=5)
+    assert sc.iters == 5
+    assert rel(host(c), ref.uT) <= 1e-12
+    assert rel(host(lc), ref.lam) <= 1e-12
+    assert np.allclose(sc.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+def test_overlapped_iterations_with_guess_and_restart():
+    nx, nv, nt, T = 64, 32, 40, 0.2
+    u0, f = inputs.random_fields(2, nx, nv)
+    kfp.set_pipeline(4)
+    bad = np.zeros((6, nt, nx))
+    bad[0, 3, 5] = np.nan
+    uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=4.0, tol=1e-11, max_iter=300,
+                              lambda_init=dev(bad))
+    assert st.restarted
+    ref = oracle.swr_solve(u0, f, T, nt, 4, 2, R, p=4.0, tol=1e-11, max_iter=300)
+    assert st.iters == ref.iters
+    assert rel(host(uT), ref.uT) <= 1e-10
+    lam0 = inputs.random_traces(3, 4, nt, nx)
+    ref = oracle.swr_solve(u0, f, T, nt, 4, 2, R, p=4.0, tol=1e-300, max_iter=4, lambda_init=lam0)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=4.0, tol=1e-300, max_iter=4,
+                                lambda_init=dev(lam0), want_lambda=True)
+    assert not st.restarted and st.iters == 4
+    assert rel(host(lam), ref.lam) <= 1e-12
 
 
 # ------------------------------------------------------------------ batch --
