@@ -118,6 +118,18 @@ kfp_status kfp_swr_solve(const kfp_grid *g, const double *u0, const double *f,
                          double *lambda_out, kfp_swr_stats *stats, void *stream);
 
 /*
+ * kfp_swr_solve_pq -- as kfp_swr_solve with the two-sided Robin operators of
+ * Section 6.3: Q_1 = p + d/dv (data for a subdomain's upper interface node),
+ * Q_2 = q - d/dv (for its lower one), OSWR(p,q) of Section 6.4.2.  Robin
+ * needs q > 0 too; kfp_swr_solve is the case q = p.
+ */
+kfp_status kfp_swr_solve_pq(const kfp_grid *g, const double *u0, const double *f,
+                            const double *s, int32_t J, int32_t overlap, int32_t tr, double p,
+                            double q, double tol, int32_t max_iter, const double *lambda_init,
+                            double *uT, double *lambda_out, kfp_swr_stats *stats,
+                            void *stream);
+
+/*
  * kfp_u0_guess -- the compatible initial traces lambda^0(n) = Q(u0) at each
  * interface node, for every time level n (Section 2: initial guesses must
  * agree with u0 at t = 0).  Same argument rules as kfp_swr_solve; writes
@@ -125,6 +137,9 @@ kfp_status kfp_swr_solve(const kfp_grid *g, const double *u0, const double *f,
  */
 kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
                         int32_t tr, double p, double *lambda, void *stream);
+/* The same with the two-sided operators (q as in kfp_swr_solve_pq). */
+kfp_status kfp_u0_guess_pq(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
+                           int32_t tr, double p, double q, double *lambda, void *stream);
 
 /* One instance of a batch ([host] struct, device pointers inside). */
 typedef struct {
@@ -136,6 +151,7 @@ typedef struct {
   const double *lambda_init; /* or NULL */
   double *uT;
   double *lambda_out;        /* or NULL */
+  double q;                  /* second Robin parameter; <= 0 for q = p */
 } kfp_instance;
 
 /*

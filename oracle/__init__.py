@@ -52,9 +52,9 @@ def _load():
         lib.oracle_partition.argtypes = [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I)]
         lib.oracle_swr_solve.argtypes = [
             I, I, I, ctypes.c_double, D, D, D, I, I, I, ctypes.c_double, ctypes.c_double,
-            I, D, D, D, ctypes.POINTER(I), D, D,
+            ctypes.c_double, I, D, D, D, ctypes.POINTER(I), D, D,
         ]
-        lib.oracle_u0_guess.argtypes = [I, I, I, D, I, I, I, ctypes.c_double, D]
+        lib.oracle_u0_guess.argtypes = [I, I, I, D, I, I, I, ctypes.c_double, ctypes.c_double, D]
         for fn in ("oracle_thomas", "oracle_transport", "oracle_mono_solve",
                    "oracle_partition", "oracle_swr_solve", "oracle_u0_guess"):
             getattr(lib, fn).restype = I
@@ -136,8 +136,9 @@ class SWRResult:
 
 
 def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter=100,
-              lambda_init=None, s=None):
-    """Parallel SWR (Section 6.3 with the Jacobi Remark).  Returns SWRResult."""
+              lambda_init=None, s=None, q=None):
+    """Parallel SWR (Section 6.3 with the Jacobi Remark).  Returns SWRResult.
+    q: second Robin parameter of OSWR(p,q); None for q = p."""
     u0, f = _f64(u0), _f64(f)
     nv, nx = u0.shape[0] - 1, u0.shape[1]
     s = None if s is None else _f64(s)
@@ -151,7 +152,8 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter
     ovl = np.zeros(max_iter)
     it = ctypes.c_int(0)
     st = _load().oracle_swr_solve(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), J, overlap,
-                                  int(transmission), float(p), float(tol), max_iter, _p(li),
+                                  int(transmission), float(p), float(p if q is None else q),
+                                  float(tol), max_iter, _p(li),
                                   _p(uT), _p(lam_out), ctypes.byref(it), _p(hist), _p(ovl))
     if st == 1:
         raise ValueError("invalid arguments")
@@ -159,12 +161,12 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter
     return SWRResult(uT, lam_out[: 2 * nI], k, hist[:k].copy(), ovl[:k].copy(), st)
 
 
-def u0_guess(u0, nt, J, overlap, transmission, p=0.0):
+def u0_guess(u0, nt, J, overlap, transmission, p=0.0, q=None):
     """Initial traces lambda^0(n) = Q(u0) at each interface node, for every n."""
     u0 = _f64(u0)
     nv, nx = u0.shape[0] - 1, u0.shape[1]
     lam = np.zeros((2 * (J - 1), nt, nx))
     if _load().oracle_u0_guess(nx, nv, nt, _p(u0), J, overlap, int(transmission), float(p),
-                               _p(lam)):
+                               float(p if q is None else q), _p(lam)):
         raise ValueError("invalid arguments")
     return lam

@@ -270,7 +270,10 @@ static int owner(int i, int nv, int J, const int *a, int tr) {
 /*
  * oracle_swr_solve: parallel SWR for J subdomains.
  *   u0, f: [nv+1][nx]; s: [nt+1] or NULL.
- *   tr: 0 Dirichlet (CSWR), 1 Robin (OSWR(p), q = p).
+ *   tr: 0 Dirichlet (CSWR), 1 Robin: OSWR(p,q) of Section 6.3, the data for
+ *     a subdomain's upper interface node is Q_1 u = (p + d/dv) u of its upper
+ *     neighbour, the data for its lower node Q_2 u = (q - d/dv) u of its
+ *     lower neighbour; q = p is the one-sided OSWR(p).
  *   lambda_init: [2(J-1)][nt][nx] or NULL (zero).  Plane 2j holds the data
  *     for subdomain j+1 at node a_{j+1} (Q_2 u_j), plane 2j+1 the data for
  *     subdomain j at node b_j (Q_1 u_{j+1}); row n-1 holds time level n.
@@ -282,7 +285,7 @@ static int owner(int i, int nv, int J, const int *a, int tr) {
  */
 int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
                      const double *f, const double *s, int J, int o, int tr,
-                     double p, double tol, int max_iter, const double *lambda_init,
+                     double p, double q, double tol, int max_iter, const double *lambda_init,
                      double *uT, double *lambda_out, int *iters, double *res_hist,
                      double *ovl_hist) {
   if (nx < 1 || nv < 2 || nt < 1 || !(T > 0) || max_iter < 1) return 1;
@@ -292,13 +295,12 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
     free(b);
     return 1;
   }
-  if (J > 1 && tr == KFP_O_ROBIN && (o < 1 || !(p > 0))) {
+  if (J > 1 && tr == KFP_O_ROBIN && (o < 1 || !(p > 0) || !(q > 0))) {
     free(a);
     free(b);
     return 1;
   }
   const double hv = 2.0 / nv;
-  const double q = p;
   const size_t P = (size_t)nt * nx; /* one trace plane */
   const int nI = J - 1;
   double *lamOld = (double *)calloc(2 * nI * P + 1, sizeof(double));
@@ -385,14 +387,14 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
 /* The "u0-extension" initial guess: lambda^0(n) = Q(u0) at the interface
  * node for every time level n (compatible with u0 at t = 0, Section 2). */
 int oracle_u0_guess(int nx, int nv, int nt, const double *u0, int J, int o, int tr,
-                    double p, double *lam) {
+                    double p, double q, double *lam) {
   int *a = (int *)malloc(sizeof(int) * J), *b = (int *)malloc(sizeof(int) * J);
   if (oracle_partition(nv, J, o, a, b)) {
     free(a);
     free(b);
     return 1;
   }
-  const double hv = 2.0 / nv, q = p;
+  const double hv = 2.0 / nv;
   const size_t P = (size_t)nt * nx;
   for (int j = 0; j + 1 < J; ++j) {
     const int al = a[j + 1], be = b[j];

@@ -39,7 +39,8 @@ class Instance(ctypes.Structure):
                 ("tr", ctypes.c_int32), ("p", ctypes.c_double),
                 ("u0", ctypes.c_void_p), ("f", ctypes.c_void_p),
                 ("s", ctypes.POINTER(ctypes.c_double)), ("lambda_init", ctypes.c_void_p),
-                ("uT", ctypes.c_void_p), ("lambda_out", ctypes.c_void_p)]
+                ("uT", ctypes.c_void_p), ("lambda_out", ctypes.c_void_p),
+                ("q", ctypes.c_double)]
 
 
 class SWRStats:
@@ -89,6 +90,9 @@ def load_library():
     lib.kfp_mono_solve.argtypes = [G, vp, vp, D, vp, vp]
     lib.kfp_swr_solve.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, i32, vp, vp, vp,
                                   ctypes.POINTER(Stats), vp]
+    lib.kfp_swr_solve_pq.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, f64, i32, vp, vp, vp,
+                                     ctypes.POINTER(Stats), vp]
+    lib.kfp_u0_guess_pq.argtypes = [G, vp, i32, i32, i32, f64, f64, vp, vp]
     lib.kfp_u0_guess.argtypes = [G, vp, i32, i32, i32, f64, vp, vp]
     lib.kfp_swr_batch.argtypes = [i32, ctypes.POINTER(Instance), f64, i32,
                                   ctypes.POINTER(Stats), vp]
@@ -103,7 +107,8 @@ def load_library():
     lib.kfp_last_error.restype = ctypes.c_char_p
     lib.kfp_last_error.argtypes = []
     lib.kfp_release_workspace.restype = None
-    for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_u0_guess", "kfp_swr_batch", "kfp_tune",
+    for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_u0_guess",
+                 "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_pipeline", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -176,8 +181,9 @@ def mono_solve(u0, f, T, nt, s=None, out=None, stream=None):
 
 def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter=200,
               lambda_init=None, s=None, want_lambda=False, history=True, stream=None,
-              raise_noconv=False):
-    """Parallel SWR solve.  Returns (uT, lambda or None, SWRStats)."""
+              raise_noconv=False, q=None):
+    """Parallel SWR solve.  Returns (uT, lambda or None, SWRStats).  q: the
+    second Robin parameter of OSWR(p,q) (None: q = p)."""
     import numpy as np
     import torch
 
@@ -192,30 +198,43 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter
     if hist is not None:
         st.res_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     g = _grid(nx, nv, nt, T)
-    rc = load_library().kfp_swr_solve(ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J),
-                                      int(overlap), int(transmission), float(p), float(tol),
-                                      int(max_iter), _ptr(lambda_init), _ptr(uT), _ptr(lam),
-                                      ctypes.byref(st), _stream(stream))
+    lib = load_library()
+    if q is None:
+        rc = lib.kfp_swr_solve(ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J), int(overlap),
+                               int(transmission), float(p), float(tol), int(max_iter),
+                               _ptr(lambda_init), _ptr(uT), _ptr(lam), ctypes.byref(st),
+                               _stream(stream))
+    else:
+        rc = lib.kfp_swr_solve_pq(ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J), int(overlap),
+                                  int(transmission), float(p), float(q), float(tol),
+                                  int(max_iter), _ptr(lambda_init), _ptr(uT), _ptr(lam),
+                                  ctypes.byref(st), _stream(stream))
     _check(rc, allow_noconv=not raise_noconv)
     h = hist[: st.iters].copy() if hist is not None else None
     return uT, lam, SWRStats(st, h)
 
 
-def u0_guess(u0, nt, J, overlap, transmission, p=0.0, stream=None):
+def u0_guess(u0, nt, J, overlap, transmission, p=0.0, stream=None, q=None):
     """Initial traces Q(u0) at every interface node and time level."""
     import torch
 
     nv, nx = _shape(u0)
     lam = torch.empty((2 * (J - 1), nt, nx), dtype=torch.float64, device=u0.device)
     g = _grid(nx, nv, nt, 0.5 * nt / nx)  # the traces do not depend on T; any CFL-valid T
-    _check(load_library().kfp_u0_guess(ctypes.byref(g), _ptr(u0), int(J), int(overlap),
-                                       int(transmission), float(p), _ptr(lam), _stream(stream)))
+    lib = load_library()
+    if q is None:
+        _check(lib.kfp_u0_guess(ctypes.byref(g), _ptr(u0), int(J), int(overlap),
+                                int(transmission), float(p), _ptr(lam), _stream(stream)))
+    else:
+        _check(lib.kfp_u0_guess_pq(ctypes.byref(g), _ptr(u0), int(J), int(overlap),
+                                   int(transmission), float(p), float(q), _ptr(lam),
+                                   _stream(stream)))
     return lam
 
 
 def swr_batch(instances, tol=1e-10, max_iter=200, history=False, stream=None):
     """Batched SWR.  `instances` is a list of dicts with keys u0, f, T, nt, J,
-    overlap, tr, p and optionally s, lambda_init, want_lambda.  Returns a list
+    overlap, tr, p and optionally q, s, lambda_init, want_lambda.  Returns a list
     of (uT, lambda or None, SWRStats) and the overall status (0 or 4)."""
     import numpy as np
     import torch
@@ -241,6 +260,7 @@ def swr_batch(instances, tol=1e-10, max_iter=200, history=False, stream=None):
         arr[i].overlap = int(d["overlap"])
         arr[i].tr = int(d["tr"])
         arr[i].p = float(d.get("p", 0.0))
+        arr[i].q = float(d["q"]) if d.get("q") is not None else 0.0
         arr[i].u0 = _ptr(u0).value
         arr[i].f = _ptr(f).value
         arr[i].s = sp

@@ -170,7 +170,7 @@ hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_count_nonfinite(const double *p, size_t n, unsigned int *count, hipStream_t s);
 // ab: device [J-1][2] = (a_{j+1}, b_j) per interface.
 hipError_t launch_u0_guess(const double *u0, int nx, int nt, int J, const int *ab, int tr,
-                           double p, double hv, double *lam, hipStream_t s);
+                           double p, double q, double hv, double *lam, hipStream_t s);
 hipError_t launch_bw_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 }  // namespace kfp

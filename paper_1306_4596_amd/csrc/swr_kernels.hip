@@ -844,8 +844,8 @@ __global__ void count_nonfinite_kernel(const double *__restrict__ p, size_t n, u
 
 // lambda^0(n) = Q(u0) at every interface node, for all time levels.
 __global__ void u0_guess_kernel(const double *__restrict__ u0, int nx, int nt, int J,
-                                const int *__restrict__ ab, int tr, double p, double hv,
-                                double *__restrict__ lam) {
+                                const int *__restrict__ ab, int tr, double p, double q,
+                                double hv, double *__restrict__ lam) {
   const size_t plane = (size_t)nt * nx;
   const size_t total = (size_t)(J - 1) * plane;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -860,8 +860,8 @@ __global__ void u0_guess_kernel(const double *__restrict__ u0, int nx, int nt, i
     if (tr == 1) {
       const double ua1 = u0[(size_t)(al + 1) * nx + m];
       const double ub1 = u0[(size_t)(be - 1) * nx + m];
-      toR = p * ua - (ua1 - ua) / hv;
-      toL = p * ub + (ub - ub1) / hv;
+      toR = q * ua - (ua1 - ua) / hv;  // Q_2 = q - d/dv at a_{j+1}
+      toL = p * ub + (ub - ub1) / hv;  // Q_1 = p + d/dv at b_j
     }
     lam[(size_t)(2 * j) * plane + off] = toR;
     lam[(size_t)(2 * j + 1) * plane + off] = toL;
@@ -914,11 +914,11 @@ hipError_t launch_count_nonfinite(const double *p, size_t n, unsigned int *count
 }
 
 hipError_t launch_u0_guess(const double *u0, int nx, int nt, int J, const int *ab, int tr,
-                           double p, double hv, double *lam, hipStream_t s) {
+                           double p, double q, double hv, double *lam, hipStream_t s) {
   const size_t n = (size_t)(J - 1) * nt * nx;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(u0_guess_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, u0, nx, nt, J, ab,
-                     tr, p, hv, lam);
+                     tr, p, q, hv, lam);
   return hipGetLastError();
 }
 

@@ -353,11 +353,10 @@ static void row_matrix(const SubGeo &s, double r, double p, double q, double hv,
 }
 
 // Appends the tables of one subdomain (partitioned into P segments).
-static void add_subdomain(const Geo &g, int j, double p, int waves, int inst, int sub_base,
+static void add_subdomain(const Geo &g, int j, double p, double q, int waves, int inst, int sub_base,
                           HostTables &t) {
   const SubGeo &s = g.sub[j];
   const double hx = 1.0 / g.nx, hv = 2.0 / g.nv, dt = g.T / g.nt, r = dt / (hv * hv);
-  const double q = p;
   const int n = s.n;
   const int P = std::max(1, std::min(waves, n / 2));
   std::vector<double> lo, di, up;
@@ -598,7 +597,8 @@ static void tridiag_inverse(const std::vector<double> &al, const std::vector<dou
   }
 }
 
-static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst, int sub_base,
+static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg, int inst,
+                                int sub_base,
                                 HostTables &t) {
   const SubGeo &s = g.sub[j];
   const double hx = 1.0 / g.nx, hv = 2.0 / g.nv, dt = g.T / g.nt, r = dt / (hv * hv);
@@ -606,7 +606,7 @@ static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst
   const int P = (n + seg - 1) / seg;
   const int pad = P * seg - n;
   std::vector<double> lo, di, up;
-  row_matrix(s, r, p, p, hv, lo, di, up);
+  row_matrix(s, r, p, q, hv, lo, di, up);
   SubDev d = sub_descriptor(g, j, inst, sub_base);
   d.tab = (int)t.mrows.size();
   d.seg = -1;
@@ -698,19 +698,20 @@ static void add_subdomain_march(const Geo &g, int j, double p, int seg, int inst
   }
 }
 
-static void add_instance(const Geo &g, double p, int waves, int inst, HostTables &t) {
+static void add_instance(const Geo &g, double p, double q, int waves, int inst, HostTables &t) {
   const int sub_base = (int)t.subs.size();
-  for (int j = 0; j < g.J; ++j) add_subdomain(g, j, p, waves, inst, sub_base, t);
+  for (int j = 0; j < g.J; ++j) add_subdomain(g, j, p, q, waves, inst, sub_base, t);
 }
 
-static void add_instance_cfg(const Geo &g, double p, int waves, int seg, int steps, int inst,
+static void add_instance_cfg(const Geo &g, double p, double q, int waves, int seg, int steps,
+                             int inst,
                              HostTables &t) {
   if (steps == 0) {
-    add_instance(g, p, waves, inst, t);
+    add_instance(g, p, q, waves, inst, t);
     return;
   }
   const int sub_base = (int)t.subs.size();
-  for (int j = 0; j < g.J; ++j) add_subdomain_march(g, j, p, seg, inst, sub_base, t);
+  for (int j = 0; j < g.J; ++j) add_subdomain_march(g, j, p, q, seg, inst, sub_base, t);
 }
 
 
@@ -1006,13 +1007,13 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out,
 
 // Uploads the per-call tables (data pointers, p, T, s) of a single instance.
 static kfp_status load_instance(Plan &pl, const double *u0, const double *f, const double *s,
-                                double p) {
+                                double p, double q) {
   const Geo &geo = pl.geo;
   HostTables h;
   const int n_inst = pl.M > 0 ? pl.M : 1;
   for (int i = 0; i < n_inst; ++i) {
     const int sub_base = (int)h.subs.size();
-    add_instance_cfg(geo, p, pl.cfg.waves, pl.cfg.seg, pl.cfg.steps, i, h);
+    add_instance_cfg(geo, p, q, pl.cfg.waves, pl.cfg.seg, pl.cfg.steps, i, h);
     make_items(geo, sub_base, tile_width(pl.cfg), h.items);
     make_ex(geo, i, h.ex);
   }
@@ -1029,7 +1030,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt;
   in.r = dt / (hv * hv);
   in.p = p;
-  in.q = p;
+  in.q = q;
   in.hv = hv;
   in.nx = geo.nx;
   in.nv = geo.nv;
@@ -1273,7 +1274,8 @@ static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double
 
 // ------------------------------------------------------------------ solves --
 static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const double *f,
-                                 const double *s, int J, int o, int tr, double p, double tol,
+                                 const double *s, int J, int o, int tr, double p, double q,
+                                 double tol,
                                  int max_iter, const double *lambda_init, double *uT,
                                  double *lambda_out, kfp_swr_stats *stats, hipStream_t user) {
   const double t_start = now_s();
@@ -1291,7 +1293,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   Plan *pl = nullptr;
   if ((st = get_plan(geo, cfg, &pl, pp))) return st;
   if ((st = sync_in(user, *pl))) return st;
-  if ((st = load_instance(*pl, u0, f, s, p))) return st;
+  if ((st = load_instance(*pl, u0, f, s, p, q))) return st;
   const size_t win = (size_t)2 * (J - 1) * geo.nt * geo.nx;
   int restarted = 0;
   // lambda^0 goes to window 0 (pipelined: read by the slot of iteration 1)
@@ -1395,7 +1397,7 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
   Plan *pl = nullptr;
   if ((st = get_plan(geo, cfg, &pl))) return st;
   if ((st = sync_in(user, *pl))) return st;
-  if ((st = load_instance(*pl, u0, f, s, 0.0))) return st;
+  if ((st = load_instance(*pl, u0, f, s, 0.0, 0.0))) return st;
   const StepTables t = pl->dt.view();
   if (cfg.steps == 0) {
     for (int n = 0; n < geo.nt; ++n)
@@ -1414,7 +1416,7 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
 // ------------------------------------------------------------------- batch --
 struct BatchInst {
   Geo geo;
-  double p;
+  double p, q;
   double *U0 = nullptr, *U1 = nullptr, *lam0 = nullptr, *lam1 = nullptr, *g = nullptr,
          *V = nullptr;
   int *rowmap = nullptr;
@@ -1468,6 +1470,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       for (int n = 0; n <= in[i].g.nt; ++n)
         if (!std::isfinite(in[i].s[n])) return fail(KFP_EINVAL, "instance %d: s not finite", i);
     bi[i].p = in[i].p;
+    bi[i].q = in[i].q > 0.0 ? in[i].q : in[i].p;  // q <= 0: one-sided
   }
   // launch classes
   std::vector<BatchClass> cls;
@@ -1550,7 +1553,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     d.V = b.V;
     d.r = dt / (hv * hv);
     d.p = b.p;
-    d.q = b.p;
+    d.q = b.q;
     d.hv = hv;
     d.nx = geo.nx;
     d.nv = geo.nv;
@@ -1577,7 +1580,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     for (int i : c.members) {
       const Geo &geo = bi[i].geo;
       const int sub_base = (int)c.h.subs.size();
-      add_instance_cfg(geo, bi[i].p, c.cfg.waves, c.cfg.seg, c.cfg.steps, i, c.h);
+      add_instance_cfg(geo, bi[i].p, bi[i].q, c.cfg.waves, c.cfg.seg, c.cfg.steps, i, c.h);
       make_ex(geo, i, c.h.ex);
       std::vector<Item> it;
       make_items(geo, sub_base, tile_width(c.cfg), it);
@@ -1616,20 +1619,42 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       }
   }
 
+  // launch classes run side by side: one stream each, forked from and joined
+  // back into the batch stream (inside the captured graph: parallel branches)
+  struct Streams {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> e;
+    ~Streams() {
+      for (auto x : s)
+        if (x) (void)hipStreamDestroy(x);
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } side;
+  side.s.assign(cls.size(), nullptr);
+  side.e.assign(cls.size() + 1, nullptr);
+  for (auto &x : side.s) HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+  for (auto &x : side.e) HIP_TRY(hipEventCreateWithFlags(&x, hipEventDisableTiming));
   auto iteration = [&](int par) -> kfp_status {
     HIP_TRY(launch_reset_res(d_inst, n_inst, cs));
-    for (auto &c : cls) {
+    HIP_TRY(hipEventRecord(side.e[cls.size()], cs));
+    for (size_t ci = 0; ci < cls.size(); ++ci) {
+      BatchClass &c = cls[ci];
+      hipStream_t s = side.s[ci];
+      HIP_TRY(hipStreamWaitEvent(s, side.e[cls.size()], 0));
       const StepTables t = view(c);
       if (c.cfg.steps == 0) {
         for (int n = 0; n <= c.nt_max; ++n)
-          HIP_TRY(launch_step(t, c.cfg.waves, c.cfg.seg, n, par, c.grid, cs));
+          HIP_TRY(launch_step(t, c.cfg.waves, c.cfg.seg, n, par, c.grid, s));
       } else {
         const int L = march_launches(c.nt_max, c.cfg);
         for (int l = 0; l < L; ++l)
           HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.seg, l * c.cfg.steps, c.cfg.steps,
-                               halo_of(c.cfg), l & 1, par, c.grid, cs));
-        HIP_TRY(launch_exchange(t, par, c.cfg.steps, cs));
+                               halo_of(c.cfg), l & 1, par, c.grid, s));
+        HIP_TRY(launch_exchange(t, par, c.cfg.steps, s));
       }
+      HIP_TRY(hipEventRecord(side.e[ci], s));
+      HIP_TRY(hipStreamWaitEvent(cs, side.e[ci], 0));
     }
     return KFP_OK;
   };
@@ -1778,7 +1803,9 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
       if (!config_supported(c)) continue;
       Plan *pl = nullptr;
       if ((st = get_plan(geo, c, &pl))) return st;
-      if ((st = load_instance(*pl, u0, f, nullptr, tr == KFP_ROBIN ? p : 1.0))) return st;
+      if ((st = load_instance(*pl, u0, f, nullptr, tr == KFP_ROBIN ? p : 1.0,
+                              tr == KFP_ROBIN ? p : 1.0)))
+        return st;
       if (geo.J > 1) HIP_TRY(launch_fill(pl->lam0.p, (size_t)2 * (geo.J - 1) * geo.nt * geo.nx, 0.0, pl->cs));
       const StepTables t = pl->dt.view();
       auto run = [&](int nsteps) -> kfp_status {
@@ -1845,12 +1872,42 @@ kfp_status kfp_swr_solve(const kfp_grid *g, const double *u0, const double *f, c
                          double *lambda_out, kfp_swr_stats *stats, void *stream) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
-  return swr_solve_impl(g, u0, f, s, J, overlap, tr, p, tol, max_iter, lambda_init, uT,
+  return swr_solve_impl(g, u0, f, s, J, overlap, tr, p, p, tol, max_iter, lambda_init, uT,
                         lambda_out, stats, (hipStream_t)stream);
 }
 
+kfp_status kfp_swr_solve_pq(const kfp_grid *g, const double *u0, const double *f,
+                            const double *s, int32_t J, int32_t overlap, int32_t tr, double p,
+                            double q, double tol, int32_t max_iter, const double *lambda_init,
+                            double *uT, double *lambda_out, kfp_swr_stats *stats,
+                            void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (tr == KFP_ROBIN && !(q > 0.0 && std::isfinite(q)))
+    return fail(KFP_EINVAL, "Robin transmission needs q > 0 (got %g)", q);
+  return swr_solve_impl(g, u0, f, s, J, overlap, tr, p, q, tol, max_iter, lambda_init, uT,
+                        lambda_out, stats, (hipStream_t)stream);
+}
+
+static kfp_status u0_guess_impl(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
+                                int32_t tr, double p, double q, double *lambda, void *stream);
+
 kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
                         int32_t tr, double p, double *lambda, void *stream) {
+  return u0_guess_impl(g, u0, J, overlap, tr, p, p, lambda, stream);
+}
+
+kfp_status kfp_u0_guess_pq(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
+                           int32_t tr, double p, double q, double *lambda, void *stream) {
+  if (tr == KFP_ROBIN && !(q > 0.0 && std::isfinite(q))) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    return fail(KFP_EINVAL, "Robin transmission needs q > 0 (got %g)", q);
+  }
+  return u0_guess_impl(g, u0, J, overlap, tr, p, q, lambda, stream);
+}
+
+static kfp_status u0_guess_impl(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
+                                int32_t tr, double p, double q, double *lambda, void *stream) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
@@ -1861,7 +1918,8 @@ kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t 
   Plan *pl = nullptr;
   if ((st = get_plan(geo, choose_config(geo), &pl))) return st;
   if ((st = sync_in((hipStream_t)stream, *pl))) return st;
-  HIP_TRY(launch_u0_guess(u0, geo.nx, geo.nt, J, pl->ab.p, tr, p, 2.0 / geo.nv, lambda, pl->cs));
+  HIP_TRY(launch_u0_guess(u0, geo.nx, geo.nt, J, pl->ab.p, tr, p, q, 2.0 / geo.nv, lambda,
+                          pl->cs));
   return sync_out((hipStream_t)stream, *pl);
 }
 
@@ -1961,7 +2019,7 @@ kfp_status kfp_debug_tables(const kfp_grid *g, int32_t J, int32_t overlap, int32
   if (waves < 1 || waves > 16) return fail(KFP_EINVAL, "waves must be in 1..16");
   if (!sub_info || !rows || !segs || !reds || !mat) return fail(KFP_EINVAL, "NULL output");
   HostTables h;
-  add_instance(geo, p, waves, 0, h);
+  add_instance(geo, p, p, waves, 0, h);
   const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt, r = dt / (hv * hv);
   for (int j = 0; j < J; ++j) {
     const SubDev &d = h.subs[j];

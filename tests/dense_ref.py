@@ -79,11 +79,13 @@ def spacetime_mono(u0, f, T, nt, s=None):
     return out
 
 
-def interface_data(U, a, b, nv, transmission, p):
+def interface_data(U, a, b, nv, transmission, p, q=None):
     """Interface variables (6.7) of a glued field history U [nt+1][nv+1][nx]
     for the partition a, b: plane 2j = Q_2 U at a_{j+1}, plane 2j+1 = Q_1 U at
-    b_j, levels 1..nt.  Q = I (Dirichlet) or Q_1 = p + d/dv, Q_2 = p - d/dv
-    with one-sided differences pointing into the subdomain that receives it."""
+    b_j, levels 1..nt.  Q = I (Dirichlet) or Q_1 = p + d/dv, Q_2 = q - d/dv
+    (q = p unless given) with one-sided differences pointing into the
+    subdomain that receives it."""
+    q = p if q is None else q
     hv = 2.0 / nv
     J = len(a)
     nt = U.shape[0] - 1
@@ -96,6 +98,6 @@ def interface_data(U, a, b, nv, transmission, p):
                 lam[2 * j, n - 1] = U[n, al]
                 lam[2 * j + 1, n - 1] = U[n, be]
             else:
-                lam[2 * j, n - 1] = p * U[n, al] - (U[n, al + 1] - U[n, al]) / hv
+                lam[2 * j, n - 1] = q * U[n, al] - (U[n, al + 1] - U[n, al]) / hv
                 lam[2 * j + 1, n - 1] = p * U[n, be] + (U[n, be] - U[n, be - 1]) / hv
     return lam

@@ -131,6 +131,33 @@ def test_error_equation_and_initial_guess():
     assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=0)
 
 
+@pytest.mark.parametrize("pq", [(11.0, 2.5), (0.8, 6.0)])
+def test_two_sided_robin_matches_oracle(pq):
+    """OSWR(p,q) of Section 6.4.2: fixed iterations and converged solves."""
+    p, q = pq
+    nx, nv, nt, T, J, o = 80, 96, 40, 0.25, 4, 2
+    u0, f = inputs.random_fields(31, nx, nv)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, R, p=p, q=q, tol=1e-300, max_iter=4)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, R, p=p, q=q, tol=1e-300,
+                                max_iter=4, want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, R, p=p, q=q, tol=1e-11, max_iter=1000)
+    uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, R, p=p, q=q, tol=1e-11,
+                              max_iter=1000)
+    assert st.iters == ref.iters
+    assert rel(host(uT), ref.uT) <= 1e-10
+    assert rel(host(uT), oracle.mono_solve(u0, f, T, nt)) <= 1e-10
+    g = host(kfp.u0_guess(dev(u0), nt, J, o, R, p=p, q=q))
+    assert rel(g, oracle.u0_guess(u0, nt, J, o, R, p=p, q=q)) <= 1e-14
+    # the batch takes q per instance
+    out, rc = kfp.swr_batch([dict(u0=dev(u0), f=dev(f), T=T, nt=nt, J=J, overlap=o, tr=R, p=p,
+                                  q=q)], tol=1e-11, max_iter=1000)
+    assert rc == 0 and out[0][2].iters == ref.iters
+    assert rel(host(out[0][0]), ref.uT) <= 1e-10
+
+
 def test_u0_guess_matches_oracle():
     nx, nv, nt = 80, 64, 20
     u0, _ = inputs.random_fields(4, nx, nv)

@@ -183,21 +183,25 @@ def test_swr_single_subdomain_is_monodomain(tr):
     assert np.array_equal(res.uT, m)
 
 
-@pytest.mark.parametrize("tr,J,o,p", [(D, 2, 4, 0.0), (D, 4, 3, 0.0), (R, 2, 2, 4.0),
-                                      (R, 4, 1, 2.0), (R, 3, 5, 8.0)])
-def test_swr_converges_to_monodomain(tr, J, o, p):
+@pytest.mark.parametrize("tr,J,o,p,q", [(D, 2, 4, 0.0, None), (D, 4, 3, 0.0, None),
+                                        (R, 2, 2, 4.0, None), (R, 4, 1, 2.0, None),
+                                        (R, 3, 5, 8.0, None), (R, 3, 2, 11.0, 2.5),
+                                        (R, 4, 2, 0.7, 6.0)])
+def test_swr_converges_to_monodomain(tr, J, o, p, q):
+    """Also two-sided OSWR(p,q): any p, q > 0 keep the monodomain solution as
+    the fixed point (Section 6.3)."""
     nx, nv, nt, T = 16, 24, 20, 0.2
     u0, f = inputs.random_fields(11, nx, nv)
     m = oracle.mono_solve(u0, f, T, nt)
-    res = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-13, max_iter=500)
+    res = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-13, max_iter=500)
     assert res.status == 0
     assert rel_l2(res.uT, m) <= 1e-10
     # (6.12) over the closed overlap equals the maximum at its two end nodes
     assert np.allclose(res.ovl_hist, res.res_hist, rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("tr,p", [(D, 0.0), (R, 3.0)])
-def test_swr_fixed_point_is_monodomain_trace_dense(tr, p):
+@pytest.mark.parametrize("tr,p,q", [(D, 0.0, None), (R, 3.0, None), (R, 3.0, 0.7)])
+def test_swr_fixed_point_is_monodomain_trace_dense(tr, p, q):
     """Assemble the affine SWR map lambda^k = K lambda^{k-1} + c densely (K
     column by column from unit traces with zero data), solve (I-K) lam = c,
     and compare with the interface data of the dense space-time monodomain
@@ -215,13 +219,14 @@ def test_swr_fixed_point_is_monodomain_trace_dense(tr, p):
     for col in range(n):
         e = np.zeros(n)
         e[col] = 1.0
-        r = oracle.swr_solve(z, z, T, nt, J, o, tr, p=p, tol=0.0, max_iter=1,
+        r = oracle.swr_solve(z, z, T, nt, J, o, tr, p=p, q=q, tol=0.0, max_iter=1,
                              lambda_init=e.reshape(shape))
         K[:, col] = r.lam.reshape(-1)
-    c = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=0.0, max_iter=1).lam.reshape(-1)
+    c = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=0.0,
+                         max_iter=1).lam.reshape(-1)
     lam_star = np.linalg.solve(np.eye(n) - K, c)
     U = dense_ref.spacetime_mono(u0, f, T, nt)
-    lam_mono = dense_ref.interface_data(U, a, b, nv, tr, p).reshape(-1)
+    lam_mono = dense_ref.interface_data(U, a, b, nv, tr, p, q).reshape(-1)
     assert np.allclose(lam_star, lam_mono, rtol=0, atol=1e-11 * np.abs(lam_mono).max())
     rho = np.abs(np.linalg.eigvals(K)).max()
     assert rho < 1.0
@@ -229,9 +234,12 @@ def test_swr_fixed_point_is_monodomain_trace_dense(tr, p):
     # the iterates shrink without a rounding floor); the operator is far from
     # normal (Volterra structure in time), so the ratio approaches rho from above
     e0 = rng.standard_normal(shape)
-    r = oracle.swr_solve(z, z, T, nt, J, o, tr, p=p, tol=0.0, max_iter=60, lambda_init=e0)
+    r = oracle.swr_solve(z, z, T, nt, J, o, tr, p=p, q=q, tol=0.0, max_iter=60,
+                         lambda_init=e0)
     h = r.res_hist
-    ratio = h[-1] / h[-2]
+    # two iterations at a time: with p != q the two interface directions
+    # contract differently and the one-step ratios alternate around rho
+    ratio = np.sqrt(h[-1] / h[-3])
     assert 0.97 * rho < ratio < 1.12 * rho, (ratio, rho)
 
 
@@ -283,6 +291,16 @@ def test_u0_guess_is_compatible_trace():
     lam = oracle.u0_guess(u0, nt, 2, 2, R, p=4.0)
     U = np.repeat(u0[None], nt + 1, axis=0)
     ref = dense_ref.interface_data(U, a, b, nv, R, 4.0)
+    assert np.allclose(lam, ref, rtol=0, atol=1e-12)
+
+
+def test_u0_guess_two_sided():
+    nx, nv, nt = 8, 16, 5
+    u0, _ = inputs.random_fields(8, nx, nv)
+    a, b = oracle.partition(nv, 4, 2)
+    lam = oracle.u0_guess(u0, nt, 4, 2, R, p=4.0, q=1.5)
+    U = np.repeat(u0[None], nt + 1, axis=0)
+    ref = dense_ref.interface_data(U, a, b, nv, R, 4.0, 1.5)
     assert np.allclose(lam, ref, rtol=0, atol=1e-12)
 
 
