@@ -186,6 +186,23 @@ kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, d
 kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps);
 
 /*
+ * kfp_set_launch / kfp_get_launch -- the same with lane groups: a march
+ * configuration (steps >= 1) may split each wavefront into `groups` (1, 2
+ * or 4) lane groups, each holding its own segment for a tile of 64/groups
+ * x-columns, so that a workgroup holds waves * groups segments: subdomains
+ * taller than 8 wavefronts of register segments then still march on chip.
+ * The halo must leave columns valid: 2 * steps * groups < 64.  The
+ * general kernel (steps = 0) takes groups = 1.  kfp_set_config(w, s, k) is
+ * kfp_set_launch(w, 1, s, k); kfp_get_config reports waves, seg_max and
+ * steps of the configuration kfp_get_launch reports in full (a tuned or
+ * built-in choice may use lane groups).  KFP_EINVAL if not compiled.
+ */
+kfp_status kfp_set_launch(int32_t waves, int32_t groups, int32_t seg_max, int32_t steps);
+kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                          int32_t *waves_out, int32_t *groups_out, int32_t *seg_max_out,
+                          int32_t *steps_out);
+
+/*
  * kfp_set_pipeline -- overlap SWR iterations in time.  Iteration k at a
  * time block needs only iteration k-1's traces of that block (the method is
  * causal in time), so iteration k+1 can march d blocks behind iteration k;

@@ -20,6 +20,7 @@ from .binding import (  # noqa: F401
     column_stats,
     destandardize,
     get_config,
+    get_launch,
     lib_path,
     load_library,
     mono_solve,

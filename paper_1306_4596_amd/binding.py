@@ -99,6 +99,8 @@ def load_library():
     pi = ctypes.POINTER(i32)
     lib.kfp_tune.argtypes = [G, i32, i32, i32, f64, pi, pi, pi, vp]
     lib.kfp_set_config.argtypes = [i32, i32, i32]
+    lib.kfp_set_launch.argtypes = [i32, i32, i32, i32]
+    lib.kfp_get_launch.argtypes = [G, i32, i32, i32, pi, pi, pi, pi]
     lib.kfp_set_pipeline.argtypes = [i32]
     lib.kfp_set_kernel_timing.argtypes = [i32]
     lib.kfp_get_config.argtypes = [G, i32, i32, i32, pi, pi, pi]
@@ -109,7 +111,7 @@ def load_library():
     lib.kfp_release_workspace.restype = None
     for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
-                 "kfp_set_config", "kfp_set_pipeline", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
+                 "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -293,9 +295,10 @@ def tune(nx, nv, nt, T, J, overlap, transmission, p=1.0, stream=None):
     return w.value, s.value, k.value
 
 
-def set_config(waves=0, seg_max=0, steps=1):
-    """Forces a launch configuration (waves=0: automatic)."""
-    _check(load_library().kfp_set_config(int(waves), int(seg_max), int(steps)))
+def set_config(waves=0, seg_max=0, steps=1, groups=1):
+    """Forces a launch configuration (waves=0: automatic); groups > 1 splits
+    each wavefront of the march kernel into lane groups."""
+    _check(load_library().kfp_set_launch(int(waves), int(groups), int(seg_max), int(steps)))
 
 
 def get_config(nx, nv, nt, T, J, overlap, transmission):
@@ -305,6 +308,16 @@ def get_config(nx, nv, nt, T, J, overlap, transmission):
     _check(load_library().kfp_get_config(ctypes.byref(g), int(J), int(overlap), int(transmission),
                                          ctypes.byref(w), ctypes.byref(s), ctypes.byref(k)))
     return w.value, s.value, k.value
+
+
+def get_launch(nx, nv, nt, T, J, overlap, transmission):
+    """(waves, seg_max, steps, groups) a solve of this shape would use."""
+    w, g_, s, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_get_launch(ctypes.byref(g), int(J), int(overlap), int(transmission),
+                                         ctypes.byref(w), ctypes.byref(g_), ctypes.byref(s),
+                                         ctypes.byref(k)))
+    return w.value, s.value, k.value, g_.value
 
 
 def subdomain_rows(nx, nv, nt, T, J, overlap, transmission):

@@ -152,9 +152,11 @@ bool step_config_supported(int waves, int seg_max);
 // Multi-step launch: advances every item by min(S, nt - n0) steps from level
 // n0, reading state parity `src` (u0 when n0 == 0) and writing 1 - src; the
 // tiles carry a halo of H >= S columns on both sides.
-hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int S, int H,
-                        int src, int par, int grid, hipStream_t s);
-bool march_config_supported(int waves, int seg_max);
+// groups: lane groups per wavefront (each holds its own segment for a tile
+// of 64/groups columns); 2 * H * groups < 64
+hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int n0, int S,
+                        int H, int src, int par, int grid, hipStream_t s);
+bool march_config_supported(int waves, int groups, int seg_max);
 // Exchange pass of the multi-step path: traces (6.9)/(6.11) of every level
 // and the residual (6.12) from the interface-node value planes.
 // S: steps per launch (pipelined tables: the exchange covers the levels of

@@ -439,7 +439,7 @@ enum Dir : int { DIR_UP = 0, DIR_LO = 1, DIR_MIX = 2 };
 
 // Segments longer than this keep only the state in registers and re-read
 // the (cache-resident) source rows every step.
-constexpr int kFRegMax = 24;
+constexpr int kFRegMax = 33;
 
 // Upper bound of the steps one multi-step launch takes (checked by the host).
 constexpr int kMaxStepsPerLaunch = 24;
@@ -482,29 +482,44 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
   });
 }
 
-template <int SEG, int NW>
+// G lane groups per wavefront: a wavefront holds G segments of a subdomain,
+// each for a tile of 64/G x-columns (lanes g*64/G .. (g+1)*64/G - 1 hold
+// segment w*G + g).  G = 1 is one segment per wavefront over 64 columns;
+// G > 1 lets a workgroup hold G times the rows of one whose wavefronts each
+// hold a single segment, for subdomains too tall for the register file of
+// one 64-column tile, at the cost of a narrower tile.  The upwind shift runs
+// across the whole wavefront: the edge lane of a group then receives a
+// value of the neighbouring group, which is halo like the zero the edge
+// lane of the wavefront receives, and the valid lanes never see it.
+template <int SEG, int NW, int G>
 __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in, int S, int H,
                                                         int src_in, int par) {
+  static_assert(G == 1 || G == 2 || G == 4, "lane groups");
+  constexpr int NV = NW * G;  // segments per workgroup
+  constexpr int TW = 64 / G;  // tile columns
   // segment end values for the reduced system, double-buffered by step
   // parity: a step's writes never meet the previous step's reads, so one
   // barrier per step suffices
-  __shared__ double sh_first[2][NW][64];
-  __shared__ double sh_last[2][NW][64];
-  __shared__ double sh_sep[2][NW][64];
+  __shared__ double sh_first[2][NV][TW];
+  __shared__ double sh_last[2][NV][TW];
+  __shared__ double sh_sep[2][NV][TW];
   // boundary data of the launch's steps (low end, high end), staged once so
   // that the step loop issues no vector loads: its stores then never hold a
   // step up, since nothing in the loop waits on vector memory
-  __shared__ double sh_bd[2][kMaxStepsPerLaunch][64];
-  // the work item's coefficient rows (per wave), reduced system and source
-  // factors, staged once per item: the step loop then issues no scalar
-  // loads either, and LDS reads (returned in order) can be waited on one by
-  // one, so they are issued well ahead of their use
-  __shared__ MarchCoef sh_mc[NW][SEG];
-  __shared__ RedCoef sh_rc[NW];
-  __shared__ double sh_rinv[(NW - 1) * (NW - 1) + 1];
+  __shared__ double sh_bd[2][kMaxStepsPerLaunch][TW];
+  // the work item's coefficient rows (per segment), reduced system and
+  // source factors, staged once per item: the step loop then issues no
+  // scalar loads either, and LDS reads (returned in order) can be waited on
+  // one by one, so they are issued well ahead of their use
+  __shared__ MarchCoef sh_mc[NV][SEG];
+  __shared__ RedCoef sh_rc[NV];
+  __shared__ double sh_rinv[(NV - 1) * (NV - 1) + 1];
   __shared__ double sh_g[NW][kMaxStepsPerLaunch];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gh = G == 1 ? 0 : lane / TW;  // lane group
+  const int tl = G == 1 ? lane : lane % TW;  // column within the tile
+  const int v = w * G + gh;               // this lane's segment
   KConst<Item> *items = as_const(t.items);
   KConst<SubDev> *subs = as_const(t.subs);
   KConst<InstDev> *insts = as_const(t.inst);
@@ -525,10 +540,10 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
     const int nt = I->nt;
     if (n0 >= nt) continue;
     const int steps = min(min(S, kMaxStepsPerLaunch), nt - n0);  // S is checked by the host
-    const int rel = lane - H;
+    const int rel = tl - H;
     int col = (x0 + rel) % nx;
     if (col < 0) col += nx;
-    const bool out = rel >= 0 && rel < 64 - 2 * H && x0 + rel < nx;
+    const bool out = rel >= 0 && rel < TW - 2 * H && x0 + rel < nx;
     const size_t plane = (size_t)nt * nx;
     const int n_rows = sd->n;
     const int row_off = sd->row_off;
@@ -542,34 +557,47 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
     const double rr = I->r;
     const bool robin = I->tr == 1;
     const int P = sd->P;
-    const bool active = w < P;
-    const bool last = w == P - 1;
-    const int k0 = last ? sd->pad : 0;  // first real row in this wave's registers
-    const int base = w * SEG - k0;      // local row of register k is base + k
+    const int pad = sd->pad;
+    // segments of this wavefront that hold rows: w*G .. w*G + nseg - 1
+    const int nseg = min(G, P - w * G);
+    const bool wave_active = nseg > 0;
+    const bool active = v < P;
+    const bool last = v == P - 1;
+    // the last segment ends on the subdomain's last row: its first `pad`
+    // registers repeat rows of the segment before it
+    auto first_reg = [&](int vv) { return vv == P - 1 ? pad : 0; };
+    auto seg_base = [&](int vv) { return vv * SEG - first_reg(vv); };
+    const int k0 = first_reg(v);  // first real row in this lane's registers
+    const int base = seg_base(v);  // local row of register k is base + k
     // rows with local index >= vsplit have v >= 0: upwind neighbour at m-1
     const int vsplit = sd->vsplit - base;
-    const int dir = vsplit <= 0 ? DIR_LO : (vsplit >= SEG ? DIR_UP : DIR_MIX);
+    // one direction for the whole wavefront when all its segments agree
+    const int vs_first = sd->vsplit - seg_base(w * G);
+    const int vs_last = sd->vsplit - seg_base(w * G + (nseg > 0 ? nseg - 1 : 0));
+    const int dir = vs_first <= 0 ? DIR_LO : (vs_last >= SEG ? DIR_UP : DIR_MIX);
     const int lo_kind = sd->lo_kind, hi_kind = sd->hi_kind;
     const int lam_lo = sd->lam_lo, lam_hi = sd->lam_hi;
     const int out_hi_plane = sd->out_hi_plane, out_hi_row = sd->out_hi_row;
     const int out_lo_plane = sd->out_lo_plane, out_lo_row = sd->out_lo_row;
-    // end rows taking boundary data: row 0 in wave 0, row n-1 in the last wave
-    const bool lo_end = active && w == 0 && lo_kind != END_PHYS;
+    // end rows taking boundary data: row 0 in segment 0, row n-1 in the last
+    const bool lo_end = active && v == 0 && lo_kind != END_PHYS;
     const bool hi_end = active && last && hi_kind != END_PHYS;
     KGlob<const double> *lin_lo = lin + (size_t)(lam_lo > 0 ? lam_lo : 0) * plane + col;
     KGlob<const double> *lin_hi = lin + (size_t)(lam_hi > 0 ? lam_hi : 0) * plane + col;
-    // staging: each wave copies its own rows, factors and boundary data
-    // (written and read by the same wave: no barrier); the reduced system is
-    // copied by wave 0 and first read after the step's first barrier (the
-    // previous item's last reads ended at its last step's second barrier)
-    const MarchCoef *mc = sh_mc[w];
-    if (active) {
-      KGlob<const double> *ct = as_glob((const double *)(t.mrows + sd->tab + w * SEG));
-      double *cs = reinterpret_cast<double *>(sh_mc[w]);
-      constexpr int NCW = SEG * (int)(sizeof(MarchCoef) / sizeof(double));
+    // staging: each wave copies its own segments' rows, factors and boundary
+    // data (written and read by the same wave: no barrier); the reduced
+    // system is copied by wave 0 and first read after the step's first
+    // barrier (the previous item's last reads ended at its last step's
+    // second barrier)
+    const MarchCoef *mc = sh_mc[v];
+    if (wave_active) {
+      KGlob<const double> *ct = as_glob((const double *)(t.mrows + sd->tab + w * G * SEG));
+      double *cs = reinterpret_cast<double *>(sh_mc[w * G]);
+      constexpr int NDB = (int)(sizeof(MarchCoef) / sizeof(double));
+      const int ncw = nseg * SEG * NDB;  // rows past the table's end are not read
 #pragma unroll
-      for (int e0 = 0; e0 < NCW; e0 += 64)
-        if (e0 + lane < NCW) cs[e0 + lane] = ct[e0 + lane];
+      for (int e0 = 0; e0 < G * SEG * NDB; e0 += 64)
+        if (e0 + lane < ncw) cs[e0 + lane] = ct[e0 + lane];
       KGlob<const double> *gt = as_glob(I->g);
       if (lane < steps) sh_g[w][lane] = gt[n0 + lane];
       if (w == 0 && P > 1) {
@@ -581,9 +609,9 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
         for (int e = lane; e < (P - 1) * (P - 1); e += 64) sh_rinv[e] = rv[e];
       }
       if (lo_end)
-        for (int s = 0; s < steps; ++s) sh_bd[0][s][lane] = lin_lo[(size_t)(n0 + s) * nx];
+        for (int s = 0; s < steps; ++s) sh_bd[0][s][tl] = lin_lo[(size_t)(n0 + s) * nx];
       if (hi_end)
-        for (int s = 0; s < steps; ++s) sh_bd[1][s][lane] = lin_hi[(size_t)(n0 + s) * nx];
+        for (int s = 0; s < steps; ++s) sh_bd[1][s][tl] = lin_hi[(size_t)(n0 + s) * nx];
     }
     SegRegs<SEG> d, fs;
     if (active) {
@@ -596,18 +624,47 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
     }
     const double lo_scale = lo_end ? mc[k0].fab * (lo_kind == END_ROBIN ? 1.0 : rr) : 0.0;
     const double hi_scale = hi_end ? mc[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : rr) : 0.0;
+    // register `pad` of every lane (a wave-uniform index): the first real row
+    // of the last segment
+    auto first_value = [&](const SegRegs<SEG> &dd) {
+      if constexpr (G == 1) {
+        return dd.get(k0);
+      } else {
+        const double a = dd.get(pad);
+        return k0 != 0 ? a : dd.template ld<0>();
+      }
+    };
+    // value of local row R to *p from the lanes holding it: the segments of
+    // this wave are walked with wave-uniform register indices
+    auto put_row = [&](int R, KGlob<double> *p) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int vv = w * G + g;
+        if (vv < P) {
+          const int kg = first_reg(vv);
+          const int r = R - seg_base(vv);
+          if (r >= kg && r < SEG) {
+            const double val = d.get(r);
+            if (gh == g && out) *p = val;
+          }
+        }
+      }
+    };
     for (int s = 0; s < steps; ++s) {
       const int n = n0 + s;
       double xlo = 0.0, xhi = 0.0;
-      // the direction split, segment count and wave index are re-derived
+      // the direction split, segment count and segment index are re-derived
       // each step, so that tests built on them are not kept as per-row
       // masks across the loop (they would not fit in scalar registers)
-      int vs = vsplit, Pq = P, wq = w;
-      asm volatile("" : "+s"(vs), "+s"(Pq), "+s"(wq));
+      int vs = vsplit, Pq = P, wq = v;
+      if constexpr (G == 1)
+        asm volatile("" : "+s"(vs), "+s"(Pq), "+s"(wq));
+      else
+        asm volatile("" : "+v"(vs), "+s"(Pq), "+v"(wq));
       if (active) {
         const double gn = sh_g[w][s];
-        const double blo = lo_end ? lo_scale * sh_bd[0][s][lane] : 0.0;
-        const double bhi = hi_end ? hi_scale * sh_bd[1][s][lane] : 0.0;
+        const double blo = lo_end ? lo_scale * sh_bd[0][s][tl] : 0.0;
+        const double bhi = hi_end ? hi_scale * sh_bd[1][s][tl] : 0.0;
         // transport + source + forward elimination, one pass
         if (dir == DIR_LO)
           march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
@@ -623,27 +680,27 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
           d.template st<k>(x);
         });
         if (Pq > 1) {
-          sh_first[s & 1][w][lane] = d.get(k0);
-          sh_last[s & 1][w][lane] = d.template ld<SEG - 2>();
-          sh_sep[s & 1][w][lane] = d.template ld<SEG - 1>();
+          sh_first[s & 1][v][tl] = first_value(d);
+          sh_last[s & 1][v][tl] = d.template ld<SEG - 2>();
+          sh_sep[s & 1][v][tl] = d.template ld<SEG - 1>();
         }
       }
       if (Pq > 1) {
         __syncthreads();
         if (active) {
           // reduced separator system, per column: right-hand sides D_r from
-          // LDS, then the two separators this wave borders (r = w-1, w) as
-          // dot products with rows of the precomputed inverse
+          // LDS, then the two separators this segment borders (r = v-1, v)
+          // as dot products with rows of the precomputed inverse
           const int m = Pq - 1;
           const double *Rl = sh_rinv + (wq > 0 ? wq - 1 : 0) * m;
           const double *Rh = sh_rinv + (wq < m ? wq : 0) * m;
           double xl = 0.0, xh = 0.0;
 #pragma unroll
-          for (int q = 0; q < NW - 1; ++q) {
+          for (int q = 0; q < NV - 1; ++q) {
             if (q < m) {
               const RedCoef &rq = sh_rc[q];
-              const double D = sh_sep[s & 1][q][lane] - rq.ra * sh_last[s & 1][q][lane] -
-                               rq.rc * sh_first[s & 1][q + 1][lane];
+              const double D = sh_sep[s & 1][q][tl] - rq.ra * sh_last[s & 1][q][tl] -
+                               rq.rc * sh_first[s & 1][q + 1][tl];
               xl = fma(Rl[q], D, xl);
               xh = fma(Rh[q], D, xh);
             }
@@ -658,28 +715,24 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
           d.template st<k>(fma(-mc[k].sl, xlo, fma(-mc[k].sr, xhi, d.template ld<k>())));
         });
         if (!last) d.template st<SEG - 1>(xhi);
-        // interface-node values of level n+1
+      }
+      // interface-node values of level n+1
+      if (wave_active) {
         const size_t lvl = (size_t)n * nx + col;
         if (out_hi_plane >= 0) {
           KGlob<double> *Vj = Vbase + (size_t)(out_hi_plane >> 1) * 6 * plane + lvl;
-          int r = out_hi_row - base;
-          if (r >= k0 && r < SEG && out) Vj[V_A_LO * plane] = d.get(r);
+          put_row(out_hi_row, Vj + V_A_LO * plane);
           if (robin) {
-            r = out_hi_row + 1 - base;
-            if (r >= k0 && r < SEG && out) Vj[V_A1_LO * plane] = d.get(r);
-            r = n_rows - 1 - base;
-            if (r >= k0 && r < SEG && out) Vj[V_B_LO * plane] = d.get(r);
+            put_row(out_hi_row + 1, Vj + V_A1_LO * plane);
+            put_row(n_rows - 1, Vj + V_B_LO * plane);
           }
         }
         if (out_lo_plane >= 0) {
           KGlob<double> *Vj = Vbase + (size_t)((out_lo_plane - 1) >> 1) * 6 * plane + lvl;
-          int r = out_lo_row - base;
-          if (r >= k0 && r < SEG && out) Vj[V_B_HI * plane] = d.get(r);
+          put_row(out_lo_row, Vj + V_B_HI * plane);
           if (robin) {
-            r = out_lo_row - 1 - base;
-            if (r >= k0 && r < SEG && out) Vj[V_B1_HI * plane] = d.get(r);
-            r = -base;
-            if (r >= k0 && r < SEG && out) Vj[V_A_HI * plane] = d.get(r);
+            put_row(out_lo_row - 1, Vj + V_B1_HI * plane);
+            put_row(0, Vj + V_A_HI * plane);
           }
         }
       }
@@ -948,28 +1001,32 @@ bool step_config_supported(int waves, int seg_max) {
   return false;
 }
 
+// (waves, seg_max, lane groups)
 #define KFP_MARCH_CONFIGS(X) \
-  X(1, 4) X(1, 8) X(1, 12) X(1, 16) X(1, 24) X(1, 32) \
-  X(2, 4) X(2, 8) X(2, 12) X(2, 16) X(2, 24) X(2, 32) \
-  X(4, 4) X(4, 6) X(4, 8) X(4, 12) X(4, 16) X(4, 20) X(4, 24) X(4, 32) \
-  X(8, 4) X(8, 6) X(8, 8) X(8, 10) X(8, 12) X(8, 14) X(8, 17) X(8, 20) X(8, 24) \
-  X(16, 4) X(16, 6) X(16, 8) X(16, 9) X(16, 10) X(16, 12) X(8, 33) X(8, 40)
+  X(1, 4, 1) X(1, 8, 1) X(1, 12, 1) X(1, 16, 1) X(1, 24, 1) X(1, 32, 1) \
+  X(2, 4, 1) X(2, 8, 1) X(2, 12, 1) X(2, 16, 1) X(2, 24, 1) X(2, 32, 1) \
+  X(4, 4, 1) X(4, 6, 1) X(4, 8, 1) X(4, 12, 1) X(4, 16, 1) X(4, 20, 1) X(4, 24, 1) X(4, 32, 1) \
+  X(8, 4, 1) X(8, 6, 1) X(8, 8, 1) X(8, 10, 1) X(8, 12, 1) X(8, 14, 1) X(8, 17, 1) X(8, 20, 1) \
+  X(8, 24, 1) X(8, 33, 1) \
+  X(16, 4, 1) X(16, 6, 1) X(16, 8, 1) X(16, 9, 1) X(16, 10, 1) X(16, 12, 1) \
+  X(4, 8, 2) X(8, 17, 2) X(8, 24, 2) X(8, 33, 2) X(8, 33, 4)
 
-bool march_config_supported(int waves, int seg_max) {
-#define KFP_CHECK(W, S) \
-  if (waves == W && seg_max == S) return true;
+bool march_config_supported(int waves, int groups, int seg_max) {
+#define KFP_CHECK(W, S, G) \
+  if (waves == W && seg_max == S && groups == G) return true;
   KFP_MARCH_CONFIGS(KFP_CHECK)
 #undef KFP_CHECK
   return false;
 }
 
-hipError_t launch_march(const StepTables &t, int waves, int seg_max, int n0, int S, int H,
-                        int src, int par, int grid, hipStream_t s) {
-  if (S < 1 || S > kMaxStepsPerLaunch || H < 1 || 2 * H >= 64) return hipErrorInvalidValue;
-#define KFP_LAUNCH(W, SM)                                                                   \
-  if (waves == W && seg_max == SM) {                                                       \
-    hipLaunchKernelGGL((march_kernel<SM, W>), dim3(grid), dim3(W * 64), 0, s, t, n0, S, H, \
-                       src, par);                                                          \
+hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int n0, int S,
+                        int H, int src, int par, int grid, hipStream_t s) {
+  if (groups < 1 || S < 1 || S > kMaxStepsPerLaunch || H < 1 || 2 * H * groups >= 64)
+    return hipErrorInvalidValue;
+#define KFP_LAUNCH(W, SM, G)                                                                \
+  if (waves == W && seg_max == SM && groups == G) {                                        \
+    hipLaunchKernelGGL((march_kernel<SM, W, G>), dim3(grid), dim3(W * 64), 0, s, t, n0, S, \
+                       H, src, par);                                                       \
     return hipGetLastError();                                                              \
   }
   KFP_MARCH_CONFIGS(KFP_LAUNCH)

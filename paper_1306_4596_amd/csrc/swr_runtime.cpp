@@ -144,11 +144,13 @@ struct Config {
   int waves = 0;
   int seg = 0;
   int steps = 0;
+  int groups = 1;  // march kernel: lane groups per wavefront (segments of 64/groups columns)
 };
 
 static bool config_supported(const Config &c) {
-  return c.steps == 0 ? step_config_supported(c.waves, c.seg)
-                      : (c.steps >= 1 && c.steps <= 24 && march_config_supported(c.waves, c.seg));
+  if (c.steps == 0) return c.groups == 1 && step_config_supported(c.waves, c.seg);
+  return c.steps >= 1 && c.steps <= 24 && 2 * c.steps * c.groups < 64 &&
+         march_config_supported(c.waves, c.groups, c.seg);
 }
 
 static int halo_of(const Config &c) { return c.steps > 1 ? c.steps : 1; }
@@ -156,15 +158,18 @@ static int halo_of(const Config &c) { return c.steps > 1 ? c.steps : 1; }
 static const int kWaves[] = {1, 2, 4, 8, 16};
 static const int kSegs[] = {8, 16, 24, 32, 48, 64};
 
-// Does a multi-step configuration hold every subdomain (P = ceil(n/SEG) <= waves)?
-static bool march_fits(int n_max, int waves, int seg) {
-  return seg >= 2 && (n_max + seg - 1) / seg <= waves;
+// Does a multi-step configuration hold every subdomain (P = ceil(n/SEG) <=
+// segments per workgroup, waves * groups)?
+static bool march_fits(int n_max, int waves, int seg, int groups = 1) {
+  return seg >= 2 && (n_max + seg - 1) / seg <= waves * groups;
 }
 
-// Smallest compiled multi-step segment length for `waves` wavefronts, 0 if none.
-static int march_seg_for(int n_max, int waves) {
+// Smallest compiled multi-step segment length for `waves` wavefronts of
+// `groups` lane groups, 0 if none.
+static int march_seg_for(int n_max, int waves, int groups = 1) {
   for (int sm = 2; sm <= 64; ++sm)
-    if (march_fits(n_max, waves, sm) && march_config_supported(waves, sm)) return sm;
+    if (march_fits(n_max, waves, sm, groups) && march_config_supported(waves, groups, sm))
+      return sm;
   return 0;
 }
 
@@ -194,18 +199,24 @@ static Config default_config(int n_max) {
   return c;
 }
 
-// Register march kernel by default: the fewest wavefronts (at most 8, where
-// the registers hold a segment without spilling) whose segment fits.
-// Default multi-step configuration: the fewest waves (at most 8) whose
-// register segment holds the subdomain, and 16 steps per launch (a 32-column
-// tile) unless the 48-column tiles of 8 steps already give every compute
-// unit two workgroups: then the smaller halo wins.  `items8`: work items of
-// the whole launch set at 8 steps per launch (0: unknown).
+// Default multi-step configuration: the fewest wavefronts (at most 8, where
+// the registers hold a segment without spilling) whose register segment
+// holds the subdomain, and 16 steps per launch (a 32-column tile) unless the
+// 48-column tiles of 8 steps already give every compute unit two
+// workgroups: then the smaller halo wins.  `items8`: work items of the whole
+// launch set at 8 steps per launch (0: unknown).
 static Config default_march(int n_max, long items8 = 0) {
   for (int w : kWaves) {
     if (w > 8) break;
     const int sm = march_seg_for(n_max, w);
     if (sm && (sm <= 24 || w == 8)) return Config{w, sm, items8 >= 2L * 256 ? 8 : 16};
+  }
+  // taller subdomains: eight wavefronts of two (then four) lane groups; the
+  // steps per launch are the measured best trade between the halo share of
+  // the narrower tile and the launches per window (6 of 32 columns, 4 of 16)
+  for (int g : {2, 4}) {
+    const int sm = march_seg_for(n_max, 8, g);
+    if (sm) return Config{8, sm, g == 2 ? 6 : 4, g};
   }
   return Config{};
 }
@@ -220,7 +231,8 @@ static const long kPipeItems = 128;
 static const long kPipeTarget = 1024;
 static bool g_ktime = false;  // time every step-kernel launch with HIP events
 
-// Tuning cache: a flat JSON object {"key": [waves, seg], ...}.
+// Tuning cache: a flat JSON object {"key": [waves, seg, steps, groups], ...}
+// (groups may be absent: 1).
 static std::string tune_path() {
   const char *e = getenv("KFP_TUNE_CACHE");
   if (e && *e) return e;
@@ -243,9 +255,10 @@ static std::map<std::string, Config> load_tune() {
     if (e == std::string::npos) break;
     std::string key = s.substr(pos + 1, e - pos - 1);
     Config c;
-    if (sscanf(s.c_str() + e + 1, " : [ %d , %d , %d ]", &c.waves, &c.seg, &c.steps) == 3 &&
-        config_supported(c))
-      out[key] = c;
+    const int got = sscanf(s.c_str() + e + 1, " : [ %d , %d , %d , %d ]", &c.waves, &c.seg,
+                           &c.steps, &c.groups);
+    if (got == 3) c.groups = 1;
+    if (got >= 3 && config_supported(c)) out[key] = c;
     pos = e + 1;
   }
   return out;
@@ -265,8 +278,8 @@ static void save_tune(const std::map<std::string, Config> &m) {
   fprintf(fp, "{\n");
   size_t i = 0;
   for (auto &kv : m)
-    fprintf(fp, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.seg,
-            kv.second.steps, ++i < m.size() ? "," : "");
+    fprintf(fp, "  \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves,
+            kv.second.seg, kv.second.steps, kv.second.groups, ++i < m.size() ? "," : "");
   fprintf(fp, "}\n");
   fclose(fp);
   rename(tmp.c_str(), path.c_str());
@@ -294,12 +307,13 @@ static std::map<std::string, Config> *g_tune = nullptr;
 static Config choose_config(const Geo &g) {
   if (g_forced.waves > 0) {
     Config c = g_forced;
-    if (c.steps >= 1 && !march_fits(g.n_max, c.waves, c.seg)) {
-      const int sm = march_seg_for(g.n_max, c.waves);
+    if (c.steps >= 1 && !march_fits(g.n_max, c.waves, c.seg, c.groups)) {
+      const int sm = march_seg_for(g.n_max, c.waves, c.groups);
       if (sm) {
         c.seg = sm;  // widen to the next compiled segment length
       } else {
         c.steps = 0;  // no register segment holds it: the general step kernel
+        c.groups = 1;
         c.seg = seg_for(g.n_max, c.waves);
       }
     }
@@ -309,8 +323,12 @@ static Config choose_config(const Geo &g) {
   }
   if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
   auto it = g_tune->find(tune_key(g));
-  if (it != g_tune->end() && (it->second.seg == 0 || segs_for(g.n_max, it->second.waves) <= it->second.seg))
-    return it->second;
+  if (it != g_tune->end()) {
+    const Config &c = it->second;
+    if (c.steps >= 1 ? march_fits(g.n_max, c.waves, c.seg, c.groups)
+                     : (c.seg == 0 || segs_for(g.n_max, c.waves) <= c.seg))
+      return c;
+  }
   if (g.J > 0 && g.nx > 0) {
     // overlapped iterations (see pipe_params) supply work items to spare:
     // then the smaller halo of 8 steps per launch
@@ -716,9 +734,11 @@ static void add_instance_cfg(const Geo &g, double p, double q, int waves, int se
 
 
 
-// Output tile width of a configuration: 64 lanes, minus the halo of the
-// multi-step kernel on both sides.
-static int tile_width(const Config &c) { return c.steps >= 1 ? 64 - 2 * halo_of(c) : 64; }
+// Output tile width of a configuration: 64 lanes (64/groups for the lane
+// groups of the multi-step kernel), minus its halo on both sides.
+static int tile_width(const Config &c) {
+  return c.steps >= 1 ? 64 / c.groups - 2 * halo_of(c) : 64;
+}
 
 static void make_items(const Geo &g, int sub_base, int width, std::vector<Item> &items) {
   // subdomain-fastest order: consecutive workgroups (and so the XCDs they are
@@ -931,8 +951,8 @@ static PipeParams pipe_params(const Geo &g, const Config &c) {
 
 static std::string plan_key(const Geo &g, const Config &c, int M) {
   char buf[200];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/s%d/k%d/M%d", g.nx, g.nv, g.nt, g.J, g.o, g.tr,
-           c.waves, c.seg, c.steps, M);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/g%d/s%d/k%d/M%d", g.nx, g.nv, g.nt, g.J, g.o,
+           g.tr, c.waves, c.groups, c.seg, c.steps, M);
   return buf;
 }
 
@@ -1074,7 +1094,7 @@ static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const
     } else {
       const int L = march_launches(nt, cfg);
       for (int l = 0; l < L; ++l)
-        HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg),
+        HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg),
                              l & 1, par, grid, s));
     }
   }
@@ -1140,7 +1160,7 @@ static kfp_status launch_pipe_chunk(Plan &pl, bool timed) {
   const Config &c = pl.cfg;
   for (int l = 0; l < pl.G; ++l) {
     if (timed) HIP_TRY(hipEventRecord(pl.tev[2 * l], pl.cs));
-    HIP_TRY(launch_march(t, c.waves, c.seg, 0, c.steps, halo_of(c), 0, 0, t.n_items, pl.cs));
+    HIP_TRY(launch_march(t, c.waves, c.groups, c.seg, 0, c.steps, halo_of(c), 0, 0, t.n_items, pl.cs));
     if (timed) HIP_TRY(hipEventRecord(pl.tev[2 * l + 1], pl.cs));
     HIP_TRY(launch_exchange(t, 0, c.steps, pl.cs));
     HIP_TRY(launch_pipe_tick(pl.ctl.p, pl.blk.p, pl.iter.p, pl.pres.p, pl.hist.p, pl.cs));
@@ -1405,7 +1425,7 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
   } else {
     const int L = march_launches(geo.nt, cfg);
     for (int l = 0; l < L; ++l)
-      HIP_TRY(launch_march(t, cfg.waves, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
+      HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
                            0, t.n_items, pl->cs));
   }
   double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
@@ -1478,7 +1498,8 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     const Config c = batch_config(bi[i].geo.n_max);
     int k = 0;
     for (; k < (int)cls.size(); ++k)
-      if (cls[k].cfg.waves == c.waves && cls[k].cfg.seg == c.seg && cls[k].cfg.steps == c.steps)
+      if (cls[k].cfg.waves == c.waves && cls[k].cfg.seg == c.seg && cls[k].cfg.steps == c.steps &&
+          cls[k].cfg.groups == c.groups)
         break;
     if (k == (int)cls.size()) {
       cls.emplace_back();
@@ -1649,7 +1670,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       } else {
         const int L = march_launches(c.nt_max, c.cfg);
         for (int l = 0; l < L; ++l)
-          HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.seg, l * c.cfg.steps, c.cfg.steps,
+          HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.groups, c.cfg.seg, l * c.cfg.steps, c.cfg.steps,
                                halo_of(c.cfg), l & 1, par, c.grid, s));
         HIP_TRY(launch_exchange(t, par, c.cfg.steps, s));
       }
@@ -1797,6 +1818,11 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
     if (sm)
       for (int k : {1, 4, 8, 12, 16}) cands.push_back(Config{w, sm, k});
   }
+  for (int g : {2, 4}) {
+    const int sm = march_seg_for(geo.n_max, 8, g);
+    if (sm)
+      for (int k : {2, 3, 4, 6, 8}) cands.push_back(Config{8, sm, k, g});
+  }
   {
     for (const Config &c : cands) {
       const int w = c.waves, sm = c.seg;
@@ -1813,8 +1839,8 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
           for (int n = 0; n < nsteps; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
         } else {
           for (int n = 0; n < nsteps; n += c.steps)
-            HIP_TRY(launch_march(t, w, sm, n, c.steps, halo_of(c), (n / c.steps) & 1, 0,
-                                 t.n_items, pl->cs));
+            HIP_TRY(launch_march(t, w, c.groups, sm, n, c.steps, halo_of(c), (n / c.steps) & 1,
+                                 0, t.n_items, pl->cs));
         }
         return KFP_OK;
       };
@@ -1952,23 +1978,29 @@ kfp_status kfp_set_pipeline(int32_t inflight) {
   return KFP_OK;
 }
 
-kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps) {
+kfp_status kfp_set_launch(int32_t waves, int32_t groups, int32_t seg_max, int32_t steps) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   if (waves == 0) {
     g_forced = Config{};
     return KFP_OK;
   }
-  const Config c{waves, seg_max, steps};
+  const Config c{waves, seg_max, steps, groups};
   if (!config_supported(c))
-    return fail(KFP_EINVAL, "configuration waves=%d seg_max=%d steps=%d is not compiled", waves,
-                seg_max, steps);
+    return fail(KFP_EINVAL,
+                "configuration waves=%d groups=%d seg_max=%d steps=%d is not compiled", waves,
+                groups, seg_max, steps);
   g_forced = c;
   return KFP_OK;
 }
 
-kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
-                          int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out) {
+kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps) {
+  return kfp_set_launch(waves, 1, seg_max, steps);
+}
+
+kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                          int32_t *waves_out, int32_t *groups_out, int32_t *seg_max_out,
+                          int32_t *steps_out) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
@@ -1976,9 +2008,15 @@ kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
   if (st) return st;
   const Config c = choose_config(geo);
   if (waves_out) *waves_out = c.waves;
+  if (groups_out) *groups_out = c.groups;
   if (seg_max_out) *seg_max_out = c.seg;
   if (steps_out) *steps_out = c.steps;
   return KFP_OK;
+}
+
+kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                          int32_t *waves_out, int32_t *seg_max_out, int32_t *steps_out) {
+  return kfp_get_launch(g, J, overlap, tr, waves_out, nullptr, seg_max_out, steps_out);
 }
 
 kfp_status kfp_subdomain_rows(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,

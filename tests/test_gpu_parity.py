@@ -270,6 +270,59 @@ def test_launch_configurations_interior_subdomains(waves, seg, steps, tr):
     assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
 
 
+# Lane groups: each wavefront holds `groups` segments of 64/groups columns.
+# The shapes fill some wavefronts, leave one with a single active group and
+# others idle, give every group count a tall case that only it holds, and
+# end the x-range in a ragged tile (or a grid narrower than one tile).
+GROUP_CASES = [
+    # nx, nv, J, (waves, seg, steps, groups)
+    (40, 64, 2, (4, 8, 1, 2)),
+    (40, 96, 3, (4, 8, 5, 2)),
+    (40, 64, 4, (4, 8, 15, 2)),
+    (50, 256, 2, (8, 17, 4, 2)),
+    (40, 512, 2, (8, 17, 8, 2)),
+    (40, 768, 3, (8, 24, 6, 2)),
+    (40, 1024, 2, (8, 33, 4, 2)),
+    (40, 1024, 2, (8, 33, 2, 4)),
+    (30, 2048, 2, (8, 33, 3, 4)),
+    (5, 512, 2, (8, 17, 4, 2)),
+]
+
+
+@pytest.mark.parametrize("case", GROUP_CASES)
+@pytest.mark.parametrize("tr", [D, R])
+def test_lane_group_configurations(case, tr):
+    nx, nv, J, (waves, seg, steps, groups) = case
+    nt, T, o = 12, 0.1, 2
+    print(f"lane groups nx={nx} nv={nv} J={J} cfg={(waves, seg, steps, groups)} tr={tr}",
+          flush=True)
+    u0, f = inputs.random_fields(31 + nv + J, nx, nv)
+    p = 4.0 if tr == R else 0.0
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3)
+    kfp.set_config(waves, seg, steps, groups=groups)
+    assert kfp.get_launch(nx, nv, nt, T, J, o, tr) == (waves, seg, steps, groups)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3,
+                                want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+def test_lane_groups_mono_and_default_choice():
+    """The monodomain march in lane groups, and the built-in choice for a
+    subdomain taller than eight wavefronts of register segments."""
+    nx, nv, nt, T = 70, 64, 20, 0.2
+    u0, f = inputs.random_fields(77, nx, nv)
+    ref = oracle.mono_solve(u0, f, T, nt)
+    kfp.set_config(4, 8, 6, groups=2)
+    assert rel(host(kfp.mono_solve(dev(u0), dev(f), T, nt)), ref) <= 1e-12
+    kfp.set_config(0)
+    got = kfp.get_launch(1024, 1024, 40, 0.01, 2, 2, R)
+    assert got[3] >= 2 and got[2] >= 1, got
+    got = kfp.get_launch(64, 2048, 40, 0.01, 2, 2, R)
+    assert got[3] == 4 and got[2] >= 1, got
+
+
 @pytest.mark.parametrize("steps", [0, 1, 8])
 def test_mono_multi_step_and_tiny_grids(steps):
     """The march kernel on grids narrower than its tiles (lanes wrap around
@@ -298,12 +351,13 @@ def test_graph_and_direct_launch_agree_and_are_deterministic():
 
 # ------------------------------------------------- overlapped iterations ----
 PIPE_CASES = [
-    # nx, nv, nt, T, J, o, tr, p, (waves, seg, steps) or None
+    # nx, nv, nt, T, J, o, tr, p, (waves, seg, steps[, groups]) or None
     (64, 64, 60, 0.3, 4, 2, R, 4.0, None),
     (64, 64, 200, 0.1, 2, 4, D, 0.0, None),
     (100, 96, 41, 0.2, 3, 3, R, 2.5, (4, 12, 4)),
     (70, 120, 30, 0.2, 8, 1, D, 0.0, (2, 12, 3)),
     (200, 128, 64, 0.25, 4, 5, R, 8.0, (4, 12, 8)),
+    (64, 256, 40, 0.2, 2, 2, R, 4.0, (8, 17, 4, 2)),
 ]
 
 
@@ -358,7 +412,7 @@ def test_overlapped_iterations_with_guess_and_restart():
 
 
 # ------------------------------------------------------------------ batch --
-@pytest.mark.parametrize("cfg", [(16, 32, 0), (16, 12, 6), (8, 24, 1)])
+@pytest.mark.parametrize("cfg", [(16, 32, 0), (16, 12, 6), (8, 24, 1), (8, 17, 4, 2)])
 def test_batch_matches_single_solves(cfg):
     specs = [
         (64, 64, 40, 0.2, 2, 2, R, 4.0),
@@ -392,6 +446,21 @@ def test_batch_matches_single_solves(cfg):
 
 
 # ------------------------------------------------------ full-size checks ----
+def test_tall_subdomains_full_size_fixed_iterations():
+    """1024 x 1024 with J = 2 (514-row subdomains, the built-in lane-group
+    march): two iterations against the oracle."""
+    nx = nv = 1024
+    nt, T = 40, 0.01
+    u0, f = inputs.random_fields(5, nx, nv)
+    print("tall subdomains oracle ...", flush=True)
+    ref = oracle.swr_solve(u0, f, T, nt, 2, 2, R, p=4.0, tol=1e-300, max_iter=2)
+    assert kfp.get_launch(nx, nv, nt, T, 2, 2, R)[3] >= 2
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 2, R, p=4.0, tol=1e-300, max_iter=2,
+                                want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+
+
 def test_cfg1_shape_fixed_iterations_short_window():
     """The 1024 x 1024, J = 8, overlap 2, Robin shape of the benchmark, with
     the same dt but a 200-step window: two iterations against the oracle."""
