@@ -31,6 +31,20 @@
  * node are one-sided first-order differences taken inside the subdomain that
  * owns the condition.
  *
+ * Without overlap (L = beta - alpha = 0, Section 6.3 allows it for OSWR) the
+ * two neighbours share the interface node.  Each one's row there is the
+ * balance of the half cell it owns next to the node, with the flux through
+ * the interface given by its Robin condition (the row linear finite elements
+ * with a lumped mass give for the natural Robin condition):
+ *   subdomain below, Q_1 u = (p + d/dv) u = lambda_1, flux d/dv u = lambda_1 - p u:
+ *     (h/2)(u^{n+1} - T u^n)/dt - (lambda_1 - p u) + (u_b - u_{b-1})/h = (h/2) s f
+ *   subdomain above, Q_2 u = (q - d/dv) u = lambda_2, flux d/dv u = q u - lambda_2.
+ * The neighbour's trace then needs no difference across the node: its
+ * derivative follows from its own Robin condition, so
+ *   Q_2 u_j = (p + q) u_j - lambda_1,   Q_1 u_{j+1} = (p + q) u_{j+1} - lambda_2
+ * (with p = q, lambda_new = 2p u - lambda_old).  At a fixed point the two
+ * half-cell rows add up to the monodomain row of the shared node.
+ *
  * Every linear system is solved by plain Thomas elimination, written out here
  * with divisions, rebuilt for every column and every step.
  */
@@ -174,6 +188,7 @@ typedef struct {
   int a, b;      /* node range of the subdomain (inclusive)            */
   int left_if;   /* 1 if the lower end a is an interface (j > 0)       */
   int right_if;  /* 1 if the upper end b is an interface (j < J-1)     */
+  int nonovl;    /* 1 if the interfaces have no overlap (shared nodes) */
 } sub_t;
 
 /* Solves one subdomain over the whole window for one SWR iteration.
@@ -188,6 +203,8 @@ static void solve_subdomain(int nx, int nv, int nt, double T, const double *u0,
   const int a = sd->a, b = sd->b, nn = b - a + 1;
   const int robL = sd->left_if && tr == KFP_O_ROBIN;
   const int robR = sd->right_if && tr == KFP_O_ROBIN;
+  const int nonovl = sd->nonovl && tr == KFP_O_ROBIN; /* half-cell interface rows */
+  const double hc = 2.0 * dt / hv;                    /* flux weight of a half-cell row */
   /* unknown nodes lo..hi; the others are fixed (zero, or Dirichlet data) */
   const int lo = robL ? a : a + 1;
   const int hi = robR ? b : b - 1;
@@ -203,7 +220,7 @@ static void solve_subdomain(int nx, int nv, int nt, double T, const double *u0,
     const double *LR = lamR ? lamR + (size_t)n * nx : NULL;
     for (int i = lo; i <= hi; ++i) {
       double *out = V + (size_t)(i - a) * nx;
-      if ((i == a && robL) || (i == b && robR)) continue; /* Robin rows */
+      if (!nonovl && ((i == a && robL) || (i == b && robR))) continue; /* Robin rows */
       double v = -1.0 + i * hv;
       transport_row(nx, v * dt / hx, U + (size_t)(i - a) * nx, out);
       for (int m = 0; m < nx; ++m) out[m] += g * f[(size_t)i * nx + m];
@@ -217,7 +234,17 @@ static void solve_subdomain(int nx, int nv, int nt, double T, const double *u0,
       for (int m = 0; m < nx; ++m) {
         for (int i = lo; i <= hi; ++i) {
           int k = i - lo;
-          if (i == a && robL) { /* Q_2 u = (q - d/dv) u at alpha */
+          if (i == a && robL && nonovl) { /* half cell above the shared node */
+            lo_[k] = 0.0;
+            di[k] = 1.0 + 2.0 * r + hc * q;
+            up[k] = -2.0 * r;
+            rhs[k] = V[(size_t)(i - a) * nx + m] + hc * LL[m];
+          } else if (i == b && robR && nonovl) { /* half cell below the shared node */
+            lo_[k] = -2.0 * r;
+            di[k] = 1.0 + 2.0 * r + hc * p;
+            up[k] = 0.0;
+            rhs[k] = V[(size_t)(i - a) * nx + m] + hc * LR[m];
+          } else if (i == a && robL) { /* Q_2 u = (q - d/dv) u at alpha */
             lo_[k] = 0.0;
             di[k] = q + 1.0 / hv;
             up[k] = -1.0 / hv;
@@ -295,7 +322,7 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
     free(b);
     return 1;
   }
-  if (J > 1 && tr == KFP_O_ROBIN && (o < 1 || !(p > 0) || !(q > 0))) {
+  if (J > 1 && tr == KFP_O_ROBIN && (!(p > 0) || !(q > 0))) {
     free(a);
     free(b);
     return 1;
@@ -313,6 +340,7 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
     sd[j].b = b[j];
     sd[j].left_if = j > 0;
     sd[j].right_if = j < J - 1;
+    sd[j].nonovl = o == 0;
     hist[j] = (double *)malloc(sizeof(double) * (size_t)(b[j] - a[j] + 1) * P);
   }
   int k = 0, status = 4;
@@ -335,10 +363,16 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
         const double *UR = hist[j + 1] + (size_t)n * nnR * nx; /* u_{j+1} */
         for (int m = 0; m < nx; ++m) {
           double uLa = UL[(size_t)(al - a[j]) * nx + m];
-          double uLa1 = UL[(size_t)(al + 1 - a[j]) * nx + m];
           double uRb = UR[(size_t)(be - a[j + 1]) * nx + m];
-          double uRb1 = UR[(size_t)(be - 1 - a[j + 1]) * nx + m];
-          if (tr == KFP_O_ROBIN) {
+          if (tr == KFP_O_ROBIN && o == 0) {
+            /* shared node: each side's derivative from its own condition */
+            const double l1 = lamOld[(size_t)(2 * j + 1) * P + (size_t)n * nx + m];
+            const double l2 = lamOld[(size_t)(2 * j) * P + (size_t)n * nx + m];
+            toR[(size_t)n * nx + m] = (p + q) * uLa - l1;
+            toL[(size_t)n * nx + m] = (p + q) * uRb - l2;
+          } else if (tr == KFP_O_ROBIN) {
+            double uLa1 = UL[(size_t)(al + 1 - a[j]) * nx + m];
+            double uRb1 = UR[(size_t)(be - 1 - a[j + 1]) * nx + m];
             toR[(size_t)n * nx + m] = q * uLa - (uLa1 - uLa) / hv;
             toL[(size_t)n * nx + m] = p * uRb + (uRb - uRb1) / hv;
           } else {

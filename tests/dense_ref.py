@@ -101,3 +101,47 @@ def interface_data(U, a, b, nv, transmission, p, q=None):
                 lam[2 * j, n - 1] = q * U[n, al] - (U[n, al + 1] - U[n, al]) / hv
                 lam[2 * j + 1, n - 1] = p * U[n, be] + (U[n, be] - U[n, be - 1]) / hv
     return lam
+
+
+def interface_data_nonoverlap(U, f, T, nv, a, b, p, q=None, s=None):
+    """Interface variables of the non-overlapping decomposition (a_{j+1} =
+    b_j: the neighbours share the node) that make the glued field history U
+    [nt+1][nv+1][nx] satisfy each subdomain's half-cell row at the shared node.
+    The row of the subdomain below (Robin condition (p + d/dv) u = lambda_1,
+    so the flux through the interface is lambda_1 - p u) times 2 dt/h_v:
+        (1 + 2r + 2 dt p / h_v) U_b - 2r U_{b-1} = (T U^{n-1})_b + dt s f_b + 2 dt/h_v lambda_1
+    and above (flux q u - lambda_2):
+        (1 + 2r + 2 dt q / h_v) U_a - 2r U_{a+1} = (T U^{n-1})_a + dt s f_a + 2 dt/h_v lambda_2.
+    Solved here for lambda from U; plane 2j = lambda_2 (for j+1), 2j+1 =
+    lambda_1 (for j), levels 1..nt."""
+    q = p if q is None else q
+    nt = U.shape[0] - 1
+    nx = U.shape[2]
+    hx, hv, dt = 1.0 / nx, 2.0 / nv, T / nt
+    r = dt / hv ** 2
+    hc = 2.0 * dt / hv
+    J = len(a)
+
+    def upwind(row, i):
+        nu = (-1.0 + i * hv) * dt / hx
+        if nu > 0:
+            nb = np.roll(row, 1)  # value at m-1
+        elif nu < 0:
+            nb = np.roll(row, -1)  # value at m+1
+        else:
+            nb = row
+        return (1.0 - abs(nu)) * row + abs(nu) * nb
+
+    lam = np.zeros((2 * (J - 1), nt, nx))
+    for j in range(J - 1):
+        c = b[j]
+        assert a[j + 1] == c
+        for n in range(1, nt + 1):
+            sn = 1.0 if s is None else s[n]
+            tu = upwind(U[n - 1, c], c)
+            src = dt * sn * f[c]
+            lam[2 * j + 1, n - 1] = ((1 + 2 * r + hc * p) * U[n, c] - 2 * r * U[n, c - 1]
+                                     - tu - src) / hc
+            lam[2 * j, n - 1] = ((1 + 2 * r + hc * q) * U[n, c] - 2 * r * U[n, c + 1]
+                                 - tu - src) / hc
+    return lam

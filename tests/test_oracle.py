@@ -186,7 +186,10 @@ def test_swr_single_subdomain_is_monodomain(tr):
 @pytest.mark.parametrize("tr,J,o,p,q", [(D, 2, 4, 0.0, None), (D, 4, 3, 0.0, None),
                                         (R, 2, 2, 4.0, None), (R, 4, 1, 2.0, None),
                                         (R, 3, 5, 8.0, None), (R, 3, 2, 11.0, 2.5),
-                                        (R, 4, 2, 0.7, 6.0)])
+                                        (R, 4, 2, 0.7, 6.0),
+                                        # no overlap (Section 6.3: OSWR only)
+                                        (R, 2, 0, 4.0, None), (R, 4, 0, 2.0, None),
+                                        (R, 3, 0, 11.0, 2.5)])
 def test_swr_converges_to_monodomain(tr, J, o, p, q):
     """Also two-sided OSWR(p,q): any p, q > 0 keep the monodomain solution as
     the fixed point (Section 6.3)."""
@@ -239,6 +242,51 @@ def test_swr_fixed_point_is_monodomain_trace_dense(tr, p, q):
     h = r.res_hist
     # two iterations at a time: with p != q the two interface directions
     # contract differently and the one-step ratios alternate around rho
+    ratio = np.sqrt(h[-1] / h[-3])
+    assert 0.97 * rho < ratio < 1.12 * rho, (ratio, rho)
+
+
+@pytest.mark.parametrize("p,q", [(3.0, None), (2.0, 5.5)])
+def test_swr_without_overlap_fixed_point_dense(p, q):
+    """Non-overlapping OSWR: the dense fixed point of the affine map (K from
+    unit traces) equals the traces that make the dense space-time monodomain
+    solution satisfy both half-cell rows at the shared node, the glued
+    iterate from those traces is the monodomain solution, and the observed
+    rate matches the spectral radius of K."""
+    nx, nv, nt, T, J, o = 4, 12, 3, 0.3, 2, 0
+    rng = np.random.default_rng(22)
+    u0 = rng.standard_normal((nv + 1, nx))
+    u0[0] = u0[-1] = 0
+    f = rng.standard_normal((nv + 1, nx))
+    a, b = oracle.partition(nv, J, o)
+    assert a[1] == b[0]
+    shape = (2 * (J - 1), nt, nx)
+    n = int(np.prod(shape))
+    z = np.zeros_like(u0)
+    K = np.zeros((n, n))
+    for col in range(n):
+        e = np.zeros(n)
+        e[col] = 1.0
+        r = oracle.swr_solve(z, z, T, nt, J, o, R, p=p, q=q, tol=0.0, max_iter=1,
+                             lambda_init=e.reshape(shape))
+        K[:, col] = r.lam.reshape(-1)
+    c = oracle.swr_solve(u0, f, T, nt, J, o, R, p=p, q=q, tol=0.0, max_iter=1).lam.reshape(-1)
+    lam_star = np.linalg.solve(np.eye(n) - K, c)
+    U = dense_ref.spacetime_mono(u0, f, T, nt)
+    lam_mono = dense_ref.interface_data_nonoverlap(U, f, T, nv, a, b, p, q)
+    assert np.allclose(lam_star, lam_mono.reshape(-1), rtol=0,
+                       atol=1e-11 * np.abs(lam_mono).max())
+    # the trace pair adds up to (p + q) times the shared node's value
+    qq = p if q is None else q
+    assert np.allclose(lam_mono[0] + lam_mono[1], (p + qq) * U[1:, b[0]], rtol=0, atol=1e-11)
+    one = oracle.swr_solve(u0, f, T, nt, J, o, R, p=p, q=q, tol=0.0, max_iter=1,
+                           lambda_init=lam_mono)
+    assert rel_l2(one.uT, U[-1]) <= 1e-12
+    rho = np.abs(np.linalg.eigvals(K)).max()
+    assert rho < 1.0
+    e0 = rng.standard_normal(shape)
+    r = oracle.swr_solve(z, z, T, nt, J, o, R, p=p, q=q, tol=0.0, max_iter=60, lambda_init=e0)
+    h = r.res_hist
     ratio = np.sqrt(h[-1] / h[-3])
     assert 0.97 * rho < ratio < 1.12 * rho, (ratio, rho)
 
@@ -350,6 +398,13 @@ def test_table1_orderings_at_coarsest_level():
         it[p] = r.iters
     assert it[4.0] - it[extra["PSTAR"]] == extra["P4_DELTA"]
     assert it[5.0] - it[extra["PSTAR"]] == extra["P5_DELTA"]
+    # without overlap (L = 0): more iterations than with L = 3 h_v, but not
+    # many more (the paper: 12 against 9 at this level)
+    r0 = oracle.swr_solve(z, z, T, nt, 2, 0, R, p=extra["PSTAR"], tol=1e-6, max_iter=100,
+                          lambda_init=lam0)
+    assert r0.status == 0
+    paper_l0 = rows[("OSWR_p", 0)][0] / rows[("OSWR_p", 3)][0]
+    assert 1.0 < r0.iters / it[extra["PSTAR"]] < 1.5 * paper_l0
     paper_ratio = rows[("OSWR_p", 3)][0] / rows[("CSWR", 3)][0]
     c = oracle.swr_solve(z, z, T, nt, 2, 3, D, tol=1e-6, max_iter=120, lambda_init=lam0)
     # CSWR has not converged after 120 iterations, far more than OSWR needs
