@@ -12,7 +12,11 @@ namespace kfp {
 enum EndKind : int {
   END_PHYS = 0,  // v = -1 or v = +1: zero Dirichlet data
   END_DIRI = 1,  // classical interface: the neighbour's trace is a fixed node
-  END_ROBIN = 2  // optimized interface: the end row is a Robin row
+  END_ROBIN = 2,  // optimized interface: the end row is a Robin row
+  // optimized interface without overlap (the two subdomains share the
+  // interface node): the end row is the node's half-cell balance, whose
+  // flux through the interface comes from the Robin condition
+  END_RFV = 3
 };
 
 // One SWR instance, resident in device memory.  All pointers are device
@@ -30,7 +34,7 @@ struct InstDev {
   double hv;                    // h_v
   int nx, nv, nt, tr;
   int active;                   // 0: frozen (converged), skipped by every kernel
-  int pad_;
+  int nonovl;                   // 1: no overlap (END_RFV interface rows)
 };
 
 // One subdomain of one instance.  Rows are local: 0 .. n-1 are the unknown

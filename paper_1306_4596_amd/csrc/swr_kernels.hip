@@ -80,7 +80,7 @@ __device__ __forceinline__ InstDev load_inst(KConst<InstDev> *p) {
   I.nt = p->nt;
   I.tr = p->tr;
   I.active = p->active;
-  I.pad_ = 0;
+  I.nonovl = p->nonovl;
   return I;
 }
 
@@ -97,10 +97,15 @@ __device__ __forceinline__ void traces_and_residual(const StepTables &t, const S
   const size_t lvl = (size_t)(n - 1) * nx;
   const double *self = S + (size_t)sd.row_off * nx;
   const bool robin = I.tr == 1;
+  // without overlap the derivative in Q comes from the subdomain's own Robin
+  // condition at the shared node: Q_2 u_j = (p+q) u_j - lambda_1 and
+  // Q_1 u_{j+1} = (p+q) u_{j+1} - lambda_2, with the traces it was solved with
   if (sd.out_hi_plane >= 0) {  // Q_2 u_j at a_{j+1}, eq. (6.9)
     const double ua = self[(size_t)sd.out_hi_row * nx + mc];
     double v = ua;
-    if (robin) {
+    if (I.nonovl) {
+      v = (I.p + I.q) * ua - lin[(size_t)sd.lam_hi * plane + lvl + mc];
+    } else if (robin) {
       const double ua1 = self[(size_t)(sd.out_hi_row + 1) * nx + mc];
       v = I.q * ua - (ua1 - ua) / I.hv;
     }
@@ -109,7 +114,9 @@ __device__ __forceinline__ void traces_and_residual(const StepTables &t, const S
   if (sd.out_lo_plane >= 0) {  // Q_1 u_j at b_{j-1}, eq. (6.11)
     const double ub = self[(size_t)sd.out_lo_row * nx + mc];
     double v = ub;
-    if (robin) {
+    if (I.nonovl) {
+      v = (I.p + I.q) * ub - lin[(size_t)sd.lam_lo * plane + lvl + mc];
+    } else if (robin) {
       const double ub1 = self[(size_t)(sd.out_lo_row - 1) * nx + mc];
       v = I.p * ub + (ub - ub1) / I.hv;
     }
@@ -137,6 +144,14 @@ __device__ __forceinline__ void traces_and_residual(const StepTables &t, const S
   }
 }
 
+// Weight of the incoming trace in the right-hand side of an end row taking
+// boundary data: a Robin row is the trace itself; a row next to a classical
+// interface node moves r times that node's value over; a half-cell row
+// (no overlap) gains the flux 2 dt / h_v times the trace.
+__device__ __forceinline__ double end_scale(int kind, const InstDev &I) {
+  return kind == END_ROBIN ? 1.0 : (kind == END_RFV ? 2.0 * I.r * I.hv : I.r);
+}
+
 // Right-hand side of local row i for step n -> n+1.
 __device__ __forceinline__ double row_rhs(const SubDev &sd, const InstDev &I, const RowCoef &c,
                                           int i, KGlob<const double> *src,
@@ -154,10 +169,10 @@ __device__ __forceinline__ double row_rhs(const SubDev &sd, const InstDev &I, co
   const double u = src[(size_t)i * nx + mc];
   const double un = src[(size_t)i * nx + mn];
   double val = (1.0 - w) * u + w * un + gn * fr[(size_t)i * nx + mc];
-  if (i == 0 && sd.lo_kind == END_DIRI)
-    val += I.r * lin[(size_t)sd.lam_lo * plane + (size_t)n * nx + mc];
-  if (i == sd.n - 1 && sd.hi_kind == END_DIRI)
-    val += I.r * lin[(size_t)sd.lam_hi * plane + (size_t)n * nx + mc];
+  if (i == 0 && (sd.lo_kind == END_DIRI || sd.lo_kind == END_RFV))
+    val += end_scale(sd.lo_kind, I) * lin[(size_t)sd.lam_lo * plane + (size_t)n * nx + mc];
+  if (i == sd.n - 1 && (sd.hi_kind == END_DIRI || sd.hi_kind == END_RFV))
+    val += end_scale(sd.hi_kind, I) * lin[(size_t)sd.lam_hi * plane + (size_t)n * nx + mc];
   return val;
 }
 
@@ -266,13 +281,14 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepTables t, int n, int 
         }
         if (w == 0 && sd.lo_kind != END_PHYS) {
           const double l = lin[(size_t)sd.lam_lo * plane + (size_t)n * nx + mc];
-          d[0] = sd.lo_kind == END_ROBIN ? l : d[0] + I.r * l;
+          d[0] = sd.lo_kind == END_ROBIN ? l : d[0] + end_scale(sd.lo_kind, I) * l;
         }
         if (w == P - 1 && sd.hi_kind != END_PHYS) {
           const double l = lin[(size_t)sd.lam_hi * plane + (size_t)n * nx + mc];
+          const double sc = end_scale(sd.hi_kind, I);
 #pragma unroll
           for (int k = 0; k < SEGMAX; ++k)
-            if (k == len - 1) d[k] = sd.hi_kind == END_ROBIN ? l : d[k] + I.r * l;
+            if (k == len - 1) d[k] = sd.hi_kind == END_ROBIN ? l : d[k] + sc * l;
         }
         // local forward elimination
         double y = 0.0;
@@ -622,8 +638,12 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
         if constexpr (SEG <= kFRegMax) fs.template st<k>(mc[k].fa * fr[(size_t)r * nx + col]);
       });
     }
-    const double lo_scale = lo_end ? mc[k0].fab * (lo_kind == END_ROBIN ? 1.0 : rr) : 0.0;
-    const double hi_scale = hi_end ? mc[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : rr) : 0.0;
+    const double rfv = 2.0 * rr * I->hv;  // flux weight of a half-cell row (no overlap)
+    const double lo_scale =
+        lo_end ? mc[k0].fab * (lo_kind == END_ROBIN ? 1.0 : (lo_kind == END_RFV ? rfv : rr)) : 0.0;
+    const double hi_scale =
+        hi_end ? mc[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : (hi_kind == END_RFV ? rfv : rr))
+               : 0.0;
     // register `pad` of every lane (a wave-uniform index): the first real row
     // of the last segment
     auto first_value = [&](const SegRegs<SEG> &dd) {
@@ -778,7 +798,12 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
     const double ua = V[V_A_LO * plane + e];
     const double ubh = V[V_B_HI * plane + e];
     double toR = ua, toL = ubh, ub_lo, ua_hi;
-    if (robin) {
+    if (I.nonovl) {  // shared node: Q from the Robin condition each side was solved with
+      toR = (I.p + I.q) * ua - lin[(size_t)(2 * j + 1) * plane + e];
+      toL = (I.p + I.q) * ubh - lin[(size_t)(2 * j) * plane + e];
+      ub_lo = ua;
+      ua_hi = ubh;
+    } else if (robin) {
       const double ua1 = V[V_A1_LO * plane + e];
       const double ub1h = V[V_B1_HI * plane + e];
       toR = I.q * ua - (ua1 - ua) / I.hv;

@@ -86,9 +86,9 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
   if (g->nv % J) return fail(KFP_EINVAL, "nv %% J != 0 (nv=%d, J=%d)", g->nv, J);
   if (o < 0) return fail(KFP_EINVAL, "overlap must be >= 0");
   if (J > 1) {
-    if (o < 1)
-      return fail(KFP_EINVAL, "overlap must be >= 1 for J > 1 (classical SWR does not converge "
-                              "without overlap; the Robin stencil needs one cell)");
+    if (o < 1 && tr == KFP_DIRICHLET)
+      return fail(KFP_EINVAL, "overlap must be >= 1 for classical SWR with J > 1 (it does not "
+                              "converge without overlap)");
     if (g->nv / J < o + 2) return fail(KFP_EINVAL, "nv/J must be >= overlap + 2");
     if (tr == KFP_ROBIN && !(p > 0.0 && std::isfinite(p)))
       return fail(KFP_EINVAL, "Robin parameter p must be > 0 (got %g)", p);
@@ -117,10 +117,13 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
     SubGeo &s = geo.sub[j];
     s.a = a[j];
     s.b = b[j];
-    s.lo_kind = j == 0 ? END_PHYS : (tr == KFP_ROBIN ? END_ROBIN : END_DIRI);
-    s.hi_kind = j == J - 1 ? END_PHYS : (tr == KFP_ROBIN ? END_ROBIN : END_DIRI);
-    s.lo = s.lo_kind == END_ROBIN ? s.a : s.a + 1;
-    s.hi = s.hi_kind == END_ROBIN ? s.b : s.b - 1;
+    // optimized interfaces: Robin rows, or with no overlap the shared node's
+    // half-cell rows; both are unknown rows of the subdomain
+    const int ifk = tr == KFP_ROBIN ? (o == 0 ? END_RFV : END_ROBIN) : END_DIRI;
+    s.lo_kind = j == 0 ? END_PHYS : ifk;
+    s.hi_kind = j == J - 1 ? END_PHYS : ifk;
+    s.lo = s.lo_kind == END_ROBIN || s.lo_kind == END_RFV ? s.a : s.a + 1;
+    s.hi = s.hi_kind == END_ROBIN || s.hi_kind == END_RFV ? s.b : s.b - 1;
     s.n = s.hi - s.lo + 1;
     geo.row_off[j] = geo.rows;
     geo.rows += s.n;
@@ -368,6 +371,21 @@ static void row_matrix(const SubGeo &s, double r, double p, double q, double hv,
     di[s.n - 1] = p + 1.0 / hv;
     up[s.n - 1] = 0.0;
   }
+  // no overlap: the shared interface node balances its half cell, the flux
+  // through the interface being lambda - q u (lower end) or lambda - p u
+  // (upper end); times 2 dt / h_v:
+  //   (1 + 2r + 2 dt q / h_v) u_0 - 2r u_1 = T u + dt s f + 2 dt/h_v lambda
+  const double fv = 2.0 * r * hv;  // 2 dt / h_v
+  if (s.lo_kind == END_RFV) {
+    lo[0] = 0.0;
+    di[0] = 1.0 + 2.0 * r + fv * q;
+    up[0] = -2.0 * r;
+  }
+  if (s.hi_kind == END_RFV) {
+    lo[s.n - 1] = -2.0 * r;
+    di[s.n - 1] = 1.0 + 2.0 * r + fv * p;
+    up[s.n - 1] = 0.0;
+  }
 }
 
 // Appends the tables of one subdomain (partitioned into P segments).
@@ -407,8 +425,8 @@ static void add_subdomain(const Geo &g, int j, double p, double q, int waves, in
   if (j < g.J - 1) {
     const SubGeo &nb = g.sub[j + 1];
     d.res_nb = sub_base + j + 1;
-    d.res_row_a_nb = nb.lo_kind == END_ROBIN ? nb.a - nb.lo : -1;
-    d.res_row_b_self = s.hi_kind == END_ROBIN ? s.b - s.lo : -1;
+    d.res_row_a_nb = nb.lo_kind == END_ROBIN || nb.lo_kind == END_RFV ? nb.a - nb.lo : -1;
+    d.res_row_b_self = s.hi_kind == END_ROBIN || s.hi_kind == END_RFV ? s.b - s.lo : -1;
     d.res_row_b_nb = s.b - nb.lo;
     d.res_plane_a = 2 * j;
     d.res_plane_b = 2 * j + 1;
@@ -574,8 +592,8 @@ static SubDev sub_descriptor(const Geo &g, int j, int inst, int sub_base) {
   if (j < g.J - 1) {
     const SubGeo &nb = g.sub[j + 1];
     d.res_nb = sub_base + j + 1;
-    d.res_row_a_nb = nb.lo_kind == END_ROBIN ? nb.a - nb.lo : -1;
-    d.res_row_b_self = s.hi_kind == END_ROBIN ? s.b - s.lo : -1;
+    d.res_row_a_nb = nb.lo_kind == END_ROBIN || nb.lo_kind == END_RFV ? nb.a - nb.lo : -1;
+    d.res_row_b_self = s.hi_kind == END_ROBIN || s.hi_kind == END_RFV ? s.b - s.lo : -1;
     d.res_row_b_nb = s.b - nb.lo;
     d.res_plane_a = 2 * j;
     d.res_plane_b = 2 * j + 1;
@@ -708,7 +726,7 @@ static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg
       cprev = cpk;
     }
     // the multi-step kernel applies the explicit inverse of the reduced
-    // system (at most 15 x 15): every separator value is then an independent
+    // system (at most 31 x 31): every separator value is then an independent
     // dot product instead of a link in a serial chain
     std::vector<double> inv;
     tridiag_inverse(al, be, ga, inv);
@@ -1056,6 +1074,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   in.nv = geo.nv;
   in.nt = geo.nt;
   in.tr = geo.tr;
+  in.nonovl = geo.J > 1 && geo.o == 0 && geo.tr == KFP_ROBIN;
   in.active = 1;
   std::vector<double> gv(geo.nt);
   for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
@@ -1580,6 +1599,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     d.nv = geo.nv;
     d.nt = geo.nt;
     d.tr = geo.tr;
+    d.nonovl = geo.J > 1 && geo.o == 0 && geo.tr == KFP_ROBIN;
     d.active = 1;
     if (b.win) {
       if (in[i].lambda_init) {

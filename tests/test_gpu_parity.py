@@ -349,6 +349,61 @@ def test_graph_and_direct_launch_agree_and_are_deterministic():
     assert torch.equal(a, c) and torch.equal(la, lc)
 
 
+# ------------------------------------------------------ no overlap (L = 0) --
+# The shared interface node is a half-cell row of both neighbours; traces
+# (p + q) u - lambda.  One-step kernels (memory-staged and register
+# segments), march kernels with and without lane groups.
+NONOVL_CONFIGS = [None, (1, 0, 0), (2, 16, 0), (4, 8, 0), (8, 0, 0), (4, 24, 1), (4, 24, 8),
+                  (8, 10, 4), (4, 8, 5, 2)]
+
+
+@pytest.mark.parametrize("cfg", NONOVL_CONFIGS)
+@pytest.mark.parametrize("J,p,q", [(2, 4.0, None), (4, 2.0, 5.0)])
+def test_without_overlap_matches_oracle(cfg, J, p, q):
+    nx, nv, nt, T = 72, 64, 24, 0.2
+    print(f"no overlap cfg={cfg} J={J} p={p} q={q}", flush=True)
+    u0, f = inputs.random_fields(40 + J, nx, nv)
+    ref = oracle.swr_solve(u0, f, T, nt, J, 0, R, p=p, q=q, tol=1e-300, max_iter=3)
+    if cfg:
+        kfp.set_config(*cfg)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, 0, R, p=p, q=q, tol=1e-300,
+                                max_iter=3, want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+def test_without_overlap_converges_overlapped_and_batched():
+    nx, nv, nt, T = 64, 64, 40, 0.2
+    u0, f = inputs.random_fields(41, nx, nv)
+    ref = oracle.swr_solve(u0, f, T, nt, 4, 0, R, p=3.0, tol=1e-11, max_iter=400)
+    assert ref.status == 0
+    runs = []
+    for mode in (0, 3):
+        kfp.set_pipeline(mode)
+        uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 0, R, p=3.0, tol=1e-11,
+                                    max_iter=400, want_lambda=True)
+        assert st.iters == ref.iters
+        assert rel(host(uT), ref.uT) <= 1e-10
+        runs.append((uT, lam))
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    kfp.set_pipeline(-1)
+    # a batch mixing overlapping and non-overlapping instances equals the singles
+    specs = [(64, 64, 40, 0.2, 4, 0, 3.0), (96, 128, 40, 0.2, 2, 2, 4.0),
+             (64, 128, 40, 0.1, 2, 0, 6.0)]
+    insts, singles = [], []
+    kfp.set_config(4, 8, 4)  # one configuration (widened per shape) for both
+    for i, (nx_, nv_, nt_, T_, J_, o_, p_) in enumerate(specs):
+        a, b = inputs.random_fields(50 + i, nx_, nv_)
+        insts.append(dict(u0=dev(a), f=dev(b), T=T_, nt=nt_, J=J_, overlap=o_, tr=R, p=p_))
+        singles.append(kfp.swr_solve(dev(a), dev(b), T_, nt_, J_, o_, R, p=p_, tol=1e-11,
+                                     max_iter=400))
+    out, rc = kfp.swr_batch(insts, tol=1e-11, max_iter=400)
+    assert rc == 0
+    for (uT, _, st), (ruT, _, rst) in zip(out, singles):
+        assert st.iters == rst.iters and torch.equal(uT, ruT)
+
+
 # ------------------------------------------------- overlapped iterations ----
 PIPE_CASES = [
     # nx, nv, nt, T, J, o, tr, p, (waves, seg, steps[, groups]) or None

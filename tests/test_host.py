@@ -55,7 +55,6 @@ def swr(lib, g, J=2, o=2, tr=1, p=4.0, tol=1e-10, max_iter=10, u0=FAKE, f=FAKE, 
     (dict(g=G(1024, 64, 10, 1.0)), "CFL"),
     (dict(J=3), "nv % J"),
     (dict(J=16, o=3), "nv/J"),
-    (dict(o=0), "overlap"),
     (dict(tr=0, o=0), "overlap"),
     (dict(p=0.0), "p must be"),
     (dict(p=-1.0), "p must be"),
@@ -97,6 +96,9 @@ def test_subdomain_rows(lib):
     assert r.value == 1023 + 7 * 3  # (nv - 1) + (J - 1)(o + 1) for Robin
     assert lib.kfp_subdomain_rows(ctypes.byref(g), 8, 2, 0, ctypes.byref(r)) == 0
     assert r.value == 1023 + 7 * 1  # (nv - 1) + (J - 1)(o - 1) for Dirichlet
+    # no overlap (Robin only): the shared node is a row of both neighbours
+    assert lib.kfp_subdomain_rows(ctypes.byref(g), 8, 0, 1, ctypes.byref(r)) == 0
+    assert r.value == 1023 + 7
 
 
 def get_tables(lib, nx, nv, nt, T, J, o, tr, p, waves):
@@ -122,9 +124,12 @@ def get_tables(lib, nx, nv, nt, T, J, o, tr, p, waves):
 def paper_matrix(nv, nt, T, lo_node, n, lo_kind, hi_kind, p):
     """Tridiagonal matrix of one subdomain's unknown rows from Section 6.2/6.3:
     implicit-Euler diffusion rows [-r, 1+2r, -r]; a Robin row (q - d/dv) at a
-    lower interface, (p + d/dv) at an upper one (q = p)."""
+    lower interface, (p + d/dv) at an upper one (q = p); without overlap the
+    shared node's half-cell row: [1+2r+2 dt p/h_v, -2r] (times 2 dt/h_v, the
+    balance of the half cell with the Robin flux)."""
     hv = 2.0 / nv
     r = (T / nt) / hv ** 2
+    hc = 2.0 * (T / nt) / hv
     A = np.zeros((n, n))
     for k in range(n):
         A[k, k] = 1 + 2 * r
@@ -138,6 +143,12 @@ def paper_matrix(nv, nt, T, lo_node, n, lo_kind, hi_kind, p):
     if hi_kind == 2:
         A[n - 1, :] = 0
         A[n - 1, n - 2], A[n - 1, n - 1] = -1 / hv, p + 1 / hv
+    if lo_kind == 3:
+        A[0, :] = 0
+        A[0, 0], A[0, 1] = 1 + 2 * r + hc * p, -2 * r
+    if hi_kind == 3:
+        A[n - 1, :] = 0
+        A[n - 1, n - 2], A[n - 1, n - 1] = -2 * r, 1 + 2 * r + hc * p
     return A
 
 
@@ -188,6 +199,7 @@ def emulate_partitioned_solve(rows, segs, reds, P, d):
     (128, 1024, 512, 0.25, 2, 2, 1, 4.0),
     (64, 48, 100, 0.1, 3, 5, 1, 0.7),
     (16, 16, 10, 0.1, 1, 0, 0, 0.0),
+    (128, 128, 100, 0.1, 4, 0, 1, 3.0),
 ])
 @pytest.mark.parametrize("waves", [1, 2, 4, 8, 16])
 def test_partitioned_tables_solve_the_paper_matrix(lib, nx, nv, nt, T, J, o, tr, p, waves):
