@@ -1,0 +1,150 @@
+"""The paper's numerical experiments (Section 6.4 and 6.5), run through the
+library on the GPU.
+
+    python -m paper_1306_4596_amd.experiments table1 [--levels 0 1 2 3 4]
+    python -m paper_1306_4596_amd.experiments sweep-p [--level 0]
+    python -m paper_1306_4596_amd.experiments sweep-pq [--level 0]
+    python -m paper_1306_4596_amd.experiments history [--level 2]
+
+Set-up (Section 6.4): two subdomains of [0,1) x [-1,1], T = 2, the error
+equation (zero source and initial value, a random initial interface
+variable, so that every frequency is present), uniform grids with
+dt = h_x = h_v = 2^-j * 0.01 at refinement level j, an overlap of three cells
+(L = 3 h_v) or none (L = 0), and the stopping test (6.12) below 1e-6.  The
+discretisation is this library's (finite differences, zero Dirichlet ends,
+an IMEX step, parallel order), not the paper's, so the iteration counts are
+compared by trend only.  Each command prints one JSON line per result.
+
+`table1`: CSWR (capped at 150 iterations, as in the table), OSWR(p) with
+p = 4.23 and OSWR(p,q) with (p, q) = (11, 2.5), with and without overlap.
+`sweep-p`: iteration counts and the error after 15 iterations for one-sided
+p (Figure 1); `sweep-pq`: the same over a (p, q) grid (Figure 2), each sweep
+solved as one batch.  `history`: the residual histories of the three
+algorithms with overlap (Figure 3).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import binding as kb
+from . import inputs
+
+T_END = 2.0
+TOL = 1e-6
+PSTAR = 4.23           # one-sided optimum of Section 6.4.1
+P2, Q2 = 11.0, 2.5     # two-sided parameters of Section 6.5
+CSWR_CAP = 150
+PAPER = {  # Table 1 of the paper: (algorithm, overlap cells) -> counts j = 0..4 (None: ">150" or "-")
+    ("CSWR", 3): [70, 105, 132, None, None],
+    ("OSWR(p)", 3): [9, 12, 15, 17, 18],
+    ("OSWR(p,q)", 3): [9, 10, 10, 10, 13],
+    ("CSWR", 0): [None] * 5,
+    ("OSWR(p)", 0): [12, 17, 20, 23, 26],
+    ("OSWR(p,q)", 0): [11, 12, 13, 14, 16],
+}
+
+
+def grid(level: int):
+    """(nx, nv, nt) of refinement level j: dt = h_x = h_v = 2^-j * 0.01."""
+    s = 2 ** level
+    return 100 * s, 200 * s, 200 * s
+
+
+def _zero_problem(level: int, seed: int = 0):
+    import torch
+
+    nx, nv, nt = grid(level)
+    z = torch.zeros((nv + 1, nx), dtype=torch.float64, device="cuda")
+    lam0 = torch.from_numpy(inputs.random_traces(seed, 2, nt, nx)).cuda()
+    return nx, nv, nt, z, lam0
+
+
+def table1(levels):
+    import torch
+
+    for j in levels:
+        nx, nv, nt, z, lam0 = _zero_problem(j)
+        for o in (3, 0):
+            algos = [("OSWR(p)", kb.ROBIN, PSTAR, None), ("OSWR(p,q)", kb.ROBIN, P2, Q2)]
+            if o > 0:
+                algos.insert(0, ("CSWR", kb.DIRICHLET, 0.0, None))
+            for name, tr, p, q in algos:
+                cap = CSWR_CAP if tr == kb.DIRICHLET else 400
+                t0 = time.perf_counter()
+                _, _, st = kb.swr_solve(z, z, T_END, nt, 2, o, tr, p=p, q=q, tol=TOL,
+                                        max_iter=cap, lambda_init=lam0)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                conv = st.residual < TOL
+                print(json.dumps({"experiment": "table1", "level": j, "nx": nx, "nv": nv, "nt": nt,
+                                  "overlap_cells": o, "algorithm": name, "p": p, "q": q,
+                                  "iters": st.iters if conv else None, "converged": bool(conv),
+                                  "residual": st.residual, "paper": PAPER[(name, o)][j],
+                                  "seconds": round(wall, 3),
+                                  "config": kb.get_launch(nx, nv, nt, T_END, 2, o, tr)}),
+                      flush=True)
+            kb.release_workspace()
+
+
+def _sweep(level: int, pairs, overlap: int, tag: str):
+    """One batch: instance i solves OSWR(p_i, q_i) from the same random trace;
+    the iteration count to 1e-6 and the residual after 15 iterations."""
+    nx, nv, nt, z, lam0 = _zero_problem(level)
+    insts = [dict(u0=z, f=z, T=T_END, nt=nt, J=2, overlap=overlap, tr=kb.ROBIN, p=p, q=q,
+                  lambda_init=lam0) for p, q in pairs]
+    out, _ = kb.swr_batch(insts, tol=TOL, max_iter=200, history=True)
+    for (p, q), (_, _, st) in zip(pairs, out):
+        h = st.res_history
+        print(json.dumps({"experiment": tag, "level": level, "overlap_cells": overlap, "p": p,
+                          "q": q, "iters": st.iters if st.residual < TOL else None,
+                          "residual_after_15": float(h[14]) if len(h) >= 15 else None}),
+              flush=True)
+    kb.release_workspace()
+
+
+def sweep_p(level: int):
+    ps = [round(x, 3) for x in np.arange(1.0, 20.01, 0.5)]
+    for o in (3, 0):
+        _sweep(level, [(p, None) for p in ps], o, "sweep-p")
+
+
+def sweep_pq(level: int):
+    ps = [2.0, 4.0, 6.0, 8.0, 11.0, 14.0, 18.0]
+    qs = [0.5, 1.0, 1.5, 2.5, 4.0, 6.0, 8.0]
+    _sweep(level, [(p, q) for p in ps for q in qs], 3, "sweep-pq")
+
+
+def history(level: int):
+    nx, nv, nt, z, lam0 = _zero_problem(level)
+    for name, tr, p, q in (("CSWR", kb.DIRICHLET, 0.0, None), ("OSWR(p)", kb.ROBIN, PSTAR, None),
+                           ("OSWR(p,q)", kb.ROBIN, P2, Q2)):
+        _, _, st = kb.swr_solve(z, z, T_END, nt, 2, 3, tr, p=p, q=q, tol=TOL, max_iter=CSWR_CAP,
+                                lambda_init=lam0)
+        print(json.dumps({"experiment": "history", "level": level, "algorithm": name,
+                          "residuals": [float(x) for x in st.res_history]}), flush=True)
+    kb.release_workspace()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["table1", "sweep-p", "sweep-pq", "history"])
+    ap.add_argument("--levels", type=int, nargs="*", default=[0, 1, 2, 3, 4])
+    ap.add_argument("--level", type=int, default=None)
+    a = ap.parse_args()
+    kb.load_library()
+    if a.which == "table1":
+        table1(a.levels)
+    elif a.which == "sweep-p":
+        sweep_p(0 if a.level is None else a.level)
+    elif a.which == "sweep-pq":
+        sweep_pq(0 if a.level is None else a.level)
+    else:
+        history(2 if a.level is None else a.level)
+
+
+if __name__ == "__main__":
+    main()
