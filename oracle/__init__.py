@@ -54,9 +54,14 @@ def _load():
             I, I, I, ctypes.c_double, D, D, D, I, I, I, ctypes.c_double, ctypes.c_double,
             ctypes.c_double, I, D, D, D, ctypes.POINTER(I), D, D,
         ]
+        lib.oracle_swr_solve_ordered.argtypes = [
+            I, I, I, ctypes.c_double, D, D, D, I, I, I, ctypes.c_double, ctypes.c_double,
+            ctypes.c_double, I, D, I, D, D, ctypes.POINTER(I), D, D,
+        ]
         lib.oracle_u0_guess.argtypes = [I, I, I, D, I, I, I, ctypes.c_double, ctypes.c_double, D]
         for fn in ("oracle_thomas", "oracle_transport", "oracle_mono_solve",
-                   "oracle_partition", "oracle_swr_solve", "oracle_u0_guess"):
+                   "oracle_partition", "oracle_swr_solve", "oracle_swr_solve_ordered",
+                   "oracle_u0_guess"):
             getattr(lib, fn).restype = I
         _lib = lib
     return _lib
@@ -136,9 +141,12 @@ class SWRResult:
 
 
 def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter=100,
-              lambda_init=None, s=None, q=None):
-    """Parallel SWR (Section 6.3 with the Jacobi Remark).  Returns SWRResult.
-    q: second Robin parameter of OSWR(p,q); None for q = p."""
+              lambda_init=None, s=None, q=None, order=0):
+    """SWR (Section 6.3).  Returns SWRResult.  q: second Robin parameter of
+    OSWR(p,q); None for q = p.  order: 0 parallel (the Jacobi Remark after
+    (6.12)), 1 multiplicative in red-black order (even subdomains, then odd
+    ones with the traces the even ones just sent; for two subdomains the
+    serial form (6.8)-(6.11))."""
     u0, f = _f64(u0), _f64(f)
     nv, nx = u0.shape[0] - 1, u0.shape[1]
     s = None if s is None else _f64(s)
@@ -151,10 +159,11 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter
     hist = np.zeros(max_iter)
     ovl = np.zeros(max_iter)
     it = ctypes.c_int(0)
-    st = _load().oracle_swr_solve(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), J, overlap,
-                                  int(transmission), float(p), float(p if q is None else q),
-                                  float(tol), max_iter, _p(li),
-                                  _p(uT), _p(lam_out), ctypes.byref(it), _p(hist), _p(ovl))
+    st = _load().oracle_swr_solve_ordered(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), J,
+                                          overlap, int(transmission), float(p),
+                                          float(p if q is None else q), float(tol), max_iter,
+                                          _p(li), int(order), _p(uT), _p(lam_out),
+                                          ctypes.byref(it), _p(hist), _p(ovl))
     if st == 1:
         raise ValueError("invalid arguments")
     k = it.value

@@ -294,13 +294,80 @@ static int owner(int i, int nv, int J, const int *a, int tr) {
   return j;
 }
 
+/* Trace that one side of interface j sends to the other, eqs. (6.9)/(6.11).
+ * side 0: plane 2j = Q_2 u_j at alpha = a_{j+1} (the data of subdomain j+1);
+ * side 1: plane 2j+1 = Q_1 u_{j+1} at beta = b_j (the data of subdomain j).
+ * Ul, Ur: iterates of subdomains j and j+1 over the window; lam_used: the
+ * traces the sending subdomain was solved with (read only without overlap,
+ * where the derivative comes from the sender's own Robin condition);
+ * lam_out: receives the plane. */
+static void emit_trace(int nx, int nt, int j, int side, const int *a, const int *b, int o,
+                       int tr, double p, double q, double hv, const double *Ul,
+                       const double *Ur, const double *lam_used, double *lam_out) {
+  const size_t P = (size_t)nt * nx;
+  const int al = a[j + 1], be = b[j];
+  const int nnL = b[j] - a[j] + 1, nnR = b[j + 1] - a[j + 1] + 1;
+  for (int n = 0; n < nt; ++n) {
+    const double *UL = Ul + (size_t)n * nnL * nx; /* u_j     */
+    const double *UR = Ur + (size_t)n * nnR * nx; /* u_{j+1} */
+    for (int m = 0; m < nx; ++m) {
+      const size_t e = (size_t)n * nx + m;
+      if (side == 0) {
+        const double uLa = UL[(size_t)(al - a[j]) * nx + m];
+        double v = uLa;
+        if (tr == KFP_O_ROBIN && o == 0) {
+          v = (p + q) * uLa - lam_used[(size_t)(2 * j + 1) * P + e];
+        } else if (tr == KFP_O_ROBIN) {
+          const double uLa1 = UL[(size_t)(al + 1 - a[j]) * nx + m];
+          v = q * uLa - (uLa1 - uLa) / hv;
+        }
+        lam_out[(size_t)(2 * j) * P + e] = v;
+      } else {
+        const double uRb = UR[(size_t)(be - a[j + 1]) * nx + m];
+        double v = uRb;
+        if (tr == KFP_O_ROBIN && o == 0) {
+          v = (p + q) * uRb - lam_used[(size_t)(2 * j) * P + e];
+        } else if (tr == KFP_O_ROBIN) {
+          const double uRb1 = UR[(size_t)(be - 1 - a[j + 1]) * nx + m];
+          v = p * uRb + (uRb - uRb1) / hv;
+        }
+        lam_out[(size_t)(2 * j + 1) * P + e] = v;
+      }
+    }
+  }
+}
+
+/* (6.12): mismatch of the iterates of subdomains j and j+1 on their overlap,
+ * over the whole window; *rk: at the two end nodes, *rov: over the closed
+ * overlap (a NaN propagates to both). */
+static void mismatch(int nx, int nt, int j, const int *a, const int *b, const double *Ul,
+                     const double *Ur, double *rk, double *rov) {
+  const int al = a[j + 1], be = b[j];
+  const int nnL = b[j] - a[j] + 1, nnR = b[j + 1] - a[j + 1] + 1;
+  for (int n = 0; n < nt; ++n) {
+    const double *UL = Ul + (size_t)n * nnL * nx;
+    const double *UR = Ur + (size_t)n * nnR * nx;
+    for (int m = 0; m < nx; ++m)
+      for (int i = al; i <= be; ++i) {
+        double d = fabs(UL[(size_t)(i - a[j]) * nx + m] - UR[(size_t)(i - a[j + 1]) * nx + m]);
+        if (!(d <= *rov)) *rov = d;
+        if ((i == al || i == be) && !(d <= *rk)) *rk = d;
+      }
+  }
+}
+
 /*
- * oracle_swr_solve: parallel SWR for J subdomains.
+ * oracle_swr_solve_ordered: SWR for J subdomains.
  *   u0, f: [nv+1][nx]; s: [nt+1] or NULL.
  *   tr: 0 Dirichlet (CSWR), 1 Robin: OSWR(p,q) of Section 6.3, the data for
  *     a subdomain's upper interface node is Q_1 u = (p + d/dv) u of its upper
  *     neighbour, the data for its lower node Q_2 u = (q - d/dv) u of its
  *     lower neighbour; q = p is the one-sided OSWR(p).
+ *   order: 0 parallel (the Remark after (6.12): every subdomain of iteration
+ *     k reads the traces of k-1); 1 multiplicative in red-black order, as
+ *     (6.8)-(6.11) are written for two subdomains: iteration k first solves
+ *     the even subdomains with the current traces, sends their traces, then
+ *     solves the odd ones with those new traces and sends theirs.
  *   lambda_init: [2(J-1)][nt][nx] or NULL (zero).  Plane 2j holds the data
  *     for subdomain j+1 at node a_{j+1} (Q_2 u_j), plane 2j+1 the data for
  *     subdomain j at node b_j (Q_1 u_{j+1}); row n-1 holds time level n.
@@ -310,12 +377,13 @@ static int owner(int i, int nv, int J, const int *a, int tr) {
  *   ovl_hist[k-1] = the maximum over the whole closed overlap (6.12).
  *   Returns 0 on convergence, 4 when max_iter is reached, 1 on bad input.
  */
-int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
-                     const double *f, const double *s, int J, int o, int tr,
-                     double p, double q, double tol, int max_iter, const double *lambda_init,
-                     double *uT, double *lambda_out, int *iters, double *res_hist,
-                     double *ovl_hist) {
-  if (nx < 1 || nv < 2 || nt < 1 || !(T > 0) || max_iter < 1) return 1;
+int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
+                             const double *f, const double *s, int J, int o, int tr, double p,
+                             double q, double tol, int max_iter, const double *lambda_init,
+                             int order, double *uT, double *lambda_out, int *iters,
+                             double *res_hist, double *ovl_hist) {
+  if (nx < 1 || nv < 2 || nt < 1 || !(T > 0) || max_iter < 1 || order < 0 || order > 1)
+    return 1;
   int *a = (int *)malloc(sizeof(int) * J), *b = (int *)malloc(sizeof(int) * J);
   if (oracle_partition(nv, J, o, a, b)) {
     free(a);
@@ -345,54 +413,43 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
   }
   int k = 0, status = 4;
   for (k = 1; k <= max_iter; ++k) {
-    /* (6.8)/(6.10), parallel form: each subdomain uses traces of k-1 */
-    for (int j = 0; j < J; ++j) {
-      const double *LL = (j > 0) ? lamOld + (size_t)(2 * (j - 1)) * P : NULL;
-      const double *LR = (j < J - 1) ? lamOld + (size_t)(2 * j + 1) * P : NULL;
-      solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);
-    }
-    /* (6.9)/(6.11): new interface variables from the neighbours */
-    double rk = 0.0, rov = 0.0;
-    for (int j = 0; j < nI; ++j) {
-      const int al = a[j + 1], be = b[j];
-      const int nnL = b[j] - a[j] + 1, nnR = b[j + 1] - a[j + 1] + 1;
-      double *toR = lamNew + (size_t)(2 * j) * P;     /* for subdomain j+1 at alpha */
-      double *toL = lamNew + (size_t)(2 * j + 1) * P; /* for subdomain j at beta   */
-      for (int n = 0; n < nt; ++n) {
-        const double *UL = hist[j] + (size_t)n * nnL * nx;     /* u_j     */
-        const double *UR = hist[j + 1] + (size_t)n * nnR * nx; /* u_{j+1} */
-        for (int m = 0; m < nx; ++m) {
-          double uLa = UL[(size_t)(al - a[j]) * nx + m];
-          double uRb = UR[(size_t)(be - a[j + 1]) * nx + m];
-          if (tr == KFP_O_ROBIN && o == 0) {
-            /* shared node: each side's derivative from its own condition */
-            const double l1 = lamOld[(size_t)(2 * j + 1) * P + (size_t)n * nx + m];
-            const double l2 = lamOld[(size_t)(2 * j) * P + (size_t)n * nx + m];
-            toR[(size_t)n * nx + m] = (p + q) * uLa - l1;
-            toL[(size_t)n * nx + m] = (p + q) * uRb - l2;
-          } else if (tr == KFP_O_ROBIN) {
-            double uLa1 = UL[(size_t)(al + 1 - a[j]) * nx + m];
-            double uRb1 = UR[(size_t)(be - 1 - a[j + 1]) * nx + m];
-            toR[(size_t)n * nx + m] = q * uLa - (uLa1 - uLa) / hv;
-            toL[(size_t)n * nx + m] = p * uRb + (uRb - uRb1) / hv;
-          } else {
-            toR[(size_t)n * nx + m] = uLa;
-            toL[(size_t)n * nx + m] = uRb;
-          }
-          /* (6.12): mismatch of the two iterates on the overlap */
-          for (int i = al; i <= be; ++i) {
-            double d = fabs(UL[(size_t)(i - a[j]) * nx + m] - UR[(size_t)(i - a[j + 1]) * nx + m]);
-            if (!(d <= rov)) rov = d; /* NaN propagates */
-            if ((i == al || i == be) && !(d <= rk)) rk = d;
-          }
+    if (order == 0) {
+      /* (6.8)/(6.10), parallel form: each subdomain uses traces of k-1 */
+      for (int j = 0; j < J; ++j) {
+        const double *LL = (j > 0) ? lamOld + (size_t)(2 * (j - 1)) * P : NULL;
+        const double *LR = (j < J - 1) ? lamOld + (size_t)(2 * j + 1) * P : NULL;
+        solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);
+      }
+      /* (6.9)/(6.11): new interface variables from the neighbours */
+      for (int j = 0; j < nI; ++j)
+        for (int side = 0; side < 2; ++side)
+          emit_trace(nx, nt, j, side, a, b, o, tr, p, q, hv, hist[j], hist[j + 1], lamOld,
+                     lamNew);
+      double *t = lamOld;
+      lamOld = lamNew;
+      lamNew = t;
+    } else {
+      /* red-black: one set of traces, updated as soon as a colour is solved */
+      for (int c = 0; c < 2; ++c) {
+        for (int j = c; j < J; j += 2) {
+          const double *LL = (j > 0) ? lamOld + (size_t)(2 * (j - 1)) * P : NULL;
+          const double *LR = (j < J - 1) ? lamOld + (size_t)(2 * j + 1) * P : NULL;
+          solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);
+        }
+        for (int j = 0; j < nI; ++j) {
+          if (j % 2 == c) /* subdomain j sends plane 2j */
+            emit_trace(nx, nt, j, 0, a, b, o, tr, p, q, hv, hist[j], hist[j + 1], lamOld,
+                       lamOld);
+          if ((j + 1) % 2 == c) /* subdomain j+1 sends plane 2j+1 */
+            emit_trace(nx, nt, j, 1, a, b, o, tr, p, q, hv, hist[j], hist[j + 1], lamOld,
+                       lamOld);
         }
       }
     }
+    double rk = 0.0, rov = 0.0;
+    for (int j = 0; j < nI; ++j) mismatch(nx, nt, j, a, b, hist[j], hist[j + 1], &rk, &rov);
     if (res_hist) res_hist[k - 1] = rk;
     if (ovl_hist) ovl_hist[k - 1] = rov;
-    double *t = lamOld;
-    lamOld = lamNew;
-    lamNew = t;
     if (rk < tol) {
       status = 0;
       break;
@@ -416,6 +473,16 @@ int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
   free(a);
   free(b);
   return status;
+}
+
+/* oracle_swr_solve: the parallel order of oracle_swr_solve_ordered. */
+int oracle_swr_solve(int nx, int nv, int nt, double T, const double *u0,
+                     const double *f, const double *s, int J, int o, int tr,
+                     double p, double q, double tol, int max_iter, const double *lambda_init,
+                     double *uT, double *lambda_out, int *iters, double *res_hist,
+                     double *ovl_hist) {
+  return oracle_swr_solve_ordered(nx, nv, nt, T, u0, f, s, J, o, tr, p, q, tol, max_iter,
+                                  lambda_init, 0, uT, lambda_out, iters, res_hist, ovl_hist);
 }
 
 /* The "u0-extension" initial guess: lambda^0(n) = Q(u0) at the interface

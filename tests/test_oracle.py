@@ -291,6 +291,85 @@ def test_swr_without_overlap_fixed_point_dense(p, q):
     assert 0.97 * rho < ratio < 1.12 * rho, (ratio, rho)
 
 
+# ------------------------------------------- multiplicative (red-black) ----
+@pytest.mark.parametrize("tr,o,p,q", [(D, 3, 0.0, None), (R, 2, 4.0, None), (R, 0, 3.0, None),
+                                      (R, 2, 11.0, 2.5)])
+def test_red_black_two_subdomains_is_every_other_parallel_iterate(tr, o, p, q):
+    """For two subdomains the parallel iteration is two interleaved copies of
+    the serial one (the Remark after (6.12) only replaces lambda_2^k by
+    lambda_2^{k-1}): m serial iterations equal 2m parallel ones in the trace
+    for the lower subdomain and in the upper subdomain's iterate."""
+    nx, nv, nt, T = 12, 24, 15, 0.2
+    u0, f = inputs.random_fields(61, nx, nv)
+    lam0 = inputs.random_traces(62, 2, nt, nx)
+    a, b = oracle.partition(nv, 2, o)
+    for m in (1, 3, 5):
+        rb = oracle.swr_solve(u0, f, T, nt, 2, o, tr, p=p, q=q, tol=0.0, max_iter=m,
+                              lambda_init=lam0, order=1)
+        ja = oracle.swr_solve(u0, f, T, nt, 2, o, tr, p=p, q=q, tol=0.0, max_iter=2 * m,
+                              lambda_init=lam0)
+        assert np.array_equal(rb.lam[1], ja.lam[1])
+        own = slice(nv // 2 + (1 if tr == D else 0), nv + 1)  # rows glued from subdomain 1
+        assert np.array_equal(rb.uT[own], ja.uT[own])
+
+
+@pytest.mark.parametrize("tr,J,o,p,q", [(D, 2, 4, 0.0, None), (D, 4, 3, 0.0, None),
+                                        (R, 3, 2, 4.0, None), (R, 4, 0, 2.0, None),
+                                        (R, 4, 1, 11.0, 2.5)])
+def test_red_black_converges_to_monodomain(tr, J, o, p, q):
+    nx, nv, nt, T = 16, 24, 20, 0.2
+    u0, f = inputs.random_fields(11, nx, nv)
+    m = oracle.mono_solve(u0, f, T, nt)
+    res = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-13, max_iter=500, order=1)
+    assert res.status == 0
+    assert rel_l2(res.uT, m) <= 1e-10
+    par = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-13, max_iter=500)
+    assert res.iters < par.iters
+    if J == 2:  # serial sweeps contract like two parallel ones
+        assert abs(res.iters - par.iters / 2) <= 1.5
+
+
+@pytest.mark.parametrize("tr,o,p", [(D, 2, 0.0), (R, 2, 3.0), (R, 0, 3.0)])
+def test_red_black_fixed_point_dense(tr, o, p):
+    """The red-black map lambda^k = K lambda^{k-1} + c has the monodomain
+    interface data as its fixed point (J = 3: both colours send and
+    receive), and contracts faster than the parallel map."""
+    nx, nv, nt, T, J = 3, 12, 3, 0.3, 3
+    rng = np.random.default_rng(23)
+    u0 = rng.standard_normal((nv + 1, nx))
+    u0[0] = u0[-1] = 0
+    f = rng.standard_normal((nv + 1, nx))
+    a, b = oracle.partition(nv, J, o)
+    shape = (2 * (J - 1), nt, nx)
+    n = int(np.prod(shape))
+    z = np.zeros_like(u0)
+
+    def affine(order):
+        K = np.zeros((n, n))
+        for col in range(n):
+            e = np.zeros(n)
+            e[col] = 1.0
+            r = oracle.swr_solve(z, z, T, nt, J, o, tr, p=p, tol=0.0, max_iter=1,
+                                 lambda_init=e.reshape(shape), order=order)
+            K[:, col] = r.lam.reshape(-1)
+        c = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=0.0, max_iter=1,
+                             order=order).lam.reshape(-1)
+        return K, c
+
+    K, c = affine(1)
+    lam_star = np.linalg.solve(np.eye(n) - K, c)
+    U = dense_ref.spacetime_mono(u0, f, T, nt)
+    if o == 0:
+        lam_mono = dense_ref.interface_data_nonoverlap(U, f, T, nv, a, b, p).reshape(-1)
+    else:
+        lam_mono = dense_ref.interface_data(U, a, b, nv, tr, p).reshape(-1)
+    assert np.allclose(lam_star, lam_mono, rtol=0, atol=1e-11 * np.abs(lam_mono).max())
+    Kp, _ = affine(0)
+    rho_rb = np.abs(np.linalg.eigvals(K)).max()
+    rho_par = np.abs(np.linalg.eigvals(Kp)).max()
+    assert rho_rb < rho_par < 1.0
+
+
 def test_dirichlet_error_equation_monotone_geometric():
     """Error equation (f = 0, u0 = 0, random lambda^0): the maximum principle
     of Section 4 makes max|lambda^k| non-increasing, strictly decreasing with
