@@ -216,6 +216,24 @@ kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
 kfp_status kfp_set_pipeline(int32_t inflight);
 
 /*
+ * kfp_set_ordering -- order of the subdomain solves within one SWR
+ * iteration of kfp_swr_solve / kfp_swr_solve_pq (Section 6.3).
+ * 0 (default): parallel, the form of the Remark after (6.12): every
+ *   subdomain of iteration k reads the traces of iteration k-1.
+ * 1: multiplicative in red-black order, the form (6.8)-(6.11) is written in
+ *   for two subdomains: the even subdomains march the window with the
+ *   current traces and send theirs, then the odd subdomains march with
+ *   those new traces and send theirs.  The residual (6.12) is that of the
+ *   iterates of the same iteration.  For two subdomains one such iteration
+ *   contracts like two parallel ones at the cost of one; the two halves run
+ *   one after the other, each with half the work items.  Needs a march
+ *   configuration (subdomains of at most 1056 rows; KFP_EINVAL otherwise);
+ *   overlapped iterations (kfp_set_pipeline) are not used in this order.
+ * Batches (kfp_swr_batch) always run in the parallel order.
+ */
+kfp_status kfp_set_ordering(int32_t order);
+
+/*
  * kfp_set_kernel_timing -- with on != 0, overlapped-iteration solves launch
  * their kernels directly (not from a replayed graph) with HIP events around
  * every time-step kernel launch, so that kfp_swr_stats.step_seconds holds

@@ -11,6 +11,8 @@ from __future__ import annotations
 from .binding import (  # noqa: F401
     DIRICHLET,
     MLP,
+    PARALLEL,
+    RED_BLACK,
     ROBIN,
     KfpError,
     SWRStats,
@@ -28,6 +30,7 @@ from .binding import (  # noqa: F401
     release_workspace,
     set_config,
     set_kernel_timing,
+    set_ordering,
     set_pipeline,
     standardize,
     subdomain_rows,

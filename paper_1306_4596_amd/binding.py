@@ -102,6 +102,7 @@ def load_library():
     lib.kfp_set_launch.argtypes = [i32, i32, i32, i32]
     lib.kfp_get_launch.argtypes = [G, i32, i32, i32, pi, pi, pi, pi]
     lib.kfp_set_pipeline.argtypes = [i32]
+    lib.kfp_set_ordering.argtypes = [i32]
     lib.kfp_set_kernel_timing.argtypes = [i32]
     lib.kfp_get_config.argtypes = [G, i32, i32, i32, pi, pi, pi]
     lib.kfp_subdomain_rows.argtypes = [G, i32, i32, i32, ctypes.POINTER(ctypes.c_int64)]
@@ -111,7 +112,8 @@ def load_library():
     lib.kfp_release_workspace.restype = None
     for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
-                 "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
+                 "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
+                 "kfp_set_ordering", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -340,6 +342,15 @@ def bw_probe(src, dst, stream=None):
 def set_pipeline(inflight=-1):
     """Overlapped SWR iterations: -1 automatic (default), 0 off, >= 2 in flight."""
     _check(load_library().kfp_set_pipeline(int(inflight)))
+
+
+PARALLEL, RED_BLACK = 0, 1
+
+
+def set_ordering(order=PARALLEL):
+    """Order of the subdomain solves in an iteration: PARALLEL (default) or
+    RED_BLACK (even subdomains, then odd ones with the traces just sent)."""
+    _check(load_library().kfp_set_ordering(int(order)))
 
 
 def set_kernel_timing(on=True):

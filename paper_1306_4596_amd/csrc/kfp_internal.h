@@ -165,7 +165,9 @@ bool march_config_supported(int waves, int groups, int seg_max);
 // and the residual (6.12) from the interface-node value planes.
 // S: steps per launch (pipelined tables: the exchange covers the levels of
 // each instance's current block only).
-hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s);
+// mode: 0 every trace and the residual; 1 / 2 the traces sent by even / odd
+// subdomains (2 also the residual)
+hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s, int mode = 0);
 hipError_t launch_pipe_tick(PipeCtl *c, int *blk, int *iter, unsigned long long *res,
                             double *hist, hipStream_t s);
 hipError_t launch_reset_res(const InstDev *inst, int n_inst, hipStream_t s);

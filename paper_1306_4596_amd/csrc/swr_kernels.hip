@@ -771,7 +771,11 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
 // Traces of every level and the residual of one interface, from the value
 // planes: lambda_{j->j+1} = Q_2 u_j at a_{j+1}, lambda_{j+1->j} = Q_1 u_{j+1}
 // at b_j, and max |u_j - u_{j+1}| at the two end nodes of the overlap.
-__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, int S) {
+// mode 0: both planes of every interface and the residual (parallel order);
+// 1: only the planes sent by even subdomains (plane 2j when j is even, plane
+// 2j+1 when j+1 is even); 2: only those sent by odd subdomains, and the
+// residual (red-black order: run after the even, then the odd half-sweep).
+__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, int S, int mode) {
   __shared__ unsigned long long red[4];
   const ExItem ex = load_const(as_const(t.ex) + blockIdx.y);
   const InstDev I = load_inst(as_const(t.inst) + ex.inst);
@@ -814,8 +818,8 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
       ub_lo = lin[(size_t)(2 * j + 1) * plane + e];
       ua_hi = lin[(size_t)(2 * j) * plane + e];
     }
-    lout[(size_t)(2 * j) * plane + e] = toR;
-    lout[(size_t)(2 * j + 1) * plane + e] = toL;
+    if (mode == 0 || (j & 1) == mode - 1) lout[(size_t)(2 * j) * plane + e] = toR;
+    if (mode == 0 || ((j + 1) & 1) == mode - 1) lout[(size_t)(2 * j + 1) * plane + e] = toL;
     const unsigned long long ra = (unsigned long long)__double_as_longlong(fabs(ua - ua_hi));
     const unsigned long long rb = (unsigned long long)__double_as_longlong(fabs(ub_lo - ubh));
     r = ra > r ? ra : r;
@@ -831,7 +835,7 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
   if (threadIdx.x == 0) {
     unsigned long long m = red[0];
     for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
-    if (m) atomicMax(I.res, m);
+    if (m && mode != 1) atomicMax(I.res, m);
   }
 }
 
@@ -1059,11 +1063,12 @@ hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s) {
+hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s, int mode) {
   if (t.n_ex == 0) return hipSuccess;
+  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
   // a block of S levels is S * nx nodes per interface: fewer workgroups then
   const unsigned gx = t.blk ? 32u : 256u;
-  hipLaunchKernelGGL(exchange_kernel, dim3(gx, t.n_ex), dim3(256), 0, s, t, par, S);
+  hipLaunchKernelGGL(exchange_kernel, dim3(gx, t.n_ex), dim3(256), 0, s, t, par, S, mode);
   return hipGetLastError();
 }
 

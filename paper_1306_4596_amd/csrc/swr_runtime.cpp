@@ -233,6 +233,10 @@ static int g_pipe = -1;  // pipelined iterations: -1 automatic, 0 off, F >= 2 in
 static const long kPipeItems = 128;
 static const long kPipeTarget = 1024;
 static bool g_ktime = false;  // time every step-kernel launch with HIP events
+// order of the subdomain solves within an iteration: 0 parallel (Jacobi),
+// 1 multiplicative red-black (even subdomains, then odd ones with the traces
+// the even ones just sent)
+static int g_order = 0;
 
 // Tuning cache: a flat JSON object {"key": [waves, seg, steps, groups], ...}
 // (groups may be absent: 1).
@@ -882,6 +886,13 @@ struct Plan {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphExec_t gexch[2] = {nullptr, nullptr};
   bool captured = false;
+  // red-black order: the work items of even subdomains come first; the odd
+  // half-sweep runs on a second stream one time block behind the even one
+  int order = 0, n_red = 0;
+  hipStream_t cs2 = nullptr, cs3 = nullptr;  // odd half-sweep; per-block exchange
+  hipEvent_t ev_fork = nullptr, ev_blk = nullptr, ev_join = nullptr, ev_mar = nullptr,
+             ev_join3 = nullptr;
+  DevBuf<int> blkseq;  // 0, 1, ..., L-1: the time block of each launch
   // pipelined iterations (M > 0): M slot instances with their own state and
   // trace window; slot i writes window i and reads window i-1 (mod M)
   int M = 0, d = 0, L = 0, G = 0;
@@ -905,6 +916,11 @@ struct Plan {
     iter.release();
     ctl.release();
     if (h_ctl) (void)hipHostFree(h_ctl);
+    blkseq.release();
+    if (cs2) (void)hipStreamDestroy(cs2);
+    if (cs3) (void)hipStreamDestroy(cs3);
+    for (hipEvent_t e : {ev_fork, ev_blk, ev_join, ev_mar, ev_join3})
+      if (e) (void)hipEventDestroy(e);
     for (auto &ge : gexch)
       if (ge) (void)hipGraphExecDestroy(ge);
     for (auto &ge : gexec)
@@ -944,7 +960,7 @@ struct PipeParams {
 // state and a trace window, within a memory budget.
 static PipeParams pipe_params(const Geo &g, const Config &c) {
   PipeParams pp;
-  if (g_pipe == 0 || c.steps < 1 || g.J < 2) return pp;
+  if (g_pipe == 0 || g_order != 0 || c.steps < 1 || g.J < 2) return pp;
   const int L = (g.nt + c.steps - 1) / c.steps;
   const long items = (long)g.J * ((g.nx + tile_width(c) - 1) / tile_width(c));
   if (g_pipe < 0 && items >= kPipeItems) return pp;
@@ -967,16 +983,16 @@ static PipeParams pipe_params(const Geo &g, const Config &c) {
   }
 }
 
-static std::string plan_key(const Geo &g, const Config &c, int M) {
+static std::string plan_key(const Geo &g, const Config &c, int M, int order) {
   char buf[200];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/g%d/s%d/k%d/M%d", g.nx, g.nv, g.nt, g.J, g.o,
-           g.tr, c.waves, c.groups, c.seg, c.steps, M);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/g%d/s%d/k%d/M%d/o%d", g.nx, g.nv, g.nt, g.J,
+           g.o, g.tr, c.waves, c.groups, c.seg, c.steps, M, order);
   return buf;
 }
 
 static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out,
-                           PipeParams pp = PipeParams()) {
-  const std::string key = plan_key(geo, cfg, pp.M);
+                           PipeParams pp = PipeParams(), int order = 0) {
+  const std::string key = plan_key(geo, cfg, pp.M, order);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     g_plan_lru.erase(std::find(g_plan_lru.begin(), g_plan_lru.end(), key));
@@ -994,6 +1010,18 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out,
   std::unique_ptr<Plan> pl(new Plan());
   pl->geo = geo;
   pl->cfg = cfg;
+  pl->order = order;
+  if (order == 1) {
+    const int L = (geo.nt + cfg.steps - 1) / cfg.steps;  // launches per window
+    std::vector<int> seq(L);
+    for (int l = 0; l < L; ++l) seq[l] = l;
+    HIP_TRY(pl->blkseq.alloc(L));
+    HIP_TRY(hipMemcpy(pl->blkseq.p, seq.data(), sizeof(int) * L, hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamCreateWithFlags(&pl->cs2, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&pl->cs3, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&pl->ev_fork, &pl->ev_blk, &pl->ev_join, &pl->ev_mar, &pl->ev_join3})
+      HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
   const size_t state = (size_t)geo.rows * geo.nx;
   const size_t win = (size_t)2 * (geo.J - 1) * geo.nt * geo.nx;
   HIP_TRY(pl->U0.alloc(state));
@@ -1055,6 +1083,12 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
     make_items(geo, sub_base, tile_width(pl.cfg), h.items);
     make_ex(geo, i, h.ex);
   }
+  pl.n_red = 0;
+  if (pl.order == 1) {  // even subdomains first (single instance: sub = j)
+    std::stable_partition(h.items.begin(), h.items.end(),
+                          [](const Item &it) { return (it.sub & 1) == 0; });
+    for (const Item &it : h.items) pl.n_red += (it.sub & 1) == 0;
+  }
   InstDev in{};
   in.U[0] = pl.U0.p;
   in.U[1] = pl.U1.p;
@@ -1062,7 +1096,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   in.f = f;
   in.g = pl.g.p;
   in.lam[0] = pl.lam0.p;
-  in.lam[1] = pl.lam1.p;
+  in.lam[1] = pl.order == 1 ? pl.lam0.p : pl.lam1.p;  // red-black: one window, in place
   in.res = pl.res.p;
   in.V = pl.V.p;
   const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt;
@@ -1121,8 +1155,74 @@ static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const
   return KFP_OK;
 }
 
+// One iteration in red-black order: the even subdomains march the window and
+// send their traces, the odd ones march with those traces and send theirs,
+// which also reduces the residual.  The method is causal in time, so the odd
+// subdomains march time block l as soon as the even ones have finished it
+// and sent its traces: the even half-sweep runs back to back on the solve's
+// stream, the traces of each block are sent on a third stream, and the odd
+// half-sweep follows on a second one, so the two halves share the device.
+// part 1: everything before the last exchange, 2: the last exchange, 0: both.
+static kfp_status launch_iteration_rb(const Plan &pl, hipStream_t s, int part = 0) {
+  const Config &cfg = pl.cfg;
+  const StepTables t = pl.dt.view();
+  StepTables tc[2] = {t, t};
+  tc[0].n_items = pl.n_red;
+  tc[1].items = t.items + pl.n_red;
+  tc[1].n_items = t.n_items - pl.n_red;
+  if (part != 2) {
+    HIP_TRY(launch_reset_res(pl.dt.inst.p, 1, s));
+    const int L = march_launches(pl.geo.nt, cfg);
+    HIP_TRY(hipEventRecord(pl.ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(pl.cs2, pl.ev_fork, 0));
+    HIP_TRY(hipStreamWaitEvent(pl.cs3, pl.ev_fork, 0));
+    for (int l = 0; l < L; ++l) {
+      // even subdomains, block l: reads only the traces of the previous
+      // iteration and writes only even rows and value planes of block l
+      if (tc[0].n_items > 0)
+        HIP_TRY(launch_march(tc[0], cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps,
+                             halo_of(cfg), l & 1, 0, tc[0].n_items, s));
+      HIP_TRY(hipEventRecord(pl.ev_mar, s));
+      HIP_TRY(hipStreamWaitEvent(pl.cs3, pl.ev_mar, 0));
+      StepTables tx = t;  // the traces of block l only
+      tx.blk = pl.blkseq.p + l;
+      HIP_TRY(launch_exchange(tx, 0, cfg.steps, pl.cs3, 1));
+      HIP_TRY(hipEventRecord(pl.ev_blk, pl.cs3));
+      HIP_TRY(hipStreamWaitEvent(pl.cs2, pl.ev_blk, 0));
+      if (tc[1].n_items > 0)
+        HIP_TRY(launch_march(tc[1], cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps,
+                             halo_of(cfg), l & 1, 0, tc[1].n_items, pl.cs2));
+    }
+    HIP_TRY(hipEventRecord(pl.ev_join, pl.cs2));
+    HIP_TRY(hipStreamWaitEvent(s, pl.ev_join, 0));
+    HIP_TRY(hipEventRecord(pl.ev_join3, pl.cs3));
+    HIP_TRY(hipStreamWaitEvent(s, pl.ev_join3, 0));
+  }
+  if (part != 1) HIP_TRY(launch_exchange(t, 0, cfg.steps, s, 2));
+  return KFP_OK;
+}
+
 static kfp_status capture_graphs(Plan &pl) {
   if (pl.captured) return KFP_OK;
+  if (pl.order == 1) {  // one pair of graphs: the window does not alternate
+    for (int part = 1; part <= 2; ++part) {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(pl.cs, hipStreamCaptureModeThreadLocal));
+      kfp_status st = launch_iteration_rb(pl, pl.cs, part);
+      hipError_t e = hipStreamEndCapture(pl.cs, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      HIP_TRY(e);
+      e = hipGraphInstantiate(part == 1 ? &pl.gexec[0] : &pl.gexch[0], graph, nullptr, nullptr,
+                              0);
+      (void)hipGraphDestroy(graph);
+      HIP_TRY(e);
+    }
+    pl.captured = true;
+    return KFP_OK;
+  }
   const StepTables t = pl.dt.view();
   const int parts = pl.cfg.steps != 0 ? 2 : 1;
   for (int par = 0; par < 2; ++par)
@@ -1328,9 +1428,14 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     for (int n = 0; n <= g->nt; ++n)
       if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
   const Config cfg = choose_config(geo);
+  const int order = J > 1 ? g_order : 0;
+  if (order == 1 && cfg.steps == 0)
+    return fail(KFP_EINVAL,
+                "red-black order needs a march configuration (subdomains of at most 1056 rows; "
+                "tallest here %d)", geo.n_max);
   const PipeParams pp = pipe_params(geo, cfg);
   Plan *pl = nullptr;
-  if ((st = get_plan(geo, cfg, &pl, pp))) return st;
+  if ((st = get_plan(geo, cfg, &pl, pp, order))) return st;
   if ((st = sync_in(user, *pl))) return st;
   if ((st = load_instance(*pl, u0, f, s, p, q))) return st;
   const size_t win = (size_t)2 * (J - 1) * geo.nt * geo.nx;
@@ -1362,20 +1467,23 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   double dev_ms = 0.0, step_ms = 0.0, r = INFINITY;
   int k = 0;
   for (k = 1; k <= max_iter; ++k) {
-    const int par = (k - 1) & 1;
+    // red-black: one window updated in place, so no parity
+    const int par = order == 1 ? 0 : (k - 1) & 1;
     HIP_TRY(hipEventRecord(pl->ev0, pl->cs));
     if (graphs) {
       HIP_TRY(hipGraphLaunch(pl->gexec[par], pl->cs));
-    } else if ((st = launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt, par, t.n_items,
-                                             pl->cs, 1))) {
+    } else if ((st = order == 1 ? launch_iteration_rb(*pl, pl->cs, 1)
+                                : launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt, par,
+                                                          t.n_items, pl->cs, 1))) {
       return st;
     }
     HIP_TRY(hipEventRecord(pl->evm, pl->cs));
     if (cfg.steps != 0) {
       if (graphs) {
         HIP_TRY(hipGraphLaunch(pl->gexch[par], pl->cs));
-      } else if ((st = launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt, par, t.n_items,
-                                               pl->cs, 2))) {
+      } else if ((st = order == 1 ? launch_iteration_rb(*pl, pl->cs, 2)
+                                  : launch_iteration_direct(t, 1, pl->dt.inst.p, cfg, geo.nt,
+                                                            par, t.n_items, pl->cs, 2))) {
         return st;
       }
     }
@@ -1405,7 +1513,9 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   if (!converged) k = max_iter;
   double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
   HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
-  if (lambda_out && win) HIP_TRY(launch_copy((k & 1) ? pl->lam1.p : pl->lam0.p, lambda_out, win, pl->cs));
+  if (lambda_out && win)
+    HIP_TRY(launch_copy((order == 0 && (k & 1)) ? pl->lam1.p : pl->lam0.p, lambda_out, win,
+                        pl->cs));
   if ((st = sync_out(user, *pl))) return st;
   HIP_TRY(hipStreamSynchronize(pl->cs));
   if (stats) {
@@ -1987,6 +2097,14 @@ kfp_status kfp_set_kernel_timing(int32_t on) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   g_ktime = on != 0;
+  return KFP_OK;
+}
+
+kfp_status kfp_set_ordering(int32_t order) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (order != 0 && order != 1) return fail(KFP_EINVAL, "order must be 0 or 1");
+  g_order = order;
   return KFP_OK;
 }
 

@@ -38,9 +38,11 @@ def rel(a, b):
 def _auto_config():
     kfp.set_config(0)
     kfp.set_pipeline(-1)
+    kfp.set_ordering(kfp.PARALLEL)
     yield
     kfp.set_config(0)
     kfp.set_pipeline(-1)
+    kfp.set_ordering(kfp.PARALLEL)
     os.environ.pop("KFP_NO_GRAPH", None)
 
 
@@ -402,6 +404,56 @@ def test_without_overlap_converges_overlapped_and_batched():
     assert rc == 0
     for (uT, _, st), (ruT, _, rst) in zip(out, singles):
         assert st.iters == rst.iters and torch.equal(uT, ruT)
+
+
+# ------------------------------------------------ red-black (multiplicative) --
+RB_CASES = [
+    # nx, nv, nt, T, J, o, tr, p, q, cfg
+    (72, 64, 30, 0.2, 2, 4, D, 0.0, None, None),
+    (72, 64, 30, 0.2, 2, 2, R, 4.0, None, (4, 8, 5)),
+    (80, 96, 24, 0.2, 3, 2, R, 11.0, 2.5, None),
+    (64, 64, 24, 0.2, 4, 0, R, 3.0, None, (2, 12, 3)),
+    (50, 128, 20, 0.2, 4, 3, D, 0.0, None, (8, 4, 1)),
+    (40, 512, 12, 0.1, 2, 2, R, 4.0, None, (8, 17, 4, 2)),
+]
+
+
+@pytest.mark.parametrize("case", RB_CASES)
+def test_red_black_matches_oracle(case):
+    nx, nv, nt, T, J, o, tr, p, q, cfg = case
+    print(f"red-black case={case}", flush=True)
+    u0, f = inputs.random_fields(70 + J, nx, nv)
+    lam0 = inputs.random_traces(71, J, nt, nx)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-300, max_iter=4,
+                           lambda_init=lam0, order=1)
+    if cfg:
+        kfp.set_config(*cfg)
+    kfp.set_ordering(kfp.RED_BLACK)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-300,
+                                max_iter=4, lambda_init=dev(lam0), want_lambda=True)
+    assert st.iters == 4
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+    # converged: same count as the oracle, the monodomain solution
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-11, max_iter=400, order=1)
+    uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-11,
+                              max_iter=400)
+    assert st.iters == ref.iters
+    assert rel(host(uT), ref.uT) <= 1e-10
+    os.environ["KFP_NO_GRAPH"] = "1"
+    uT2, _, st2 = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-11,
+                                max_iter=400)
+    assert st2.iters == st.iters and torch.equal(uT, uT2)
+
+
+def test_red_black_rejects_the_one_step_kernel():
+    nx, nv, nt, T = 32, 64, 10, 0.1
+    u0, f = inputs.random_fields(3, nx, nv)
+    kfp.set_ordering(kfp.RED_BLACK)
+    kfp.set_config(4, 0, 0)
+    with pytest.raises(kfp.KfpError):
+        kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 2, R, p=4.0, tol=1e-10, max_iter=10)
 
 
 # ------------------------------------------------- overlapped iterations ----
