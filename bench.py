@@ -15,7 +15,10 @@ achieved bandwidth counts the algorithmic 24 bytes of one time step of one
 cell (read U^n and f, write U^{n+1}, FP64) against the HBM peak, the measure
 a one-step-per-launch streaming kernel is held to.  The multi-step kernel
 moves fewer bytes than that (it keeps U in registers across the steps of a
-launch); `traffic` reports the bytes its counters saw, when measured.
+launch); `traffic` is the HBM rate its counters saw (bytes per launch from
+rocprofv3 FETCH_SIZE and WRITE_SIZE at the live launch duration), or null
+when the kernel sources differ from the ones those counters were taken on.
+The same solve in red-black order is reported beside it.
 """
 from __future__ import annotations
 
@@ -43,6 +46,38 @@ BYTES_PER_CELL_STEP = 24.0  # one-step streaming: read U^n, read f, write U^{n+1
 # 2 fma), forward elimination (1 fma), back substitution (1 fma), segment
 # correction (2 fma) = 13 flops; the reduced separator system is not counted
 FLOPS_PER_CELL_STEP = 13.0
+# HBM bytes per launch of the march kernel at this workload and launch
+# configuration (8 wavefronts x 17 rows, 16 steps per launch), from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (separate runs, mean over
+# the 8125 dispatches of one solve), each scaled by what the counter reads
+# for the library's copy kernel of 1 GiB in the same process (FETCH_SIZE x
+# 1.99991, WRITE_SIZE x 1.00000).  Valid only for the kernel sources they
+# were measured on: any change to them and `traffic` is reported as null.
+TRAFFIC = {
+    "config": (8, 17, 16),
+    "sha256": {
+        "paper_1306_4596_amd/csrc/swr_kernels.hip":
+            "7513ee3bf545649c7651bb4cd8c15d4333eb00f5881ecea3b7b97e28b2e00586",
+        "paper_1306_4596_amd/csrc/kfp_internal.h":
+            "8d41beba0e5f360d20ad30f25702a2c956d1fd8224629a26ae0724c32a4f7899",
+    },
+    "read_bytes": 9401.7 * 1024 * 1.99991,
+    "write_bytes": 13728.0 * 1024 * 1.00000,
+}
+
+
+def measured_traffic(config):
+    """HBM bytes per launch from the counters, or None when the kernel
+    sources or the launch configuration differ from the measured ones."""
+    import hashlib
+
+    if tuple(config) != TRAFFIC["config"]:
+        return None
+    for rel, digest in TRAFFIC["sha256"].items():
+        with open(os.path.join(ROOT, rel), "rb") as fp:
+            if hashlib.sha256(fp.read()).hexdigest() != digest:
+                return None
+    return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
 
 
 def parse():
@@ -52,7 +87,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--traffic-gb", type=float, default=None,
+    ap.add_argument("--traffic-gb", type=float, default=None,  # overrides the measured bytes
                     help="HBM bytes per step-kernel launch measured by counters (GB)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
@@ -146,9 +181,14 @@ def main():
     bytes_launch = BYTES_PER_CELL_STEP * cells_launch
     achieved = bytes_launch / avg_launch_s / 1e9
     alu = FLOPS_PER_CELL_STEP * cells_launch / avg_launch_s / 1e12
+    # traffic: the counters' HBM bytes per launch as a rate at the live
+    # launch duration (the unit of `achieved`)
+    tbytes = args.traffic_gb * 1e9 if args.traffic_gb else measured_traffic((waves, seg, kper))
+    traffic = round(tbytes / avg_launch_s / 1e9, 1) if tbytes else None
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": args.traffic_gb, "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "traffic": traffic, "traffic_bytes_per_launch": tbytes,
+            "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "bytes_per_cell_step": BYTES_PER_CELL_STEP, "cell_steps_per_launch": cells_launch,
             "alg_bytes_per_launch": bytes_launch,
             "fp64_tflops": round(alu, 3), "fp64_frac": round(alu / FP64_PEAK_TFLOPS, 4),
@@ -185,6 +225,19 @@ def main():
             sweep[str(p)] = {"iters": st.iters, "seconds": round(time.perf_counter() - t1, 4),
                              "residual": st.residual}
         out["p_sweep"] = sweep
+        # the same solve in red-black order (even subdomains, then odd ones
+        # with the traces just sent): about half the iterations; reported
+        # beside the parallel-order metric, not in it
+        kfp.set_ordering(kfp.RED_BLACK)
+        solve(P_MAIN)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, st = solve(P_MAIN)
+        torch.cuda.synchronize()
+        out["red_black"] = {"iters": st.iters, "time_to_tol_s": round(time.perf_counter() - t1, 4),
+                            "residual": st.residual,
+                            "cell_steps_per_s": st.cell_steps / st.device_seconds}
+        kfp.set_ordering(kfp.PARALLEL)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -224,3 +224,25 @@ def test_partitioned_tables_solve_the_paper_matrix(lib, nx, nv, nt, T, J, o, tr,
         ref = np.linalg.solve(A, d)
         assert np.allclose(x, ref, rtol=0, atol=1e-12 * np.abs(ref).max()), (j, P)
         red_off += P - 1
+
+
+def test_bench_traffic_only_for_the_measured_kernel(tmp_path, monkeypatch):
+    """The roofline's counter traffic is reported only for the launch
+    configuration and kernel sources the counters were taken on."""
+    import importlib
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    bench = importlib.import_module("bench")
+    assert bench.measured_traffic((1, 2, 3)) is None
+    got = bench.measured_traffic(bench.TRAFFIC["config"])
+    assert got is None or got == bench.TRAFFIC["read_bytes"] + bench.TRAFFIC["write_bytes"]
+    # a copy of the tree with one changed source byte reports nothing
+    for rel in bench.TRAFFIC["sha256"]:
+        src = os.path.join(root, rel)
+        dst = tmp_path / rel
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        dst.write_bytes(open(src, "rb").read() + b" ")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic(bench.TRAFFIC["config"]) is None
