@@ -170,6 +170,32 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter
     return SWRResult(uT, lam_out[: 2 * nI], k, hist[:k].copy(), ovl[:k].copy(), st)
 
 
+def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter=100,
+                      n_windows=1, s=None, q=None, guess=False):
+    """SWR on time windows: [0, T] is cut into n_windows windows of whole
+    steps (window w takes steps floor(w nt / W) .. floor((w+1) nt / W) - 1),
+    and each is solved by swr_solve to the tolerance, starting from the glued
+    iterate at the end of the window before (window 0 from u0), with zero
+    initial traces or (guess) the u0_guess extension of that start state.
+    Returns (uT, per-window iteration counts, per-window statuses)."""
+    u0 = _f64(u0)
+    dt = T / nt
+    start = u0
+    iters, status = [], []
+    for w in range(n_windows):
+        n0 = w * nt // n_windows
+        n1 = (w + 1) * nt // n_windows
+        ntw = n1 - n0
+        sw = None if s is None else _f64(s)[n0:n1 + 1]
+        lam0 = u0_guess(start, ntw, J, overlap, transmission, p, q) if guess and J > 1 else None
+        r = swr_solve(start, f, ntw * dt, ntw, J, overlap, transmission, p=p, tol=tol,
+                      max_iter=max_iter, lambda_init=lam0, s=sw, q=q)
+        iters.append(r.iters)
+        status.append(r.status)
+        start = r.uT
+    return start, iters, status
+
+
 def u0_guess(u0, nt, J, overlap, transmission, p=0.0, q=None):
     """Initial traces lambda^0(n) = Q(u0) at each interface node, for every n."""
     u0 = _f64(u0)

@@ -370,6 +370,47 @@ def test_red_black_fixed_point_dense(tr, o, p):
     assert rho_rb < rho_par < 1.0
 
 
+# ------------------------------------------------------------ time windows --
+def test_windows_compose_to_the_monodomain_solution():
+    """Converged SWR on consecutive windows reproduces the monodomain march
+    over the whole [0, T] (the time step is Markov: each window starts from
+    the glued end state of the one before, with the source's time levels
+    shifted), including uneven windows and one-step windows; one window is
+    the plain solve, bit for bit."""
+    nx, nv, nt, T = 16, 24, 23, 0.3
+    u0, f = inputs.random_fields(81, nx, nv)
+    s = 1.0 + 0.5 * np.sin(3.0 * np.arange(nt + 1))
+    m = oracle.mono_solve(u0, f, T, nt, s)
+    for tr, p in ((R, 4.0), (D, 0.0)):
+        one, it1, _ = oracle.swr_solve_windows(u0, f, T, nt, 3, 2, tr, p=p, tol=1e-13,
+                                                max_iter=500, n_windows=1, s=s)
+        plain = oracle.swr_solve(u0, f, T, nt, 3, 2, tr, p=p, tol=1e-13, max_iter=500, s=s)
+        assert np.array_equal(one, plain.uT) and it1 == [plain.iters]
+        for W in (2, 5, nt):
+            uT, its, st = oracle.swr_solve_windows(u0, f, T, nt, 3, 2, tr, p=p, tol=1e-13,
+                                                   max_iter=500, n_windows=W, s=s)
+            assert all(x == 0 for x in st) and len(its) == W
+            assert rel_l2(uT, m) <= 1e-10, (tr, W)
+    # and from the extension of each start state as initial traces
+    uT, _, _ = oracle.swr_solve_windows(u0, f, T, nt, 3, 2, R, p=4.0, tol=1e-13, max_iter=500,
+                                        n_windows=4, s=s, guess=True)
+    assert rel_l2(uT, m) <= 1e-10
+
+
+def test_windows_need_fewer_iterations_per_window():
+    """Waveform relaxation converges faster on shorter windows; the
+    extension of the start state as initial traces saves iterations."""
+    nx, nv, nt, T = 16, 32, 40, 0.8
+    u0, f = inputs.random_fields(82, nx, nv)
+    _, it1, _ = oracle.swr_solve_windows(u0, f, T, nt, 2, 2, D, tol=1e-10, max_iter=500)
+    _, it4, _ = oracle.swr_solve_windows(u0, f, T, nt, 2, 2, D, tol=1e-10, max_iter=500,
+                                         n_windows=4)
+    _, it4g, _ = oracle.swr_solve_windows(u0, f, T, nt, 2, 2, D, tol=1e-10, max_iter=500,
+                                          n_windows=4, guess=True)
+    assert max(it4) < it1[0]
+    assert sum(it4g) <= sum(it4)
+
+
 def test_dirichlet_error_equation_monotone_geometric():
     """Error equation (f = 0, u0 = 0, random lambda^0): the maximum principle
     of Section 4 makes max|lambda^k| non-increasing, strictly decreasing with
