@@ -18,7 +18,7 @@ moves fewer bytes than that (it keeps U in registers across the steps of a
 launch); `traffic` is the HBM rate its counters saw (bytes per launch from
 rocprofv3 FETCH_SIZE and WRITE_SIZE at the live launch duration), or null
 when the kernel sources differ from the ones those counters were taken on.
-The same solve in red-black order is reported beside it.
+The same solve in red-black order and on 4 time windows is reported beside it.
 """
 from __future__ import annotations
 
@@ -238,6 +238,19 @@ def main():
                             "residual": st.residual,
                             "cell_steps_per_s": st.cell_steps / st.device_seconds}
         kfp.set_ordering(kfp.PARALLEL)
+        # and on 4 time windows, each started from the extension of the
+        # glued state the window before ends with
+        kfp.swr_solve_windows(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL, max_iter=1000,
+                              n_windows=4, guess=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, its, st = kfp.swr_solve_windows(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL,
+                                           max_iter=1000, n_windows=4, guess=True)
+        torch.cuda.synchronize()
+        out["time_windows"] = {"n_windows": 4, "iters": its,
+                               "time_to_tol_s": round(time.perf_counter() - t1, 4),
+                               "residual": st.residual,
+                               "cell_steps_per_s": st.cell_steps / st.device_seconds}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -234,6 +234,37 @@ kfp_status kfp_set_pipeline(int32_t inflight);
 kfp_status kfp_set_ordering(int32_t order);
 
 /*
+ * kfp_swr_solve_windows -- SWR on time windows.  [0, T] is cut into
+ * n_windows windows of whole time steps (window w takes the steps
+ * floor(w nt / n_windows) .. floor((w+1) nt / n_windows) - 1, all with
+ * dt = T / nt), and each window is solved by SWR (as kfp_swr_solve_pq, in
+ * the order kfp_set_ordering selects) to the tolerance, starting from the
+ * glued iterate at the end of the window before (window 0 from u0) and
+ * taking the source levels s[n] of its own steps.  Only one window's trace
+ * planes are held, 2(J-1) x (nt / n_windows) x nx per buffer, and
+ * waveform relaxation converges in fewer iterations on shorter windows.
+ * Converged windows compose to the monodomain solution over [0, T] (the
+ * time step is Markov).
+ *   guess: initial traces of each window: 0 zero, 1 the extension Q(start
+ *     state) of kfp_u0_guess_pq.
+ *   window_iters: [host] n_windows, or NULL: the iterations of each window.
+ *   stats: iteration counts, cell-steps and times summed over the windows,
+ *     residual = the largest final residual of a window; res_history, if
+ *     given, has n_windows * max_iter entries: window w's history at
+ *     w * max_iter.
+ *   Arguments as kfp_swr_solve_pq (u0 and uT may be the same buffer);
+ *   1 <= n_windows <= nt, else KFP_EINVAL.  The call allocates two
+ *   intermediate fields and (guess = 1) one window of traces, and returns
+ *   when the caller's stream has finished with them.  KFP_ENOCONV if a
+ *   window did not converge (the remaining windows are still solved).
+ */
+kfp_status kfp_swr_solve_windows(const kfp_grid *g, const double *u0, const double *f,
+                                 const double *s, int32_t J, int32_t overlap, int32_t tr,
+                                 double p, double q, double tol, int32_t max_iter,
+                                 int32_t n_windows, int32_t guess, double *uT,
+                                 int32_t *window_iters, kfp_swr_stats *stats, void *stream);
+
+/*
  * kfp_set_kernel_timing -- with on != 0, overlapped-iteration solves launch
  * their kernels directly (not from a replayed graph) with HIP events around
  * every time-step kernel launch, so that kfp_swr_stats.step_seconds holds

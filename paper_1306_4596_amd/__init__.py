@@ -36,6 +36,7 @@ from .binding import (  # noqa: F401
     subdomain_rows,
     swr_batch,
     swr_solve,
+    swr_solve_windows,
     tune,
     u0_guess,
 )

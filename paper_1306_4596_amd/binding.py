@@ -93,6 +93,9 @@ def load_library():
     lib.kfp_swr_solve_pq.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, f64, i32, vp, vp, vp,
                                      ctypes.POINTER(Stats), vp]
     lib.kfp_u0_guess_pq.argtypes = [G, vp, i32, i32, i32, f64, f64, vp, vp]
+    lib.kfp_swr_solve_windows.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, f64, i32, i32,
+                                          i32, vp, ctypes.POINTER(i32), ctypes.POINTER(Stats),
+                                          vp]
     lib.kfp_u0_guess.argtypes = [G, vp, i32, i32, i32, f64, vp, vp]
     lib.kfp_swr_batch.argtypes = [i32, ctypes.POINTER(Instance), f64, i32,
                                   ctypes.POINTER(Stats), vp]
@@ -110,7 +113,8 @@ def load_library():
     lib.kfp_last_error.restype = ctypes.c_char_p
     lib.kfp_last_error.argtypes = []
     lib.kfp_release_workspace.restype = None
-    for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_u0_guess",
+    for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_swr_solve_windows",
+                 "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
                  "kfp_set_ordering", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
@@ -216,6 +220,28 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter
     _check(rc, allow_noconv=not raise_noconv)
     h = hist[: st.iters].copy() if hist is not None else None
     return uT, lam, SWRStats(st, h)
+
+
+def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter=200,
+                      n_windows=1, s=None, q=None, guess=False, stream=None):
+    """SWR on n_windows consecutive time windows (each from the glued end
+    state of the one before).  Returns (uT, per-window iteration counts,
+    SWRStats summed over the windows)."""
+    import numpy as np
+    import torch
+
+    nv, nx = _shape(u0)
+    uT = torch.empty_like(u0)
+    keep, sp = _host_s(s, nt)
+    its = (ctypes.c_int32 * int(n_windows))()
+    st = Stats()
+    g = _grid(nx, nv, nt, T)
+    rc = load_library().kfp_swr_solve_windows(
+        ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J), int(overlap), int(transmission),
+        float(p), float(p if q is None else q), float(tol), int(max_iter), int(n_windows),
+        1 if guess else 0, _ptr(uT), its, ctypes.byref(st), _stream(stream))
+    _check(rc, allow_noconv=True)
+    return uT, [int(x) for x in its], SWRStats(st, None)
 
 
 def u0_guess(u0, nt, J, overlap, transmission, p=0.0, stream=None, q=None):

@@ -2048,6 +2048,106 @@ kfp_status kfp_swr_solve_pq(const kfp_grid *g, const double *u0, const double *f
 static kfp_status u0_guess_impl(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
                                 int32_t tr, double p, double q, double *lambda, void *stream);
 
+// Time windows: [0, T] cut into W windows of whole steps (window w takes the
+// steps floor(w nt / W) .. floor((w+1) nt / W) - 1, the same dt); each is
+// solved by SWR to the tolerance from the glued iterate at the end of the
+// window before (window 0 from u0), with the source levels of its steps, so
+// only one window's traces are held.  guess: initial traces of each window
+// 0 zero, 1 the extension Q(start state) of kfp_u0_guess.
+static kfp_status swr_windows_impl(const kfp_grid *g, const double *u0, const double *f,
+                                   const double *s, int J, int o, int tr, double p, double q,
+                                   double tol, int max_iter, int W, int guess, double *uT,
+                                   int32_t *window_iters, kfp_swr_stats *stats,
+                                   hipStream_t user) {
+  const double t_start = now_s();
+  Geo geo;
+  kfp_status st = make_geo(g, J, o, tr, p, geo);
+  if (st) return st;
+  if (W < 1 || W > g->nt) return fail(KFP_EINVAL, "n_windows must be in 1..nt (got %d)", W);
+  if (guess != 0 && guess != 1) return fail(KFP_EINVAL, "guess must be 0 or 1");
+  if (!u0 || !f || !uT) return fail(KFP_EINVAL, "u0, f and uT must be non-NULL");
+  if (!(tol > 0.0)) return fail(KFP_EINVAL, "tol must be > 0");
+  if (max_iter < 1) return fail(KFP_EINVAL, "max_iter must be >= 1");
+  const double dt = g->T / g->nt;
+  const size_t field = (size_t)(g->nv + 1) * g->nx;
+  const int ntw_max = (g->nt + W - 1) / W;
+  struct Bufs {
+    double *tmp = nullptr, *lam = nullptr;
+    int *ab = nullptr;
+    ~Bufs() {
+      if (tmp) (void)hipFree(tmp);
+      if (lam) (void)hipFree(lam);
+      if (ab) (void)hipFree(ab);
+    }
+  } b;
+  if (W > 1) HIP_TRY(hipMalloc((void **)&b.tmp, 2 * field * sizeof(double)));
+  const bool use_guess = guess == 1 && J > 1;
+  if (use_guess) {
+    HIP_TRY(hipMalloc((void **)&b.lam, (size_t)2 * (J - 1) * ntw_max * g->nx * sizeof(double)));
+    std::vector<int> ab;
+    for (int j = 0; j + 1 < J; ++j) {
+      ab.push_back(geo.sub[j + 1].a);
+      ab.push_back(geo.sub[j].b);
+    }
+    HIP_TRY(hipMalloc((void **)&b.ab, ab.size() * sizeof(int)));
+    HIP_TRY(hipMemcpy(b.ab, ab.data(), ab.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  kfp_swr_stats agg{};
+  kfp_status worst = KFP_OK;
+  const double *start = u0;
+  for (int w = 0; w < W; ++w) {
+    const int n0 = (int)((long)w * g->nt / W);
+    const int n1 = (int)((long)(w + 1) * g->nt / W);
+    const int ntw = n1 - n0;
+    kfp_grid gw = *g;
+    gw.nt = ntw;
+    gw.T = ntw * dt;
+    double *out = (w == W - 1) ? uT : b.tmp + (size_t)(w & 1) * field;
+    if (use_guess)
+      HIP_TRY(launch_u0_guess(start, g->nx, ntw, J, b.ab, tr, p, q, 2.0 / g->nv, b.lam, user));
+    kfp_swr_stats sw{};
+    if (stats && stats->res_history) sw.res_history = stats->res_history + (size_t)w * max_iter;
+    st = swr_solve_impl(&gw, start, f, s ? s + n0 : nullptr, J, o, tr, p, q, tol, max_iter,
+                        use_guess ? b.lam : nullptr, out, nullptr, &sw, user);
+    if (st != KFP_OK && st != KFP_ENOCONV) return st;
+    if (st == KFP_ENOCONV) worst = KFP_ENOCONV;
+    if (window_iters) window_iters[w] = sw.iters;
+    agg.iters += sw.iters;
+    agg.restarted |= sw.restarted;
+    agg.residual = std::max(agg.residual, sw.residual);
+    agg.device_seconds += sw.device_seconds;
+    agg.step_seconds += sw.step_seconds;
+    agg.step_launches += sw.step_launches;
+    agg.cell_steps += sw.cell_steps;
+    agg.alg_bytes += sw.alg_bytes;
+    start = out;
+  }
+  // the window buffers are freed on return: the caller's stream must have
+  // consumed them (the last window wrote uT itself)
+  HIP_TRY(hipStreamSynchronize(user));
+  if (stats) {
+    double *h = stats->res_history;
+    *stats = agg;
+    stats->res_history = h;
+    stats->seconds = now_s() - t_start;
+  }
+  if (worst) return fail(KFP_ENOCONV, "a window did not converge in %d iterations", max_iter);
+  return KFP_OK;
+}
+
+kfp_status kfp_swr_solve_windows(const kfp_grid *g, const double *u0, const double *f,
+                                 const double *s, int32_t J, int32_t overlap, int32_t tr,
+                                 double p, double q, double tol, int32_t max_iter,
+                                 int32_t n_windows, int32_t guess, double *uT,
+                                 int32_t *window_iters, kfp_swr_stats *stats, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (tr == KFP_ROBIN && !(q > 0.0 && std::isfinite(q)))
+    return fail(KFP_EINVAL, "Robin transmission needs q > 0 (got %g)", q);
+  return swr_windows_impl(g, u0, f, s, J, overlap, tr, p, q, tol, max_iter, n_windows, guess,
+                          uT, window_iters, stats, (hipStream_t)stream);
+}
+
 kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,
                         int32_t tr, double p, double *lambda, void *stream) {
   return u0_guess_impl(g, u0, J, overlap, tr, p, p, lambda, stream);

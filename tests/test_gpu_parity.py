@@ -456,6 +456,46 @@ def test_red_black_rejects_the_one_step_kernel():
         kfp.swr_solve(dev(u0), dev(f), T, nt, 2, 2, R, p=4.0, tol=1e-10, max_iter=10)
 
 
+# ------------------------------------------------------------ time windows --
+WINDOW_CASES = [
+    # nx, nv, nt, T, J, o, tr, p, q, windows, guess, ordering
+    (48, 64, 37, 0.2, 2, 2, R, 4.0, None, 4, False, 0),
+    (48, 64, 37, 0.2, 4, 2, R, 3.0, 1.5, 5, True, 0),
+    (40, 64, 12, 0.1, 2, 4, D, 0.0, None, 12, True, 0),
+    (64, 96, 30, 0.2, 3, 0, R, 5.0, None, 3, True, 1),
+    (32, 32, 20, 0.1, 1, 0, D, 0.0, None, 2, False, 0),
+]
+
+
+@pytest.mark.parametrize("case", WINDOW_CASES)
+def test_time_windows_match_oracle(case):
+    nx, nv, nt, T, J, o, tr, p, q, W, guess, order = case
+    print(f"windows case={case}", flush=True)
+    u0, f = inputs.random_fields(90 + W, nx, nv)
+    s = 1.0 + 0.3 * np.cos(np.arange(nt + 1))
+    kfp.set_ordering(order)
+    ref, rit, _ = oracle.swr_solve_windows(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-11,
+                                           max_iter=400, n_windows=W, s=s, guess=guess)
+    if order:  # the oracle in the same order
+        start = u0
+        rit = []
+        for w in range(W):
+            n0, n1 = w * nt // W, (w + 1) * nt // W
+            lam0 = oracle.u0_guess(start, n1 - n0, J, o, tr, p, q) if guess and J > 1 else None
+            r = oracle.swr_solve(start, f, (n1 - n0) * (T / nt), n1 - n0, J, o, tr, p=p, q=q,
+                                 tol=1e-11, max_iter=400, lambda_init=lam0, s=s[n0:n1 + 1],
+                                 order=1)
+            rit.append(r.iters)
+            start = r.uT
+        ref = start
+    uT, its, st = kfp.swr_solve_windows(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-11,
+                                        max_iter=400, n_windows=W, s=s, guess=guess)
+    assert its == rit and st.iters == sum(rit)
+    assert rel(host(uT), ref) <= 1e-10
+    m = oracle.mono_solve(u0, f, T, nt, s)
+    assert rel(host(uT), m) <= 1e-9
+
+
 # ------------------------------------------------- overlapped iterations ----
 PIPE_CASES = [
     # nx, nv, nt, T, J, o, tr, p, (waves, seg, steps[, groups]) or None
