@@ -35,6 +35,8 @@ struct InstDev {
   int nx, nv, nt, tr;
   int active;                   // 0: frozen (converged), skipped by every kernel
   int nonovl;                   // 1: no overlap (END_RFV interface rows)
+  int xmode;                    // exchange mode when a launch leaves it to the instance
+  int pad_;
 };
 
 // One subdomain of one instance.  Rows are local: 0 .. n-1 are the unknown
@@ -139,6 +141,7 @@ struct PipeCtl {
   int M, d, L;   // slots, lag between iterations (launches), launches per window
   int restart_on_nonfinite;
   int last_busy; // last launch index with any slot scheduled
+  int rb;        // 1: the units are red-black half-sweeps (iteration k = units 2k-1, 2k)
   double tol;
 };
 

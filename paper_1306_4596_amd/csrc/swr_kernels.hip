@@ -81,6 +81,8 @@ __device__ __forceinline__ InstDev load_inst(KConst<InstDev> *p) {
   I.tr = p->tr;
   I.active = p->active;
   I.nonovl = p->nonovl;
+  I.xmode = p->xmode;
+  I.pad_ = 0;
   return I;
 }
 
@@ -775,11 +777,14 @@ __global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in,
 // 1: only the planes sent by even subdomains (plane 2j when j is even, plane
 // 2j+1 when j+1 is even); 2: only those sent by odd subdomains, and the
 // residual (red-black order: run after the even, then the odd half-sweep).
-__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, int S, int mode) {
+// A launch with mode 0 takes each instance's own mode (InstDev::xmode).
+__global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, int S, int mode_in) {
   __shared__ unsigned long long red[4];
   const ExItem ex = load_const(as_const(t.ex) + blockIdx.y);
   const InstDev I = load_inst(as_const(t.inst) + ex.inst);
   if (!I.active) return;
+  // mode 0 at launch: the instance's own (red-black half-sweep slots)
+  const int mode = mode_in != 0 ? mode_in : I.xmode;
   const size_t plane = (size_t)I.nt * I.nx;
   // levels covered: the whole window, or (pipelined) the instance's block
   size_t e_begin = 0, e_end = plane;
@@ -820,6 +825,14 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
     }
     if (mode == 0 || (j & 1) == mode - 1) lout[(size_t)(2 * j) * plane + e] = toR;
     if (mode == 0 || ((j + 1) & 1) == mode - 1) lout[(size_t)(2 * j + 1) * plane + e] = toL;
+    // overlapped red-black half-sweeps write a window of their own: the even
+    // half-sweep also carries over the odd subdomains' traces it was solved
+    // with, which the odd half-sweep's residual needs (Dirichlet: the fixed
+    // node values of the even subdomains)
+    if (mode == 1 && lout != lin) {
+      const size_t other = (size_t)(2 * j + ((j & 1) ? 0 : 1)) * plane + e;
+      lout[other] = lin[other];
+    }
     const unsigned long long ra = (unsigned long long)__double_as_longlong(fabs(ua - ua_hi));
     const unsigned long long rb = (unsigned long long)__double_as_longlong(fabs(ub_lo - ubh));
     r = ra > r ? ra : r;
@@ -842,15 +855,21 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
 // Scheduler of pipelined iterations, run by one lane after every launch:
 // records the iterations whose last block just ran (residual history,
 // convergence, the first non-finite residual), then assigns each slot its
-// block of the next launch (slot i: the iteration k = i mod M, if any, with
-// 0 <= t - d (k-1) < L), clearing the residual of iterations that start.
+// block of the next launch (slot i: the unit k = i mod M, if any, with
+// 0 <= t - d (k-1) < L), clearing the residual of units that start.  A unit
+// is an iteration, or in red-black order a half-sweep (unit 2k-1 marches the
+// even subdomains of iteration k, unit 2k the odd ones and closes it).
 __global__ void pipe_tick_kernel(PipeCtl *c, int *blk, int *iter, unsigned long long *res,
                                  double *hist) {
   if (threadIdx.x != 0) return;
   const int M = c->M, d = c->d, L = c->L;
+  // red-black: the units are half-sweeps, unit 2k closing iteration k
+  const int rb = c->rb;
   for (int i = 0; i < M; ++i) {
     if (blk[i] != L - 1) continue;
-    const int k = iter[i];
+    const int u = iter[i];
+    if (rb && (u & 1)) continue;  // an even-subdomain half-sweep: no residual yet
+    const int k = rb ? u / 2 : u;
     const double r = __longlong_as_double((long long)res[i]);
     hist[k - 1] = r;
     c->done = k;
@@ -864,11 +883,12 @@ __global__ void pipe_tick_kernel(PipeCtl *c, int *blk, int *iter, unsigned long 
   const int t1 = c->t + 1;
   c->t = t1;
   const int khi = t1 / d + 1;
+  const int umax = rb ? 2 * c->kmax : c->kmax;
   bool any = false;
   for (int i = 0; i < M; ++i) {
     int b = -1;
     const int k = khi - (((khi - i) % M) + M) % M;
-    if (c->stop == 0 && k >= 1 && k <= c->kmax) {
+    if (c->stop == 0 && k >= 1 && k <= umax) {
       const int bb = t1 - d * (k - 1);
       if (bb >= 0 && bb < L) b = bb;
     }
@@ -898,6 +918,7 @@ __global__ void assemble_kernel(const double *__restrict__ U, const int *__restr
     const int i = (int)(e / nx);
     const int m = (int)(e - (size_t)i * nx);
     const int r = rowmap[i];
+    if (r == -2) continue;  // node taken from another state
     uT[e] = r >= 0 ? U[(size_t)r * nx + m] : 0.0;
   }
 }

@@ -893,6 +893,9 @@ struct Plan {
   hipEvent_t ev_fork = nullptr, ev_blk = nullptr, ev_join = nullptr, ev_mar = nullptr,
              ev_join3 = nullptr;
   DevBuf<int> blkseq;  // 0, 1, ..., L-1: the time block of each launch
+  // [2][nv+1]: rowmap restricted to nodes owned by even / odd subdomains
+  // (-2 elsewhere), for the output of pipelined red-black iterations
+  DevBuf<int> rowmap_rb;
   // pipelined iterations (M > 0): M slot instances with their own state and
   // trace window; slot i writes window i and reads window i-1 (mod M)
   int M = 0, d = 0, L = 0, G = 0;
@@ -917,6 +920,7 @@ struct Plan {
     ctl.release();
     if (h_ctl) (void)hipHostFree(h_ctl);
     blkseq.release();
+    rowmap_rb.release();
     if (cs2) (void)hipStreamDestroy(cs2);
     if (cs3) (void)hipStreamDestroy(cs3);
     for (hipEvent_t e : {ev_fork, ev_blk, ev_join, ev_mar, ev_join3})
@@ -958,12 +962,16 @@ struct PipeParams {
 // work: F iterations in flight (d = L / F launches apart) so that a launch
 // holds about kPipeTarget work items; M = ceil(L/d) + 1 slots, each with a
 // state and a trace window, within a memory budget.
-static PipeParams pipe_params(const Geo &g, const Config &c) {
+// Red-black order (order 1): the units in flight are half-sweeps, each with
+// the work items of one colour; they overlap below half the target, and the
+// slot count is even, so that every slot serves one colour.
+static PipeParams pipe_params(const Geo &g, const Config &c, int order = 0) {
   PipeParams pp;
-  if (g_pipe == 0 || g_order != 0 || c.steps < 1 || g.J < 2) return pp;
+  if (g_pipe == 0 || c.steps < 1 || g.J < 2) return pp;
   const int L = (g.nt + c.steps - 1) / c.steps;
-  const long items = (long)g.J * ((g.nx + tile_width(c) - 1) / tile_width(c));
-  if (g_pipe < 0 && items >= kPipeItems) return pp;
+  const long tiles = (g.nx + tile_width(c) - 1) / tile_width(c);
+  const long items = order == 1 ? (long)((g.J + 1) / 2) * tiles : (long)g.J * tiles;
+  if (g_pipe < 0 && items >= (order == 1 ? kPipeTarget / 2 : kPipeItems)) return pp;
   long F = g_pipe > 0 ? g_pipe : (kPipeTarget + items - 1) / items;
   F = std::min<long>(F, L);
   if (F < 2) return pp;
@@ -971,7 +979,8 @@ static PipeParams pipe_params(const Geo &g, const Config &c) {
   const double per_slot = 8.0 * ((double)2 * (g.J - 1) * g.nt * g.nx + 2.0 * g.rows * g.nx);
   const double budget = 24e9;
   for (;;) {
-    const int M = (L + d - 1) / d + 1;
+    int M = (L + d - 1) / d + 1;
+    if (order == 1) M += M & 1;
     if (M * per_slot <= budget || d >= L) {
       if (M >= 3) {
         pp.M = M;
@@ -1017,6 +1026,20 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out,
     for (int l = 0; l < L; ++l) seq[l] = l;
     HIP_TRY(pl->blkseq.alloc(L));
     HIP_TRY(hipMemcpy(pl->blkseq.p, seq.data(), sizeof(int) * L, hipMemcpyHostToDevice));
+    std::vector<int> rm(2 * (size_t)(geo.nv + 1), -2);
+    for (int i = 0; i <= geo.nv; ++i) {
+      const int r = geo.rowmap[i];
+      if (r < 0) {
+        rm[i] = rm[geo.nv + 1 + i] = r;
+        continue;
+      }
+      int j = 0;
+      while (j + 1 < geo.J && r >= geo.row_off[j + 1]) ++j;
+      rm[(j & 1) * (geo.nv + 1) + i] = r;
+    }
+    HIP_TRY(pl->rowmap_rb.alloc(rm.size()));
+    HIP_TRY(hipMemcpy(pl->rowmap_rb.p, rm.data(), sizeof(int) * rm.size(),
+                      hipMemcpyHostToDevice));
     HIP_TRY(hipStreamCreateWithFlags(&pl->cs2, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&pl->cs3, hipStreamNonBlocking));
     for (hipEvent_t *e : {&pl->ev_fork, &pl->ev_blk, &pl->ev_join, &pl->ev_mar, &pl->ev_join3})
@@ -1080,11 +1103,21 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   for (int i = 0; i < n_inst; ++i) {
     const int sub_base = (int)h.subs.size();
     add_instance_cfg(geo, p, q, pl.cfg.waves, pl.cfg.seg, pl.cfg.steps, i, h);
-    make_items(geo, sub_base, tile_width(pl.cfg), h.items);
+    if (pl.M > 0 && pl.order == 1) {
+      // red-black half-sweep slots: odd slots march the even subdomains,
+      // even slots the odd ones
+      std::vector<Item> all;
+      make_items(geo, sub_base, tile_width(pl.cfg), all);
+      const int colour = (i & 1) ? 0 : 1;
+      for (const Item &it : all)
+        if (((it.sub - sub_base) & 1) == colour) h.items.push_back(it);
+    } else {
+      make_items(geo, sub_base, tile_width(pl.cfg), h.items);
+    }
     make_ex(geo, i, h.ex);
   }
   pl.n_red = 0;
-  if (pl.order == 1) {  // even subdomains first (single instance: sub = j)
+  if (pl.order == 1 && pl.M == 0) {  // even subdomains first (single instance: sub = j)
     std::stable_partition(h.items.begin(), h.items.end(),
                           [](const Item &it) { return (it.sub & 1) == 0; });
     for (const Item &it : h.items) pl.n_red += (it.sub & 1) == 0;
@@ -1123,6 +1156,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
       ins[i].lam[0] = pl.W.p + (size_t)((i + pl.M - 1) % pl.M) * win;  // read: iteration k-1
       ins[i].lam[1] = pl.W.p + (size_t)i * win;                        // written: iteration k
       ins[i].res = pl.pres.p + i;
+      if (pl.order == 1) ins[i].xmode = (i & 1) ? 1 : 2;  // the traces its colour sends
     }
   }
   HIP_TRY(pl.dt.upload(h, ins, pl.cs));
@@ -1322,7 +1356,8 @@ static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double
     if (st) return st;
     pl.gpipe_hist = pl.hist.p;
   }
-  const long max_launches = (long)pl.L + (long)pl.d * (max_iter - 1) + pl.G;
+  const long units = pl.order == 1 ? 2L * max_iter : (long)max_iter;
+  const long max_launches = (long)pl.L + (long)pl.d * (units - 1) + pl.G;
   double dev_ms = 0.0, step_ms = 0.0;
   long launches = 0;
   for (;;) {
@@ -1334,6 +1369,7 @@ static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double
     c.L = pl.L;
     c.restart_on_nonfinite = (had_guess && !restarted) ? 1 : 0;
     c.last_busy = -1;
+    c.rb = pl.order == 1 ? 1 : 0;
     c.tol = tol;
     HIP_TRY(hipMemcpyAsync(pl.ctl.p, &c, sizeof c, hipMemcpyHostToDevice, pl.cs));
     HIP_TRY(hipMemsetAsync(pl.blk.p, 0xff, sizeof(int) * pl.M, pl.cs));  // all idle
@@ -1384,11 +1420,31 @@ static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double
                          pl.cs));
   HIP_TRY(hipStreamSynchronize(pl.cs));
   const double r = hist[k - 1];
-  const int slot = k % pl.M;
-  const double *U = pl.slotU.p + (size_t)slot * 2 * state + ((pl.L & 1) ? state : 0);
-  HIP_TRY(launch_assemble(U, pl.rowmap.p, uT, geo.nv, geo.nx, pl.cs));
-  if (lambda_out && win)
-    HIP_TRY(launch_copy(pl.W.p + (size_t)slot * win, lambda_out, win, pl.cs));
+  const size_t fin = (pl.L & 1) ? state : 0;  // ping-pong half holding level nt
+  if (pl.order == 1) {
+    // iteration k: the even subdomains' state and traces from the slot of
+    // half-sweep 2k-1, the odd ones' from the slot of half-sweep 2k
+    const int sr = (2 * k - 1) % pl.M, sb = (2 * k) % pl.M;
+    HIP_TRY(launch_assemble(pl.slotU.p + (size_t)sr * 2 * state + fin, pl.rowmap_rb.p, uT,
+                            geo.nv, geo.nx, pl.cs));
+    HIP_TRY(launch_assemble(pl.slotU.p + (size_t)sb * 2 * state + fin,
+                            pl.rowmap_rb.p + (geo.nv + 1), uT, geo.nv, geo.nx, pl.cs));
+    if (lambda_out && win) {
+      const size_t plane = (size_t)geo.nt * geo.nx;
+      for (int pidx = 0; pidx < 2 * (geo.J - 1); ++pidx) {
+        const int j = pidx / 2, sender = (pidx & 1) ? j + 1 : j;
+        const int slot = (sender & 1) ? sb : sr;
+        HIP_TRY(launch_copy(pl.W.p + (size_t)slot * win + pidx * plane,
+                            lambda_out + pidx * plane, plane, pl.cs));
+      }
+    }
+  } else {
+    const int slot = k % pl.M;
+    HIP_TRY(launch_assemble(pl.slotU.p + (size_t)slot * 2 * state + fin, pl.rowmap.p, uT,
+                            geo.nv, geo.nx, pl.cs));
+    if (lambda_out && win)
+      HIP_TRY(launch_copy(pl.W.p + (size_t)slot * win, lambda_out, win, pl.cs));
+  }
   kfp_status st2 = sync_out(user, pl);
   if (st2) return st2;
   HIP_TRY(hipStreamSynchronize(pl.cs));
@@ -1433,7 +1489,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     return fail(KFP_EINVAL,
                 "red-black order needs a march configuration (subdomains of at most 1056 rows; "
                 "tallest here %d)", geo.n_max);
-  const PipeParams pp = pipe_params(geo, cfg);
+  const PipeParams pp = pipe_params(geo, cfg, order);
   Plan *pl = nullptr;
   if ((st = get_plan(geo, cfg, &pl, pp, order))) return st;
   if ((st = sync_in(user, *pl))) return st;

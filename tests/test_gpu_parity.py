@@ -447,6 +447,35 @@ def test_red_black_matches_oracle(case):
     assert st2.iters == st.iters and torch.equal(uT, uT2)
 
 
+@pytest.mark.parametrize("case", [RB_CASES[0], RB_CASES[2], RB_CASES[3], RB_CASES[5]])
+@pytest.mark.parametrize("inflight", [2, 5])
+def test_red_black_overlapped_half_sweeps_equal_staggered(case, inflight):
+    """Red-black half-sweeps overlapped in time (slots of one colour each)
+    reproduce the staggered red-black iteration bit for bit: iterate,
+    traces, count and residual history."""
+    nx, nv, nt, T, J, o, tr, p, q, cfg = case
+    print(f"red-black overlapped case={case} inflight={inflight}", flush=True)
+    u0, f = inputs.random_fields(72 + J, nx, nv)
+    if cfg:
+        kfp.set_config(*cfg)
+    kfp.set_ordering(kfp.RED_BLACK)
+    runs = []
+    for mode in (0, inflight):
+        kfp.set_pipeline(mode)
+        runs.append(kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-11,
+                                  max_iter=400, want_lambda=True))
+    (a, la, sa), (b, lb, sb) = runs
+    assert sa.iters == sb.iters and sa.residual < 1e-11
+    assert torch.equal(a, b) and torch.equal(la, lb)
+    assert np.array_equal(sa.res_history, sb.res_history)
+    kfp.set_pipeline(inflight)
+    c, lc, sc = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-300,
+                              max_iter=3, want_lambda=True)
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-300, max_iter=3, order=1)
+    assert sc.iters == 3
+    assert rel(host(c), ref.uT) <= 1e-12 and rel(host(lc), ref.lam) <= 1e-12
+
+
 def test_red_black_rejects_the_one_step_kernel():
     nx, nv, nt, T = 32, 64, 10, 0.1
     u0, f = inputs.random_fields(3, nx, nv)
