@@ -1,7 +1,7 @@
 """The paper's numerical experiments (Section 6.4 and 6.5), run through the
 library on the GPU.
 
-    python -m paper_1306_4596_amd.experiments table1 [--levels 0 1 2 3 4]
+    python -m paper_1306_4596_amd.experiments table1 [--levels 0 1 2 3 4] [--order 0|1]
     python -m paper_1306_4596_amd.experiments sweep-p [--level 0]
     python -m paper_1306_4596_amd.experiments sweep-pq [--level 0]
     python -m paper_1306_4596_amd.experiments history [--level 2]
@@ -12,11 +12,15 @@ variable, so that every frequency is present), uniform grids with
 dt = h_x = h_v = 2^-j * 0.01 at refinement level j, an overlap of three cells
 (L = 3 h_v) or none (L = 0), and the stopping test (6.12) below 1e-6.  The
 discretisation is this library's (finite differences, zero Dirichlet ends,
-an IMEX step, parallel order), not the paper's, so the iteration counts are
-compared by trend only.  Each command prints one JSON line per result.
+an IMEX step), not the paper's, so the iteration counts are compared by
+trend only.  Each command prints one JSON line per result.
 
 `table1`: CSWR (capped at 150 iterations, as in the table), OSWR(p) with
-p = 4.23 and OSWR(p,q) with (p, q) = (11, 2.5), with and without overlap.
+p = 4.23 and OSWR(p,q) with (p, q) = (11, 2.5), with and without overlap, in
+the parallel order (default) or, `--order 1`, the serial order (6.8)-(6.11)
+is written in (red-black, which for two subdomains is that form; it needs
+the march kernel, so levels with subdomains taller than 1056 rows are
+skipped).
 `sweep-p`: iteration counts and the error after 15 iterations for one-sided
 p (Figure 1); `sweep-pq`: the same over a (p, q) grid (Figure 2), each sweep
 solved as one batch.  `history`: the residual histories of the three
@@ -63,11 +67,17 @@ def _zero_problem(level: int, seed: int = 0):
     return nx, nv, nt, z, lam0
 
 
-def table1(levels):
+def table1(levels, order=0):
     import torch
 
+    kb.set_ordering(order)
     for j in levels:
         nx, nv, nt, z, lam0 = _zero_problem(j)
+        if order == 1 and nv // 2 + 3 > 1056:
+            print(json.dumps({"experiment": "table1", "level": j, "order": order,
+                              "skipped": "subdomains taller than the march kernel holds"}),
+                  flush=True)
+            continue
         for o in (3, 0):
             algos = [("OSWR(p)", kb.ROBIN, PSTAR, None), ("OSWR(p,q)", kb.ROBIN, P2, Q2)]
             if o > 0:
@@ -80,7 +90,8 @@ def table1(levels):
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t0
                 conv = st.residual < TOL
-                print(json.dumps({"experiment": "table1", "level": j, "nx": nx, "nv": nv, "nt": nt,
+                print(json.dumps({"experiment": "table1", "order": order, "level": j, "nx": nx,
+                                  "nv": nv, "nt": nt,
                                   "overlap_cells": o, "algorithm": name, "p": p, "q": q,
                                   "iters": st.iters if conv else None, "converged": bool(conv),
                                   "residual": st.residual, "paper": PAPER[(name, o)][j],
@@ -88,6 +99,7 @@ def table1(levels):
                                   "config": kb.get_launch(nx, nv, nt, T_END, 2, o, tr)}),
                       flush=True)
             kb.release_workspace()
+    kb.set_ordering(0)
 
 
 def _sweep(level: int, pairs, overlap: int, tag: str):
@@ -134,10 +146,11 @@ def main():
     ap.add_argument("which", choices=["table1", "sweep-p", "sweep-pq", "history"])
     ap.add_argument("--levels", type=int, nargs="*", default=[0, 1, 2, 3, 4])
     ap.add_argument("--level", type=int, default=None)
+    ap.add_argument("--order", type=int, default=0, choices=[0, 1])
     a = ap.parse_args()
     kb.load_library()
     if a.which == "table1":
-        table1(a.levels)
+        table1(a.levels, a.order)
     elif a.which == "sweep-p":
         sweep_p(0 if a.level is None else a.level)
     elif a.which == "sweep-pq":
