@@ -529,3 +529,20 @@ def test_table1_orderings_at_coarsest_level():
     c = oracle.swr_solve(z, z, T, nt, 2, 3, D, tol=1e-6, max_iter=120, lambda_init=lam0)
     # CSWR has not converged after 120 iterations, far more than OSWR needs
     assert c.status == 4 and it[extra["PSTAR"]] / 120 < 2 * paper_ratio
+
+
+def test_table1_serial_order_at_coarsest_level():
+    """Table 1 was computed in the serial order (6.8)-(6.11), which for two
+    subdomains is the red-black order: at level 0 this discretisation's OSWR
+    counts in that order lie within two iterations of the printed ones, with
+    and without overlap (the parallel order needs about twice as many)."""
+    rows, extra = _golden_table1()
+    nx, nv, nt, T = 100, 200, 200, 2.0
+    z = np.zeros((nv + 1, nx))
+    lam0 = inputs.random_traces(0, 2, nt, nx)
+    for o in (3, 0):
+        for key, p, q in (("OSWR_p", extra["PSTAR"], None), ("OSWR_pq", 11.0, 2.5)):
+            r = oracle.swr_solve(z, z, T, nt, 2, o, R, p=p, q=q, tol=1e-6, max_iter=100,
+                                 lambda_init=lam0, order=1)
+            assert r.status == 0
+            assert abs(r.iters - rows[(key, o)][0]) <= 2, (key, o, r.iters)
