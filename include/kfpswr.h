@@ -229,7 +229,8 @@ kfp_status kfp_set_pipeline(int32_t inflight);
  *   one after the other, each with half the work items.  Needs a march
  *   configuration (subdomains of at most 1056 rows; KFP_EINVAL otherwise);
  *   overlapped iterations (kfp_set_pipeline) are not used in this order.
- * Batches (kfp_swr_batch) always run in the parallel order.
+ * Also applies to kfp_swr_batch (each launch class runs its two half-sweeps
+ * in turn, the classes side by side) and kfp_swr_solve_windows.
  */
 kfp_status kfp_set_ordering(int32_t order);
 

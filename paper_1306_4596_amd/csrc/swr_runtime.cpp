@@ -1638,6 +1638,7 @@ struct BatchClass {
   DevTables dt;
   int grid = 1;
   int nt_max = 0;
+  int n_red = 0;  // red-black order: the work items of even subdomains come first
 };
 
 static Config batch_config(int n_max) {
@@ -1662,6 +1663,7 @@ static Config batch_config(int n_max) {
 static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol, int max_iter,
                                  kfp_swr_stats *stats, hipStream_t user) {
   const double t_start = now_s();
+  const int order = g_order;
   if (n_inst < 1 || !in) return fail(KFP_EINVAL, "batch needs n >= 1 instances");
   if (!(tol > 0.0)) return fail(KFP_EINVAL, "tol must be > 0");
   if (max_iter < 1) return fail(KFP_EINVAL, "max_iter must be >= 1");
@@ -1694,6 +1696,11 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     cls[k].nt_max = std::max(cls[k].nt_max, bi[i].geo.nt);
     bi[i].cls = k;
   }
+  if (order == 1)
+    for (const auto &c : cls)
+      if (c.cfg.steps == 0)
+        return fail(KFP_EINVAL, "red-black order needs a march configuration for every "
+                                "instance (subdomains of at most 1056 rows)");
 
   hipStream_t cs;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1754,7 +1761,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     d.f = in[i].f;
     d.g = b.g;
     d.lam[0] = b.lam0;
-    d.lam[1] = b.lam1;
+    d.lam[1] = order == 1 ? b.lam0 : b.lam1;  // red-black: one window, in place
     d.res = res + i;
     d.V = b.V;
     d.r = dt / (hv * hv);
@@ -1781,7 +1788,8 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev_id) == hipSuccess) cus = prop.multiProcessorCount;
   }
-  // per class: tables, items sorted largest first (LPT) for the persistent grid
+  // per class: tables, items sorted largest first (LPT) for the persistent
+  // grid (red-black: the even subdomains' items first, each colour LPT)
   for (auto &c : cls) {
     std::vector<std::pair<long, Item>> weighted;
     for (int i : c.members) {
@@ -1791,13 +1799,19 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       make_ex(geo, i, c.h.ex);
       std::vector<Item> it;
       make_items(geo, sub_base, tile_width(c.cfg), it);
-      for (const Item &x : it) weighted.push_back({(long)c.h.subs[x.sub].n * geo.nt, x});
+      for (const Item &x : it) {
+        const long odd = order == 1 ? ((x.sub - sub_base) & 1) : 0;
+        weighted.push_back({(long)c.h.subs[x.sub].n * geo.nt - (odd << 40), x});
+      }
     }
     std::stable_sort(weighted.begin(), weighted.end(),
                      [](const std::pair<long, Item> &x, const std::pair<long, Item> &y) {
                        return x.first > y.first;
                      });
-    for (auto &w : weighted) c.h.items.push_back(w.second);
+    for (auto &w : weighted) {
+      c.h.items.push_back(w.second);
+      if (w.first >= 0) ++c.n_red;
+    }
     HIP_TRY(c.dt.upload(c.h, {}, cs));
     c.grid = std::max(1, std::min<int>((int)c.h.items.size(),
                                        cus * std::max(1, 32 / c.cfg.waves)));
@@ -1850,7 +1864,23 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       hipStream_t s = side.s[ci];
       HIP_TRY(hipStreamWaitEvent(s, side.e[cls.size()], 0));
       const StepTables t = view(c);
-      if (c.cfg.steps == 0) {
+      if (order == 1) {
+        // red-black: the even subdomains march the window and send their
+        // traces, then the odd ones march with them and send theirs
+        StepTables tc[2] = {t, t};
+        tc[0].n_items = c.n_red;
+        tc[1].items = t.items + c.n_red;
+        tc[1].n_items = t.n_items - c.n_red;
+        const int L = march_launches(c.nt_max, c.cfg);
+        for (int h = 0; h < 2; ++h) {
+          const int grid = std::min(c.grid, tc[h].n_items);
+          if (grid > 0)
+            for (int l = 0; l < L; ++l)
+              HIP_TRY(launch_march(tc[h], c.cfg.waves, c.cfg.groups, c.cfg.seg, l * c.cfg.steps,
+                                   c.cfg.steps, halo_of(c.cfg), l & 1, 0, grid, s));
+          HIP_TRY(launch_exchange(t, 0, c.cfg.steps, s, h + 1));
+        }
+      } else if (c.cfg.steps == 0) {
         for (int n = 0; n <= c.nt_max; ++n)
           HIP_TRY(launch_step(t, c.cfg.waves, c.cfg.seg, n, par, c.grid, s));
       } else {
@@ -1904,7 +1934,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
   double dev_ms = 0.0;
   int active = n_inst;
   for (int k = 1; k <= max_iter && active > 0; ++k) {
-    const int par = (k - 1) & 1;
+    const int par = order == 1 ? 0 : (k - 1) & 1;
     HIP_TRY(hipEventRecord(e0, cs));
     if (graphs) {
       HIP_TRY(hipGraphLaunch(guard.ge[par], cs));
@@ -1945,7 +1975,8 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     double *Ufin = (march_launches(geo.nt, cls[b.cls].cfg) & 1) ? b.U1 : b.U0;
     HIP_TRY(launch_assemble(Ufin, b.rowmap, in[i].uT, geo.nv, geo.nx, cs));
     if (in[i].lambda_out && b.win)
-      HIP_TRY(launch_copy((iters[i] & 1) ? b.lam1 : b.lam0, in[i].lambda_out, b.win, cs));
+      HIP_TRY(launch_copy((order == 0 && (iters[i] & 1)) ? b.lam1 : b.lam0, in[i].lambda_out,
+                          b.win, cs));
   }
   HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(ev, cs));

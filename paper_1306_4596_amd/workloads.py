@@ -1,11 +1,11 @@
 """Throughput of the SWR path on the workloads beside the benchmark one.
 
-    python -m paper_1306_4596_amd.workloads batch [--n 256]
+    python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1]
     python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8]
 
 `batch`: uneven instances (Nx, Nv from {128, 256, 512, 1024}, J from
 {2, 4, 8, 16}, Nt = 512, T = 0.25, overlap 2, Robin p = 4) solved together
-by kfp_swr_batch to 1e-10.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J = 32,
+by kfp_swr_batch to 1e-10, in the parallel order or (--order 1) red-black.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J = 32,
 overlap 2, Robin p = 8, a fixed number of SWR iterations (a full solve takes
 minutes), once per launch configuration.  Each prints one JSON line per
 measurement.  Inputs are seeded and synthetic (inputs.py).
@@ -22,9 +22,10 @@ from . import binding as kb
 from . import inputs
 
 
-def run_batch(n: int, reps: int = 2):
+def run_batch(n: int, reps: int = 2, order: int = 0):
     import torch
 
+    kb.set_ordering(order)
     specs = inputs.batch_specs(n)
     insts = []
     for sp in specs:
@@ -40,7 +41,8 @@ def run_batch(n: int, reps: int = 2):
         wall = time.perf_counter() - t0
         cells = sum(r[2].cell_steps for r in res)
         its = [r[2].iters for r in res]
-        print(json.dumps({"workload": f"batch of {n} uneven SWR instances", "rep": rep, "status": rc,
+        print(json.dumps({"workload": f"batch of {n} uneven SWR instances", "order": order,
+                          "rep": rep, "status": rc,
                           "wall_s": wall, "device_s": res[0][2].device_seconds,
                           "cell_steps": cells, "cell_steps_per_s": cells / wall,
                           "iters_min": min(its), "iters_mean": float(np.mean(its)),
@@ -81,12 +83,13 @@ def main():
     ap.add_argument("which", choices=["batch", "large"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=1)
+    ap.add_argument("--order", type=int, default=0, choices=[0, 1])
     ap.add_argument("--configs", nargs="*", default=[],
                     help="launch configurations waves,seg,steps (default: the library's choice)")
     a = ap.parse_args()
     kb.load_library()
     if a.which == "batch":
-        run_batch(a.n)
+        run_batch(a.n, order=a.order)
     else:
         cfgs = [tuple(int(x) for x in c.split(",")) for c in a.configs] or [None]
         run_large(a.iters, cfgs)

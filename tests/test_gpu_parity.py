@@ -476,6 +476,35 @@ def test_red_black_overlapped_half_sweeps_equal_staggered(case, inflight):
     assert rel(host(c), ref.uT) <= 1e-12 and rel(host(lc), ref.lam) <= 1e-12
 
 
+def test_red_black_batch_matches_single_solves():
+    """Red-black order in a batch of uneven instances (several launch
+    classes, odd and even J, with and without overlap) equals the single
+    red-black solves bit for bit, and the oracle to the tolerance."""
+    specs = [(64, 64, 40, 0.2, 2, 2, R, 4.0), (128, 32, 40, 0.1, 4, 2, R, 2.0),
+             (96, 96, 40, 0.3, 3, 2, D, 0.0), (64, 256, 40, 0.2, 2, 0, R, 8.0),
+             (80, 512, 30, 0.2, 2, 2, R, 4.0), (64, 64, 40, 0.15, 1, 0, R, 1.0)]
+    kfp.set_ordering(kfp.RED_BLACK)
+    kfp.set_pipeline(0)  # the single solves in the staggered form
+    insts, singles = [], []
+    for i, (nx, nv, nt, T, J, o, tr, p) in enumerate(specs):
+        u0, f = inputs.random_fields(120 + i, nx, nv)
+        insts.append(dict(u0=dev(u0), f=dev(f), T=T, nt=nt, J=J, overlap=o, tr=tr, p=p,
+                          want_lambda=True))
+        singles.append(kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-11,
+                                     max_iter=400, want_lambda=True))
+    out, rc = kfp.swr_batch(insts, tol=1e-11, max_iter=400)
+    assert rc == 0
+    for i, ((uT, lam, st), (ruT, rlam, rst)) in enumerate(zip(out, singles)):
+        assert st.iters == rst.iters, i
+        assert torch.equal(uT, ruT), i
+        if lam is not None:
+            assert torch.equal(lam, rlam), i
+        nx, nv, nt, T, J, o, tr, p = specs[i]
+        u0, f = inputs.random_fields(120 + i, nx, nv)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-11, max_iter=400, order=1)
+        assert st.iters == ref.iters and rel(host(uT), ref.uT) <= 1e-10, i
+
+
 def test_red_black_rejects_the_one_step_kernel():
     nx, nv, nt, T = 32, 64, 10, 0.1
     u0, f = inputs.random_fields(3, nx, nv)
