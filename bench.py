@@ -50,19 +50,20 @@ FLOPS_PER_CELL_STEP = 13.0
 # configuration (8 wavefronts x 17 rows, 16 steps per launch), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (separate runs, mean over
 # the 8125 dispatches of one solve), each scaled by what the counter reads
-# for the library's copy kernel of 1 GiB in the same process (FETCH_SIZE x
-# 1.99991, WRITE_SIZE x 1.00000).  Valid only for the kernel sources they
-# were measured on: any change to them and `traffic` is reported as null.
+# for the library's copy kernel of 1 GiB in the same process (FETCH_SIZE
+# 524311.12 KiB and WRITE_SIZE 1048576.62 KiB for 1 GiB read and written).
+# Valid only for the kernel sources they were measured on: any change to
+# them and `traffic` is reported as null.
 TRAFFIC = {
     "config": (8, 17, 16),
     "sha256": {
         "paper_1306_4596_amd/csrc/swr_kernels.hip":
-            "7513ee3bf545649c7651bb4cd8c15d4333eb00f5881ecea3b7b97e28b2e00586",
+            "e92cc1eb9f55f894a214a516b165d75e0162ae48f48e7b7df9bd30e4955027ff",
         "paper_1306_4596_amd/csrc/kfp_internal.h":
-            "8d41beba0e5f360d20ad30f25702a2c956d1fd8224629a26ae0724c32a4f7899",
+            "80c7c52abcafdb68686a45052d0aef990023af4ee99d2be214d6b1d72ff1f411",
     },
-    "read_bytes": 9401.7 * 1024 * 1.99991,
-    "write_bytes": 13728.0 * 1024 * 1.00000,
+    "read_bytes": 9400.75 * 1024 * (1048576.0 / 524311.12),
+    "write_bytes": 13728.0 * 1024 * (1048576.0 / 1048576.62),
 }
 
 

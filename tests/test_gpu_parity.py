@@ -505,6 +505,44 @@ def test_red_black_batch_matches_single_solves():
         assert st.iters == ref.iters and rel(host(uT), ref.uT) <= 1e-10, i
 
 
+@pytest.mark.parametrize("inflight", [0, 4])
+def test_red_black_guess_restart_and_iteration_cap(inflight):
+    """Red-black order, staggered and overlapped: a non-finite initial guess
+    restarts from zero traces; a solve stopped by max_iter returns that
+    iterate (the oracle's after the same count) and reports no convergence."""
+    nx, nv, nt, T, J = 64, 32, 40, 0.2, 4
+    u0, f = inputs.random_fields(2, nx, nv)
+    kfp.set_ordering(kfp.RED_BLACK)
+    kfp.set_pipeline(inflight)
+    bad = np.zeros((2 * (J - 1), nt, nx))
+    bad[1, 3, 5] = np.inf
+    uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, 2, R, p=4.0, tol=1e-11, max_iter=300,
+                              lambda_init=dev(bad))
+    assert st.restarted
+    ref = oracle.swr_solve(u0, f, T, nt, J, 2, R, p=4.0, tol=1e-11, max_iter=300, order=1)
+    assert st.iters == ref.iters and rel(host(uT), ref.uT) <= 1e-10
+    with pytest.raises(kfp.KfpError):
+        kfp.swr_solve(dev(u0), dev(f), T, nt, J, 2, R, p=4.0, tol=1e-14, max_iter=2,
+                      raise_noconv=True)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, 2, R, p=4.0, tol=1e-14, max_iter=2,
+                                want_lambda=True)
+    ref = oracle.swr_solve(u0, f, T, nt, J, 2, R, p=4.0, tol=1e-14, max_iter=2, order=1)
+    assert st.iters == 2 and ref.status == 4
+    assert rel(host(uT), ref.uT) <= 1e-12 and rel(host(lam), ref.lam) <= 1e-12
+
+
+def test_windows_report_a_window_that_does_not_converge():
+    nx, nv, nt, T = 48, 64, 30, 0.2
+    u0, f = inputs.random_fields(4, nx, nv)
+    uT, its, st = kfp.swr_solve_windows(dev(u0), dev(f), T, nt, 2, 2, R, p=4.0, tol=1e-15,
+                                        max_iter=3, n_windows=3)
+    assert its == [3, 3, 3] and st.iters == 9 and not st.residual < 1e-15
+    ref, rit, rst = oracle.swr_solve_windows(u0, f, T, nt, 2, 2, R, p=4.0, tol=1e-15,
+                                             max_iter=3, n_windows=3)
+    assert rit == its and all(x == 4 for x in rst)
+    assert rel(host(uT), ref) <= 1e-12
+
+
 def test_red_black_rejects_the_one_step_kernel():
     nx, nv, nt, T = 32, 64, 10, 0.1
     u0, f = inputs.random_fields(3, nx, nv)
