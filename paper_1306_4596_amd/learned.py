@@ -343,6 +343,8 @@ def main():
     ap.add_argument("--base", default="u0", choices=["u0", "zero"])
     ap.add_argument("--variants", default="mlp,linear_x3",
                     help="comma-separated from " + ",".join(VARIANTS))
+    ap.add_argument("--orders", default="0",
+                    help="evaluation in these solve orders: 0 parallel, 1 red-black")
     args = ap.parse_args()
 
     def log(msg):
@@ -374,11 +376,19 @@ def main():
         log(f"trained {name} in {train[name]['seconds']:.1f} s")
     del X, Y0
     torch.cuda.empty_cache()
-    ev = evaluate(shape, range(20000, 20000 + args.eval), guesses, log=log)
+    summaries = {}
+    for order in (int(x) for x in args.orders.split(",") if x):
+        # the converged traces do not depend on the order: the same networks
+        # serve both
+        kb.set_ordering(order)
+        ev = evaluate(shape, range(20000, 20000 + args.eval), guesses, log=log)
+        summaries["parallel" if order == 0 else "red-black"] = summarize(ev)
+    kb.set_ordering(0)
     res = {"shape": asdict(shape), "base": args.base, "train_seeds": args.train,
            "eval_seeds": args.eval, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
            "generate_seconds": t_gen, "train_iters_mean": float(iters.mean()),
-           "train": train, "summary": summarize(ev)}
+           "train": train, "summary": summaries.get("parallel") or next(iter(summaries.values())),
+           "summary_by_order": summaries}
     with open(args.out, "w") as fp:
         json.dump(res, fp, indent=1)
     log(json.dumps(res["summary"]))
