@@ -509,9 +509,12 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
 // across the whole wavefront: the edge lane of a group then receives a
 // value of the neighbouring group, which is halo like the zero the edge
 // lane of the wavefront receives, and the valid lanes never see it.
-template <int SEG, int NW, int G>
-__global__ __launch_bounds__(NW * 64) void march_kernel(StepTables t, int n0_in, int S, int H,
-                                                        int src_in, int par) {
+// OCC: wavefronts per SIMD the register allocation must allow (1: no limit
+// beyond one workgroup).  A build of the same code for more resident
+// workgroups, for launches with several work items per compute unit.
+template <int SEG, int NW, int G, int OCC = 1>
+__global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n0_in, int S,
+                                                             int H, int src_in, int par) {
   static_assert(G == 1 || G == 2 || G == 4, "lane groups");
   constexpr int NV = NW * G;  // segments per workgroup
   constexpr int TW = 64 / G;  // tile columns
@@ -1069,10 +1072,34 @@ bool march_config_supported(int waves, int groups, int seg_max) {
   return false;
 }
 
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
 hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int n0, int S,
                         int H, int src, int par, int grid, hipStream_t s) {
   if (groups < 1 || S < 1 || S > kMaxStepsPerLaunch || H < 1 || 2 * H * groups >= 64)
     return hipErrorInvalidValue;
+  // 8 wavefronts of 17 rows (the 131-row subdomains of J = 8 on 1024 and
+  // J = 32 on 4096 v-cells): with two or more work items per compute unit,
+  // the build limited to 128 registers (two resident workgroups per compute
+  // unit, a few spilled values) is the faster one; with one item per
+  // compute unit the unlimited build is.  Same arithmetic, same results.
+  if (waves == 8 && seg_max == 17 && groups == 1 && grid >= 2 * device_cus()) {
+    hipLaunchKernelGGL((march_kernel<17, 8, 1, 4>), dim3(grid), dim3(8 * 64), 0, s, t, n0, S, H,
+                       src, par);
+    return hipGetLastError();
+  }
 #define KFP_LAUNCH(W, SM, G)                                                                \
   if (waves == W && seg_max == SM && groups == G) {                                        \
     hipLaunchKernelGGL((march_kernel<SM, W, G>), dim3(grid), dim3(W * 64), 0, s, t, n0, S, \

@@ -725,6 +725,22 @@ def test_batch_matches_single_solves(cfg):
 
 
 # ------------------------------------------------------ full-size checks ----
+def test_many_items_register_limited_build():
+    """8 wavefronts x 17 rows with at least two work items per compute unit
+    runs the build limited to 128 registers: 3072 x 1024, J = 8 at 8 steps
+    per launch (512 items), two iterations against the oracle."""
+    nx, nv, nt, T = 3072, 1024, 24, 0.005
+    u0, f = inputs.random_fields(8, nx, nv)
+    print("many items oracle ...", flush=True)
+    ref = oracle.swr_solve(u0, f, T, nt, 8, 2, R, p=8.0, tol=1e-300, max_iter=2)
+    kfp.set_config(8, 17, 8)
+    kfp.set_pipeline(0)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 8, 2, R, p=8.0, tol=1e-300, max_iter=2,
+                                want_lambda=True)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+
+
 def test_tall_subdomains_full_size_fixed_iterations():
     """1024 x 1024 with J = 2 (514-row subdomains, the built-in lane-group
     march): two iterations against the oracle."""
