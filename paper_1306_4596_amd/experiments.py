@@ -2,8 +2,8 @@
 library on the GPU.
 
     python -m paper_1306_4596_amd.experiments table1 [--levels 0 1 2 3 4] [--order 0|1]
-    python -m paper_1306_4596_amd.experiments sweep-p [--level 0]
-    python -m paper_1306_4596_amd.experiments sweep-pq [--level 0]
+    python -m paper_1306_4596_amd.experiments sweep-p [--level 0] [--order 0|1] [--fine]
+    python -m paper_1306_4596_amd.experiments sweep-pq [--level 0] [--order 0|1]
     python -m paper_1306_4596_amd.experiments history [--level 2]
 
 Set-up (Section 6.4): two subdomains of [0,1) x [-1,1], T = 2, the error
@@ -22,8 +22,9 @@ is written in (red-black, which for two subdomains is that form; it needs
 the march kernel, so levels with subdomains taller than 1056 rows are
 skipped).
 `sweep-p`: iteration counts and the error after 15 iterations for one-sided
-p (Figure 1); `sweep-pq`: the same over a (p, q) grid (Figure 2), each sweep
-solved as one batch.  `history`: the residual histories of the three
+p (Figure 1; `--fine`: p in (4, 5) by 0.01, where Section 6.4.1 locates its
+optimum); `sweep-pq`: the same over a (p, q) grid (Figure 2); each sweep is
+solved as one batch, in either order.  `history`: the residual histories of the three
 algorithms with overlap (Figure 3).
 """
 from __future__ import annotations
@@ -102,32 +103,39 @@ def table1(levels, order=0):
     kb.set_ordering(0)
 
 
-def _sweep(level: int, pairs, overlap: int, tag: str):
+def _sweep(level: int, pairs, overlap: int, tag: str, order: int = 0):
     """One batch: instance i solves OSWR(p_i, q_i) from the same random trace;
     the iteration count to 1e-6 and the residual after 15 iterations."""
     nx, nv, nt, z, lam0 = _zero_problem(level)
     insts = [dict(u0=z, f=z, T=T_END, nt=nt, J=2, overlap=overlap, tr=kb.ROBIN, p=p, q=q,
                   lambda_init=lam0) for p, q in pairs]
+    kb.set_ordering(order)
     out, _ = kb.swr_batch(insts, tol=TOL, max_iter=200, history=True)
+    kb.set_ordering(0)
     for (p, q), (_, _, st) in zip(pairs, out):
         h = st.res_history
-        print(json.dumps({"experiment": tag, "level": level, "overlap_cells": overlap, "p": p,
+        print(json.dumps({"experiment": tag, "order": order, "level": level,
+                          "overlap_cells": overlap, "p": p,
                           "q": q, "iters": st.iters if st.residual < TOL else None,
                           "residual_after_15": float(h[14]) if len(h) >= 15 else None}),
               flush=True)
     kb.release_workspace()
 
 
-def sweep_p(level: int):
+def sweep_p(level: int, order: int = 0, fine: bool = False):
+    if fine:
+        ps = [round(4.0 + 0.01 * i, 2) for i in range(101)]
+        _sweep(level, [(p, None) for p in ps], 3, "sweep-p-fine", order)
+        return
     ps = [round(x, 3) for x in np.arange(1.0, 20.01, 0.5)]
     for o in (3, 0):
-        _sweep(level, [(p, None) for p in ps], o, "sweep-p")
+        _sweep(level, [(p, None) for p in ps], o, "sweep-p", order)
 
 
-def sweep_pq(level: int):
+def sweep_pq(level: int, order: int = 0):
     ps = [2.0, 4.0, 6.0, 8.0, 11.0, 14.0, 18.0]
     qs = [0.5, 1.0, 1.5, 2.5, 4.0, 6.0, 8.0]
-    _sweep(level, [(p, q) for p in ps for q in qs], 3, "sweep-pq")
+    _sweep(level, [(p, q) for p in ps for q in qs], 3, "sweep-pq", order)
 
 
 def history(level: int):
@@ -147,14 +155,15 @@ def main():
     ap.add_argument("--levels", type=int, nargs="*", default=[0, 1, 2, 3, 4])
     ap.add_argument("--level", type=int, default=None)
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--fine", action="store_true")
     a = ap.parse_args()
     kb.load_library()
     if a.which == "table1":
         table1(a.levels, a.order)
     elif a.which == "sweep-p":
-        sweep_p(0 if a.level is None else a.level)
+        sweep_p(0 if a.level is None else a.level, a.order, a.fine)
     elif a.which == "sweep-pq":
-        sweep_pq(0 if a.level is None else a.level)
+        sweep_pq(0 if a.level is None else a.level, a.order)
     else:
         history(2 if a.level is None else a.level)
 
