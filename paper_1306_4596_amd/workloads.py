@@ -2,12 +2,15 @@
 
     python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1]
     python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8]
+    python -m paper_1306_4596_amd.workloads large-solve
 
 `batch`: uneven instances (Nx, Nv from {128, 256, 512, 1024}, J from
 {2, 4, 8, 16}, Nt = 512, T = 0.25, overlap 2, Robin p = 4) solved together
 by kfp_swr_batch to 1e-10, in the parallel order or (--order 1) red-black.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J = 32,
-overlap 2, Robin p = 8, a fixed number of SWR iterations (a full solve takes
-minutes), once per launch configuration.  Each prints one JSON line per
+overlap 2, Robin p = 8, a fixed number of SWR iterations, once per launch
+configuration.  `large-solve`: the same shape solved to 1e-10 from zero
+traces and from the u0 extension, in the parallel and the red-black order,
+and on 4 time windows.  Each prints one JSON line per
 measurement.  Inputs are seeded and synthetic (inputs.py).
 """
 from __future__ import annotations
@@ -78,9 +81,44 @@ def run_large(iters: int, configs):
     kb.set_config(0)
 
 
+def run_large_solve():
+    import torch
+
+    nx = nv = 4096
+    nt, T, J, o, p = 8192, 1.0, 32, 2, 8.0
+    u0, f = inputs.random_fields(0, nx, nv)
+    U0 = torch.from_numpy(u0).cuda()
+    F = torch.from_numpy(f).cuda()
+    del u0, f
+    for order in (0, 1):
+        kb.set_ordering(order)
+        for guess in ("zero", "u0", "windows4"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if guess == "windows4":
+                _, its, st = kb.swr_solve_windows(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
+                                                  max_iter=400, n_windows=4, guess=True)
+                iters = its
+            else:
+                lam0 = kb.u0_guess(U0, nt, J, o, kb.ROBIN, p) if guess == "u0" else None
+                _, _, st = kb.swr_solve(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
+                                        max_iter=400, lambda_init=lam0, history=False)
+                iters = st.iters
+                del lam0
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            print(json.dumps({"workload": "4096x4096 Nt=8192 T=1 J=32 overlap=2 Robin p=8 to 1e-10",
+                              "order": "red-black" if order else "parallel", "start": guess,
+                              "iterations": iters, "residual": st.residual,
+                              "time_to_tol_s": round(wall, 3),
+                              "cell_steps_per_s": st.cell_steps / wall}), flush=True)
+            kb.release_workspace()
+    kb.set_ordering(0)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "large"])
+    ap.add_argument("which", choices=["batch", "large", "large-solve"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
@@ -90,6 +128,8 @@ def main():
     kb.load_library()
     if a.which == "batch":
         run_batch(a.n, order=a.order)
+    elif a.which == "large-solve":
+        run_large_solve()
     else:
         cfgs = [tuple(int(x) for x in c.split(",")) for c in a.configs] or [None]
         run_large(a.iters, cfgs)
