@@ -246,3 +246,30 @@ def test_bench_traffic_only_for_the_measured_kernel(tmp_path, monkeypatch):
         dst.write_bytes(open(src, "rb").read() + b" ")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic(bench.TRAFFIC["config"]) is None
+
+
+def test_ordering_launch_and_window_arguments(lib):
+    """Validation of the ordering, lane-group launch and time-window entry
+    points (no device call is reached)."""
+    assert lib.kfp_set_ordering(2) == binding.KFP_EINVAL
+    assert lib.kfp_set_ordering(-1) == binding.KFP_EINVAL
+    assert lib.kfp_set_ordering(0) == 0
+    # lane groups: compiled set, halo must leave columns (2 * steps * groups < 64)
+    assert lib.kfp_set_launch(8, 2, 33, 6) == 0
+    assert lib.kfp_set_launch(8, 2, 33, 16) == binding.KFP_EINVAL
+    assert lib.kfp_set_launch(8, 4, 33, 8) == binding.KFP_EINVAL
+    assert lib.kfp_set_launch(8, 3, 33, 4) == binding.KFP_EINVAL
+    assert lib.kfp_set_launch(4, 2, 8, 0) == binding.KFP_EINVAL  # one-step kernel: groups 1
+    assert lib.kfp_set_launch(0, 1, 0, 0) == 0
+    g = G(64, 64, 10, 0.1)
+    its = (ctypes.c_int32 * 4)()
+
+    def win(n_windows, guess=0, J=2, o=2, tr=1, u0=FAKE):
+        return lib.kfp_swr_solve_windows(ctypes.byref(g), u0, FAKE, None, J, o, tr, 4.0, 4.0,
+                                         1e-10, 10, n_windows, guess, FAKE, its, None, None)
+    assert win(0) == binding.KFP_EINVAL and "n_windows" in lib.kfp_last_error().decode()
+    assert win(11) == binding.KFP_EINVAL
+    assert win(2, guess=2) == binding.KFP_EINVAL
+    assert win(2, u0=None) == binding.KFP_EINVAL
+    assert win(2, J=3) == binding.KFP_EINVAL and "nv % J" in lib.kfp_last_error().decode()
+    assert win(2, tr=0, o=0) == binding.KFP_EINVAL
