@@ -23,6 +23,8 @@ _LIB = os.path.join(_HERE, "libkfp_oracle.so")
 
 DIRICHLET = 0
 ROBIN = 1
+FD = 0   # finite differences in v, IMEX step (the default discretisation)
+FEM = 1  # linear finite elements, diffusion then transport (Section 6.2 as printed)
 
 _lib = None
 
@@ -58,10 +60,15 @@ def _load():
             I, I, I, ctypes.c_double, D, D, D, I, I, I, ctypes.c_double, ctypes.c_double,
             ctypes.c_double, I, D, I, D, D, ctypes.POINTER(I), D, D,
         ]
+        lib.oracle_swr_solve_scheme.argtypes = [
+            I, I, I, ctypes.c_double, D, D, D, I, I, I, ctypes.c_double, ctypes.c_double,
+            ctypes.c_double, I, D, I, I, D, D, ctypes.POINTER(I), D, D,
+        ]
+        lib.oracle_fem_mono_solve.argtypes = [I, I, I, ctypes.c_double, D, D, D, D]
         lib.oracle_u0_guess.argtypes = [I, I, I, D, I, I, I, ctypes.c_double, ctypes.c_double, D]
         for fn in ("oracle_thomas", "oracle_transport", "oracle_mono_solve",
                    "oracle_partition", "oracle_swr_solve", "oracle_swr_solve_ordered",
-                   "oracle_u0_guess"):
+                   "oracle_swr_solve_scheme", "oracle_fem_mono_solve", "oracle_u0_guess"):
             getattr(lib, fn).restype = I
         _lib = lib
     return _lib
@@ -115,13 +122,18 @@ def partition(nv, J, o):
     return list(a), list(b)
 
 
-def mono_solve(u0, f, T, nt, s=None):
-    """Monodomain discrete solution at t = T, [nv+1][nx]."""
+def mono_solve(u0, f, T, nt, s=None, scheme=FD):
+    """Monodomain discrete solution at t = T, [nv+1][nx].  scheme FD: finite
+    differences with zero values at v = +-1; FEM: linear finite elements with
+    Neumann ends, diffusion then transport (Section 6.2)."""
     u0, f = _f64(u0), _f64(f)
     nv, nx = u0.shape[0] - 1, u0.shape[1]
     s = None if s is None else _f64(s)
     uT = np.empty_like(u0)
-    if _load().oracle_mono_solve(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), _p(uT)):
+    fn = _load().oracle_fem_mono_solve if scheme == FEM else _load().oracle_mono_solve
+    if scheme not in (FD, FEM):
+        raise ValueError("unknown scheme")
+    if fn(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), _p(uT)):
         raise ValueError("invalid arguments")
     return uT
 
@@ -141,12 +153,13 @@ class SWRResult:
 
 
 def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter=100,
-              lambda_init=None, s=None, q=None, order=0):
+              lambda_init=None, s=None, q=None, order=0, scheme=FD):
     """SWR (Section 6.3).  Returns SWRResult.  q: second Robin parameter of
     OSWR(p,q); None for q = p.  order: 0 parallel (the Jacobi Remark after
     (6.12)), 1 multiplicative in red-black order (even subdomains, then odd
     ones with the traces the even ones just sent; for two subdomains the
-    serial form (6.8)-(6.11))."""
+    serial form (6.8)-(6.11)).  scheme: FD or FEM (see mono_solve); with FEM
+    the iterates, traces and residual are those of the diffusion stage."""
     u0, f = _f64(u0), _f64(f)
     nv, nx = u0.shape[0] - 1, u0.shape[1]
     s = None if s is None else _f64(s)
@@ -159,11 +172,11 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter
     hist = np.zeros(max_iter)
     ovl = np.zeros(max_iter)
     it = ctypes.c_int(0)
-    st = _load().oracle_swr_solve_ordered(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), J,
-                                          overlap, int(transmission), float(p),
-                                          float(p if q is None else q), float(tol), max_iter,
-                                          _p(li), int(order), _p(uT), _p(lam_out),
-                                          ctypes.byref(it), _p(hist), _p(ovl))
+    st = _load().oracle_swr_solve_scheme(nx, nv, nt, float(T), _p(u0), _p(f), _p(s), J,
+                                         overlap, int(transmission), float(p),
+                                         float(p if q is None else q), float(tol), max_iter,
+                                         _p(li), int(order), int(scheme), _p(uT), _p(lam_out),
+                                         ctypes.byref(it), _p(hist), _p(ovl))
     if st == 1:
         raise ValueError("invalid arguments")
     k = it.value
@@ -171,7 +184,7 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter
 
 
 def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, max_iter=100,
-                      n_windows=1, s=None, q=None, guess=False):
+                      n_windows=1, s=None, q=None, guess=False, order=0, scheme=FD):
     """SWR on time windows: [0, T] is cut into n_windows windows of whole
     steps (window w takes steps floor(w nt / W) .. floor((w+1) nt / W) - 1),
     and each is solved by swr_solve to the tolerance, starting from the glued
@@ -189,7 +202,8 @@ def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-12, 
         sw = None if s is None else _f64(s)[n0:n1 + 1]
         lam0 = u0_guess(start, ntw, J, overlap, transmission, p, q) if guess and J > 1 else None
         r = swr_solve(start, f, ntw * dt, ntw, J, overlap, transmission, p=p, tol=tol,
-                      max_iter=max_iter, lambda_init=lam0, s=sw, q=q)
+                      max_iter=max_iter, lambda_init=lam0, s=sw, q=q, order=order,
+                      scheme=scheme)
         iters.append(r.iters)
         status.append(r.status)
         start = r.uT

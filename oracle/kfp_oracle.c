@@ -45,6 +45,11 @@
  * (with p = q, lambda_new = 2p u - lambda_old).  At a fixed point the two
  * half-cell rows add up to the monodomain row of the shared node.
  *
+ * A second discretisation, Section 6.2 as printed (linear finite elements
+ * with the consistent mass matrix, Neumann ends, diffusion then transport),
+ * is selected by scheme KFP_O_FEM; its definition is given with its code
+ * below (fem_solve_subdomain, fem_emit_trace).
+ *
  * Every linear system is solved by plain Thomas elimination, written out here
  * with divisions, rebuilt for every column and every step.
  */
@@ -54,6 +59,8 @@
 
 #define KFP_O_DIRICHLET 0
 #define KFP_O_ROBIN 1
+#define KFP_O_FD 0  /* finite differences, IMEX step (the default discretisation) */
+#define KFP_O_FEM 1 /* linear finite elements, diffusion then transport (Section 6.2) */
 
 /* ------------------------------------------------------------------ */
 /* Thomas elimination for a tridiagonal system.                        */
@@ -284,6 +291,186 @@ static void solve_subdomain(int nx, int nv, int nt, double T, const double *u0,
   free(V);
 }
 
+/* ------------------------------------------------------------------ */
+/* The paper's own discretisation (Section 6.2, scheme KFP_O_FEM).      */
+/* ------------------------------------------------------------------ */
+/* Linear finite elements in v on the same nodes: the mass matrix M and the
+ * stiffness matrix S of (6.3) have the exact element integrals (the Remark
+ * after (6.5): Simpson's rule is exact for them), per element [v_e, v_{e+1}]
+ *   M_e = h/6 [[2, 1], [1, 2]],   S_e = 1/h [[1, -1], [-1, 1]].
+ * v = -1 and v = +1 carry the homogeneous Neumann condition of (6.1), which
+ * is natural: the end nodes are unknowns and their rows hold one element.
+ * A time step is the splitting of Section 6.2 in its order:
+ *   Step 1  (M/dt + S) W^{n+1} = M/dt G^n,  G^n = U^n + dt s(t_{n+1}) f
+ *           (implicit Euler for the v-diffusion, the source taken with it),
+ *   Step 2  U^{n+1} = T W^{n+1}, the upwind transport (6.4)/(6.5),
+ * both stages over the whole step dt (the half step printed for them would
+ * advance the solution by dt/2 per step); U^0 = u0.
+ * Every row is multiplied by dt/h, so an element adds
+ *   (1/6) [[2, 1], [1, 2]] + r [[1, -1], [-1, 1]],   r = dt/h^2,
+ * to the matrix and (1/6) [[2, 1], [1, 2]] G to the right-hand side.
+ * Interface conditions act in Step 1.  A Robin condition is natural:
+ *   Q_1 u = (p + d/dv) u = lambda_1 at beta (upper end): the boundary term
+ *     -u_v(beta) phi_beta = (p u - lambda_1) phi_beta adds dt/h p to the
+ *     diagonal and dt/h lambda_1 to the right-hand side;
+ *   Q_2 u = (q - d/dv) u = lambda_2 at alpha (lower end): likewise with q.
+ * This holds with or without overlap.  A classical (Dirichlet) interface
+ * node is a fixed node holding the trace; its element still contributes to
+ * the row next to it. */
+
+/* Builds the state U^n of node i (index i - a in the subdomain's history)
+ * for column m: u0 at n = 0, else the transport of W^n. */
+static double fem_stage_input(int nx, int nv, int nt, double T, const double *u0, int a,
+                              int nn, const double *hist, int i, int n, int m) {
+  if (n == 0) return u0[(size_t)i * nx + m];
+  const double hx = 1.0 / nx, hv = 2.0 / nv, dt = T / nt;
+  const double nu = (-1.0 + i * hv) * dt / hx, w = fabs(nu);
+  const double *row = hist + ((size_t)(n - 1) * nn + (i - a)) * nx;
+  int nb = m;
+  if (nu > 0.0) nb = (m - 1 + nx) % nx;
+  if (nu < 0.0) nb = (m + 1) % nx;
+  return (1.0 - w) * row[m] + w * row[nb];
+}
+
+/* One subdomain over the whole window: W^{n+1} of every level of its nodes
+ * a..b (fixed nodes included) to hist[n][i-a][m]. */
+static void fem_solve_subdomain(int nx, int nv, int nt, double T, const double *u0,
+                                const double *f, const double *s, const sub_t *sd, int tr,
+                                double p, double q, const double *lamL, const double *lamR,
+                                double *hist) {
+  const double hx = 1.0 / nx, hv = 2.0 / nv, dt = T / nt, r = dt / (hv * hv), k = dt / hv;
+  const int a = sd->a, b = sd->b, nn = b - a + 1;
+  const int dirL = sd->left_if && tr == KFP_O_DIRICHLET;
+  const int dirR = sd->right_if && tr == KFP_O_DIRICHLET;
+  const int robL = sd->left_if && tr == KFP_O_ROBIN;
+  const int robR = sd->right_if && tr == KFP_O_ROBIN;
+  const int lo = dirL ? a + 1 : a, hi = dirR ? b - 1 : b, nu_ = hi - lo + 1;
+  const size_t plane = (size_t)nn * nx;
+  double *U = (double *)malloc(sizeof(double) * plane); /* U^n */
+  double *G = (double *)malloc(sizeof(double) * plane);
+  for (int i = a; i <= b; ++i)
+    memcpy(U + (size_t)(i - a) * nx, u0 + (size_t)i * nx, sizeof(double) * nx);
+  for (int n = 0; n < nt; ++n) {
+    const double gs = dt * (s ? s[n + 1] : 1.0);
+    for (int i = a; i <= b; ++i)
+      for (int m = 0; m < nx; ++m)
+        G[(size_t)(i - a) * nx + m] = U[(size_t)(i - a) * nx + m] + gs * f[(size_t)i * nx + m];
+    double *W = hist + (size_t)n * plane;
+    const double *LL = lamL ? lamL + (size_t)n * nx : NULL; /* level n+1 */
+    const double *LR = lamR ? lamR + (size_t)n * nx : NULL;
+#pragma omp parallel
+    {
+      double *lo_ = (double *)malloc(sizeof(double) * nu_ * 7);
+      double *di = lo_ + nu_, *up = di + nu_, *rhs = up + nu_, *cp = rhs + nu_,
+             *dp = cp + nu_, *x = dp + nu_;
+#pragma omp for schedule(static)
+      for (int m = 0; m < nx; ++m) {
+        for (int t = 0; t < nu_; ++t) lo_[t] = di[t] = up[t] = rhs[t] = 0.0;
+        /* element by element */
+        for (int e = a; e < b; ++e) {
+          for (int ii = 0; ii < 2; ++ii) {
+            const int i = e + ii; /* row */
+            if (i < lo || i > hi) continue;
+            for (int jj = 0; jj < 2; ++jj) {
+              const int jn = e + jj; /* column */
+              const double me = (ii == jj ? 2.0 : 1.0) / 6.0;
+              const double ke = (ii == jj ? r : -r);
+              rhs[i - lo] += me * G[(size_t)(jn - a) * nx + m];
+              if (jn >= lo && jn <= hi) {
+                if (jn == i) di[i - lo] += me + ke;
+                else if (jn < i) lo_[i - lo] += me + ke;
+                else up[i - lo] += me + ke;
+              } else { /* a fixed (Dirichlet) node: its level n+1 value moves over */
+                const double fixed = (jn == a) ? LL[m] : LR[m];
+                rhs[i - lo] -= (me + ke) * fixed;
+              }
+            }
+          }
+        }
+        if (robL) { /* (q - d/dv) u = lambda_2 at alpha */
+          di[0] += k * q;
+          rhs[0] += k * LL[m];
+        }
+        if (robR) { /* (p + d/dv) u = lambda_1 at beta */
+          di[nu_ - 1] += k * p;
+          rhs[nu_ - 1] += k * LR[m];
+        }
+        thomas(nu_, lo_, di, up, rhs, x, cp, dp);
+        for (int i = lo; i <= hi; ++i) W[(size_t)(i - a) * nx + m] = x[i - lo];
+        if (dirL) W[m] = LL[m];
+        if (dirR) W[(size_t)(b - a) * nx + m] = LR[m];
+      }
+      free(lo_);
+    }
+    /* Step 2: U^{n+1} = T W^{n+1}, row by row */
+    for (int i = a; i <= b; ++i) {
+      const double v = -1.0 + i * hv;
+      transport_row(nx, v * dt / hx, W + (size_t)(i - a) * nx, U + (size_t)(i - a) * nx);
+    }
+  }
+  free(U);
+  free(G);
+}
+
+/* Interface data of the finite-element scheme with overlap.  The derivative
+ * in Q is the flux the sender's own elements next to the node carry: the
+ * weak form of Step 1 over the element below node i gives u_v(v_i) as
+ *   F_lo(i) = h/(6 dt) [(W_{i-1} - G_{i-1}) + 2 (W_i - G_i)] + (W_i - W_{i-1})/h,
+ * and over the element above, -u_v(v_i) as
+ *   F_up(i) = h/(6 dt) [2 (W_i - G_i) + (W_{i+1} - G_{i+1})] + (W_i - W_{i+1})/h.
+ * Q_2 u_j = q W - F_lo at alpha = a_{j+1} (elements of u_j below alpha) and
+ * Q_1 u_{j+1} = p W - F_up at beta = b_j (elements of u_{j+1} above beta).
+ * The monodomain row of an interior node is F_lo + F_up = 0, so the
+ * monodomain solution is a fixed point of the iteration. */
+static void fem_emit_trace(int nx, int nv, int nt, double T, const double *u0, const double *f,
+                           const double *s, int j, int side, const int *a, const int *b, int o,
+                           int tr, double p, double q, const double *Ul, const double *Ur,
+                           const double *lam_used, double *lam_out) {
+  const size_t P = (size_t)nt * nx;
+  const double hv = 2.0 / nv, dt = T / nt, cm = hv / (6.0 * dt);
+  const int al = a[j + 1], be = b[j];
+  const int nnL = b[j] - a[j] + 1, nnR = b[j + 1] - a[j + 1] + 1;
+  for (int n = 0; n < nt; ++n) {
+    const double gs = dt * (s ? s[n + 1] : 1.0);
+    const double *UL = Ul + (size_t)n * nnL * nx; /* W^{n+1} of u_j */
+    const double *UR = Ur + (size_t)n * nnR * nx; /* W^{n+1} of u_{j+1} */
+    for (int m = 0; m < nx; ++m) {
+      const size_t e = (size_t)n * nx + m;
+      if (side == 0) {
+        const double w0 = UL[(size_t)(al - a[j]) * nx + m];
+        double v = w0;
+        if (tr == KFP_O_ROBIN && o == 0) {
+          v = (p + q) * w0 - lam_used[(size_t)(2 * j + 1) * P + e];
+        } else if (tr == KFP_O_ROBIN) {
+          const double w1 = UL[(size_t)(al - 1 - a[j]) * nx + m];
+          const double g0 = fem_stage_input(nx, nv, nt, T, u0, a[j], nnL, Ul, al, n, m) +
+                            gs * f[(size_t)al * nx + m];
+          const double g1 = fem_stage_input(nx, nv, nt, T, u0, a[j], nnL, Ul, al - 1, n, m) +
+                            gs * f[(size_t)(al - 1) * nx + m];
+          const double flo = cm * ((w1 - g1) + 2.0 * (w0 - g0)) + (w0 - w1) / hv;
+          v = q * w0 - flo;
+        }
+        lam_out[(size_t)(2 * j) * P + e] = v;
+      } else {
+        const double w0 = UR[(size_t)(be - a[j + 1]) * nx + m];
+        double v = w0;
+        if (tr == KFP_O_ROBIN && o == 0) {
+          v = (p + q) * w0 - lam_used[(size_t)(2 * j) * P + e];
+        } else if (tr == KFP_O_ROBIN) {
+          const double w1 = UR[(size_t)(be + 1 - a[j + 1]) * nx + m];
+          const double g0 = fem_stage_input(nx, nv, nt, T, u0, a[j + 1], nnR, Ur, be, n, m) +
+                            gs * f[(size_t)be * nx + m];
+          const double g1 = fem_stage_input(nx, nv, nt, T, u0, a[j + 1], nnR, Ur, be + 1, n, m) +
+                            gs * f[(size_t)(be + 1) * nx + m];
+          const double fup = cm * (2.0 * (w0 - g0) + (w1 - g1)) + (w0 - w1) / hv;
+          v = p * w0 - fup;
+        }
+        lam_out[(size_t)(2 * j + 1) * P + e] = v;
+      }
+    }
+  }
+}
+
 /* Owner of node i when the subdomain pieces are glued into one field:
  * the subdomain whose core [c_j, c_{j+1}) holds i, moved one down when i is
  * that subdomain's fixed Dirichlet node. */
@@ -377,12 +564,13 @@ static void mismatch(int nx, int nt, int j, const int *a, const int *b, const do
  *   ovl_hist[k-1] = the maximum over the whole closed overlap (6.12).
  *   Returns 0 on convergence, 4 when max_iter is reached, 1 on bad input.
  */
-int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
-                             const double *f, const double *s, int J, int o, int tr, double p,
-                             double q, double tol, int max_iter, const double *lambda_init,
-                             int order, double *uT, double *lambda_out, int *iters,
-                             double *res_hist, double *ovl_hist) {
-  if (nx < 1 || nv < 2 || nt < 1 || !(T > 0) || max_iter < 1 || order < 0 || order > 1)
+int oracle_swr_solve_scheme(int nx, int nv, int nt, double T, const double *u0,
+                            const double *f, const double *s, int J, int o, int tr, double p,
+                            double q, double tol, int max_iter, const double *lambda_init,
+                            int order, int scheme, double *uT, double *lambda_out, int *iters,
+                            double *res_hist, double *ovl_hist) {
+  if (nx < 1 || nv < 2 || nt < 1 || !(T > 0) || max_iter < 1 || order < 0 || order > 1 ||
+      scheme < KFP_O_FD || scheme > KFP_O_FEM)
     return 1;
   int *a = (int *)malloc(sizeof(int) * J), *b = (int *)malloc(sizeof(int) * J);
   if (oracle_partition(nv, J, o, a, b)) {
@@ -411,6 +599,23 @@ int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
     sd[j].nonovl = o == 0;
     hist[j] = (double *)malloc(sizeof(double) * (size_t)(b[j] - a[j] + 1) * P);
   }
+  /* one subdomain solve and one trace, in the chosen discretisation */
+#define SOLVE(j, LL, LR)                                                                  \
+  do {                                                                                    \
+    if (scheme == KFP_O_FEM)                                                              \
+      fem_solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);    \
+    else                                                                                  \
+      solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);        \
+  } while (0)
+#define EMIT(j, side, used, out)                                                          \
+  do {                                                                                    \
+    if (scheme == KFP_O_FEM)                                                              \
+      fem_emit_trace(nx, nv, nt, T, u0, f, s, j, side, a, b, o, tr, p, q, hist[j],        \
+                     hist[(j) + 1], used, out);                                           \
+    else                                                                                  \
+      emit_trace(nx, nt, j, side, a, b, o, tr, p, q, hv, hist[j], hist[(j) + 1], used,    \
+                 out);                                                                    \
+  } while (0)
   int k = 0, status = 4;
   for (k = 1; k <= max_iter; ++k) {
     if (order == 0) {
@@ -418,13 +623,11 @@ int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
       for (int j = 0; j < J; ++j) {
         const double *LL = (j > 0) ? lamOld + (size_t)(2 * (j - 1)) * P : NULL;
         const double *LR = (j < J - 1) ? lamOld + (size_t)(2 * j + 1) * P : NULL;
-        solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);
+        SOLVE(j, LL, LR);
       }
       /* (6.9)/(6.11): new interface variables from the neighbours */
       for (int j = 0; j < nI; ++j)
-        for (int side = 0; side < 2; ++side)
-          emit_trace(nx, nt, j, side, a, b, o, tr, p, q, hv, hist[j], hist[j + 1], lamOld,
-                     lamNew);
+        for (int side = 0; side < 2; ++side) EMIT(j, side, lamOld, lamNew);
       double *t = lamOld;
       lamOld = lamNew;
       lamNew = t;
@@ -434,15 +637,13 @@ int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
         for (int j = c; j < J; j += 2) {
           const double *LL = (j > 0) ? lamOld + (size_t)(2 * (j - 1)) * P : NULL;
           const double *LR = (j < J - 1) ? lamOld + (size_t)(2 * j + 1) * P : NULL;
-          solve_subdomain(nx, nv, nt, T, u0, f, s, &sd[j], tr, p, q, LL, LR, hist[j]);
+          SOLVE(j, LL, LR);
         }
         for (int j = 0; j < nI; ++j) {
           if (j % 2 == c) /* subdomain j sends plane 2j */
-            emit_trace(nx, nt, j, 0, a, b, o, tr, p, q, hv, hist[j], hist[j + 1], lamOld,
-                       lamOld);
+            EMIT(j, 0, lamOld, lamOld);
           if ((j + 1) % 2 == c) /* subdomain j+1 sends plane 2j+1 */
-            emit_trace(nx, nt, j, 1, a, b, o, tr, p, q, hv, hist[j], hist[j + 1], lamOld,
-                       lamOld);
+            EMIT(j, 1, lamOld, lamOld);
         }
       }
     }
@@ -457,11 +658,19 @@ int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
   }
   if (k > max_iter) k = max_iter;
   *iters = k;
-  /* output: glue the final iterates at t = T */
+#undef SOLVE
+#undef EMIT
+  /* output: glue the final iterates at t = T (finite elements: glue W^nt,
+   * then Step 2 of the last step, row by row) */
   for (int i = 0; i <= nv; ++i) {
     int j = owner(i, nv, J, a, tr);
     const double *src = hist[j] + (size_t)(nt - 1) * (b[j] - a[j] + 1) * nx +
                         (size_t)(i - a[j]) * nx;
+    if (scheme == KFP_O_FEM) {
+      const double v = -1.0 + i * hv;
+      transport_row(nx, v * (T / nt) * nx, src, uT + (size_t)i * nx);
+      continue;
+    }
     for (int m = 0; m < nx; ++m) uT[(size_t)i * nx + m] = (i == 0 || i == nv) ? 0.0 : src[m];
   }
   if (lambda_out && nI > 0) memcpy(lambda_out, lamOld, sizeof(double) * 2 * nI * P);
@@ -473,6 +682,34 @@ int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
   free(a);
   free(b);
   return status;
+}
+
+/* oracle_swr_solve_ordered: oracle_swr_solve_scheme with finite differences. */
+int oracle_swr_solve_ordered(int nx, int nv, int nt, double T, const double *u0,
+                             const double *f, const double *s, int J, int o, int tr, double p,
+                             double q, double tol, int max_iter, const double *lambda_init,
+                             int order, double *uT, double *lambda_out, int *iters,
+                             double *res_hist, double *ovl_hist) {
+  return oracle_swr_solve_scheme(nx, nv, nt, T, u0, f, s, J, o, tr, p, q, tol, max_iter,
+                                 lambda_init, order, KFP_O_FD, uT, lambda_out, iters, res_hist,
+                                 ovl_hist);
+}
+
+/* Monodomain solution of the finite-element scheme (nodes 0..nv, Neumann
+ * ends): U^nt = T W^nt. */
+int oracle_fem_mono_solve(int nx, int nv, int nt, double T, const double *u0, const double *f,
+                          const double *s, double *uT) {
+  if (nx < 1 || nv < 2 || nt < 1 || !(T > 0)) return 1;
+  sub_t sd = {0, nv, 0, 0, 0};
+  const size_t plane = (size_t)(nv + 1) * nx;
+  double *hist = (double *)malloc(sizeof(double) * plane * nt);
+  fem_solve_subdomain(nx, nv, nt, T, u0, f, s, &sd, KFP_O_DIRICHLET, 0.0, 0.0, NULL, NULL, hist);
+  const double hv = 2.0 / nv;
+  for (int i = 0; i <= nv; ++i)
+    transport_row(nx, (-1.0 + i * hv) * (T / nt) * nx, hist + (size_t)(nt - 1) * plane + (size_t)i * nx,
+                  uT + (size_t)i * nx);
+  free(hist);
+  return 0;
 }
 
 /* oracle_swr_solve: the parallel order of oracle_swr_solve_ordered. */
