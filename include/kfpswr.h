@@ -57,6 +57,8 @@ typedef enum {
 } kfp_status;
 
 typedef enum { KFP_DIRICHLET = 0, KFP_ROBIN = 1 } kfp_transmission;
+/* Discretisation of the v-diffusion (kfp_set_scheme). */
+typedef enum { KFP_SCHEME_FD = 0, KFP_SCHEME_FEM = 1 } kfp_scheme;
 
 /* The space-time grid of Section 6.2.  x in [0,1) periodic with nx cells,
  * v in [-1,1] with nv cells (nv+1 nodes), nt steps of dt = T/nt. */
@@ -233,6 +235,29 @@ kfp_status kfp_set_pipeline(int32_t inflight);
  * in turn, the classes side by side) and kfp_swr_solve_windows.
  */
 kfp_status kfp_set_ordering(int32_t order);
+
+/*
+ * kfp_set_scheme -- discretisation used by every later solve
+ * (kfp_mono_solve, kfp_swr_solve / _pq, kfp_swr_batch,
+ * kfp_swr_solve_windows; not kfp_u0_guess, whose traces are a guess for
+ * either scheme: one-sided differences of the start state).
+ * KFP_SCHEME_FD (default): finite differences in v, one IMEX step
+ *   (transport, source, implicit diffusion), zero values at v = +-1.
+ * KFP_SCHEME_FEM: the discretisation of Section 6.2 as printed: linear
+ *   finite elements in v with the consistent mass matrix and the stiffness
+ *   matrix of (6.3), homogeneous Neumann conditions at v = +-1 (6.1), and a
+ *   time step that first solves the diffusion stage
+ *   (M/dt + S) W^{n+1} = M/dt (U^n + dt s(t_{n+1}) f) and then transports
+ *   its result, U^{n+1} = T W^{n+1} ((6.4)/(6.5)), each stage over the whole
+ *   step dt; U^0 = u0.  Robin transmission is a natural condition (with or
+ *   without overlap); a trace sent across an overlap takes the derivative
+ *   in Q from the flux of the sender's element next to the interface node;
+ *   the iterates, traces and residual (6.12) are those of the diffusion
+ *   stage, and uT is U^nt.  Runs on the march kernel only: subdomains of at
+ *   most 1056 rows, KFP_EINVAL otherwise (at the solve).
+ * Returns KFP_EINVAL for any other value.
+ */
+kfp_status kfp_set_scheme(int32_t scheme);
 
 /*
  * kfp_swr_solve_windows -- SWR on time windows.  [0, T] is cut into

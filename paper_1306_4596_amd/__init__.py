@@ -13,6 +13,8 @@ from .binding import (  # noqa: F401
     MLP,
     PARALLEL,
     RED_BLACK,
+    FD,
+    FEM,
     ROBIN,
     KfpError,
     SWRStats,
@@ -31,6 +33,7 @@ from .binding import (  # noqa: F401
     set_config,
     set_kernel_timing,
     set_ordering,
+    set_scheme,
     set_pipeline,
     standardize,
     subdomain_rows,

@@ -106,6 +106,7 @@ def load_library():
     lib.kfp_get_launch.argtypes = [G, i32, i32, i32, pi, pi, pi, pi]
     lib.kfp_set_pipeline.argtypes = [i32]
     lib.kfp_set_ordering.argtypes = [i32]
+    lib.kfp_set_scheme.argtypes = [i32]
     lib.kfp_set_kernel_timing.argtypes = [i32]
     lib.kfp_get_config.argtypes = [G, i32, i32, i32, pi, pi, pi]
     lib.kfp_subdomain_rows.argtypes = [G, i32, i32, i32, ctypes.POINTER(ctypes.c_int64)]
@@ -117,7 +118,7 @@ def load_library():
                  "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
-                 "kfp_set_ordering", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
+                 "kfp_set_ordering", "kfp_set_scheme", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -371,12 +372,21 @@ def set_pipeline(inflight=-1):
 
 
 PARALLEL, RED_BLACK = 0, 1
+FD, FEM = 0, 1
 
 
 def set_ordering(order=PARALLEL):
     """Order of the subdomain solves in an iteration: PARALLEL (default) or
     RED_BLACK (even subdomains, then odd ones with the traces just sent)."""
     _check(load_library().kfp_set_ordering(int(order)))
+
+
+def set_scheme(scheme=FD):
+    """Discretisation of every later solve: FD (default; finite differences,
+    IMEX step, zero values at v = +-1) or FEM (Section 6.2 as printed: linear
+    finite elements with the consistent mass matrix, Neumann ends, the
+    diffusion stage before the transport)."""
+    _check(load_library().kfp_set_scheme(int(scheme)))
 
 
 def set_kernel_timing(on=True):

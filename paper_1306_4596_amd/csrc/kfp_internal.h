@@ -36,8 +36,18 @@ struct InstDev {
   int active;                   // 0: frozen (converged), skipped by every kernel
   int nonovl;                   // 1: no overlap (END_RFV interface rows)
   int xmode;                    // exchange mode when a launch leaves it to the instance
-  int pad_;
+  int scheme;                   // 0 finite differences; 1 finite elements (FEM_* tables)
 };
+
+// Discretisations of the v-diffusion.  SCHEME_FD: finite differences, one
+// IMEX step (transport, source, implicit diffusion), zero values at v = +-1.
+// SCHEME_FEM: Section 6.2 as printed: linear finite elements with the
+// consistent mass matrix, Neumann ends, the diffusion stage before the
+// transport.  The march then carries W^n, the diffusion stage's result
+// (U^n = T W^n): a step forms G = T W^n + dt s f (G = u0 + dt s f at the
+// first step, where nothing has been transported yet) and solves
+// (M/dt + S) W^{n+1} = M/dt G; the output is T W^nt.
+enum Scheme : int { SCHEME_FD = 0, SCHEME_FEM = 1 };
 
 // One subdomain of one instance.  Rows are local: 0 .. n-1 are the unknown
 // rows, row 0 has the smallest v.  Planes index the instance's trace window.
@@ -91,6 +101,30 @@ struct MarchCoef {
   double fab;    // 1 / pivot of an end row that takes boundary data, else 0
 };
 
+// The finite-element layout of the same rows (rows scaled by dt/h_v: an
+// element adds (1/6)[[2,1],[1,2]] + r[[1,-1],[-1,1]]).  A step first forms G
+// in every register (transport with the unscaled weights a, b), then
+// eliminates with right-hand sides wl G_{k-1} + wm G_k + wu G_{k+1}: the
+// mass weights times 1 / pivot (unscaled on separator rows).  Rows whose
+// neighbour in G lies outside the segment (the first real row below, a
+// separator or the subdomain's last row above) have that weight zero here:
+// it is applied from FemSeg or, for a separator, in the reduced system.
+struct FemCoef {
+  double a, b;        // transport: 1 - |nu|, |nu|
+  double wl, wm, wu;  // mass weights of G_{k-1}, G_k, G_{k+1}, times 1 / pivot
+  double fb, bc, sl, sr;  // as in MarchCoef
+  double fab;         // 1 / pivot of an end row that takes boundary data, else 0
+};
+
+// Per segment of the finite-element layout: the G of the node just below
+// the segment's first real row (the separator of the segment below, or the
+// fixed node under a classical interface) and just above the subdomain's
+// last row (a fixed node above, last segment only).
+struct FemSeg {
+  double nul, wol;  // signed Courant number of the node below, weight of its G
+  double nua, woa;  // the same for the node above
+};
+
 // Per separator row of the reduced system.
 struct RedCoef {
   double ra;  // sub-diagonal coefficient of the separator row
@@ -98,6 +132,7 @@ struct RedCoef {
   double g1;  // 1 / pivot of the reduced elimination
   double g2;  // -alpha / pivot
   double h;   // -gamma'
+  double rg;  // finite elements: weight of G of the next segment's first row (0 otherwise)
 };
 
 // A workgroup's unit of work: subdomain `sub`, x-columns x0 .. x0+63.
@@ -110,6 +145,7 @@ struct Item {
 struct ExItem {
   int inst;
   int j;      // interface between subdomains j and j+1
+  int a, b;   // its nodes a_{j+1} and b_j
 };
 
 struct StepTables {
@@ -121,11 +157,14 @@ struct StepTables {
   const int *segs;
   const ExItem *ex;
   const MarchCoef *mrows;
+  const FemCoef *frows;  // finite-element layout (instead of mrows)
+  const FemSeg *fsegs;   // finite-element layout: per segment, from SubDev::seg
   const double *rinv;  // per multi-step subdomain: (P-1) x (P-1) inverse, row-major
   const int *blk;      // pipelined iterations: time block of each instance this launch
                        // (-1: idle), or nullptr
   int n_items;
   int n_ex;
+  int fem;             // the tables are the finite-element layout
 };
 
 // Pipelined iterations.  Waveform relaxation is causal in time: iteration k
@@ -147,7 +186,9 @@ struct PipeCtl {
 
 // Slots of the interface-node value planes written by the multi-step kernel:
 // the lower subdomain j gives u_j(a_{j+1}), u_j(a_{j+1}+1), u_j(b_j); the
-// upper one gives u_{j+1}(a_{j+1}), u_{j+1}(b_j), u_{j+1}(b_j - 1).
+// upper one gives u_{j+1}(a_{j+1}), u_{j+1}(b_j), u_{j+1}(b_j - 1).  With
+// finite elements the slots A1_LO / B1_HI hold u_j(a_{j+1}-1) /
+// u_{j+1}(b_j+1): the nodes of the element on the sender's side.
 enum VSlot : int { V_A_LO = 0, V_A1_LO = 1, V_B_LO = 2, V_A_HI = 3, V_B_HI = 4, V_B1_HI = 5 };
 
 // Kernel launchers (swr_kernels.hip).  Return hipSuccess or the launch error.
@@ -174,8 +215,10 @@ hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s, i
 hipError_t launch_pipe_tick(PipeCtl *c, int *blk, int *iter, unsigned long long *res,
                             double *hist, hipStream_t s);
 hipError_t launch_reset_res(const InstDev *inst, int n_inst, hipStream_t s);
+// nudt: dt / h_x for the finite-element scheme (the last step's transport
+// of every row, v_i = -1 + i hv), 0 for a plain copy.
 hipError_t launch_assemble(const double *Ufinal, const int *rowmap, double *uT, int nv, int nx,
-                           hipStream_t s);
+                           hipStream_t s, double nudt = 0.0, double hv = 0.0);
 hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_count_nonfinite(const double *p, size_t n, unsigned int *count, hipStream_t s);

@@ -82,7 +82,7 @@ __device__ __forceinline__ InstDev load_inst(KConst<InstDev> *p) {
   I.active = p->active;
   I.nonovl = p->nonovl;
   I.xmode = p->xmode;
-  I.pad_ = 0;
+  I.scheme = p->scheme;
   return I;
 }
 
@@ -500,6 +500,74 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
   });
 }
 
+// Finite elements, first half of a step: G_k = T W^n + dt s f in every
+// register (DIR_NONE at the first step of a solve: nothing transported yet).
+constexpr int DIR_NONE = 3;
+template <int SEG, int DIR>
+__device__ __forceinline__ void fem_stage(SegRegs<SEG> &d, const SegRegs<SEG> &fs,
+                                          const FemCoef *mc, double gn, int vsplit,
+                                          KGlob<const double> *fr, int base, int nx, int col) {
+  static_for<0, SEG>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double u = d.template ld<k>();
+    double fk;
+    if constexpr (SEG <= kFRegMax)
+      fk = fs.template ld<k>();
+    else
+      fk = fr[(size_t)max(base + k, 0) * nx + col];
+    double g;
+    if constexpr (DIR == DIR_NONE) {
+      g = fma(gn, fk, u);
+    } else {
+      double nb;
+      if constexpr (DIR == DIR_LO) {
+        nb = from_lower_lane(u);
+      } else if constexpr (DIR == DIR_UP) {
+        nb = from_upper_lane(u);
+      } else {
+        const double a = from_lower_lane(u), c = from_upper_lane(u);
+        nb = (k >= vsplit) ? a : c;
+      }
+      g = fma(mc[k].a, u, fma(mc[k].b, nb, gn * fk));
+    }
+    d.template st<k>(g);
+  });
+}
+
+// G of one node outside the segment (its state u in every lane): signed
+// Courant number nu, source value fv.
+__device__ __forceinline__ double fem_edge_g(double u, double nu, double gn, double fv,
+                                             bool first) {
+  const double lo = from_lower_lane(u), up = from_upper_lane(u);
+  if (first) return fma(gn, fv, u);
+  const double w = fabs(nu);
+  const double nb = nu > 0.0 ? lo : (nu < 0.0 ? up : u);
+  return fma(1.0 - w, u, fma(w, nb, gn * fv));
+}
+
+// Finite elements, second half: forward elimination with the mass-matrix
+// right-hand side.  ylo: the starting value (boundary data and the G of the
+// node below, already weighted); bhi: the same for the last register.
+template <int SEG>
+__device__ __forceinline__ void fem_forward(SegRegs<SEG> &d, const FemCoef *mc, double ylo,
+                                            double bhi) {
+  double y = ylo;
+  double gprev = 0.0;
+  static_for<0, SEG>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double gk = d.template ld<k>();
+    double t = mc[k].wm * gk;
+    if constexpr (k > 0) t = fma(mc[k].wl, gprev, t);
+    if constexpr (k < SEG - 1)
+      t = fma(mc[k].wu, d.template ld<k + 1>(), t);
+    else
+      t += bhi;
+    gprev = gk;
+    y = fma(mc[k].fb, y, t);
+    d.template st<k>(y);
+  });
+}
+
 // G lane groups per wavefront: a wavefront holds G segments of a subdomain,
 // each for a tile of 64/G x-columns (lanes g*64/G .. (g+1)*64/G - 1 hold
 // segment w*G + g).  G = 1 is one segment per wavefront over 64 columns;
@@ -512,10 +580,17 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
 // OCC: wavefronts per SIMD the register allocation must allow (1: no limit
 // beyond one workgroup).  A build of the same code for more resident
 // workgroups, for launches with several work items per compute unit.
-template <int SEG, int NW, int G, int OCC = 1>
+// FEM: the finite-element scheme (FemCoef tables; the step forms G in every
+// register first, then eliminates with the mass-matrix right-hand side; the
+// G of the node below a segment comes from that node's state, which the
+// lane holds: the separator value the reduced system gave it, or the fixed
+// node's trace; the separator's G of the node above enters the reduced
+// system from LDS).
+template <int SEG, int NW, int G, int OCC = 1, bool FEM = false>
 __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n0_in, int S,
                                                              int H, int src_in, int par) {
   static_assert(G == 1 || G == 2 || G == 4, "lane groups");
+  using MC = typename std::conditional<FEM, FemCoef, MarchCoef>::type;
   constexpr int NV = NW * G;  // segments per workgroup
   constexpr int TW = 64 / G;  // tile columns
   // segment end values for the reduced system, double-buffered by step
@@ -532,8 +607,11 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
   // source factors, staged once per item: the step loop then issues no
   // scalar loads either, and LDS reads (returned in order) can be waited on
   // one by one, so they are issued well ahead of their use
-  __shared__ MarchCoef sh_mc[NV][SEG];
+  __shared__ MC sh_mc[NV][SEG];
   __shared__ RedCoef sh_rc[NV];
+  // finite elements: G of every segment's first real row, for the separator
+  // below it (double-buffered like the reduced system's values)
+  __shared__ double sh_gf[FEM ? 2 : 1][FEM ? NV : 1][FEM ? TW : 1];
   __shared__ double sh_rinv[(NV - 1) * (NV - 1) + 1];
   __shared__ double sh_g[NW][kMaxStepsPerLaunch];
   const int lane = threadIdx.x & 63;
@@ -610,11 +688,12 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
     // system is copied by wave 0 and first read after the step's first
     // barrier (the previous item's last reads ended at its last step's
     // second barrier)
-    const MarchCoef *mc = sh_mc[v];
+    const MC *mc = sh_mc[v];
     if (wave_active) {
-      KGlob<const double> *ct = as_glob((const double *)(t.mrows + sd->tab + w * G * SEG));
+      const MC *tab = FEM ? (const MC *)t.frows : (const MC *)t.mrows;
+      KGlob<const double> *ct = as_glob((const double *)(tab + sd->tab + w * G * SEG));
       double *cs = reinterpret_cast<double *>(sh_mc[w * G]);
-      constexpr int NDB = (int)(sizeof(MarchCoef) / sizeof(double));
+      constexpr int NDB = (int)(sizeof(MC) / sizeof(double));
       const int ncw = nseg * SEG * NDB;  // rows past the table's end are not read
 #pragma unroll
       for (int e0 = 0; e0 < G * SEG * NDB; e0 += 64)
@@ -640,15 +719,55 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
         constexpr int k = decltype(kc)::value;
         const int r = max(base + k, 0);
         d.template st<k>(src[(size_t)r * nx + col]);
-        if constexpr (SEG <= kFRegMax) fs.template st<k>(mc[k].fa * fr[(size_t)r * nx + col]);
+        if constexpr (SEG <= kFRegMax) {
+          if constexpr (FEM)
+            fs.template st<k>(fr[(size_t)r * nx + col]);
+          else
+            fs.template st<k>(mc[k].fa * fr[(size_t)r * nx + col]);
+        }
       });
     }
-    const double rfv = 2.0 * rr * I->hv;  // flux weight of a half-cell row (no overlap)
-    const double lo_scale =
-        lo_end ? mc[k0].fab * (lo_kind == END_ROBIN ? 1.0 : (lo_kind == END_RFV ? rfv : rr)) : 0.0;
-    const double hi_scale =
-        hi_end ? mc[SEG - 1].fab * (hi_kind == END_ROBIN ? 1.0 : (hi_kind == END_RFV ? rfv : rr))
-               : 0.0;
+    // weight of the incoming trace in an end row: finite differences: 1 (a
+    // Robin row), 2 dt / h_v (half-cell row), r (next to a fixed node);
+    // finite elements (rows times dt / h_v): dt / h_v for a Robin row with or
+    // without overlap (a natural condition), r - 1/6 next to a fixed node
+    const double rfv = 2.0 * rr * I->hv;
+    auto end_w = [&](int kind) {
+      if constexpr (FEM)
+        return kind == END_DIRI ? rr - 1.0 / 6.0 : rr * I->hv;
+      else
+        return kind == END_ROBIN ? 1.0 : (kind == END_RFV ? rfv : rr);
+    };
+    const double lo_scale = lo_end ? mc[k0].fab * end_w(lo_kind) : 0.0;
+    const double hi_scale = hi_end ? mc[SEG - 1].fab * end_w(hi_kind) : 0.0;
+    // finite elements: the nodes next to the segment (below its first real
+    // row; above the subdomain's last row), their source values and states
+    double nul = 0.0, wol = 0.0, nua = 0.0, woa = 0.0;
+    double fbelow = 0.0, ubelow = 0.0, fabove = 0.0, uabove = 0.0;
+    if constexpr (FEM) {
+      if (active) {
+        KGlob<const double> *fsg = as_glob((const double *)(t.fsegs + sd->seg + v));
+        nul = fsg[0];
+        wol = fsg[1];
+        nua = fsg[2];
+        woa = fsg[3];
+        const int rb = base + k0 - 1;  // local row below the first real row
+        KGlob<const double> *f0 = as_glob(I->f);
+        KGlob<const double> *u00 = as_glob(I->u0);
+        if (wol != 0.0) {
+          fbelow = f0[(size_t)(g_lo + rb) * nx + col];
+          if (rb >= 0)
+            ubelow = src[(size_t)rb * nx + col];
+          else
+            ubelow = n0 == 0 ? u00[(size_t)(g_lo - 1) * nx + col] : lin_lo[(size_t)(n0 - 1) * nx];
+        }
+        if (woa != 0.0) {
+          fabove = f0[(size_t)(g_lo + n_rows) * nx + col];
+          uabove = n0 == 0 ? u00[(size_t)(g_lo + n_rows) * nx + col]
+                           : lin_hi[(size_t)(n0 - 1) * nx];
+        }
+      }
+    }
     // register `pad` of every lane (a wave-uniform index): the first real row
     // of the last segment
     auto first_value = [&](const SegRegs<SEG> &dd) {
@@ -690,13 +809,30 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
         const double gn = sh_g[w][s];
         const double blo = lo_end ? lo_scale * sh_bd[0][s][tl] : 0.0;
         const double bhi = hi_end ? hi_scale * sh_bd[1][s][tl] : 0.0;
-        // transport + source + forward elimination, one pass
-        if (dir == DIR_LO)
-          march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
-        else if (dir == DIR_UP)
-          march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
-        else
-          march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
+        if constexpr (FEM) {
+          // G in every register, then the elimination with the mass matrix
+          const bool first = n == 0;
+          if (first)
+            fem_stage<SEG, DIR_NONE>(d, fs, mc, gn, vs, fr, base, nx, col);
+          else if (dir == DIR_LO)
+            fem_stage<SEG, DIR_LO>(d, fs, mc, gn, vs, fr, base, nx, col);
+          else if (dir == DIR_UP)
+            fem_stage<SEG, DIR_UP>(d, fs, mc, gn, vs, fr, base, nx, col);
+          else
+            fem_stage<SEG, DIR_MIX>(d, fs, mc, gn, vs, fr, base, nx, col);
+          const double gb = fem_edge_g(ubelow, nul, gn, fbelow, first);
+          const double ga = fem_edge_g(uabove, nua, gn, fabove, first);
+          if (Pq > 1) sh_gf[s & 1][v][tl] = first_value(d);
+          fem_forward<SEG>(d, mc, fma(wol, gb, blo), fma(woa, ga, bhi));
+        } else {
+          // transport + source + forward elimination, one pass
+          if (dir == DIR_LO)
+            march_forward<SEG, NW, DIR_LO>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
+          else if (dir == DIR_UP)
+            march_forward<SEG, NW, DIR_UP>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
+          else
+            march_forward<SEG, NW, DIR_MIX>(d, fs, mc, gn, blo, bhi, vs, fr, base, nx, col);
+        }
         // back substitution
         double x = d.template ld<SEG - 1>();
         static_for<0, SEG - 1>([&](auto kc) {
@@ -724,8 +860,9 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
           for (int q = 0; q < NV - 1; ++q) {
             if (q < m) {
               const RedCoef &rq = sh_rc[q];
-              const double D = sh_sep[s & 1][q][tl] - rq.ra * sh_last[s & 1][q][tl] -
-                               rq.rc * sh_first[s & 1][q + 1][tl];
+              double D = sh_sep[s & 1][q][tl] - rq.ra * sh_last[s & 1][q][tl] -
+                         rq.rc * sh_first[s & 1][q + 1][tl];
+              if constexpr (FEM) D = fma(rq.rg, sh_gf[s & 1][q + 1][tl], D);
               xl = fma(Rl[q], D, xl);
               xh = fma(Rh[q], D, xh);
             }
@@ -741,6 +878,15 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
         });
         if (!last) d.template st<SEG - 1>(xhi);
       }
+      if constexpr (FEM) {
+        // states of the outside nodes at level n+1: the separator below (from
+        // the reduced system), or the fixed nodes' traces
+        if (v > 0)
+          ubelow = xlo;
+        else if (lo_end)
+          ubelow = sh_bd[0][s][tl];
+        if (hi_end) uabove = sh_bd[1][s][tl];
+      }
       // interface-node values of level n+1
       if (wave_active) {
         const size_t lvl = (size_t)n * nx + col;
@@ -748,7 +894,7 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
           KGlob<double> *Vj = Vbase + (size_t)(out_hi_plane >> 1) * 6 * plane + lvl;
           put_row(out_hi_row, Vj + V_A_LO * plane);
           if (robin) {
-            put_row(out_hi_row + 1, Vj + V_A1_LO * plane);
+            put_row(out_hi_row + (FEM ? -1 : 1), Vj + V_A1_LO * plane);
             put_row(n_rows - 1, Vj + V_B_LO * plane);
           }
         }
@@ -756,7 +902,7 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
           KGlob<double> *Vj = Vbase + (size_t)((out_lo_plane - 1) >> 1) * 6 * plane + lvl;
           put_row(out_lo_row, Vj + V_B_HI * plane);
           if (robin) {
-            put_row(out_lo_row - 1, Vj + V_B1_HI * plane);
+            put_row(out_lo_row + (FEM ? 1 : -1), Vj + V_B1_HI * plane);
             put_row(0, Vj + V_A_HI * plane);
           }
         }
@@ -815,6 +961,40 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
       toL = (I.p + I.q) * ubh - lin[(size_t)(2 * j) * plane + e];
       ub_lo = ua;
       ua_hi = ubh;
+    } else if (robin && I.scheme == SCHEME_FEM) {
+      // finite elements: the derivative in Q is the flux the sender's element
+      // next to the node carries (weak form of the diffusion stage):
+      //   below a: F = h/(6dt) [(W_{a-1} - G_{a-1}) + 2 (W_a - G_a)] + (W_a - W_{a-1})/h,
+      //   above b: F = h/(6dt) [2 (W_b - G_b) + (W_{b+1} - G_{b+1})] + (W_b - W_{b+1})/h,
+      // Q_2 u_j = q W_a - F(a), Q_1 u_{j+1} = p W_b - F(b); G = T W^n + dt s f
+      // from the previous level of the same value plane (u0 at the first)
+      const int nx = I.nx;
+      const int lv = (int)(e / nx), m = (int)(e - (size_t)lv * nx);
+      const double dt = I.r * I.hv * I.hv;
+      const double gn = I.g[lv];
+      const double cm = I.hv / (6.0 * dt);
+      auto stage = [&](int slot, int node) {
+        double u;
+        if (lv == 0) {
+          u = I.u0[(size_t)node * nx + m];
+        } else {
+          const double nu = (-1.0 + node * I.hv) * dt * nx;
+          const double *row = V + (size_t)slot * plane + (size_t)(lv - 1) * nx;
+          int mn = m + (nu > 0.0 ? -1 : (nu < 0.0 ? 1 : 0));
+          mn = mn < 0 ? mn + nx : (mn >= nx ? mn - nx : mn);
+          const double w = fabs(nu);
+          u = fma(1.0 - w, row[m], w * row[mn]);
+        }
+        return fma(gn, I.f[(size_t)node * nx + m], u);
+      };
+      const double ua1 = V[V_A1_LO * plane + e];   // W_j(a-1)
+      const double ub1h = V[V_B1_HI * plane + e];  // W_{j+1}(b+1)
+      const double ga = stage(V_A_LO, ex.a), ga1 = stage(V_A1_LO, ex.a - 1);
+      const double gb = stage(V_B_HI, ex.b), gb1 = stage(V_B1_HI, ex.b + 1);
+      toR = I.q * ua - (cm * ((ua1 - ga1) + 2.0 * (ua - ga)) + (ua - ua1) / I.hv);
+      toL = I.p * ubh - (cm * (2.0 * (ubh - gb) + (ub1h - gb1)) + (ubh - ub1h) / I.hv);
+      ub_lo = V[V_B_LO * plane + e];
+      ua_hi = V[V_A_HI * plane + e];
     } else if (robin) {
       const double ua1 = V[V_A1_LO * plane + e];
       const double ub1h = V[V_B1_HI * plane + e];
@@ -913,8 +1093,11 @@ __global__ void reset_res_kernel(const InstDev *inst, int n_inst) {
   if (i < n_inst && inst[i].active) *inst[i].res = 0ull;
 }
 
+// Glued output.  nudt > 0 (finite elements): the transport stage of the last
+// step, row i with Courant number (-1 + i hv) nudt.
 __global__ void assemble_kernel(const double *__restrict__ U, const int *__restrict__ rowmap,
-                                double *__restrict__ uT, int nv, int nx) {
+                                double *__restrict__ uT, int nv, int nx, double nudt,
+                                double hv) {
   const size_t total = (size_t)(nv + 1) * nx;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -922,7 +1105,20 @@ __global__ void assemble_kernel(const double *__restrict__ U, const int *__restr
     const int m = (int)(e - (size_t)i * nx);
     const int r = rowmap[i];
     if (r == -2) continue;  // node taken from another state
-    uT[e] = r >= 0 ? U[(size_t)r * nx + m] : 0.0;
+    if (r < 0) {
+      uT[e] = 0.0;
+      continue;
+    }
+    const double *row = U + (size_t)r * nx;
+    const double nu = (-1.0 + i * hv) * nudt;
+    if (nudt == 0.0 || nu == 0.0) {
+      uT[e] = row[m];
+      continue;
+    }
+    int mn = m + (nu > 0.0 ? -1 : 1);
+    mn = mn < 0 ? mn + nx : (mn >= nx ? mn - nx : mn);
+    const double w = fabs(nu);
+    uT[e] = fma(1.0 - w, row[m], w * row[mn]);
   }
 }
 
@@ -994,10 +1190,10 @@ hipError_t launch_reset_res(const InstDev *inst, int n_inst, hipStream_t s) {
 }
 
 hipError_t launch_assemble(const double *U, const int *rowmap, double *uT, int nv, int nx,
-                           hipStream_t s) {
+                           hipStream_t s, double nudt, double hv) {
   const size_t n = (size_t)(nv + 1) * nx;
   hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, U, rowmap, uT, nv,
-                     nx);
+                     nx, nudt, hv);
   return hipGetLastError();
 }
 
@@ -1095,6 +1291,17 @@ hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max,
   // the build limited to 128 registers (two resident workgroups per compute
   // unit, a few spilled values) is the faster one; with one item per
   // compute unit the unlimited build is.  Same arithmetic, same results.
+  if (t.fem) {
+#define KFP_LAUNCH_FEM(W, SM, G)                                                           \
+  if (waves == W && seg_max == SM && groups == G) {                                       \
+    hipLaunchKernelGGL((march_kernel<SM, W, G, 1, true>), dim3(grid), dim3(W * 64), 0, s, t, \
+                       n0, S, H, src, par);                                               \
+    return hipGetLastError();                                                             \
+  }
+    KFP_MARCH_CONFIGS(KFP_LAUNCH_FEM)
+#undef KFP_LAUNCH_FEM
+    return hipErrorInvalidValue;
+  }
   if (waves == 8 && seg_max == 17 && groups == 1 && grid >= 2 * device_cus()) {
     hipLaunchKernelGGL((march_kernel<17, 8, 1, 4>), dim3(grid), dim3(8 * 64), 0, s, t, n0, S, H,
                        src, par);

@@ -56,6 +56,7 @@ struct SubGeo {
 
 struct Geo {
   int nx, nv, nt, J, o, tr;
+  int scheme = SCHEME_FD;
   double T;
   std::vector<SubGeo> sub;
   std::vector<int> row_off;
@@ -78,7 +79,9 @@ static kfp_status validate_grid(const kfp_grid *g) {
   return KFP_OK;
 }
 
-static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Geo &geo) {
+// scheme: SCHEME_FEM makes v = -1 and v = +1 unknown rows (Neumann ends).
+static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Geo &geo,
+                           int scheme) {
   kfp_status st = validate_grid(g);
   if (st) return st;
   if (J < 1) return fail(KFP_EINVAL, "J must be >= 1 (got %d)", J);
@@ -100,6 +103,7 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
   geo.J = J;
   geo.o = o;
   geo.tr = tr;
+  geo.scheme = scheme;
   const int w = g->nv / J;
   std::vector<int> a(J), b(J);
   a[0] = 0;
@@ -122,15 +126,19 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
     const int ifk = tr == KFP_ROBIN ? (o == 0 ? END_RFV : END_ROBIN) : END_DIRI;
     s.lo_kind = j == 0 ? END_PHYS : ifk;
     s.hi_kind = j == J - 1 ? END_PHYS : ifk;
-    s.lo = s.lo_kind == END_ROBIN || s.lo_kind == END_RFV ? s.a : s.a + 1;
-    s.hi = s.hi_kind == END_ROBIN || s.hi_kind == END_RFV ? s.b : s.b - 1;
+    const bool fem = scheme == SCHEME_FEM;
+    s.lo = s.lo_kind == END_ROBIN || s.lo_kind == END_RFV || (fem && s.lo_kind == END_PHYS)
+               ? s.a : s.a + 1;
+    s.hi = s.hi_kind == END_ROBIN || s.hi_kind == END_RFV || (fem && s.hi_kind == END_PHYS)
+               ? s.b : s.b - 1;
     s.n = s.hi - s.lo + 1;
     geo.row_off[j] = geo.rows;
     geo.rows += s.n;
     geo.n_max = std::max(geo.n_max, s.n);
   }
   geo.rowmap.assign(g->nv + 1, -1);
-  for (int i = 1; i < g->nv; ++i) {
+  const int i_end = scheme == SCHEME_FEM ? g->nv : g->nv - 1;
+  for (int i = scheme == SCHEME_FEM ? 0 : 1; i <= i_end; ++i) {
     int j = std::min(J - 1, i / w);
     if (j > 0 && i == geo.sub[j].a && tr == KFP_DIRICHLET) j -= 1;
     const SubGeo &s = geo.sub[j];
@@ -237,6 +245,22 @@ static bool g_ktime = false;  // time every step-kernel launch with HIP events
 // 1 multiplicative red-black (even subdomains, then odd ones with the traces
 // the even ones just sent)
 static int g_order = 0;
+// discretisation of every solve (SCHEME_FD or SCHEME_FEM), set by kfp_set_scheme
+static int g_scheme = SCHEME_FD;
+
+// The output's last transport stage (finite elements): dt / h_x, else 0.
+static double out_nudt(const Geo &g) {
+  return g.scheme == SCHEME_FEM ? (g.T / g.nt) * g.nx : 0.0;
+}
+
+// The finite-element scheme runs on the march kernel only.
+static kfp_status fem_needs_march(const Geo &g, const Config &c) {
+  if (g.scheme == SCHEME_FEM && c.steps == 0)
+    return fail(KFP_EINVAL,
+                "the finite-element scheme needs a march configuration (subdomains of at most "
+                "1056 rows; tallest here %d)", g.n_max);
+  return KFP_OK;
+}
 
 // Tuning cache: a flat JSON object {"key": [waves, seg, steps, groups], ...}
 // (groups may be absent: 1).
@@ -304,8 +328,8 @@ static std::string arch_name() {
 
 static std::string tune_key(const Geo &g) {
   char buf[160];
-  snprintf(buf, sizeof buf, "%s/nx%d/nmax%d/J%d/tr%d", arch_name().c_str(), g.nx, g.n_max, g.J,
-           g.tr);
+  snprintf(buf, sizeof buf, "%s/nx%d/nmax%d/J%d/tr%d%s", arch_name().c_str(), g.nx, g.n_max, g.J,
+           g.tr, g.scheme == SCHEME_FEM ? "/fem" : "");
   return buf;
 }
 
@@ -349,9 +373,12 @@ static Config choose_config(const Geo &g) {
 
 // ------------------------------------------------------------------ tables --
 struct HostTables {
+  bool fem = false;  // the march tables are the finite-element layout
   std::vector<SubDev> subs;
   std::vector<RowCoef> rows;
   std::vector<MarchCoef> mrows;
+  std::vector<FemCoef> frows;
+  std::vector<FemSeg> fsegs;
   std::vector<double> rinv;
   std::vector<RedCoef> reds;
   std::vector<int> segs;
@@ -389,6 +416,57 @@ static void row_matrix(const SubGeo &s, double r, double p, double q, double hv,
     lo[s.n - 1] = -2.0 * r;
     di[s.n - 1] = 1.0 + 2.0 * r + fv * p;
     up[s.n - 1] = 0.0;
+  }
+}
+
+// The finite-element rows of subdomain s (Section 6.2: linear elements,
+// rows times dt / h_v), assembled element by element: each element
+// [v_e, v_{e+1}] inside [a, b] adds (1/6)[[2,1],[1,2]] + r[[1,-1],[-1,1]] to
+// the matrix and (1/6)[[2,1],[1,2]] to the mass weights ml, mm, mu of the
+// right-hand side M/dt G.  A Robin condition is natural at its end node, with
+// or without overlap: dt/h_v p (upper end) or dt/h_v q (lower end) on the
+// diagonal.  A fixed (classical) node's coupling moves to the right-hand side
+// with the trace (weight r - 1/6 of the row next to it) and its G enters
+// through the mass weight of that row.
+static void fem_row_matrix(const SubGeo &s, double r, double p, double q, double hv,
+                           std::vector<double> &lo, std::vector<double> &di,
+                           std::vector<double> &up, std::vector<double> &ml,
+                           std::vector<double> &mm, std::vector<double> &mu) {
+  lo.assign(s.n, 0.0);
+  di.assign(s.n, 0.0);
+  up.assign(s.n, 0.0);
+  ml.assign(s.n, 0.0);
+  mm.assign(s.n, 0.0);
+  mu.assign(s.n, 0.0);
+  for (int k = 0; k < s.n; ++k) {
+    const int i = s.lo + k;  // node
+    if (i > s.a) {           // the element below the node
+      lo[k] += 1.0 / 6.0 - r;
+      di[k] += 1.0 / 3.0 + r;
+      ml[k] += 1.0 / 6.0;
+      mm[k] += 1.0 / 3.0;
+    }
+    if (i < s.b) {  // the element above
+      up[k] += 1.0 / 6.0 - r;
+      di[k] += 1.0 / 3.0 + r;
+      mu[k] += 1.0 / 6.0;
+      mm[k] += 1.0 / 3.0;
+    }
+  }
+  const double kr = r * hv;  // dt / h_v
+  if (s.lo_kind == END_ROBIN || s.lo_kind == END_RFV) di[0] += kr * q;
+  if (s.hi_kind == END_ROBIN || s.hi_kind == END_RFV) di[s.n - 1] += kr * p;
+}
+
+// The matrix of either scheme.
+static void any_row_matrix(const SubGeo &s, int scheme, double r, double p, double q, double hv,
+                           std::vector<double> &lo, std::vector<double> &di,
+                           std::vector<double> &up) {
+  if (scheme == SCHEME_FEM) {
+    std::vector<double> ml, mm, mu;
+    fem_row_matrix(s, r, p, q, hv, lo, di, up, ml, mm, mu);
+  } else {
+    row_matrix(s, r, p, q, hv, lo, di, up);
   }
 }
 
@@ -645,11 +723,16 @@ static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg
   const int n = s.n;
   const int P = (n + seg - 1) / seg;
   const int pad = P * seg - n;
-  std::vector<double> lo, di, up;
-  row_matrix(s, r, p, q, hv, lo, di, up);
+  const bool fem = g.scheme == SCHEME_FEM;
+  std::vector<double> lo, di, up, ml, mm, mu;
+  if (fem)
+    fem_row_matrix(s, r, p, q, hv, lo, di, up, ml, mm, mu);
+  else
+    row_matrix(s, r, p, q, hv, lo, di, up);
+  t.fem = fem;
   SubDev d = sub_descriptor(g, j, inst, sub_base);
-  d.tab = (int)t.mrows.size();
-  d.seg = -1;
+  d.tab = fem ? (int)t.frows.size() : (int)t.mrows.size();
+  d.seg = fem ? (int)t.fsegs.size() : -1;
   d.red = (int)t.reds.size();
   d.rinv = (int)t.rinv.size();
   d.P = P;
@@ -704,7 +787,56 @@ static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg
       c.fab = takes_data(i) ? fa : 0.0;
     }
   }
-  for (auto &c : mc) t.mrows.push_back(c);
+  if (fem) {
+    // the same partition in the finite-element layout
+    auto nu_of = [&](int i) { return (-1.0 + (s.lo + i) * hv) * dt / hx; };
+    for (int w = 0; w < P; ++w) {
+      const int k0 = (w == P - 1) ? pad : 0;
+      FemSeg sg{0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < seg; ++k) {
+        FemCoef c{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (k < k0) {  // padding: passes the starting value on
+          c.fb = 1.0;
+          t.frows.push_back(c);
+          continue;
+        }
+        const int i = w * seg + k - k0;
+        const double wgt = std::fabs(nu_of(i));
+        c.a = 1.0 - wgt;
+        c.b = wgt;
+        if (w < P - 1 && k == seg - 1) {  // separator: its unscaled right-hand side
+          c.wl = ml[i];
+          c.wm = mm[i];
+          c.wu = 0.0;  // G of the next segment's first row: in the reduced system
+          c.fab = takes_data(i) ? 1.0 : 0.0;
+          t.frows.push_back(c);
+          continue;
+        }
+        const int kb = i - b0[w];
+        const double fa = 1.0 / bf[w].piv[kb];
+        c.wl = k == k0 ? 0.0 : fa * ml[i];
+        c.wm = fa * mm[i];
+        c.wu = k == seg - 1 ? 0.0 : fa * mu[i];
+        c.fb = (kb == 0) ? 1.0 : -lo[i] * fa;
+        c.bc = (i < b1[w]) ? -bf[w].cp[kb] : 0.0;
+        c.sl = bf[w].gL[kb];
+        c.sr = bf[w].gR[kb];
+        c.fab = takes_data(i) ? fa : 0.0;
+        if (k == k0) {  // the node below the first real row
+          sg.nul = nu_of(i - 1);
+          sg.wol = fa * ml[i];
+        }
+        if (i == n - 1) {  // the node above the subdomain's last row
+          sg.nua = nu_of(i + 1);
+          sg.woa = fa * mu[i];
+        }
+        t.frows.push_back(c);
+      }
+      t.fsegs.push_back(sg);
+    }
+  } else {
+    for (auto &c : mc) t.mrows.push_back(c);
+  }
   if (P > 1) {
     const int m = P - 1;
     std::vector<double> al(m), be(m), ga(m);
@@ -717,6 +849,7 @@ static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg
       RedCoef c{};
       c.ra = a_r;
       c.rc = c_r;
+      c.rg = fem ? mu[rho] : 0.0;
       t.reds.push_back(c);
     }
     double cprev = 0.0;
@@ -771,7 +904,7 @@ static void make_items(const Geo &g, int sub_base, int width, std::vector<Item> 
 }
 
 static void make_ex(const Geo &g, int inst, std::vector<ExItem> &ex) {
-  for (int j = 0; j + 1 < g.J; ++j) ex.push_back(ExItem{inst, j});
+  for (int j = 0; j + 1 < g.J; ++j) ex.push_back(ExItem{inst, j, g.sub[j + 1].a, g.sub[j].b});
 }
 
 // ------------------------------------------------------------------ device --
@@ -805,7 +938,10 @@ struct DevTables {
   DevBuf<int> segs;
   DevBuf<ExItem> ex;
   DevBuf<MarchCoef> mrows;
+  DevBuf<FemCoef> frows;
+  DevBuf<FemSeg> fsegs;
   DevBuf<double> rinv;
+  bool fem = false;
   StepTables view() const {
     StepTables t;
     t.inst = inst.p;
@@ -816,10 +952,13 @@ struct DevTables {
     t.segs = segs.p;
     t.ex = ex.p;
     t.mrows = mrows.p;
+    t.frows = frows.p;
+    t.fsegs = fsegs.p;
     t.rinv = rinv.p;
     t.blk = nullptr;
     t.n_items = (int)items.n;
     t.n_ex = (int)ex.n;
+    t.fem = fem ? 1 : 0;
     return t;
   }
   hipError_t upload(const HostTables &h, const std::vector<InstDev> &in, hipStream_t s) {
@@ -832,6 +971,9 @@ struct DevTables {
     if ((e = segs.alloc(h.segs.size())) != hipSuccess) return e;
     if ((e = ex.alloc(std::max<size_t>(h.ex.size(), 1))) != hipSuccess) return e;
     if ((e = mrows.alloc(std::max<size_t>(h.mrows.size(), 1))) != hipSuccess) return e;
+    if ((e = frows.alloc(std::max<size_t>(h.frows.size(), 1))) != hipSuccess) return e;
+    if ((e = fsegs.alloc(std::max<size_t>(h.fsegs.size(), 1))) != hipSuccess) return e;
+    fem = h.fem;
     if ((e = rinv.alloc(std::max<size_t>(h.rinv.size(), 1))) != hipSuccess) return e;
     items.n = h.items.size();
     ex.n = h.ex.size();
@@ -847,6 +989,10 @@ struct DevTables {
     if ((e = cp(ex.p, h.ex.data(), h.ex.size() * sizeof(ExItem))) != hipSuccess) return e;
     if ((e = cp(mrows.p, h.mrows.data(), h.mrows.size() * sizeof(MarchCoef))) != hipSuccess)
       return e;
+    if ((e = cp(frows.p, h.frows.data(), h.frows.size() * sizeof(FemCoef))) != hipSuccess)
+      return e;
+    if ((e = cp(fsegs.p, h.fsegs.data(), h.fsegs.size() * sizeof(FemSeg))) != hipSuccess)
+      return e;
     if ((e = cp(rinv.p, h.rinv.data(), h.rinv.size() * sizeof(double))) != hipSuccess) return e;
     return hipStreamSynchronize(s);  // host vectors may go out of scope
   }
@@ -860,6 +1006,8 @@ struct DevTables {
     ex.release();
     rinv.release();
     mrows.release();
+    frows.release();
+    fsegs.release();
   }
 };
 
@@ -976,7 +1124,11 @@ static PipeParams pipe_params(const Geo &g, const Config &c, int order = 0) {
   F = std::min<long>(F, L);
   if (F < 2) return pp;
   int d = std::max(1, (int)(L / F));
-  const double per_slot = 8.0 * ((double)2 * (g.J - 1) * g.nt * g.nx + 2.0 * g.rows * g.nx);
+  // trace window and state per slot (and, finite elements in the parallel
+  // order, the interface-node value planes: see get_plan)
+  const double v_planes = order == 0 && g.scheme == SCHEME_FEM ? 6.0 * (g.J - 1) * g.nt * g.nx : 0.0;
+  const double per_slot =
+      8.0 * ((double)2 * (g.J - 1) * g.nt * g.nx + 2.0 * g.rows * g.nx + v_planes);
   const double budget = 24e9;
   for (;;) {
     int M = (L + d - 1) / d + 1;
@@ -994,8 +1146,8 @@ static PipeParams pipe_params(const Geo &g, const Config &c, int order = 0) {
 
 static std::string plan_key(const Geo &g, const Config &c, int M, int order) {
   char buf[200];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/g%d/s%d/k%d/M%d/o%d", g.nx, g.nv, g.nt, g.J,
-           g.o, g.tr, c.waves, c.groups, c.seg, c.steps, M, order);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/w%d/g%d/s%d/k%d/M%d/o%d/e%d", g.nx, g.nv, g.nt,
+           g.J, g.o, g.tr, c.waves, c.groups, c.seg, c.steps, M, order, g.scheme);
   return buf;
 }
 
@@ -1052,7 +1204,15 @@ static kfp_status get_plan(const Geo &geo, const Config &cfg, Plan **out,
   HIP_TRY(pl->lam0.alloc(std::max<size_t>(win, 1)));
   HIP_TRY(pl->lam1.alloc(std::max<size_t>(win, 1)));
   HIP_TRY(pl->g.alloc(geo.nt));
-  if (cfg.steps >= 1 && geo.J > 1) HIP_TRY(pl->V.alloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx));
+  // interface-node value planes.  Overlapped iterations in the parallel
+  // order with finite elements keep one set per slot: the exchange of a block
+  // reads the level before it, which the next iteration, one launch behind,
+  // rewrites in the same launch.  (Red-black half-sweeps share one set: the
+  // two colours write different entries, the closing residual reads both,
+  // and a colour's next half-sweep runs two units behind.)
+  const bool v_per_slot = pp.M > 0 && order == 0 && geo.scheme == SCHEME_FEM;
+  if (cfg.steps >= 1 && geo.J > 1)
+    HIP_TRY(pl->V.alloc((size_t)6 * (geo.J - 1) * geo.nt * geo.nx * (v_per_slot ? pp.M : 1)));
   HIP_TRY(pl->rowmap.alloc(geo.nv + 1));
   HIP_TRY(pl->ab.alloc(std::max(2 * (geo.J - 1), 1)));
   HIP_TRY(pl->res.alloc(1));
@@ -1142,6 +1302,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   in.nt = geo.nt;
   in.tr = geo.tr;
   in.nonovl = geo.J > 1 && geo.o == 0 && geo.tr == KFP_ROBIN;
+  in.scheme = geo.scheme;
   in.active = 1;
   std::vector<double> gv(geo.nt);
   for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
@@ -1156,6 +1317,8 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
       ins[i].lam[0] = pl.W.p + (size_t)((i + pl.M - 1) % pl.M) * win;  // read: iteration k-1
       ins[i].lam[1] = pl.W.p + (size_t)i * win;                        // written: iteration k
       ins[i].res = pl.pres.p + i;
+      if (geo.scheme == SCHEME_FEM && pl.order == 0 && pl.V.p)
+        ins[i].V = pl.V.p + (size_t)i * 6 * (geo.J - 1) * geo.nt * geo.nx;
       if (pl.order == 1) ins[i].xmode = (i & 1) ? 1 : 2;  // the traces its colour sends
     }
   }
@@ -1426,9 +1589,10 @@ static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double
     // half-sweep 2k-1, the odd ones' from the slot of half-sweep 2k
     const int sr = (2 * k - 1) % pl.M, sb = (2 * k) % pl.M;
     HIP_TRY(launch_assemble(pl.slotU.p + (size_t)sr * 2 * state + fin, pl.rowmap_rb.p, uT,
-                            geo.nv, geo.nx, pl.cs));
+                            geo.nv, geo.nx, pl.cs, out_nudt(geo), 2.0 / geo.nv));
     HIP_TRY(launch_assemble(pl.slotU.p + (size_t)sb * 2 * state + fin,
-                            pl.rowmap_rb.p + (geo.nv + 1), uT, geo.nv, geo.nx, pl.cs));
+                            pl.rowmap_rb.p + (geo.nv + 1), uT, geo.nv, geo.nx, pl.cs,
+                            out_nudt(geo), 2.0 / geo.nv));
     if (lambda_out && win) {
       const size_t plane = (size_t)geo.nt * geo.nx;
       for (int pidx = 0; pidx < 2 * (geo.J - 1); ++pidx) {
@@ -1441,7 +1605,7 @@ static kfp_status pipe_solve(Plan &pl, const Geo &geo, const Config &cfg, double
   } else {
     const int slot = k % pl.M;
     HIP_TRY(launch_assemble(pl.slotU.p + (size_t)slot * 2 * state + fin, pl.rowmap.p, uT,
-                            geo.nv, geo.nx, pl.cs));
+                            geo.nv, geo.nx, pl.cs, out_nudt(geo), 2.0 / geo.nv));
     if (lambda_out && win)
       HIP_TRY(launch_copy(pl.W.p + (size_t)slot * win, lambda_out, win, pl.cs));
   }
@@ -1475,7 +1639,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
                                  double *lambda_out, kfp_swr_stats *stats, hipStream_t user) {
   const double t_start = now_s();
   Geo geo;
-  kfp_status st = make_geo(g, J, o, tr, p, geo);
+  kfp_status st = make_geo(g, J, o, tr, p, geo, g_scheme);
   if (st) return st;
   if (!u0 || !f || !uT) return fail(KFP_EINVAL, "u0, f and uT must be non-NULL");
   if (!(tol > 0.0)) return fail(KFP_EINVAL, "tol must be > 0");
@@ -1484,6 +1648,7 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
     for (int n = 0; n <= g->nt; ++n)
       if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
   const Config cfg = choose_config(geo);
+  if ((st = fem_needs_march(geo, cfg))) return st;
   const int order = J > 1 ? g_order : 0;
   if (order == 1 && cfg.steps == 0)
     return fail(KFP_EINVAL,
@@ -1568,7 +1733,8 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   const bool converged = k <= max_iter;
   if (!converged) k = max_iter;
   double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
-  HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
+  HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs, out_nudt(geo),
+                          2.0 / geo.nv));
   if (lambda_out && win)
     HIP_TRY(launch_copy((order == 0 && (k & 1)) ? pl->lam1.p : pl->lam0.p, lambda_out, win,
                         pl->cs));
@@ -1592,13 +1758,14 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
 static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const double *f,
                                   const double *s, double *uT, hipStream_t user) {
   Geo geo;
-  kfp_status st = make_geo(g, 1, 0, KFP_DIRICHLET, 0.0, geo);
+  kfp_status st = make_geo(g, 1, 0, KFP_DIRICHLET, 0.0, geo, g_scheme);
   if (st) return st;
   if (!u0 || !f || !uT) return fail(KFP_EINVAL, "u0, f and uT must be non-NULL");
   if (s)
     for (int n = 0; n <= g->nt; ++n)
       if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
   const Config cfg = choose_config(geo);
+  if ((st = fem_needs_march(geo, cfg))) return st;
   Plan *pl = nullptr;
   if ((st = get_plan(geo, cfg, &pl))) return st;
   if ((st = sync_in(user, *pl))) return st;
@@ -1614,7 +1781,8 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
                            0, t.n_items, pl->cs));
   }
   double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
-  HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs));
+  HIP_TRY(launch_assemble(Ufin, pl->rowmap.p, uT, geo.nv, geo.nx, pl->cs, out_nudt(geo),
+                          2.0 / geo.nv));
   return sync_out(user, *pl);
 }
 
@@ -1669,7 +1837,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
   if (max_iter < 1) return fail(KFP_EINVAL, "max_iter must be >= 1");
   std::vector<BatchInst> bi(n_inst);
   for (int i = 0; i < n_inst; ++i) {
-    kfp_status st = make_geo(&in[i].g, in[i].J, in[i].overlap, in[i].tr, in[i].p, bi[i].geo);
+    kfp_status st = make_geo(&in[i].g, in[i].J, in[i].overlap, in[i].tr, in[i].p, bi[i].geo, g_scheme);
     if (st) return fail(st, "instance %d: %s", i, g_err.c_str());
     if (!in[i].u0 || !in[i].f || !in[i].uT)
       return fail(KFP_EINVAL, "instance %d: u0, f and uT must be non-NULL", i);
@@ -1695,6 +1863,10 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     cls[k].members.push_back(i);
     cls[k].nt_max = std::max(cls[k].nt_max, bi[i].geo.nt);
     bi[i].cls = k;
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    kfp_status st = fem_needs_march(bi[i].geo, cls[bi[i].cls].cfg);
+    if (st) return fail(st, "instance %d: %s", i, g_err.c_str());
   }
   if (order == 1)
     for (const auto &c : cls)
@@ -1773,6 +1945,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     d.nt = geo.nt;
     d.tr = geo.tr;
     d.nonovl = geo.J > 1 && geo.o == 0 && geo.tr == KFP_ROBIN;
+    d.scheme = geo.scheme;
     d.active = 1;
     if (b.win) {
       if (in[i].lambda_init) {
@@ -1973,7 +2146,8 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     const BatchInst &b = bi[i];
     const Geo &geo = b.geo;
     double *Ufin = (march_launches(geo.nt, cls[b.cls].cfg) & 1) ? b.U1 : b.U0;
-    HIP_TRY(launch_assemble(Ufin, b.rowmap, in[i].uT, geo.nv, geo.nx, cs));
+    HIP_TRY(launch_assemble(Ufin, b.rowmap, in[i].uT, geo.nv, geo.nx, cs, out_nudt(geo),
+                            2.0 / geo.nv));
     if (in[i].lambda_out && b.win)
       HIP_TRY(launch_copy((order == 0 && (iters[i] & 1)) ? b.lam1 : b.lam0, in[i].lambda_out,
                           b.win, cs));
@@ -2006,7 +2180,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
 static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, int *w_out,
                             int *s_out, int *k_out, hipStream_t user) {
   Geo geo;
-  kfp_status st = make_geo(g, J, o, tr, p, geo);
+  kfp_status st = make_geo(g, J, o, tr, p, geo, g_scheme);
   if (st) return st;
   const size_t nfield = (size_t)(g->nv + 1) * g->nx;
   double *u0 = nullptr, *f = nullptr;
@@ -2044,6 +2218,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
     for (const Config &c : cands) {
       const int w = c.waves, sm = c.seg;
       if (!config_supported(c)) continue;
+      if (geo.scheme == SCHEME_FEM && c.steps == 0) continue;  // march kernel only
       Plan *pl = nullptr;
       if ((st = get_plan(geo, c, &pl))) return st;
       if ((st = load_instance(*pl, u0, f, nullptr, tr == KFP_ROBIN ? p : 1.0,
@@ -2085,6 +2260,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
     }
   }
   g_forced = saved;
+  if (best.waves == 0) return fem_needs_march(geo, Config{});
   if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
   (*g_tune)[tune_key(geo)] = best;
   save_tune(*g_tune);
@@ -2148,7 +2324,7 @@ static kfp_status swr_windows_impl(const kfp_grid *g, const double *u0, const do
                                    hipStream_t user) {
   const double t_start = now_s();
   Geo geo;
-  kfp_status st = make_geo(g, J, o, tr, p, geo);
+  kfp_status st = make_geo(g, J, o, tr, p, geo, g_scheme);
   if (st) return st;
   if (W < 1 || W > g->nt) return fail(KFP_EINVAL, "n_windows must be in 1..nt (got %d)", W);
   if (guess != 0 && guess != 1) return fail(KFP_EINVAL, "guess must be 0 or 1");
@@ -2254,7 +2430,7 @@ static kfp_status u0_guess_impl(const kfp_grid *g, const double *u0, int32_t J, 
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
-  kfp_status st = make_geo(g, J, overlap, tr, p, geo);
+  kfp_status st = make_geo(g, J, overlap, tr, p, geo, g_scheme);
   if (st) return st;
   if (!u0 || (!lambda && J > 1)) return fail(KFP_EINVAL, "u0 and lambda must be non-NULL");
   if (J == 1) return KFP_OK;
@@ -2295,6 +2471,15 @@ kfp_status kfp_set_ordering(int32_t order) {
   return KFP_OK;
 }
 
+kfp_status kfp_set_scheme(int32_t scheme) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (scheme != KFP_SCHEME_FD && scheme != KFP_SCHEME_FEM)
+    return fail(KFP_EINVAL, "scheme must be 0 (finite differences) or 1 (finite elements)");
+  g_scheme = scheme;
+  return KFP_OK;
+}
+
 kfp_status kfp_set_pipeline(int32_t inflight) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
@@ -2329,7 +2514,7 @@ kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
-  kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo);
+  kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo, g_scheme);
   if (st) return st;
   const Config c = choose_config(geo);
   if (waves_out) *waves_out = c.waves;
@@ -2349,7 +2534,7 @@ kfp_status kfp_subdomain_rows(const kfp_grid *g, int32_t J, int32_t overlap, int
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
-  kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo);
+  kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo, g_scheme);
   if (st) return st;
   if (!rows_out) return fail(KFP_EINVAL, "rows_out is NULL");
   *rows_out = geo.rows;
@@ -2377,7 +2562,7 @@ kfp_status kfp_debug_tables(const kfp_grid *g, int32_t J, int32_t overlap, int32
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
-  kfp_status st = make_geo(g, J, overlap, tr, p, geo);
+  kfp_status st = make_geo(g, J, overlap, tr, p, geo, g_scheme);
   if (st) return st;
   if (waves < 1 || waves > 16) return fail(KFP_EINVAL, "waves must be in 1..16");
   if (!sub_info || !rows || !segs || !reds || !mat) return fail(KFP_EINVAL, "NULL output");
@@ -2396,7 +2581,7 @@ kfp_status kfp_debug_tables(const kfp_grid *g, int32_t J, int32_t overlap, int32
     o[6] = d.tab;
     o[7] = d.seg;
     std::vector<double> lo, di, up;
-    row_matrix(geo.sub[j], r, p, p, hv, lo, di, up);
+    any_row_matrix(geo.sub[j], geo.scheme, r, p, p, hv, lo, di, up);
     for (int k = 0; k < d.n; ++k) {
       mat[3 * (d.tab + k) + 0] = lo[k];
       mat[3 * (d.tab + k) + 1] = di[k];

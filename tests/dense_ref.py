@@ -166,14 +166,16 @@ def hat_slope(i, v, nv):
     return 1.0 / h if v < vi else -1.0 / h
 
 
-def fem_matrices(nv):
+def fem_matrices(nv, lo=0, hi=None):
     """Mass and stiffness matrices (6.3) on nodes 0..nv, each entry summed
     element by element with Simpson's rule (exact for these integrands, the
-    Remark after (6.5)).  The slope is evaluated at interior points only."""
+    Remark after (6.5)).  The slope is evaluated at interior points only.
+    lo, hi: only the elements inside [v_lo, v_hi] (a subdomain's own)."""
     h = 2.0 / nv
+    hi = nv if hi is None else hi
     M = np.zeros((nv + 1, nv + 1))
     S = np.zeros((nv + 1, nv + 1))
-    for e in range(nv):
+    for e in range(lo, hi):
         v0, v1 = -1.0 + e * h, -1.0 + (e + 1) * h
         vm = 0.5 * (v0 + v1)
         for i in (e, e + 1):

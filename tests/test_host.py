@@ -273,3 +273,57 @@ def test_ordering_launch_and_window_arguments(lib):
     assert win(2, u0=None) == binding.KFP_EINVAL
     assert win(2, J=3) == binding.KFP_EINVAL and "nv % J" in lib.kfp_last_error().decode()
     assert win(2, tr=0, o=0) == binding.KFP_EINVAL
+
+
+@pytest.mark.parametrize("J,o,tr,p", [(1, 0, 0, 0.0), (2, 2, 1, 4.0), (3, 0, 1, 3.0),
+                                      (3, 3, 0, 0.0), (4, 1, 1, 2.5)])
+def test_fem_rows_are_the_element_matrices(lib, J, o, tr, p):
+    """With the finite-element scheme each subdomain's matrix is dt/h_v times
+    (M/dt + S) of its own elements (Simpson-integrated basis functions), with
+    dt/h_v p (q) on a Robin end row and the fixed nodes of a classical
+    interface removed; v = -1 and v = +1 are unknown rows (Neumann)."""
+    nx, nv, nt, T = 32, 48, 40, 0.5
+    assert lib.kfp_set_scheme(1) == 0
+    try:
+        info, rows, segs, reds, mat = get_tables(lib, nx, nv, nt, T, J, o, tr, p, 4)
+        r = ctypes.c_int64()
+        g = G(nx, nv, nt, T)
+        assert lib.kfp_subdomain_rows(ctypes.byref(g), J, o, tr, ctypes.byref(r)) == 0
+    finally:
+        assert lib.kfp_set_scheme(0) == 0
+    assert r.value == nv + 1 + (J - 1) * (o + 1 if tr == 1 else o - 1)
+    import oracle
+    from tests import dense_ref
+    a, b = oracle.partition(nv, J, o)
+    hv, dt = 2.0 / nv, T / nt
+    for j in range(J):
+        n, row_off, g_lo, P, lo_kind, hi_kind, tab, seg = info[j]
+        M, S = dense_ref.fem_matrices(nv, a[j], b[j])
+        A = (M / dt + S) * (dt / hv)
+        lo = a[j] if (j == 0 or tr == 1) else a[j] + 1
+        hi = b[j] if (j == J - 1 or tr == 1) else b[j] - 1
+        assert (g_lo, n) == (lo, hi - lo + 1)
+        if tr == 1 and j > 0:
+            A[a[j], a[j]] += dt / hv * p
+        if tr == 1 and j < J - 1:
+            A[b[j], b[j]] += dt / hv * p
+        A = A[lo:hi + 1, lo:hi + 1]
+        sub = mat[tab:tab + n]
+        assert np.allclose(sub[:, 1], np.diag(A), rtol=1e-13, atol=0)
+        assert np.allclose(sub[1:, 0], np.diag(A, -1), rtol=1e-13, atol=0)
+        assert np.allclose(sub[:-1, 2], np.diag(A, 1), rtol=1e-13, atol=0)
+
+
+def test_fem_scheme_arguments(lib):
+    assert lib.kfp_set_scheme(2) == binding.KFP_EINVAL
+    assert lib.kfp_set_scheme(-1) == binding.KFP_EINVAL
+    assert lib.kfp_set_scheme(1) == 0
+    try:
+        # one subdomain of 4097 rows: no march configuration holds it
+        g = G(64, 4096, 64, 0.5)
+        st = lib.kfp_swr_solve(ctypes.byref(g), FAKE, FAKE, None, 1, 0, 0, 0.0, 1e-10, 5, None,
+                               FAKE, None, None, None)
+        assert st == binding.KFP_EINVAL
+        assert "finite-element scheme" in lib.kfp_last_error().decode()
+    finally:
+        assert lib.kfp_set_scheme(0) == 0
