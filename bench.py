@@ -18,7 +18,10 @@ moves fewer bytes than that (it keeps U in registers across the steps of a
 launch); `traffic` is the HBM rate its counters saw (bytes per launch from
 rocprofv3 FETCH_SIZE and WRITE_SIZE at the live launch duration), or null
 when the kernel sources differ from the ones those counters were taken on.
-The same solve in red-black order and on 4 time windows is reported beside it.
+The same solve in red-black order, on 4 time windows, and with the paper's
+own discretisation (linear finite elements, `finite_elements`) is reported
+beside it.  `--scheme fem` times the finite-element solve instead (for its
+kernel profile; the default line is the finite-difference one).
 """
 from __future__ import annotations
 
@@ -51,19 +54,19 @@ FLOPS_PER_CELL_STEP = 13.0
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (separate runs, mean over
 # the 8125 dispatches of one solve), each scaled by what the counter reads
 # for the library's copy kernel of 1 GiB in the same process (FETCH_SIZE
-# 524312.44 KiB and WRITE_SIZE 1048576.12 KiB for 1 GiB read and written).
+# 524312.25 KiB and WRITE_SIZE 1048576.0 KiB for 1 GiB read and written).
 # Valid only for the kernel sources they were measured on: any change to
 # them and `traffic` is reported as null.
 TRAFFIC = {
     "config": (8, 17, 16),
     "sha256": {
         "paper_1306_4596_amd/csrc/swr_kernels.hip":
-            "f87a075e930b4de6e16ded8de2a8f3a041397f7793b718ca229dd21b62eff62e",
+            "34cbdfdc6c6fee8e34953f3fdeecc3153a28132352831c873bf56cf94eb09988",
         "paper_1306_4596_amd/csrc/kfp_internal.h":
-            "80c7c52abcafdb68686a45052d0aef990023af4ee99d2be214d6b1d72ff1f411",
+            "4547e821e4bad0e7b39c70b30b3b51ce2bd240e391ae82d66f9c40ae8af00f28",
     },
-    "read_bytes": 9394.94 * 1024 * (1048576.0 / 524312.44),
-    "write_bytes": 13728.0 * 1024 * (1048576.0 / 1048576.12),
+    "read_bytes": 9403.13 * 1024 * (1048576.0 / 524312.25),
+    "write_bytes": 13728.0 * 1024 * (1048576.0 / 1048576.0),
 }
 
 
@@ -88,6 +91,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scheme", choices=["fd", "fem"], default="fd",
+                    help="discretisation of the timed solves (default fd)")
     ap.add_argument("--traffic-gb", type=float, default=None,  # overrides the measured bytes
                     help="HBM bytes per step-kernel launch measured by counters (GB)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -134,6 +139,7 @@ def main():
     u0, f = inputs.random_fields(0, NX, NV)
     U0 = torch.from_numpy(u0).to(dev)
     F = torch.from_numpy(f).to(dev)
+    kfp.set_scheme(kfp.FEM if args.scheme == "fem" else kfp.FD)
     rows = kfp.subdomain_rows(NX, NV, NT, T, J, OVERLAP, TR)
     waves, seg, kper = kfp.get_config(NX, NV, NT, T, J, OVERLAP, TR)
 
@@ -184,7 +190,8 @@ def main():
     alu = FLOPS_PER_CELL_STEP * cells_launch / avg_launch_s / 1e12
     # traffic: the counters' HBM bytes per launch as a rate at the live
     # launch duration (the unit of `achieved`)
-    tbytes = args.traffic_gb * 1e9 if args.traffic_gb else measured_traffic((waves, seg, kper))
+    tbytes = args.traffic_gb * 1e9 if args.traffic_gb else (
+        measured_traffic((waves, seg, kper)) if args.scheme == "fd" else None)
     traffic = round(tbytes / avg_launch_s / 1e9, 1) if tbytes else None
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -211,7 +218,9 @@ def main():
         "config": {"workload": "SWR Kolmogorov 1024x1024 Nt=2000 T=0.5 J=8 overlap=2 Robin p=8 "
                                "tol=1e-10, random Fourier-Legendre f,u0 seed 0",
                    "nx": NX, "nv": NV, "nt": NT, "J": J, "overlap": OVERLAP, "p": P_MAIN,
-                   "tol": TOL, "waves": waves, "seg_max": seg, "steps_per_launch": kper},
+                   "tol": TOL, "waves": waves, "seg_max": seg, "steps_per_launch": kper,
+                   "scheme": "finite differences" if args.scheme == "fd" else
+                             "finite elements"},
         "iters": iters,
         "time_to_tol_s": wall / args.steps,
         "effective_GBps": value * BYTES_PER_CELL_STEP / 1e9,
@@ -252,6 +261,29 @@ def main():
                                "time_to_tol_s": round(time.perf_counter() - t1, 4),
                                "residual": st.residual,
                                "cell_steps_per_s": st.cell_steps / st.device_seconds}
+        # the paper's own discretisation (Section 6.2: linear finite elements
+        # with the consistent mass matrix, Neumann ends, diffusion then
+        # transport), parallel and red-black order
+        if args.scheme == "fd":
+            kfp.set_scheme(kfp.FEM)
+            fem = {"rows": kfp.subdomain_rows(NX, NV, NT, T, J, OVERLAP, TR),
+                   "config": list(kfp.get_config(NX, NV, NT, T, J, OVERLAP, TR))}
+            for name, order in (("parallel", kfp.PARALLEL), ("red_black", kfp.RED_BLACK)):
+                kfp.set_ordering(order)
+                solve(P_MAIN)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, _, st = solve(P_MAIN)
+                torch.cuda.synchronize()
+                wall1 = time.perf_counter() - t1
+                kl = st.iters * (-(-NT // fem["config"][2]))
+                fem[name] = {"iters": st.iters, "time_to_tol_s": round(wall1, 4),
+                             "residual": st.residual, "cell_steps_per_s": st.cell_steps / wall1,
+                             "march_launch_us": round(st.step_seconds / kl * 1e6, 3)
+                             if order == kfp.PARALLEL else None}
+            kfp.set_ordering(kfp.PARALLEL)
+            kfp.set_scheme(kfp.FD)
+            out["finite_elements"] = fem
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
