@@ -103,14 +103,14 @@ struct MarchCoef {
 
 // The finite-element layout of the same rows (rows scaled by dt/h_v: an
 // element adds (1/6)[[2,1],[1,2]] + r[[1,-1],[-1,1]]).  A step first forms G
-// in every register (transport with the unscaled weights a, b), then
-// eliminates with right-hand sides wl G_{k-1} + wm G_k + wu G_{k+1}: the
-// mass weights times 1 / pivot (unscaled on separator rows).  Rows whose
-// neighbour in G lies outside the segment (the first real row below, a
-// separator or the subdomain's last row above) have that weight zero here:
-// it is applied from FemSeg or, for a separator, in the reduced system.
+// in every register (the transport weight |nu| of a row is affine in its
+// index and computed in registers), then eliminates with right-hand sides
+// wl G_{k-1} + wm G_k + wu G_{k+1}: the mass weights times 1 / pivot
+// (unscaled on separator rows).  Rows whose neighbour in G lies outside the
+// segment (the first real row below, a separator or the subdomain's last
+// row above) have that weight zero here: it is applied from FemSeg or, for a
+// separator, in the reduced system.
 struct FemCoef {
-  double a, b;        // transport: 1 - |nu|, |nu|
   double wl, wm, wu;  // mass weights of G_{k-1}, G_k, G_{k+1}, times 1 / pivot
   double fb, bc, sl, sr;  // as in MarchCoef
   double fab;         // 1 / pivot of an end row that takes boundary data, else 0

@@ -502,10 +502,12 @@ __device__ __forceinline__ void march_forward(SegRegs<SEG> &d, const SegRegs<SEG
 
 // Finite elements, first half of a step: G_k = T W^n + dt s f in every
 // register (DIR_NONE at the first step of a solve: nothing transported yet).
+// The Courant number of register k is nu0 + k dnu (no table read: the pass
+// issues no LDS loads and waits on none).
 constexpr int DIR_NONE = 3;
 template <int SEG, int DIR>
-__device__ __forceinline__ void fem_stage(SegRegs<SEG> &d, const SegRegs<SEG> &fs,
-                                          const FemCoef *mc, double gn, int vsplit,
+__device__ __forceinline__ void fem_stage(SegRegs<SEG> &d, const SegRegs<SEG> &fs, double nu0,
+                                          double dnu, double gn, int vsplit,
                                           KGlob<const double> *fr, int base, int nx, int col) {
   static_for<0, SEG>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -528,7 +530,8 @@ __device__ __forceinline__ void fem_stage(SegRegs<SEG> &d, const SegRegs<SEG> &f
         const double a = from_lower_lane(u), c = from_upper_lane(u);
         nb = (k >= vsplit) ? a : c;
       }
-      g = fma(mc[k].a, u, fma(mc[k].b, nb, gn * fk));
+      const double w = fabs(fma((double)k, dnu, nu0));
+      g = fma(w, nb - u, fma(gn, fk, u));
     }
     d.template st<k>(g);
   });
@@ -548,22 +551,37 @@ __device__ __forceinline__ double fem_edge_g(double u, double nu, double gn, dou
 // Finite elements, second half: forward elimination with the mass-matrix
 // right-hand side.  ylo: the starting value (boundary data and the G of the
 // node below, already weighted); bhi: the same for the last register.
+// The coefficients of row k+2 are loaded before row k is computed (LDS
+// reads return in order, so the wait for a row's coefficients overlaps two
+// rows of arithmetic); the scheduling barrier keeps that order.
+struct FemRow {
+  double wl, wm, wu, fb;
+};
+__device__ __forceinline__ FemRow fem_row(const FemCoef *mc, int k) {
+  return FemRow{mc[k].wl, mc[k].wm, mc[k].wu, mc[k].fb};
+}
 template <int SEG>
 __device__ __forceinline__ void fem_forward(SegRegs<SEG> &d, const FemCoef *mc, double ylo,
                                             double bhi) {
   double y = ylo;
   double gprev = 0.0;
+  FemRow c0 = fem_row(mc, 0);
+  FemRow c1 = fem_row(mc, SEG > 1 ? 1 : 0);
   static_for<0, SEG>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
+    const FemRow c = c0;
+    c0 = c1;
+    if constexpr (k + 2 < SEG) c1 = fem_row(mc, k + 2);
+    __builtin_amdgcn_sched_barrier(0);
     const double gk = d.template ld<k>();
-    double t = mc[k].wm * gk;
-    if constexpr (k > 0) t = fma(mc[k].wl, gprev, t);
+    double t = c.wm * gk;
+    if constexpr (k > 0) t = fma(c.wl, gprev, t);
     if constexpr (k < SEG - 1)
-      t = fma(mc[k].wu, d.template ld<k + 1>(), t);
+      t = fma(c.wu, d.template ld<k + 1>(), t);
     else
       t += bhi;
     gprev = gk;
-    y = fma(mc[k].fb, y, t);
+    y = fma(c.fb, y, t);
     d.template st<k>(y);
   });
 }
@@ -744,6 +762,10 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
     // row; above the subdomain's last row), their source values and states
     double nul = 0.0, wol = 0.0, nua = 0.0, woa = 0.0;
     double fbelow = 0.0, ubelow = 0.0, fabove = 0.0, uabove = 0.0;
+    // Courant number of register k: nu0 + k dnu, v_i = -1 + i h_v, dt/h_x = r h_v^2 nx
+    const double dtx = rr * I->hv * I->hv * nx;
+    const double dnu = I->hv * dtx;
+    const double nu0 = (-1.0 + (g_lo + base) * I->hv) * dtx;
     if constexpr (FEM) {
       if (active) {
         KGlob<const double> *fsg = as_glob((const double *)(t.fsegs + sd->seg + v));
@@ -813,13 +835,13 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
           // G in every register, then the elimination with the mass matrix
           const bool first = n == 0;
           if (first)
-            fem_stage<SEG, DIR_NONE>(d, fs, mc, gn, vs, fr, base, nx, col);
+            fem_stage<SEG, DIR_NONE>(d, fs, nu0, dnu, gn, vs, fr, base, nx, col);
           else if (dir == DIR_LO)
-            fem_stage<SEG, DIR_LO>(d, fs, mc, gn, vs, fr, base, nx, col);
+            fem_stage<SEG, DIR_LO>(d, fs, nu0, dnu, gn, vs, fr, base, nx, col);
           else if (dir == DIR_UP)
-            fem_stage<SEG, DIR_UP>(d, fs, mc, gn, vs, fr, base, nx, col);
+            fem_stage<SEG, DIR_UP>(d, fs, nu0, dnu, gn, vs, fr, base, nx, col);
           else
-            fem_stage<SEG, DIR_MIX>(d, fs, mc, gn, vs, fr, base, nx, col);
+            fem_stage<SEG, DIR_MIX>(d, fs, nu0, dnu, gn, vs, fr, base, nx, col);
           const double gb = fem_edge_g(ubelow, nul, gn, fbelow, first);
           const double ga = fem_edge_g(uabove, nua, gn, fabove, first);
           if (Pq > 1) sh_gf[s & 1][v][tl] = first_value(d);

@@ -794,16 +794,13 @@ static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg
       const int k0 = (w == P - 1) ? pad : 0;
       FemSeg sg{0.0, 0.0, 0.0, 0.0};
       for (int k = 0; k < seg; ++k) {
-        FemCoef c{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        FemCoef c{0, 0, 0, 0, 0, 0, 0, 0};
         if (k < k0) {  // padding: passes the starting value on
           c.fb = 1.0;
           t.frows.push_back(c);
           continue;
         }
         const int i = w * seg + k - k0;
-        const double wgt = std::fabs(nu_of(i));
-        c.a = 1.0 - wgt;
-        c.b = wgt;
         if (w < P - 1 && k == seg - 1) {  // separator: its unscaled right-hand side
           c.wl = ml[i];
           c.wm = mm[i];
