@@ -553,7 +553,9 @@ __device__ __forceinline__ double fem_edge_g(double u, double nu, double gn, dou
 // node below, already weighted); bhi: the same for the last register.
 // The coefficients of row k+2 are loaded before row k is computed (LDS
 // reads return in order, so the wait for a row's coefficients overlaps two
-// rows of arithmetic); the scheduling barrier keeps that order.
+// rows of arithmetic); the scheduling barrier keeps the loads in that
+// order.  (The same in the finite-difference pass made it slower: there the
+// compiler's own placement already hides most of the latency.)
 struct FemRow {
   double wl, wm, wu, fb;
 };
@@ -572,7 +574,7 @@ __device__ __forceinline__ void fem_forward(SegRegs<SEG> &d, const FemCoef *mc, 
     const FemRow c = c0;
     c0 = c1;
     if constexpr (k + 2 < SEG) c1 = fem_row(mc, k + 2);
-    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0x1);  // arithmetic may cross, memory operations not
     const double gk = d.template ld<k>();
     double t = c.wm * gk;
     if constexpr (k > 0) t = fma(c.wl, gprev, t);
