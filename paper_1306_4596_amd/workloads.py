@@ -1,7 +1,7 @@
 """Throughput of the SWR path on the workloads beside the benchmark one.
 
-    python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1]
-    python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8]
+    python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1] [--scheme fd|fem]
+    python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8] [--scheme fd|fem]
     python -m paper_1306_4596_amd.workloads large-solve
 
 `batch`: uneven instances (Nx, Nv from {128, 256, 512, 1024}, J from
@@ -10,8 +10,10 @@ by kfp_swr_batch to 1e-10, in the parallel order or (--order 1) red-black.  `lar
 overlap 2, Robin p = 8, a fixed number of SWR iterations, once per launch
 configuration.  `large-solve`: the same shape solved to 1e-10 from zero
 traces and from the u0 extension, in the parallel and the red-black order,
-and on 4 time windows.  Each prints one JSON line per
-measurement.  Inputs are seeded and synthetic (inputs.py).
+and on 4 time windows.  `--scheme fem` runs `batch` or `large` with the
+paper's finite-element discretisation instead of finite differences.  Each
+prints one JSON line per measurement.  Inputs are seeded and synthetic
+(inputs.py).
 """
 from __future__ import annotations
 
@@ -23,6 +25,13 @@ import numpy as np
 
 from . import binding as kb
 from . import inputs
+
+
+_SCHEME = [0]
+
+
+def _scheme():
+    return _SCHEME[0]
 
 
 def run_batch(n: int, reps: int = 2, order: int = 0):
@@ -45,6 +54,7 @@ def run_batch(n: int, reps: int = 2, order: int = 0):
         cells = sum(r[2].cell_steps for r in res)
         its = [r[2].iters for r in res]
         print(json.dumps({"workload": f"batch of {n} uneven SWR instances", "order": order,
+                          "scheme": "fem" if kb.FEM == _scheme() else "fd",
                           "rep": rep, "status": rc,
                           "wall_s": wall, "device_s": res[0][2].device_seconds,
                           "cell_steps": cells, "cell_steps_per_s": cells / wall,
@@ -71,6 +81,7 @@ def run_large(iters: int, configs):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         print(json.dumps({"workload": "4096x4096 Nt=8192 T=1 J=32 overlap=2 Robin p=8",
+                          "scheme": "fem" if kb.FEM == _scheme() else "fd",
                           "iterations": st.iters, "config": used, "rows": rows,
                           "wall_s_incl_setup": wall, "device_s": st.device_seconds,
                           "step_kernel_s": st.step_seconds,
@@ -122,10 +133,13 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
     ap.add_argument("--configs", nargs="*", default=[],
                     help="launch configurations waves,seg,steps (default: the library's choice)")
     a = ap.parse_args()
     kb.load_library()
+    _SCHEME[0] = kb.FEM if a.scheme == "fem" else kb.FD
+    kb.set_scheme(_SCHEME[0])
     if a.which == "batch":
         run_batch(a.n, order=a.order)
     elif a.which == "large-solve":
