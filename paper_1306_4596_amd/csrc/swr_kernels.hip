@@ -562,7 +562,7 @@ struct FemRow {
 __device__ __forceinline__ FemRow fem_row(const FemCoef *mc, int k) {
   return FemRow{mc[k].wl, mc[k].wm, mc[k].wu, mc[k].fb};
 }
-template <int SEG>
+template <int SEG, bool AHEAD = true>
 __device__ __forceinline__ void fem_forward(SegRegs<SEG> &d, const FemCoef *mc, double ylo,
                                             double bhi) {
   double y = ylo;
@@ -571,10 +571,15 @@ __device__ __forceinline__ void fem_forward(SegRegs<SEG> &d, const FemCoef *mc, 
   FemRow c1 = fem_row(mc, SEG > 1 ? 1 : 0);
   static_for<0, SEG>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    const FemRow c = c0;
-    c0 = c1;
-    if constexpr (k + 2 < SEG) c1 = fem_row(mc, k + 2);
-    __builtin_amdgcn_sched_barrier(0x1);  // arithmetic may cross, memory operations not
+    FemRow c;
+    if constexpr (AHEAD) {
+      c = c0;
+      c0 = c1;
+      if constexpr (k + 2 < SEG) c1 = fem_row(mc, k + 2);
+      __builtin_amdgcn_sched_barrier(0x1);  // arithmetic may cross, memory operations not
+    } else {
+      c = fem_row(mc, k);
+    }
     const double gk = d.template ld<k>();
     double t = c.wm * gk;
     if constexpr (k > 0) t = fma(c.wl, gprev, t);
@@ -613,12 +618,28 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
   using MC = typename std::conditional<FEM, FemCoef, MarchCoef>::type;
   constexpr int NV = NW * G;  // segments per workgroup
   constexpr int TW = 64 / G;  // tile columns
-  // segment end values for the reduced system, double-buffered by step
-  // parity: a step's writes never meet the previous step's reads, so one
-  // barrier per step suffices
-  __shared__ double sh_first[2][NV][TW];
-  __shared__ double sh_last[2][NV][TW];
-  __shared__ double sh_sep[2][NV][TW];
+  // The reduced (separator) system.  Finite elements in workgroups of at
+  // most 8 segments (RR):
+  // each segment forms its own parts of the reduced right-hand sides before
+  // the barrier, E_v = sep_v - ra_v last_v and F_v = -rc_{v-1} first_v (with
+  // finite elements + rg_{v-1} G(first_v)), and each lane keeps the two rows
+  // of the reduced inverse it needs in registers for the whole item, so the
+  // sum after the barrier reads two LDS values per separator and no
+  // coefficient, with no branch (per launch 64.9 -> 51.8 us on 1024 x 1024,
+  // J = 8).  Otherwise the segment end values and the inverse are staged in
+  // LDS: wider workgroups, longer segments and the builds limited in
+  // registers would spill, and the finite-difference kernel measured no
+  // gain (44.8 against 44.2 us).  Either way the values are double-buffered by step parity: a step's
+  // writes never meet the previous step's reads, so one barrier per step
+  // suffices.
+  constexpr bool RR = FEM && NV <= 8 && OCC == 1 && SEG <= 17;
+  constexpr int NB = RR ? 1 : 2, NS = RR ? 1 : NV, NT = RR ? 1 : TW;
+  constexpr int EB = RR ? 2 : 1, ES = RR ? NV : 1, ET = RR ? TW : 1;
+  __shared__ double sh_first[NB][NS][NT];
+  __shared__ double sh_last[NB][NS][NT];
+  __shared__ double sh_sep[NB][NS][NT];
+  __shared__ double sh_E[EB][ES][ET];
+  __shared__ double sh_F[EB][ES][ET];
   // boundary data of the launch's steps (low end, high end), staged once so
   // that the step loop issues no vector loads: its stores then never hold a
   // step up, since nothing in the loop waits on vector memory
@@ -628,11 +649,12 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
   // scalar loads either, and LDS reads (returned in order) can be waited on
   // one by one, so they are issued well ahead of their use
   __shared__ MC sh_mc[NV][SEG];
-  __shared__ RedCoef sh_rc[NV];
-  // finite elements: G of every segment's first real row, for the separator
-  // below it (double-buffered like the reduced system's values)
-  __shared__ double sh_gf[FEM ? 2 : 1][FEM ? NV : 1][FEM ? TW : 1];
-  __shared__ double sh_rinv[(NV - 1) * (NV - 1) + 1];
+  __shared__ RedCoef sh_rc[RR ? 1 : NV];
+  // finite elements, wider workgroups: G of every segment's first real row,
+  // for the separator below it (double-buffered like the values above)
+  constexpr bool GF = FEM && !RR;
+  __shared__ double sh_gf[GF ? 2 : 1][GF ? NV : 1][GF ? TW : 1];
+  __shared__ double sh_rinv[RR ? 1 : (NV - 1) * (NV - 1) + 1];
   __shared__ double sh_g[NW][kMaxStepsPerLaunch];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -720,7 +742,7 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
         if (e0 + lane < ncw) cs[e0 + lane] = ct[e0 + lane];
       KGlob<const double> *gt = as_glob(I->g);
       if (lane < steps) sh_g[w][lane] = gt[n0 + lane];
-      if (w == 0 && P > 1) {
+      if (!RR && w == 0 && P > 1) {
         constexpr int NRW = (int)(sizeof(RedCoef) / sizeof(double));
         KGlob<const double> *rt = as_glob((const double *)(t.reds + sd->red));
         double *rs = reinterpret_cast<double *>(sh_rc);
@@ -733,6 +755,42 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
       if (hi_end)
         for (int s = 0; s < steps; ++s) sh_bd[1][s][tl] = lin_hi[(size_t)(n0 + s) * nx];
     }
+    // RR: rows v-1 and v of the reduced inverse (zero past the subdomain's
+    // separators), this segment's separator coefficient ra_v and the
+    // coefficients rc_{v-1}, rg_{v-1} of the separator below; the slots of
+    // segments the subdomain does not use are zeroed, so the branch-free sum
+    // only adds zeros for them
+    constexpr int NR1 = RR && NV > 1 ? NV - 1 : 1;
+    double RL[NR1], RH[NR1];
+    double ra_s = 0.0, rc_s = 0.0, rg_s = 0.0;
+    if constexpr (RR) {
+#pragma unroll
+      for (int q = 0; q < NR1; ++q) RL[q] = RH[q] = 0.0;
+      if (P > 1) {
+        if (active) {
+          const int m = P - 1;
+          KGlob<const double> *rv = as_glob(t.rinv + sd->rinv);
+#pragma unroll
+          for (int q = 0; q < NV - 1; ++q) {
+            if (q < m) {
+              if (v > 0) RL[q] = rv[(size_t)(v - 1) * m + q];
+              if (v < m) RH[q] = rv[(size_t)v * m + q];
+            }
+          }
+          KGlob<const double> *rt = as_glob((const double *)(t.reds + sd->red));
+          constexpr int NRW = (int)(sizeof(RedCoef) / sizeof(double));
+          if (v < m) ra_s = rt[(size_t)v * NRW + 0];
+          if (v > 0) {
+            rc_s = rt[(size_t)(v - 1) * NRW + 1];
+            rg_s = rt[(size_t)(v - 1) * NRW + 5];
+          }
+        } else if (v < NV) {
+          sh_E[0][v][tl] = sh_E[1][v][tl] = 0.0;
+          sh_F[0][v][tl] = sh_F[1][v][tl] = 0.0;
+        }
+      }
+    }
+    double gf1 = 0.0;  // finite elements, RR: G of the first real row
     SegRegs<SEG> d, fs;
     if (active) {
       static_for<0, SEG>([&](auto kc) {
@@ -767,7 +825,7 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
     // Courant number of register k: nu0 + k dnu, v_i = -1 + i h_v, dt/h_x = r h_v^2 nx
     const double dtx = rr * I->hv * I->hv * nx;
     const double dnu = I->hv * dtx;
-    const double nu0 = (-1.0 + (g_lo + base) * I->hv) * dtx;
+    const double nu0_item = (-1.0 + (g_lo + base) * I->hv) * dtx;
     if constexpr (FEM) {
       if (active) {
         KGlob<const double> *fsg = as_glob((const double *)(t.fsegs + sd->seg + v));
@@ -834,7 +892,13 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
         const double blo = lo_end ? lo_scale * sh_bd[0][s][tl] : 0.0;
         const double bhi = hi_end ? hi_scale * sh_bd[1][s][tl] : 0.0;
         if constexpr (FEM) {
-          // G in every register, then the elimination with the mass matrix
+          // G in every register, then the elimination with the mass matrix.
+          // Builds with longer or more segments recompute the Courant numbers
+          // each step (kept across the loop, one per register, they spill);
+          // 8 wavefronts of at most 17 rows keep them (51.8 against 53.3 us
+          // per launch on 1024 x 1024, J = 8)
+          double nu0 = nu0_item;
+          if constexpr (NW > 8 || SEG > 17) asm volatile("" : "+v"(nu0));
           const bool first = n == 0;
           if (first)
             fem_stage<SEG, DIR_NONE>(d, fs, nu0, dnu, gn, vs, fr, base, nx, col);
@@ -846,8 +910,15 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
             fem_stage<SEG, DIR_MIX>(d, fs, nu0, dnu, gn, vs, fr, base, nx, col);
           const double gb = fem_edge_g(ubelow, nul, gn, fbelow, first);
           const double ga = fem_edge_g(uabove, nua, gn, fabove, first);
-          if (Pq > 1) sh_gf[s & 1][v][tl] = first_value(d);
-          fem_forward<SEG>(d, mc, fma(wol, gb, blo), fma(woa, ga, bhi));
+          if (Pq > 1) {
+            if constexpr (RR)
+              gf1 = first_value(d);
+            else
+              sh_gf[s & 1][v][tl] = first_value(d);
+          }
+          // (no loads ahead in 16-wave builds, 128 registers, or for segments
+          // longer than 20 rows: the extra registers would spill)
+          fem_forward<SEG, (NW <= 8 && SEG <= 20)>(d, mc, fma(wol, gb, blo), fma(woa, ga, bhi));
         } else {
           // transport + source + forward elimination, one pass
           if (dir == DIR_LO)
@@ -865,14 +936,35 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
           d.template st<k>(x);
         });
         if (Pq > 1) {
-          sh_first[s & 1][v][tl] = first_value(d);
-          sh_last[s & 1][v][tl] = d.template ld<SEG - 2>();
-          sh_sep[s & 1][v][tl] = d.template ld<SEG - 1>();
+          if constexpr (RR) {
+            const double Ev =
+                last ? 0.0 : fma(-ra_s, d.template ld<SEG - 2>(), d.template ld<SEG - 1>());
+            double Fv = -rc_s * first_value(d);
+            if constexpr (FEM) Fv = fma(rg_s, gf1, Fv);
+            sh_E[s & 1][v][tl] = Ev;
+            sh_F[s & 1][v][tl] = Fv;
+          } else {
+            sh_first[s & 1][v][tl] = first_value(d);
+            sh_last[s & 1][v][tl] = d.template ld<SEG - 2>();
+            sh_sep[s & 1][v][tl] = d.template ld<SEG - 1>();
+          }
         }
       }
       if (Pq > 1) {
         __syncthreads();
-        if (active) {
+        if constexpr (RR) {
+          if (active) {
+            double xl = 0.0, xh = 0.0;
+#pragma unroll
+            for (int q = 0; q < NV - 1; ++q) {
+              const double D = sh_E[s & 1][q][tl] + sh_F[s & 1][q + 1][tl];
+              xl = fma(RL[q], D, xl);
+              xh = fma(RH[q], D, xh);
+            }
+            xlo = xl;
+            xhi = xh;
+          }
+        } else if (active) {
           // reduced separator system, per column: right-hand sides D_r from
           // LDS, then the two separators this segment borders (r = v-1, v)
           // as dot products with rows of the precomputed inverse
