@@ -118,6 +118,7 @@ CONFIGS = [
     (40, 64, 4, (8, 4, 2)),
     (40, 96, 3, (8, 6, 7)),
     (40, 128, 2, (16, 6, 4)),
+    (40, 64, 2, (4, 8, 3, 2)),
     (50, 256, 2, (8, 17, 4, 2)),
     (40, 768, 3, (8, 24, 6, 2)),
     (40, 1024, 2, (8, 33, 2, 4)),
@@ -128,7 +129,8 @@ CONFIGS = [
 @pytest.mark.parametrize("tr", [D, R])
 def test_fem_launch_configurations(case, tr):
     """Segments of every length and count (a padded last segment, lane
-    groups) against the oracle, three iterations."""
+    groups, fewer segments than the workgroup holds, the reduced system in
+    registers and in LDS) against the oracle, three iterations."""
     nx, nv, J, cfg = case
     nt, T, o = 12, 0.1, 2
     print(f"fem config nx={nx} nv={nv} J={J} cfg={cfg} tr={tr}", flush=True)
