@@ -318,7 +318,7 @@ kfp_status kfp_bw_probe(const void *src, void *dst, int64_t bytes, void *stream)
  * (u0, f) to the converged interface traces of one problem shape
  * (standardised per output).  Its prediction is passed to kfp_swr_solve as
  * lambda_init.  The SWR iteration still runs to the same tolerance, so it is
- * both the fallback and the judge of the network's error.
+ * both the fallback and the measure of the network's error.
  *
  * Network: depth hidden layers Linear(hidden) -> GELU (erf form), then
  * Linear(out).  Weights W[out][in] with FP32 master copies and BF16 copies

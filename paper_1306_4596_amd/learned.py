@@ -5,7 +5,7 @@ converged interface traces of one problem shape.  It is trained on solves the
 SWR path itself generates (kfp_swr_batch), with the library's own forward,
 backward and Adam kernels.  At solve time its prediction is the initial guess
 lambda^0; the SWR iteration still runs to the same tolerance, so it is both
-the fallback and the judge of the network's error.
+the fallback and the measure of the network's error.
 
 The map from coefficients to converged traces is linear (the equation and
 the discretisation are linear, and the fields are linear in the
