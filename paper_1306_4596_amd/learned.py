@@ -21,6 +21,9 @@ BF16 network leaves a much smaller absolute error in lambda^0.  base="zero"
 learns the traces themselves.
 
     python -m paper_1306_4596_amd.learned --train 20000 --eval 2000 --out results.json
+
+`--scheme fem` does the same with the paper's finite-element discretisation
+(training solves, targets and evaluation all in that scheme).
 """
 from __future__ import annotations
 
@@ -345,7 +348,10 @@ def main():
                     help="comma-separated from " + ",".join(VARIANTS))
     ap.add_argument("--orders", default="0",
                     help="evaluation in these solve orders: 0 parallel, 1 red-black")
+    ap.add_argument("--scheme", choices=["fd", "fem"], default="fd",
+                    help="discretisation of every solve (default fd)")
     args = ap.parse_args()
+    kb.set_scheme(kb.FEM if args.scheme == "fem" else kb.FD)
 
     def log(msg):
         print(msg, flush=True)
@@ -384,7 +390,8 @@ def main():
         ev = evaluate(shape, range(20000, 20000 + args.eval), guesses, log=log)
         summaries["parallel" if order == 0 else "red-black"] = summarize(ev)
     kb.set_ordering(0)
-    res = {"shape": asdict(shape), "base": args.base, "train_seeds": args.train,
+    res = {"shape": asdict(shape), "scheme": args.scheme, "base": args.base,
+           "train_seeds": args.train,
            "eval_seeds": args.eval, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
            "generate_seconds": t_gen, "train_iters_mean": float(iters.mean()),
            "train": train, "summary": summaries.get("parallel") or next(iter(summaries.values())),
