@@ -232,3 +232,22 @@ def test_fem_table1_serial_order_at_coarsest_level():
             got[(key, o)] = r.iters
     for key, it in got.items():
         assert abs(it - rows[key][0]) <= 2, (key, it, rows[key][0], got)
+
+
+def test_fem_dirichlet_error_equation_monotone():
+    """Error equation (f = 0, u0 = 0, random lambda^0) with classical
+    transmission: for r = dt/h^2 >= 1/6 the element rows are M-matrix rows
+    whose right-hand sides are convex combinations, the transport is convex,
+    so the discrete maximum principle of Section 4 holds and max|lambda^k|
+    strictly decreases with overlap (Theorem 4.1)."""
+    nx, nv, nt, T, J, o = 16, 32, 20, 0.5, 2, 3
+    assert (T / nt) / (2.0 / nv) ** 2 >= 1 / 6
+    z = np.zeros((nv + 1, nx))
+    lam = inputs.random_traces(4, J, nt, nx)
+    prev = np.abs(lam).max()
+    for k in range(12):
+        r = oracle.swr_solve(z, z, T, nt, J, o, D, tol=0.0, max_iter=1, lambda_init=lam,
+                             scheme=FEM)
+        cur = np.abs(r.lam).max()
+        assert cur < prev
+        prev, lam = cur, r.lam
