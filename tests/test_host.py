@@ -327,3 +327,22 @@ def test_fem_scheme_arguments(lib):
         assert "finite-element scheme" in lib.kfp_last_error().decode()
     finally:
         assert lib.kfp_set_scheme(0) == 0
+
+
+def test_fem_batch_rejects_tall_instances(lib):
+    """A batch instance whose subdomains no march configuration holds is
+    rejected under the finite-element scheme, before any device call."""
+    inst = (binding.Instance * 2)()
+    inst[0].g = G(64, 64, 10, 0.1)
+    inst[0].J, inst[0].overlap, inst[0].tr, inst[0].p = 2, 2, 1, 4.0
+    inst[1].g = G(64, 4096, 10, 0.1)
+    inst[1].J, inst[1].overlap, inst[1].tr, inst[1].p = 1, 0, 0, 0.0
+    for i in range(2):
+        inst[i].u0 = inst[i].f = inst[i].uT = FAKE
+    assert lib.kfp_set_scheme(1) == 0
+    try:
+        assert lib.kfp_swr_batch(2, inst, 1e-10, 10, None, None) == binding.KFP_EINVAL
+        msg = lib.kfp_last_error().decode()
+        assert "instance 1" in msg and "finite-element" in msg
+    finally:
+        assert lib.kfp_set_scheme(0) == 0
