@@ -2,8 +2,8 @@
 library on the GPU.
 
     python -m paper_1306_4596_amd.experiments table1 [--levels 0 1 2 3 4] [--order 0|1] [--scheme fd|fem]
-    python -m paper_1306_4596_amd.experiments sweep-p [--level 0] [--order 0|1] [--fine]
-    python -m paper_1306_4596_amd.experiments sweep-pq [--level 0] [--order 0|1]
+    python -m paper_1306_4596_amd.experiments sweep-p [--level 0] [--order 0|1] [--fine] [--scheme fd|fem]
+    python -m paper_1306_4596_amd.experiments sweep-pq [--level 0] [--order 0|1] [--scheme fd|fem]
     python -m paper_1306_4596_amd.experiments history [--level 2]
 
 Set-up (Section 6.4): two subdomains of [0,1) x [-1,1], T = 2, the error
@@ -12,7 +12,7 @@ variable, so that every frequency is present), uniform grids with
 dt = h_x = h_v = 2^-j * 0.01 at refinement level j, an overlap of three cells
 (L = 3 h_v) or none (L = 0), and the stopping test (6.12) below 1e-6.  The
 discretisation is this library's default (finite differences, zero
-Dirichlet ends, an IMEX step) or, `--scheme fem` (table1), the paper's own
+Dirichlet ends, an IMEX step) or, `--scheme fem`, the paper's own
 (linear finite elements with the consistent mass matrix, Neumann ends,
 diffusion then transport); the iteration counts are compared by trend only.
 Each command prints one JSON line per result.
@@ -109,6 +109,9 @@ def table1(levels, order=0, scheme="fd"):
     kb.set_scheme(kb.FD)
 
 
+_scheme = [0]
+
+
 def _sweep(level: int, pairs, overlap: int, tag: str, order: int = 0):
     """One batch: instance i solves OSWR(p_i, q_i) from the same random trace;
     the iteration count to 1e-6 and the residual after 15 iterations."""
@@ -120,7 +123,8 @@ def _sweep(level: int, pairs, overlap: int, tag: str, order: int = 0):
     kb.set_ordering(0)
     for (p, q), (_, _, st) in zip(pairs, out):
         h = st.res_history
-        print(json.dumps({"experiment": tag, "order": order, "level": level,
+        print(json.dumps({"experiment": tag, "order": order,
+                          "scheme": "fem" if kb.FEM == _scheme[0] else "fd", "level": level,
                           "overlap_cells": overlap, "p": p,
                           "q": q, "iters": st.iters if st.residual < TOL else None,
                           "residual_after_15": float(h[14]) if len(h) >= 15 else None}),
@@ -165,6 +169,8 @@ def main():
     ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
     a = ap.parse_args()
     kb.load_library()
+    _scheme[0] = kb.FEM if a.scheme == "fem" else kb.FD
+    kb.set_scheme(_scheme[0])
     if a.which == "table1":
         table1(a.levels, a.order, a.scheme)
     elif a.which == "sweep-p":
