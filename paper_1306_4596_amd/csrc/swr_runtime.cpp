@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "../../include/kfpswr.h"
 #include "../../include/kfpswr_debug.h"
 #include "kfp_internal.h"
@@ -295,14 +297,17 @@ static std::map<std::string, Config> load_tune() {
   return out;
 }
 
+// Creates every missing folder of `dir` (no child process: the caller's
+// process holds a GPU context).
+static void make_dirs(const std::string &dir) {
+  for (size_t i = 1; i <= dir.size(); ++i)
+    if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+}
+
 static void save_tune(const std::map<std::string, Config> &m) {
   const std::string path = tune_path();
   const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    std::string dir = path.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-    if (system(cmd.c_str()) != 0) return;
-  }
+  if (slash != std::string::npos && slash > 0) make_dirs(path.substr(0, slash));
   std::string tmp = path + ".tmp";
   FILE *fp = fopen(tmp.c_str(), "w");
   if (!fp) return;

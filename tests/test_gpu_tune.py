@@ -1,0 +1,55 @@
+"""The launch-configuration autotuner (kfp_tune): it times the compiled
+configurations that hold a shape, caches the fastest per shape and
+discretisation, and later solves of that shape use it."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1306_4596_amd as kfp  # noqa: E402
+from paper_1306_4596_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(autouse=True)
+def _reset():
+    kfp.set_config(0)
+    kfp.set_pipeline(-1)
+    kfp.set_ordering(kfp.PARALLEL)
+    yield
+    kfp.set_scheme(kfp.FD)
+
+
+def test_autotuner_choice_is_cached_and_used(tmp_path, monkeypatch):
+    cache = tmp_path / "a" / "b" / "tune.json"  # folders created by the library
+    monkeypatch.setenv("KFP_TUNE_CACHE", str(cache))
+    # a shape no other test uses (the choice stays in the process's table)
+    nx, nv, nt, T, J, o, p = 36, 48, 24, 0.2, 2, 2, 4.0
+    u0, f = inputs.random_fields(36, nx, nv)
+    for scheme in (oracle.FD, oracle.FEM):
+        print(f"tune scheme={scheme}", flush=True)
+        kfp.set_scheme(kfp.FEM if scheme == oracle.FEM else kfp.FD)
+        w, seg, k = kfp.tune(nx, nv, nt, T, J, o, kfp.ROBIN, p=p)
+        assert w in (1, 2, 4, 8, 16) and seg >= 0 and k >= 0
+        if scheme == oracle.FEM:
+            assert k >= 1  # the finite-element scheme runs on the march kernel only
+        assert kfp.get_launch(nx, nv, nt, T, J, o, kfp.ROBIN)[:3] == (w, seg, k)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, oracle.ROBIN, p=p, tol=1e-11, max_iter=300,
+                               scheme=scheme)
+        uT, _, st = kfp.swr_solve(torch.from_numpy(u0).cuda(), torch.from_numpy(f).cuda(), T,
+                                  nt, J, o, kfp.ROBIN, p=p, tol=1e-11, max_iter=300)
+        assert st.iters == ref.iters
+        assert rel(uT.cpu().numpy(), ref.uT) <= 1e-10
+    assert os.path.exists(cache)
+    keys = list(json.load(open(cache)))
+    assert any(key.endswith("/fem") and "/nx36/" in key for key in keys), keys
+    assert any(not key.endswith("/fem") and "/nx36/" in key for key in keys), keys
