@@ -32,7 +32,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the C oracle into ``oracle/libkfp_oracle.so``."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"  # one per process: concurrent builds do not mix
         subprocess.check_call(
             ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
         )
