@@ -188,6 +188,15 @@ kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, d
 kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps);
 
 /*
+ * kfp_reload_tune_cache -- forgets the tuning choices held in memory; the
+ * next solve re-reads the cache file ($KFP_TUNE_CACHE as it is then).  For a
+ * caller that replaces or edits that file while the library is loaded.  A
+ * tuned one-step choice (steps = 0) is passed over by red-black solves,
+ * which need a march configuration, whenever one holds the shape.
+ */
+kfp_status kfp_reload_tune_cache(void);
+
+/*
  * kfp_set_launch / kfp_get_launch -- the same with lane groups: a march
  * configuration (steps >= 1) may split each wavefront into `groups` (1, 2
  * or 4) lane groups, each holding its own segment for a tile of 64/groups

@@ -30,6 +30,7 @@ from .binding import (  # noqa: F401
     mono_solve,
     mul_f32,
     release_workspace,
+    reload_tune_cache,
     set_config,
     set_kernel_timing,
     set_ordering,

@@ -175,11 +175,47 @@ def _shape(u0):
     return u0.shape[0] - 1, u0.shape[1]
 
 
+def _expect(t, shape, name):
+    """Raises ValueError unless tensor `t` (if given) has exactly `shape`: a
+    mis-sized buffer would otherwise be read or written out of bounds by the
+    kernels, which only see its pointer."""
+    if t is None:
+        return
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _check_fields(u0, f, nt, J, lambda_init=None, out=None):
+    """Shapes of one SWR instance's inputs: f and out like u0 ([nv+1][nx]),
+    lambda_init [2(J-1)][nt][nx].  Returns (nv, nx)."""
+    nv, nx = _shape(u0)
+    _expect(f, u0.shape, "f")
+    _expect(out, u0.shape, "out")
+    if lambda_init is not None:
+        if int(J) < 2:
+            raise ValueError("lambda_init is given but J < 2 has no interfaces")
+        _expect(lambda_init, (2 * (int(J) - 1), int(nt), nx), "lambda_init")
+    return nv, nx
+
+
+def check_mlp_io(n_in, n_out, X, T=None, out=None):
+    """Shapes of a network call: X [B][n_in], T and out [B][n_out].  Returns B."""
+    if X.dim() != 2:
+        raise ValueError(f"X must be [B][{n_in}], got shape {tuple(X.shape)}")
+    B = int(X.shape[0])
+    if B < 1:
+        raise ValueError("the batch is empty")
+    _expect(X, (B, n_in), "X")
+    _expect(T, (B, n_out), "T")
+    _expect(out, (B, n_out), "out")
+    return B
+
+
 def mono_solve(u0, f, T, nt, s=None, out=None, stream=None):
     """Monodomain discrete solution at t = T ([nv+1][nx] float64 on the GPU)."""
     import torch
 
-    nv, nx = _shape(u0)
+    nv, nx = _check_fields(u0, f, nt, 1, out=out)
     uT = out if out is not None else torch.empty_like(u0)
     keep, sp = _host_s(s, nt)
     g = _grid(nx, nv, nt, T)
@@ -196,7 +232,7 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter
     import numpy as np
     import torch
 
-    nv, nx = _shape(u0)
+    nv, nx = _check_fields(u0, f, nt, J, lambda_init)
     uT = torch.empty_like(u0)
     lam = None
     if want_lambda and J > 1:
@@ -231,7 +267,9 @@ def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, 
     import numpy as np
     import torch
 
-    nv, nx = _shape(u0)
+    nv, nx = _check_fields(u0, f, nt, J)
+    if int(n_windows) < 1:
+        raise ValueError("n_windows must be >= 1")
     uT = torch.empty_like(u0)
     keep, sp = _host_s(s, nt)
     its = (ctypes.c_int32 * int(n_windows))()
@@ -278,8 +316,8 @@ def swr_batch(instances, tol=1e-10, max_iter=200, history=False, stream=None):
     hists = []
     for i, d in enumerate(instances):
         u0, f = d["u0"], d["f"]
-        nv, nx = _shape(u0)
         nt, J = int(d["nt"]), int(d["J"])
+        nv, nx = _check_fields(u0, f, nt, J, d.get("lambda_init"))
         uT = torch.empty_like(u0)
         lam = None
         if d.get("want_lambda") and J > 1:
@@ -322,6 +360,14 @@ def tune(nx, nv, nt, T, J, overlap, transmission, p=1.0, stream=None):
                                    float(p), ctypes.byref(w), ctypes.byref(s), ctypes.byref(k),
                                    _stream(stream)))
     return w.value, s.value, k.value
+
+
+def reload_tune_cache():
+    """Forgets the tuning choices in memory; the next solve re-reads the
+    cache file named by $KFP_TUNE_CACHE."""
+    lib = load_library()
+    lib.kfp_reload_tune_cache.restype = ctypes.c_int
+    _check(lib.kfp_reload_tune_cache())
 
 
 def set_config(waves=0, seg_max=0, steps=1, groups=1):
@@ -498,8 +544,8 @@ class MLP:
     def forward(self, X, out=None, stream=None):
         import torch
 
-        B = X.shape[0]
         n_out = self.shape(self.layers() - 1)[1]
+        B = check_mlp_io(self.shape(0)[0], n_out, X, out=out)
         Y = out if out is not None else torch.empty((B, n_out), dtype=torch.float32, device=X.device)
         _check(self._lib.kfp_mlp_forward(self._h, int(B), _fptr(X, torch.float32),
                                          _fptr(Y, torch.float32), _stream(stream)))
@@ -508,6 +554,7 @@ class MLP:
     def backward(self, X, T, stream=None):
         import torch
 
+        check_mlp_io(self.shape(0)[0], self.shape(self.layers() - 1)[1], X, T)
         loss = ctypes.c_double()
         _check(self._lib.kfp_mlp_backward(self._h, int(X.shape[0]), _fptr(X, torch.float32),
                                           _fptr(T, torch.float32), ctypes.byref(loss),
@@ -520,6 +567,7 @@ class MLP:
     def train_step(self, X, T, lr, stream=None):
         import torch
 
+        check_mlp_io(self.shape(0)[0], self.shape(self.layers() - 1)[1], X, T)
         loss = ctypes.c_double()
         _check(self._lib.kfp_mlp_train_step(self._h, int(X.shape[0]), _fptr(X, torch.float32),
                                             _fptr(T, torch.float32), float(lr),
@@ -541,6 +589,8 @@ class MLP:
         import torch
 
         code = {"W": 0, "b": 1}[which]
+        i, o = self.shape(layer)
+        _expect(value, (o, i) if code == 0 else (o,), which)
         v = value.to(device="cuda", dtype=torch.float32).contiguous()
         _check(self._lib.kfp_mlp_param(self._h, int(layer), code, 1, _fptr(v), _stream(stream)))
         torch.cuda.current_stream().synchronize()
@@ -598,6 +648,8 @@ def standardize(X, mean, std, stream=None):
 
     lib = _mlp_sigs(load_library())
     rows, cols = X.shape
+    _expect(mean, (cols,), "mean")
+    _expect(std, (cols,), "std")
     _check(lib.kfp_standardize(_fptr(X, torch.float32), int(rows), int(cols), _fptr(mean),
                                _fptr(std), _stream(stream)))
 
@@ -608,6 +660,10 @@ def destandardize(Y, mean, std, out=None, base=None, stream=None):
 
     lib = _mlp_sigs(load_library())
     rows, cols = Y.shape
+    _expect(mean, (cols,), "mean")
+    _expect(std, (cols,), "std")
+    if out is not None and out.numel() != rows * cols:
+        raise ValueError("destandardize: out has the wrong size")
     lam = out if out is not None else torch.empty((rows, cols), dtype=torch.float64, device=Y.device)
     if base is not None and base.numel() != rows * cols:
         raise KfpError(KFP_EINVAL, "destandardize: base has the wrong size")

@@ -1,6 +1,6 @@
 """Builds libkfpswr.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-    python -m paper_1306_4596_amd.build
+    python -m paper_1306_4596_amd.build [--incremental]
 
 Every source under csrc/ is compiled to an object in _build/ (in parallel),
 then linked into paper_1306_4596_amd/_lib/libkfpswr.so.
@@ -43,8 +43,19 @@ def sources():
     return out
 
 
-def _compile(src):
+def _headers():
+    out = []
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        out += [os.path.join(d, n) for n in os.listdir(d) if n.endswith(".h")]
+    return out
+
+
+def _compile(src, force=True):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not force and os.path.exists(obj):
+        newest = max(os.path.getmtime(x) for x in [src] + _headers())
+        if os.path.getmtime(obj) >= newest:
+            return obj, ""
     cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -53,13 +64,15 @@ def _compile(src):
     return obj, warn
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compiles every source (force=False: only those older than their
+    object file or a header) and links the library."""
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(OUT_DIR, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=max(jobs, 1)) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda src: _compile(src, force), srcs))
     if verbose:
         for obj, warn in results:
             if warn:
@@ -75,4 +88,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, force="--incremental" not in sys.argv[1:]))

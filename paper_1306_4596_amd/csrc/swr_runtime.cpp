@@ -97,6 +97,15 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
     if (g->nv / J < o + 2) return fail(KFP_EINVAL, "nv/J must be >= overlap + 2");
     if (tr == KFP_ROBIN && !(p > 0.0 && std::isfinite(p)))
       return fail(KFP_EINVAL, "Robin parameter p must be > 0 (got %g)", p);
+    // The mismatch (6.12) is reduced at the two end nodes of each overlap.
+    // That equals the maximum over the whole overlap by the discrete maximum
+    // principle, which the finite-element step satisfies only while its
+    // element matrix is an M-matrix (off-diagonal 1/6 - r <= 0).
+    const double hv = 2.0 / g->nv, r = (g->T / g->nt) / (hv * hv);
+    if (scheme == SCHEME_FEM && r < 1.0 / 6.0)
+      return fail(KFP_EINVAL,
+                  "the finite-element scheme needs r = dt/h_v^2 >= 1/6 with J > 1 (got r = %g): "
+                  "below it the end-node mismatch can understate (6.12)", r);
   }
   geo.nx = g->nx;
   geo.nv = g->nv;
@@ -340,7 +349,9 @@ static std::string tune_key(const Geo &g) {
 
 static std::map<std::string, Config> *g_tune = nullptr;
 
-static Config choose_config(const Geo &g) {
+// order: the solve order the configuration will run in (1: red-black, which
+// needs a march configuration; a tuned one-step choice is then passed over).
+static Config choose_config(const Geo &g, int order = 0) {
   if (g_forced.waves > 0) {
     Config c = g_forced;
     if (c.steps >= 1 && !march_fits(g.n_max, c.waves, c.seg, c.groups)) {
@@ -361,9 +372,10 @@ static Config choose_config(const Geo &g) {
   auto it = g_tune->find(tune_key(g));
   if (it != g_tune->end()) {
     const Config &c = it->second;
-    if (c.steps >= 1 ? march_fits(g.n_max, c.waves, c.seg, c.groups)
-                     : (c.seg == 0 || segs_for(g.n_max, c.waves) <= c.seg))
-      return c;
+    const bool usable = c.steps >= 1 ? march_fits(g.n_max, c.waves, c.seg, c.groups)
+                                     : (c.seg == 0 || segs_for(g.n_max, c.waves) <= c.seg) &&
+                                           !(order == 1 && march_seg_for(g.n_max, 8, 4));
+    if (usable) return c;
   }
   if (g.J > 0 && g.nx > 0) {
     // overlapped iterations (see pipe_params) supply work items to spare:
@@ -1649,9 +1661,9 @@ static kfp_status swr_solve_impl(const kfp_grid *g, const double *u0, const doub
   if (s)
     for (int n = 0; n <= g->nt; ++n)
       if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
-  const Config cfg = choose_config(geo);
-  if ((st = fem_needs_march(geo, cfg))) return st;
   const int order = J > 1 ? g_order : 0;
+  const Config cfg = choose_config(geo, order);
+  if ((st = fem_needs_march(geo, cfg))) return st;
   if (order == 1 && cfg.steps == 0)
     return fail(KFP_EINVAL,
                 "red-black order needs a march configuration (subdomains of at most 1056 rows; "
@@ -2458,6 +2470,14 @@ kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, d
   return tune_impl(g, J, overlap, tr, p, waves_out, seg_max_out, steps_out, (hipStream_t)stream);
 }
 
+kfp_status kfp_reload_tune_cache(void) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  delete g_tune;
+  g_tune = nullptr;
+  return KFP_OK;
+}
+
 kfp_status kfp_set_kernel_timing(int32_t on) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
@@ -2518,7 +2538,7 @@ kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
   Geo geo;
   kfp_status st = make_geo(g, J, overlap, tr, 1.0, geo, g_scheme);
   if (st) return st;
-  const Config c = choose_config(geo);
+  const Config c = choose_config(geo, J > 1 ? g_order : 0);
   if (waves_out) *waves_out = c.waves;
   if (groups_out) *groups_out = c.groups;
   if (seg_max_out) *seg_max_out = c.seg;

@@ -53,3 +53,34 @@ def test_autotuner_choice_is_cached_and_used(tmp_path, monkeypatch):
     keys = list(json.load(open(cache)))
     assert any(key.endswith("/fem") and "/nx36/" in key for key in keys), keys
     assert any(not key.endswith("/fem") and "/nx36/" in key for key in keys), keys
+
+
+def test_tuned_one_step_choice_is_passed_over_in_red_black_order(tmp_path, monkeypatch):
+    """A cached one-step configuration (steps = 0) of a shape serves the
+    parallel order; a red-black solve of the same shape, which needs a march
+    configuration, falls back to the built-in march choice and still
+    matches the oracle."""
+    nx, nv, nt, T, J, o, p = 40, 64, 30, 0.2, 2, 2, 4.0
+    # Robin, J = 2, overlap 2: both subdomains hold 33 unknown rows
+    key = f"gfx950/nx{nx}/nmax33/J{J}/tr1"
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({key: [4, 16, 0, 1]}))
+    monkeypatch.setenv("KFP_TUNE_CACHE", str(cache))
+    kfp.reload_tune_cache()
+    try:
+        assert kfp.get_launch(nx, nv, nt, T, J, o, kfp.ROBIN) == (4, 16, 0, 1)
+        kfp.set_ordering(kfp.RED_BLACK)
+        w, seg, k, g = kfp.get_launch(nx, nv, nt, T, J, o, kfp.ROBIN)
+        assert k >= 1, (w, seg, k, g)
+        u0, f = inputs.random_fields(40, nx, nv)
+        print("red-black solve with a cached one-step choice", flush=True)
+        uT, _, st = kfp.swr_solve(torch.from_numpy(u0).cuda(), torch.from_numpy(f).cuda(), T,
+                                  nt, J, o, kfp.ROBIN, p=p, tol=1e-11, max_iter=300)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, oracle.ROBIN, p=p, tol=1e-11, max_iter=300,
+                               order=1)
+        assert st.iters == ref.iters
+        assert rel(uT.cpu().numpy(), ref.uT) <= 1e-10
+    finally:
+        kfp.set_ordering(kfp.PARALLEL)
+        monkeypatch.undo()
+        kfp.reload_tune_cache()

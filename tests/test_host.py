@@ -346,3 +346,84 @@ def test_fem_batch_rejects_tall_instances(lib):
         assert "instance 1" in msg and "finite-element" in msg
     finally:
         assert lib.kfp_set_scheme(0) == 0
+
+
+def test_fem_rejects_r_below_one_sixth(lib):
+    """With finite elements the end-node mismatch equals the overlap maximum
+    (6.12) only while the element matrix is an M-matrix (r >= 1/6): SWR
+    solves below that are rejected; the monodomain solve is not affected."""
+    assert lib.kfp_set_scheme(1) == 0
+    try:
+        # r = (T/nt) / (2/nv)^2 = (0.01/100) / (1/32)^2 = 0.1024 < 1/6
+        g = G(64, 64, 100, 0.01)
+        st = lib.kfp_swr_solve(ctypes.byref(g), FAKE, FAKE, None, 2, 2, 1, 4.0, 1e-10, 5, None,
+                               FAKE, None, None, None)
+        assert st == binding.KFP_EINVAL
+        assert "1/6" in lib.kfp_last_error().decode()
+        r = ctypes.c_int64()
+        assert lib.kfp_subdomain_rows(ctypes.byref(g), 1, 0, 0, ctypes.byref(r)) == 0
+    finally:
+        assert lib.kfp_set_scheme(0) == 0
+    # finite differences: the same shape is accepted as far as validation goes
+    g = G(64, 64, 100, 0.01)
+    r = ctypes.c_int64()
+    assert lib.kfp_subdomain_rows(ctypes.byref(g), 2, 2, 1, ctypes.byref(r)) == 0
+
+
+def _meta(*shape, dtype=None):
+    import torch
+
+    return torch.empty(shape, dtype=dtype or torch.float64, device="meta")
+
+
+@pytest.mark.parametrize("call,frag", [
+    ("mono_f", "f has shape"),
+    ("mono_out", "out has shape"),
+    ("swr_f", "f has shape"),
+    ("swr_lam", "lambda_init has shape"),
+    ("swr_lam_J1", "J < 2"),
+    ("win_f", "f has shape"),
+    ("batch_lam", "lambda_init has shape"),
+])
+def test_binding_rejects_mis_sized_tensors(call, frag):
+    """Every tensor is checked against its documented shape before any
+    pointer reaches the library (the kernels would read or write past a
+    short buffer): f and uT like u0, lambda_init [2(J-1)][nt][nx]."""
+    u0 = _meta(65, 64)
+    nt = 10
+    with pytest.raises(ValueError, match=frag):
+        if call == "mono_f":
+            binding.mono_solve(u0, _meta(65, 63), 0.1, nt)
+        elif call == "mono_out":
+            binding.mono_solve(u0, _meta(65, 64), 0.1, nt, out=_meta(64, 64))
+        elif call == "swr_f":
+            binding.swr_solve(u0, _meta(64, 64), 0.1, nt, 2, 2, 1, p=4.0)
+        elif call == "swr_lam":
+            binding.swr_solve(u0, _meta(65, 64), 0.1, nt, 2, 2, 1, p=4.0,
+                              lambda_init=_meta(2, nt - 1, 64))
+        elif call == "swr_lam_J1":
+            binding.swr_solve(u0, _meta(65, 64), 0.1, nt, 1, 0, 0, lambda_init=_meta(0, nt, 64))
+        elif call == "win_f":
+            binding.swr_solve_windows(u0, _meta(65, 32), 0.1, nt, 2, 2, 1, p=4.0, n_windows=2)
+        elif call == "batch_lam":
+            binding.swr_batch([dict(u0=u0, f=_meta(65, 64), T=0.1, nt=nt, J=4, overlap=2, tr=1,
+                                    p=4.0, lambda_init=_meta(2, nt, 64))])
+
+
+def test_network_io_shapes():
+    """X is [B][n_in], T and out [B][n_out]: anything else is rejected before
+    the GEMM kernels see the pointers."""
+    import torch
+
+    f32 = torch.float32
+    assert binding.check_mlp_io(64, 10, _meta(8, 64, dtype=f32), _meta(8, 10, dtype=f32)) == 8
+    for X, T, out, frag in [
+        (_meta(8, 63, dtype=f32), None, None, "X has shape"),
+        (_meta(8, 64, dtype=f32), _meta(8, 11, dtype=f32), None, "T has shape"),
+        (_meta(8, 64, dtype=f32), _meta(7, 10, dtype=f32), None, "T has shape"),
+        (_meta(8, 64, dtype=f32), None, _meta(8, 9, dtype=f32), "out has shape"),
+        (_meta(64, dtype=f32), None, None, "X must be"),
+        (_meta(0, 64, dtype=f32), None, None, "empty"),
+    ]:
+        with pytest.raises(ValueError, match=frag):
+            binding.check_mlp_io(64, 10, X, T, out)
