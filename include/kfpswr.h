@@ -96,6 +96,25 @@ kfp_status kfp_mono_solve(const kfp_grid *g, const double *u0, const double *f,
                           const double *s, double *uT, void *stream);
 
 /*
+ * kfp_mono_solve_static -- kfp_mono_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, same kernels and the same result
+ * as kfp_mono_solve.  It calls no hipMalloc/hipFree and creates no stream or
+ * event: the state ping-pong and the coefficient tables live in a static
+ * device workspace of 64 MiB per GPU (held until the process ends), and all
+ * work runs on `stream`.
+ *   Limit: 2 (nv-1) nx doubles of state plus the tables must fit in 64 MiB
+ *   (e.g. nv = 1024 with nx up to about 4000); larger grids return
+ *   KFP_EINVAL with nothing written.
+ *   The tables are copied in with `stream` synchronised once before the
+ *   launches; the march itself is asynchronous on `stream`.
+ *   Every call on one GPU shares that GPU's workspace: calls that overlap
+ *   in time on one GPU (other streams, other host threads' streams) race.
+ */
+kfp_status kfp_mono_solve_static(const kfp_grid *g, const double *u0, const double *f,
+                                 const double *s, double *uT, void *stream);
+
+/*
  * kfp_swr_solve -- parallel SWR (Section 6.3, eqs. (6.8)-(6.12)) over J
  * subdomains split in v with an overlap of `overlap` cells.
  *   J:           1 <= J, nv % J == 0, nv/J >= overlap + 2

@@ -28,6 +28,7 @@ from .binding import (  # noqa: F401
     lib_path,
     load_library,
     mono_solve,
+    mono_solve_static,
     mul_f32,
     release_workspace,
     reload_tune_cache,

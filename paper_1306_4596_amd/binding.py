@@ -88,6 +88,7 @@ def load_library():
     G = ctypes.POINTER(Grid)
     D = ctypes.POINTER(ctypes.c_double)
     lib.kfp_mono_solve.argtypes = [G, vp, vp, D, vp, vp]
+    lib.kfp_mono_solve_static.argtypes = [G, vp, vp, D, vp, vp]
     lib.kfp_swr_solve.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, i32, vp, vp, vp,
                                   ctypes.POINTER(Stats), vp]
     lib.kfp_swr_solve_pq.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, f64, i32, vp, vp, vp,
@@ -114,7 +115,7 @@ def load_library():
     lib.kfp_last_error.restype = ctypes.c_char_p
     lib.kfp_last_error.argtypes = []
     lib.kfp_release_workspace.restype = None
-    for name in ("kfp_mono_solve", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_swr_solve_windows",
+    for name in ("kfp_mono_solve", "kfp_mono_solve_static", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_swr_solve_windows",
                  "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
@@ -221,6 +222,20 @@ def mono_solve(u0, f, T, nt, s=None, out=None, stream=None):
     g = _grid(nx, nv, nt, T)
     _check(load_library().kfp_mono_solve(ctypes.byref(g), _ptr(u0), _ptr(f), sp, _ptr(uT),
                                          _stream(stream)))
+    return uT
+
+
+def mono_solve_static(u0, f, T, nt, s=None, out=None, stream=None):
+    """mono_solve through the entry point that allocates nothing (its state
+    and tables live in the library's static per-GPU workspace)."""
+    import torch
+
+    nv, nx = _check_fields(u0, f, nt, 1, out=out)
+    uT = out if out is not None else torch.empty_like(u0)
+    keep, sp = _host_s(s, nt)
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_mono_solve_static(ctypes.byref(g), _ptr(u0), _ptr(f), sp,
+                                                _ptr(uT), _stream(stream)))
     return uT
 
 

@@ -1800,6 +1800,143 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
   return sync_out(user, *pl);
 }
 
+// ------------------------------------------------------- static workspace --
+// Workspace of kfp_mono_solve_static, for callers that cannot allocate: a
+// file-scope device array (each GPU the library runs on holds its own copy
+// until the process ends).  In host code the array's name is only a
+// stand-in: the device address of the current GPU's copy is looked up once
+// per device with hipGetSymbolAddress and only that address is handed to
+// kernels and copies.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static std::map<int, unsigned char *> g_scratch_ptr;  // device -> address of its copy
+
+static kfp_status static_scratch(unsigned char **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(KFP_EDEVICE, "no device address for the static workspace");
+    it = g_scratch_ptr.emplace(dev, static_cast<unsigned char *>(p)).first;
+  }
+  *out = it->second;
+  return KFP_OK;
+}
+
+// The monodomain march of mono_solve_impl with every buffer carved out of the
+// static workspace, launched on the caller's stream: no device allocation,
+// no stream or event of its own.  The tables are copied in and the stream is
+// synchronised once before the launches (the host tables are temporaries).
+static kfp_status mono_solve_static_impl(const kfp_grid *g, const double *u0, const double *f,
+                                         const double *s, double *uT, hipStream_t stream) {
+  Geo geo;
+  kfp_status st = make_geo(g, 1, 0, KFP_DIRICHLET, 0.0, geo, g_scheme);
+  if (st) return st;
+  if (!u0 || !f || !uT) return fail(KFP_EINVAL, "u0, f and uT must be non-NULL");
+  if (s)
+    for (int n = 0; n <= g->nt; ++n)
+      if (!std::isfinite(s[n])) return fail(KFP_EINVAL, "s[%d] is not finite", n);
+  const Config cfg = choose_config(geo);
+  if ((st = fem_needs_march(geo, cfg))) return st;
+  HostTables h;
+  add_instance_cfg(geo, 0.0, 0.0, cfg.waves, cfg.seg, cfg.steps, 0, h);
+  make_items(geo, 0, tile_width(cfg), h.items);
+  // the layout of the workspace: 256-byte aligned parts
+  size_t used = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = used;
+    used += (std::max<size_t>(bytes, 8) + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t state = (size_t)geo.rows * geo.nx;
+  const size_t o_u0 = take(state * 8), o_u1 = take(state * 8), o_g = take((size_t)geo.nt * 8);
+  const size_t o_lam = take(8), o_res = take(8), o_rowmap = take((size_t)(geo.nv + 1) * 4);
+  const size_t o_inst = take(sizeof(InstDev)), o_subs = take(h.subs.size() * sizeof(SubDev));
+  const size_t o_items = take(h.items.size() * sizeof(Item));
+  const size_t o_rows = take(h.rows.size() * sizeof(RowCoef));
+  const size_t o_reds = take(h.reds.size() * sizeof(RedCoef));
+  const size_t o_segs = take(h.segs.size() * sizeof(int));
+  const size_t o_mrows = take(h.mrows.size() * sizeof(MarchCoef));
+  const size_t o_frows = take(h.frows.size() * sizeof(FemCoef));
+  const size_t o_fsegs = take(h.fsegs.size() * sizeof(FemSeg));
+  const size_t o_rinv = take(h.rinv.size() * sizeof(double));
+  if (used > kStaticScratchBytes)
+    return fail(KFP_EINVAL,
+                "kfp_mono_solve_static: this grid needs %zu bytes of workspace; the static "
+                "workspace holds %zu (state of (nv-1) x nx doubles twice, plus tables)",
+                used, kStaticScratchBytes);
+  unsigned char *base = nullptr;
+  if ((st = static_scratch(&base))) return st;
+  auto at = [&](size_t o) { return (void *)(base + o); };
+  InstDev in{};
+  in.U[0] = (double *)at(o_u0);
+  in.U[1] = (double *)at(o_u1);
+  in.u0 = u0;
+  in.f = f;
+  in.g = (const double *)at(o_g);
+  in.lam[0] = in.lam[1] = (double *)at(o_lam);
+  in.res = (unsigned long long *)at(o_res);
+  in.V = nullptr;
+  const double hv = 2.0 / geo.nv, dt = geo.T / geo.nt;
+  in.r = dt / (hv * hv);
+  in.hv = hv;
+  in.nx = geo.nx;
+  in.nv = geo.nv;
+  in.nt = geo.nt;
+  in.tr = geo.tr;
+  in.scheme = geo.scheme;
+  in.active = 1;
+  std::vector<double> gv(geo.nt);
+  for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
+  auto cp = [&](size_t o, const void *src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(at(o), src, bytes, hipMemcpyHostToDevice, stream) : hipSuccess;
+  };
+  HIP_TRY(cp(o_g, gv.data(), gv.size() * 8));
+  HIP_TRY(cp(o_rowmap, geo.rowmap.data(), (size_t)(geo.nv + 1) * 4));
+  HIP_TRY(cp(o_inst, &in, sizeof in));
+  HIP_TRY(cp(o_subs, h.subs.data(), h.subs.size() * sizeof(SubDev)));
+  HIP_TRY(cp(o_items, h.items.data(), h.items.size() * sizeof(Item)));
+  HIP_TRY(cp(o_rows, h.rows.data(), h.rows.size() * sizeof(RowCoef)));
+  HIP_TRY(cp(o_reds, h.reds.data(), h.reds.size() * sizeof(RedCoef)));
+  HIP_TRY(cp(o_segs, h.segs.data(), h.segs.size() * sizeof(int)));
+  HIP_TRY(cp(o_mrows, h.mrows.data(), h.mrows.size() * sizeof(MarchCoef)));
+  HIP_TRY(cp(o_frows, h.frows.data(), h.frows.size() * sizeof(FemCoef)));
+  HIP_TRY(cp(o_fsegs, h.fsegs.data(), h.fsegs.size() * sizeof(FemSeg)));
+  HIP_TRY(cp(o_rinv, h.rinv.data(), h.rinv.size() * sizeof(double)));
+  HIP_TRY(hipStreamSynchronize(stream));  // the host tables go out of scope
+  StepTables t{};
+  t.inst = (const InstDev *)at(o_inst);
+  t.subs = (const SubDev *)at(o_subs);
+  t.items = (const Item *)at(o_items);
+  t.rows = (const RowCoef *)at(o_rows);
+  t.reds = (const RedCoef *)at(o_reds);
+  t.segs = (const int *)at(o_segs);
+  t.ex = nullptr;
+  t.mrows = (const MarchCoef *)at(o_mrows);
+  t.frows = (const FemCoef *)at(o_frows);
+  t.fsegs = (const FemSeg *)at(o_fsegs);
+  t.rinv = (const double *)at(o_rinv);
+  t.blk = nullptr;
+  t.n_items = (int)h.items.size();
+  t.n_ex = 0;
+  t.fem = h.fem ? 1 : 0;
+  if (cfg.steps == 0) {
+    for (int n = 0; n < geo.nt; ++n)
+      HIP_TRY(launch_step(t, cfg.waves, cfg.seg, n, 0, t.n_items, stream));
+  } else {
+    const int L = march_launches(geo.nt, cfg);
+    for (int l = 0; l < L; ++l)
+      HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps,
+                           halo_of(cfg), l & 1, 0, t.n_items, stream));
+  }
+  const double *Ufin = (march_launches(geo.nt, cfg) & 1) ? in.U[1] : in.U[0];
+  HIP_TRY(launch_assemble(Ufin, (const int *)at(o_rowmap), uT, geo.nv, geo.nx, stream,
+                          out_nudt(geo), 2.0 / geo.nv));
+  return KFP_OK;
+}
+
 // ------------------------------------------------------------------- batch --
 struct BatchInst {
   Geo geo;
@@ -2297,6 +2434,13 @@ kfp_status kfp_mono_solve(const kfp_grid *g, const double *u0, const double *f, 
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   return mono_solve_impl(g, u0, f, s, uT, (hipStream_t)stream);
+}
+
+kfp_status kfp_mono_solve_static(const kfp_grid *g, const double *u0, const double *f,
+                                 const double *s, double *uT, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  return mono_solve_static_impl(g, u0, f, s, uT, (hipStream_t)stream);
 }
 
 kfp_status kfp_swr_solve(const kfp_grid *g, const double *u0, const double *f, const double *s,

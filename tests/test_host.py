@@ -89,6 +89,22 @@ def test_mono_and_batch_invalid_arguments(lib):
     assert lib.kfp_bw_probe(FAKE, FAKE, 10, None) == binding.KFP_EINVAL
 
 
+def test_static_mono_validation(lib):
+    """The no-allocation monodomain entry point validates like kfp_mono_solve
+    and rejects a grid whose state and tables exceed its static workspace,
+    before any device call."""
+    g = G(64, 64, 10, 0.1)
+    assert lib.kfp_mono_solve_static(ctypes.byref(g), None, FAKE, None, FAKE,
+                                     None) == binding.KFP_EINVAL
+    bad = G(64, 64, 10, 100.0)
+    assert lib.kfp_mono_solve_static(ctypes.byref(bad), FAKE, FAKE, None, FAKE,
+                                     None) == binding.KFP_EINVAL
+    big = G(4096, 4096, 100, 0.01)  # 2 x 4095 x 4096 doubles of state: 268 MB
+    assert lib.kfp_mono_solve_static(ctypes.byref(big), FAKE, FAKE, None, FAKE,
+                                     None) == binding.KFP_EINVAL
+    assert "static workspace" in lib.kfp_last_error().decode()
+
+
 def test_subdomain_rows(lib):
     r = ctypes.c_int64()
     g = G(1024, 1024, 2000, 0.5)
