@@ -233,6 +233,25 @@ kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
                           int32_t *steps_out);
 
 /*
+ * kfp_set_launch_tiles / kfp_get_launch_tiles -- the same with the march
+ * kernel variant: tiles = 0 is the general march kernel above; tiles = 1 or
+ * 2 (finite differences, groups = 1, 1 <= steps <= 16) the multi-tile march
+ * kernel, whose wavefronts each hold their segment for `tiles` x-tiles of 64
+ * columns (shared coefficient reads and barrier, independent elimination
+ * chains) and whose tiles carry the halo of `steps` columns only on the
+ * upwind sides of each subdomain's rows (one side when all its rows have
+ * v >= 0 or all v <= 0).  Same arithmetic and results as the general march
+ * kernel.  A forced multi-tile configuration falls back to the general
+ * kernel of the same shape for the finite-element scheme or a subdomain
+ * taller than waves * seg_max.  KFP_EINVAL if not compiled.
+ */
+kfp_status kfp_set_launch_tiles(int32_t waves, int32_t groups, int32_t seg_max, int32_t steps,
+                                int32_t tiles);
+kfp_status kfp_get_launch_tiles(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                                int32_t *waves_out, int32_t *groups_out, int32_t *seg_max_out,
+                                int32_t *steps_out, int32_t *tiles_out);
+
+/*
  * kfp_set_pipeline -- overlap SWR iterations in time.  Iteration k at a
  * time block needs only iteration k-1's traces of that block (the method is
  * causal in time), so iteration k+1 can march d blocks behind iteration k;

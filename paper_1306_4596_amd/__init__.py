@@ -25,6 +25,7 @@ from .binding import (  # noqa: F401
     destandardize,
     get_config,
     get_launch,
+    get_launch_tiles,
     lib_path,
     load_library,
     mono_solve,

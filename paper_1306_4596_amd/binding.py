@@ -104,6 +104,8 @@ def load_library():
     lib.kfp_tune.argtypes = [G, i32, i32, i32, f64, pi, pi, pi, vp]
     lib.kfp_set_config.argtypes = [i32, i32, i32]
     lib.kfp_set_launch.argtypes = [i32, i32, i32, i32]
+    lib.kfp_set_launch_tiles.argtypes = [i32, i32, i32, i32, i32]
+    lib.kfp_get_launch_tiles.argtypes = [G, i32, i32, i32, pi, pi, pi, pi, pi]
     lib.kfp_get_launch.argtypes = [G, i32, i32, i32, pi, pi, pi, pi]
     lib.kfp_set_pipeline.argtypes = [i32]
     lib.kfp_set_ordering.argtypes = [i32]
@@ -119,6 +121,7 @@ def load_library():
                  "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
+                 "kfp_set_launch_tiles", "kfp_get_launch_tiles",
                  "kfp_set_ordering", "kfp_set_scheme", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -385,10 +388,12 @@ def reload_tune_cache():
     _check(lib.kfp_reload_tune_cache())
 
 
-def set_config(waves=0, seg_max=0, steps=1, groups=1):
+def set_config(waves=0, seg_max=0, steps=1, groups=1, tiles=0):
     """Forces a launch configuration (waves=0: automatic); groups > 1 splits
-    each wavefront of the march kernel into lane groups."""
-    _check(load_library().kfp_set_launch(int(waves), int(groups), int(seg_max), int(steps)))
+    each wavefront of the march kernel into lane groups; tiles 1 or 2 selects
+    the multi-tile finite-difference march kernel."""
+    _check(load_library().kfp_set_launch_tiles(int(waves), int(groups), int(seg_max), int(steps),
+                                               int(tiles)))
 
 
 def get_config(nx, nv, nt, T, J, overlap, transmission):
@@ -408,6 +413,16 @@ def get_launch(nx, nv, nt, T, J, overlap, transmission):
                                          ctypes.byref(w), ctypes.byref(g_), ctypes.byref(s),
                                          ctypes.byref(k)))
     return w.value, s.value, k.value, g_.value
+
+
+def get_launch_tiles(nx, nv, nt, T, J, overlap, transmission):
+    """(waves, seg_max, steps, groups, tiles) a solve of this shape would use."""
+    v = [ctypes.c_int32() for _ in range(5)]
+    g = _grid(nx, nv, nt, T)
+    _check(load_library().kfp_get_launch_tiles(ctypes.byref(g), int(J), int(overlap),
+                                               int(transmission), *[ctypes.byref(x) for x in v]))
+    w, g_, s, k, tl = (x.value for x in v)
+    return w, s, k, g_, tl
 
 
 def subdomain_rows(nx, nv, nt, T, J, overlap, transmission):

@@ -72,6 +72,8 @@ struct SubDev {
   int pad;            // multi-step layout: leading identity rows of the last segment
   int vsplit;         // first local row with v >= 0 (upwind neighbour at m-1)
   int rinv;           // multi-step layout: first entry of the reduced-system inverse
+  int hsides;         // upwind sides of the rows: bit 0 some row has v > 0 (its upwind
+                      // neighbour is at m-1), bit 1 some row has v < 0 (at m+1)
 };
 
 // Per unknown row: transport weight and the factors of the local (segment)
@@ -91,13 +93,16 @@ struct RowCoef {
 // the transport: y_k = alpha u_k + beta u_nb + g fs_k + fb y_{k-1}, with
 // fs = fa f pre-scaled once per launch; the upwind neighbour u_nb is the
 // column at m-1 for v >= 0 and at m+1 for v < 0 (SubDev::vsplit).
+// The fields are ordered by the pass that reads them (16-byte pairs): the
+// forward elimination (alpha, beta, fb), the spike correction (sl, sr), the
+// back substitution (bc); fa and fab are read once per launch.
 struct MarchCoef {
   double alpha;  // fa (1 - |nu|)
   double beta;   // fa |nu|
   double fb;     // -sub / pivot
-  double bc;     // -c'
-  double sl, sr; // spikes (zero on separator and identity rows)
   double fa;     // 1 / pivot (0 on Robin and identity rows: no source there)
+  double sl, sr; // spikes (zero on separator and identity rows)
+  double bc;     // -c'
   double fab;    // 1 / pivot of an end row that takes boundary data, else 0
 };
 
@@ -202,9 +207,16 @@ bool step_config_supported(int waves, int seg_max);
 // tiles carry a halo of H >= S columns on both sides.
 // groups: lane groups per wavefront (each holds its own segment for a tile
 // of 64/groups columns); 2 * H * groups < 64
-hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int n0, int S,
-                        int H, int src, int par, int grid, hipStream_t s);
+// tiles: 0 the general march kernel (halo on both sides); 1 or 2 the
+// finite-difference march kernel with `tiles` x-tiles per wavefront and the
+// halo on the upwind sides of each subdomain only (SubDev::hsides; items
+// made for it; groups = 1, S <= 16)
+hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int tiles,
+                        int n0, int S, int H, int src, int par, int grid, hipStream_t s);
 bool march_config_supported(int waves, int groups, int seg_max);
+bool fd_config_supported(int waves, int seg_max, int tiles);
+// Compute units of the current device (256 if it cannot be queried).
+int device_cu_count();
 // Exchange pass of the multi-step path: traces (6.9)/(6.11) of every level
 // and the residual (6.12) from the interface-node value planes.
 // S: steps per launch (pipelined tables: the exchange covers the levels of

@@ -409,6 +409,14 @@ __device__ __forceinline__ double from_upper_lane(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// A wave-uniform double moved to scalar registers (FP64 vector instructions
+// take it as a scalar operand, so it holds no vector register).
+__device__ __forceinline__ double wave_uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // A wave's column segment of SEG <= 48 rows held in registers.  Up to three
 // vectors of at most 16 doubles, so that a wave-uniform run-time index
 // compiles to relative register addressing (longer vectors would be spilled
@@ -853,6 +861,10 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
     // register `pad` of every lane (a wave-uniform index): the first real row
     // of the last segment
     auto first_value = [&](const SegRegs<SEG> &dd) {
+      // finite differences: the back substitution copies the first real row
+      // into the padding registers below it (their bc is 1), so after it
+      // register 0 holds that row in every segment
+      if constexpr (!FEM) return dd.template ld<0>();
       if constexpr (G == 1) {
         return dd.get(k0);
       } else {
@@ -1032,6 +1044,389 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_kernel(StepTables t, int n
         if (k >= k0) dst[(size_t)(base + k) * nx + col] = d.template ld<k>();
       });
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finite-difference march over TPW x-tiles per wavefront (the default for
+// finite differences when one workgroup of NW wavefronts holds a subdomain).
+// The arithmetic of a step is that of march_kernel (transport, source and
+// forward elimination in one pass, back substitution, reduced separator
+// system, spike correction), organised for fewer instructions per cell:
+//  * every wavefront holds its segment for TPW tiles of 64 columns: the
+//    coefficient reads (wave-uniform LDS broadcasts), the loop and the
+//    barrier are shared by TPW independent columns per lane, which also
+//    gives the dependent elimination chains TPW-fold instruction-level
+//    parallelism;
+//  * a subdomain whose rows all move the same way in x (all v >= 0 or all
+//    v <= 0) needs its halo only on the upwind side: the tile then yields
+//    64 - S columns instead of 64 - 2S (SubDev::hsides);
+//  * the back substitution copies the first real row of the last segment into
+//    its padding registers (their bc is 1), so every segment's first row is
+//    register 0 (no run-time register index);
+//  * the reduced system: each segment forms its own parts of the separator
+//    right-hand sides before the barrier, E_v = sep_v - ra_v last_v and
+//    F_v = -rc_{v-1} first_v, and each lane keeps the two rows of the reduced
+//    inverse it needs in registers, so after the barrier a separator costs two
+//    LDS reads and two FMAs per tile.
+// Items: (sub, x0) with x0 the first output column of tile 0; tile t outputs
+// columns x0 + t W .. x0 + (t+1) W - 1 (W = 64 - halo sides), lane l holds
+// column x0 + t W - HL + l.
+constexpr int kMaxStepsFd = 16;
+#define KFP_FD_SCHED 1
+
+
+// A column segment in registers, indexed at compile time only: each row is
+// its own value, so a step's results take the registers of its inputs (a
+// vector type would be rebuilt and copied back every step).
+template <int N>
+struct ColRegs {
+  double r[N];
+  template <int K>
+  __device__ __forceinline__ double ld() const {
+    return r[K];
+  }
+  template <int K>
+  __device__ __forceinline__ void st(double v) {
+    r[K] = v;
+  }
+};
+
+template <int SEG, int NW, int TPW, int OCC>
+__global__ __launch_bounds__(NW * 64, OCC) void march_fd_kernel(StepTables t, int n0_in, int S,
+                                                                int H, int src_in, int par) {
+  static_assert(TPW == 1 || TPW == 2, "tiles per wavefront");
+  static_assert(SEG <= kFRegMax, "the source segment is held in registers");
+  constexpr int NR = NW > 1 ? NW - 1 : 1;  // separators of a full workgroup
+  // separator v's right-hand side parts, side by side: E_v (from segment v)
+  // and F_{v+1} (from segment v+1), read as one 16-byte value
+  __shared__ double2 sh_EF[2][NW][TPW][64];
+  __shared__ double sh_bd[2][kMaxStepsFd][TPW][64];
+  __shared__ MarchCoef sh_mc[NW][SEG];
+  __shared__ double sh_g[NW][kMaxStepsFd];
+  // the reduced inverse of the item's subdomain, transposed: sh_ri[q][v + 1]
+  // is row v, column q (zero past the subdomain's separators; column 0 and
+  // columns past the last separator zero), so that a segment's two rows are
+  // adjacent
+  __shared__ double sh_ri[NR][NW + 1];
+  const int lane = threadIdx.x & 63;
+  const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's segment
+  KConst<Item> *items = as_const(t.items);
+  KConst<SubDev> *subs = as_const(t.subs);
+  KConst<InstDev> *insts = as_const(t.inst);
+  for (int it = blockIdx.x; it < t.n_items; it += gridDim.x) {
+    const int sub = items[it].sub;
+    const int x0 = items[it].x0;
+    KConst<SubDev> *sd = subs + sub;
+    KConst<InstDev> *I = insts + sd->inst;
+    if (!I->active) continue;
+    int n0 = n0_in, src_par = src_in;
+    if (t.blk) {  // pipelined iterations: this instance's block of this launch
+      const int b = as_const(t.blk)[sd->inst];
+      if (b < 0) continue;
+      n0 = b * S;
+      src_par = b & 1;
+    }
+    const int nx = I->nx;
+    const int nt = I->nt;
+    if (n0 >= nt) continue;
+    const int steps = min(min(S, kMaxStepsFd), nt - n0);  // S is checked by the host
+    const int hs = sd->hsides;
+    const int HL = (hs & 1) ? H : 0, HR = (hs & 2) ? H : 0;
+    const int W = 64 - HL - HR;
+    const int rel = lane - HL;
+    int col[TPW];
+    bool out[TPW];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+      const int xo = x0 + tt * W;  // first output column of the tile
+      int c = (xo + rel) % nx;
+      if (c < 0) c += nx;
+      col[tt] = c;
+      out[tt] = rel >= 0 && rel < W && xo + rel < nx;
+    }
+    const size_t plane = (size_t)nt * nx;
+    const int n_rows = sd->n;
+    const int row_off = sd->row_off;
+    const int g_lo = sd->g_lo;
+    KGlob<const double> *src = as_glob((n0 == 0) ? I->u0 + (size_t)g_lo * nx
+                                                 : I->U[src_par] + (size_t)row_off * nx);
+    KGlob<double> *dst = as_glob(I->U[src_par ^ 1] + (size_t)row_off * nx);
+    KGlob<const double> *fr = as_glob(I->f + (size_t)g_lo * nx);
+    KGlob<const double> *lin = as_glob((const double *)I->lam[par]);
+    KGlob<double> *Vbase = as_glob(I->V);
+    const double rr = I->r;
+    const bool robin = I->tr == 1;
+    const int P = sd->P;
+    const int pad = sd->pad;
+    const bool active = v < P;
+    const bool last = v == P - 1;
+    const int k0 = last ? pad : 0;             // first real row in this wave's registers
+    const int base = v * SEG - (last ? pad : 0);  // local row of register 0
+    const int vsplit = sd->vsplit - base;      // registers >= vsplit have v >= 0
+    const int dir = vsplit <= 0 ? DIR_LO : (vsplit >= SEG ? DIR_UP : DIR_MIX);
+    const int lo_kind = sd->lo_kind, hi_kind = sd->hi_kind;
+    const int lam_lo = sd->lam_lo, lam_hi = sd->lam_hi;
+    const int out_hi_plane = sd->out_hi_plane, out_hi_row = sd->out_hi_row;
+    const int out_lo_plane = sd->out_lo_plane, out_lo_row = sd->out_lo_row;
+    const bool lo_end = active && v == 0 && lo_kind != END_PHYS;
+    const bool hi_end = active && last && hi_kind != END_PHYS;
+    // staging (each wave its own rows, factors and boundary data: written and
+    // read by the same wave; the zeroed reduced-system slots of unused
+    // segments are first read after the first step's barrier)
+    const MarchCoef *mc = sh_mc[v];
+    {
+      // a wave without rows (v >= P) runs the same steps on zero rows and
+      // zero state: its results stay zero and are never stored
+      KGlob<const double> *ct = as_glob((const double *)(t.mrows + sd->tab + v * SEG));
+      double *cs = reinterpret_cast<double *>(sh_mc[v]);
+      constexpr int NDB = (int)(sizeof(MarchCoef) / sizeof(double));
+#pragma unroll
+      for (int e0 = 0; e0 < SEG * NDB; e0 += 64) {
+        if (e0 + lane < SEG * NDB) {
+          double c = 0.0;
+          if (active) c = ct[e0 + lane];  // rows past the subdomain's table are not read
+          cs[e0 + lane] = c;
+        }
+      }
+      KGlob<const double> *gt = as_glob(I->g);
+      if (lane < steps) sh_g[v][lane] = gt[n0 + lane];
+    }
+    if (active) {
+#pragma unroll
+      for (int tt = 0; tt < TPW; ++tt) {
+        if (lo_end) {
+          KGlob<const double> *p = lin + (size_t)lam_lo * plane + col[tt];
+          for (int s = 0; s < steps; ++s) sh_bd[0][s][tt][lane] = p[(size_t)(n0 + s) * nx];
+        }
+        if (hi_end) {
+          KGlob<const double> *p = lin + (size_t)lam_hi * plane + col[tt];
+          for (int s = 0; s < steps; ++s) sh_bd[1][s][tt][lane] = p[(size_t)(n0 + s) * nx];
+        }
+      }
+    }
+    // the reduced inverse, row v staged by the wave of segment v (the wave
+    // of segment v reads rows v - 1 and v: separators v - 1 and v); the
+    // separator coefficient ra_v and rc_{v-1}
+    double ra_s = 0.0, rc_s = 0.0;
+    if (P > 1) {
+      const int m = P - 1;
+      KGlob<const double> *rv = as_glob(t.rinv + sd->rinv);
+      if (lane < NR) {
+        double e = 0.0;
+        if (v < m && lane < m) e = rv[(size_t)v * m + lane];
+        sh_ri[lane][v + 1] = e;
+        if (v == 0) sh_ri[lane][0] = 0.0;
+      }
+    }
+    if (P > 1 && active) {
+      const int m = P - 1;
+      KGlob<const double> *rt = as_glob((const double *)(t.reds + sd->red));
+      constexpr int NRW = (int)(sizeof(RedCoef) / sizeof(double));
+      if (v < m) ra_s = rt[(size_t)v * NRW + 0];
+      if (v > 0) rc_s = rt[(size_t)(v - 1) * NRW + 1];
+    }
+    ra_s = wave_uniform(ra_s);
+    rc_s = wave_uniform(rc_s);
+    // weight of the incoming trace in an end row: 1 (a Robin row), 2 dt / h_v
+    // (half-cell row), r (next to a fixed node)
+    const double rfv = 2.0 * rr * I->hv;
+    auto end_w = [&](int kind) {
+      return kind == END_ROBIN ? 1.0 : (kind == END_RFV ? rfv : rr);
+    };
+    const double lo_scale = wave_uniform(lo_end ? mc[k0].fab * end_w(lo_kind) : 0.0);
+    const double hi_scale = wave_uniform(hi_end ? mc[SEG - 1].fab * end_w(hi_kind) : 0.0);
+    // the item's march, one copy per upwind direction of the wave's rows
+    // (loads, steps, stores: the state's registers are assigned within one
+    // copy), with no branch on the wave's rows in the step loop (a wave
+    // without rows steps zeros)
+    auto march_steps = [&](auto dirc) {
+      constexpr int DIR = decltype(dirc)::value;
+      // (row pointers are wave-uniform: each load is a scalar base plus the
+      // lane's 32-bit column offset, so no 64-bit address per row is held)
+      ColRegs<SEG> d[TPW], fs[TPW];
+      static_for<0, SEG>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int r = max(base + k, 0);
+        const double fa = mc[k].fa;
+        KGlob<const double> *srow = src + (size_t)r * nx;
+        KGlob<const double> *frow = fr + (size_t)r * nx;
+  #pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+          double u = 0.0, fv = 0.0;
+          if (active) {  // a wave without rows reads nothing
+            u = srow[(unsigned)col[tt]];
+            fv = fa * frow[(unsigned)col[tt]];
+          }
+          d[tt].template st<k>(u);
+          fs[tt].template st<k>(fv);
+        }
+      });
+      // value of local row R of every tile to p[tt]: the register is selected
+      // with wave-uniform branches (no run-time register index)
+      auto put_row = [&](int R, KGlob<double> *p) {
+        const int r = R - base;
+        if (r >= k0 && r < SEG) {
+          static_for<0, SEG>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if (r == k) {
+  #pragma unroll
+              for (int tt = 0; tt < TPW; ++tt)
+                if (out[tt]) p[(unsigned)col[tt]] = d[tt].template ld<k>();
+            }
+          });
+        }
+      };
+      for (int s = 0; s < steps; ++s) {
+        const int n = n0 + s;
+        // re-derived each step, so that tests built on them are not kept as
+        // per-row masks across the loop
+        int vs = vsplit, Pq = P;
+        asm volatile("" : "+s"(vs), "+s"(Pq));
+        const double gn = wave_uniform(sh_g[v][s]);
+        double y[TPW], bh[TPW];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+          y[tt] = lo_end ? lo_scale * sh_bd[0][s][tt][lane] : 0.0;
+          bh[tt] = hi_end ? hi_scale * sh_bd[1][s][tt][lane] : 0.0;
+        }
+        // transport + source + forward elimination, one pass.  The
+        // coefficients of row k+2 are read before row k is computed, and the
+        // scheduling barrier keeps the reads in that order (LDS reads return
+        // in order: each wait overlaps two rows of arithmetic, and no more
+        // rows' coefficients than that are held in registers)
+        double2 ab0 = *(const double2 *)&mc[0].alpha, ab1 = *(const double2 *)&mc[1].alpha;
+        double fb0 = mc[0].fb, fb1 = mc[1].fb;
+        static_for<0, SEG>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double al = ab0.x, be = ab0.y, fb = fb0;
+          ab0 = ab1;
+          fb0 = fb1;
+          if constexpr (k + 2 < SEG) {
+            ab1 = *(const double2 *)&mc[k + 2].alpha;
+            fb1 = mc[k + 2].fb;
+          }
+          __builtin_amdgcn_sched_barrier(KFP_FD_SCHED);
+#pragma unroll
+          for (int tt = 0; tt < TPW; ++tt) {
+            const double u = d[tt].template ld<k>();
+            double nb;
+            if constexpr (DIR == DIR_LO) {
+              nb = from_lower_lane(u);
+            } else if constexpr (DIR == DIR_UP) {
+              nb = from_upper_lane(u);
+            } else {
+              const double a = from_lower_lane(u), c = from_upper_lane(u);
+              nb = (k >= vs) ? a : c;
+            }
+            double tk = fma(al, u, fma(be, nb, gn * fs[tt].template ld<k>()));
+            if constexpr (k == SEG - 1) tk += bh[tt];
+            y[tt] = fma(fb, y[tt], tk);
+            d[tt].template st<k>(y[tt]);
+          }
+        });
+        // back substitution
+        double x[TPW];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) x[tt] = d[tt].template ld<SEG - 1>();
+        double bc0 = mc[SEG - 2].bc, bc1 = mc[SEG > 2 ? SEG - 3 : 0].bc;
+        static_for<0, SEG - 1>([&](auto kc) {
+          constexpr int k = SEG - 2 - decltype(kc)::value;
+          const double bc = bc0;
+          bc0 = bc1;
+          if constexpr (k - 2 >= 0) bc1 = mc[k - 2].bc;
+          __builtin_amdgcn_sched_barrier(KFP_FD_SCHED);
+#pragma unroll
+          for (int tt = 0; tt < TPW; ++tt) {
+            x[tt] = fma(bc, x[tt], d[tt].template ld<k>());
+            d[tt].template st<k>(x[tt]);
+          }
+        });
+        // reduced separator system
+        double xlo[TPW], xhi[TPW];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) xlo[tt] = xhi[tt] = 0.0;
+        if (Pq > 1) {
+#pragma unroll
+          for (int tt = 0; tt < TPW; ++tt) {
+            sh_EF[s & 1][v][tt][lane].x =
+                last ? 0.0
+                     : fma(-ra_s, d[tt].template ld<SEG - 2>(), d[tt].template ld<SEG - 1>());
+            if (v > 0) sh_EF[s & 1][v - 1][tt][lane].y = -rc_s * d[tt].template ld<0>();
+          }
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            const double rl = sh_ri[q][v], rh = sh_ri[q][v + 1];
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) {
+              const double2 ef = sh_EF[s & 1][q][tt][lane];
+              const double D = ef.x + ef.y;
+              xlo[tt] = fma(rl, D, xlo[tt]);
+              xhi[tt] = fma(rh, D, xhi[tt]);
+            }
+          }
+        }
+        // spike correction; a non-final segment's last register is its separator
+        double2 sp0 = *(const double2 *)&mc[0].sl, sp1 = *(const double2 *)&mc[1].sl;
+        static_for<0, SEG>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double sl = sp0.x, sr = sp0.y;
+          sp0 = sp1;
+          if constexpr (k + 2 < SEG) sp1 = *(const double2 *)&mc[k + 2].sl;
+          __builtin_amdgcn_sched_barrier(KFP_FD_SCHED);
+#pragma unroll
+          for (int tt = 0; tt < TPW; ++tt)
+            d[tt].template st<k>(fma(-sl, xlo[tt], fma(-sr, xhi[tt], d[tt].template ld<k>())));
+        });
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt)
+          d[tt].template st<SEG - 1>(last ? d[tt].template ld<SEG - 1>() : xhi[tt]);
+        // interface-node values of level n+1
+        const size_t lvl = (size_t)n * nx;
+        if (out_hi_plane >= 0) {
+          KGlob<double> *Vj = Vbase + (size_t)(out_hi_plane >> 1) * 6 * plane + lvl;
+          put_row(out_hi_row, Vj + V_A_LO * plane);
+          if (robin) {
+            put_row(out_hi_row + 1, Vj + V_A1_LO * plane);
+            put_row(n_rows - 1, Vj + V_B_LO * plane);
+          }
+        }
+        if (out_lo_plane >= 0) {
+          KGlob<double> *Vj = Vbase + (size_t)((out_lo_plane - 1) >> 1) * 6 * plane + lvl;
+          put_row(out_lo_row, Vj + V_B_HI * plane);
+          if (robin) {
+            put_row(out_lo_row - 1, Vj + V_B1_HI * plane);
+            put_row(0, Vj + V_A_HI * plane);
+          }
+        }
+      }
+      // the next item restages the tables and reuses the slots
+      if (P > 1) __syncthreads();
+      if (active) {
+        // addresses formed anew: offsets kept from the loads before the loop
+        // would hold registers across it
+        int nxs = nx;
+        asm volatile("" : "+s"(nxs));
+  #pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) asm volatile("" : "+v"(col[tt]));
+        static_for<0, SEG>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          if (k >= k0) {
+            KGlob<double> *drow = dst + (size_t)(base + k) * nxs;
+  #pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+              if (out[tt]) drow[(unsigned)col[tt]] = d[tt].template ld<k>();
+          }
+        });
+      }
+    };
+    if (dir == DIR_LO)
+      march_steps(std::integral_constant<int, DIR_LO>{});
+    else if (dir == DIR_UP)
+      march_steps(std::integral_constant<int, DIR_UP>{});
+    else
+      march_steps(std::integral_constant<int, DIR_MIX>{});
   }
 }
 
@@ -1384,6 +1779,9 @@ bool march_config_supported(int waves, int groups, int seg_max) {
   return false;
 }
 
+static int device_cus();
+int device_cu_count() { return device_cus(); }
+
 static int device_cus() {
   static int cus = 0;
   if (cus == 0) {
@@ -1398,8 +1796,51 @@ static int device_cus() {
   return cus;
 }
 
-hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int n0, int S,
-                        int H, int src, int par, int grid, hipStream_t s) {
+// (waves, seg_max, tiles per wavefront) of the multi-tile finite-difference
+// march, built for up to 256 registers (one 8-wave workgroup per compute
+// unit); the one-tile builds of at most 17 rows also for 128 registers (two
+// workgroups per compute unit), which launches with two or more work items
+// per compute unit run
+#define KFP_FD_CONFIGS(X) \
+  X(8, 17, 2) X(8, 17, 1) X(8, 12, 2) X(8, 12, 1) X(8, 24, 1) X(8, 33, 1) \
+  X(4, 20, 2) X(4, 20, 1) X(4, 12, 2) X(4, 8, 2)
+
+bool fd_config_supported(int waves, int seg_max, int tiles) {
+#define KFP_CHECK(W, S, T) \
+  if (waves == W && seg_max == S && tiles == T) return true;
+  KFP_FD_CONFIGS(KFP_CHECK)
+#undef KFP_CHECK
+  return false;
+}
+
+static hipError_t launch_march_fd(const StepTables &t, int waves, int seg_max, int tiles, int n0,
+                                  int S, int H, int src, int par, int grid, hipStream_t s) {
+  if (t.fem || S < 1 || S > kMaxStepsFd || H < 1 || 2 * H >= 64) return hipErrorInvalidValue;
+  if (tiles == 1 && waves == 8 && (seg_max == 17 || seg_max == 12) && grid >= 2 * device_cus()) {
+    if (seg_max == 17)
+      hipLaunchKernelGGL((march_fd_kernel<17, 8, 1, 4>), dim3(grid), dim3(512), 0, s, t, n0, S, H,
+                         src, par);
+    else
+      hipLaunchKernelGGL((march_fd_kernel<12, 8, 1, 4>), dim3(grid), dim3(512), 0, s, t, n0, S, H,
+                         src, par);
+    return hipGetLastError();
+  }
+#define KFP_LAUNCH(W, SM, T)                                                               \
+  if (waves == W && seg_max == SM && tiles == T) {                                        \
+    hipLaunchKernelGGL((march_fd_kernel<SM, W, T, 2>), dim3(grid), dim3(W * 64), 0, s, t, n0, \
+                       S, H, src, par);                                                   \
+    return hipGetLastError();                                                             \
+  }
+  KFP_FD_CONFIGS(KFP_LAUNCH)
+#undef KFP_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max, int tiles,
+                        int n0, int S, int H, int src, int par, int grid, hipStream_t s) {
+  if (tiles > 0)
+    return groups == 1 ? launch_march_fd(t, waves, seg_max, tiles, n0, S, H, src, par, grid, s)
+                       : hipErrorInvalidValue;
   if (groups < 1 || S < 1 || S > kMaxStepsPerLaunch || H < 1 || 2 * H * groups >= 64)
     return hipErrorInvalidValue;
   // 8 wavefronts of 17 rows (the 131-row subdomains of J = 8 on 1024 and

@@ -158,6 +158,14 @@ static kfp_status make_geo(const kfp_grid *g, int J, int o, int tr, double p, Ge
   return KFP_OK;
 }
 
+// Upwind sides of subdomain j's rows (SubDev::hsides): bit 0 a row with
+// v > 0, bit 1 a row with v < 0 (v_i = -1 + i h_v as in the tables).
+static int sub_hsides(const Geo &g, int j) {
+  const SubGeo &s = g.sub[j];
+  const double hv = 2.0 / g.nv;
+  return (-1.0 + (s.lo + s.n - 1) * hv > 0.0 ? 1 : 0) | (-1.0 + s.lo * hv < 0.0 ? 2 : 0);
+}
+
 // ---------------------------------------------------------- launch config --
 // steps == 0: the general one-step kernel (any segment length, traces fused
 // one level behind); steps >= 1: the register march kernel, `steps` time
@@ -167,9 +175,13 @@ struct Config {
   int seg = 0;
   int steps = 0;
   int groups = 1;  // march kernel: lane groups per wavefront (segments of 64/groups columns)
+  int tiles = 0;   // 1, 2: the finite-difference march kernel, x-tiles per wavefront
 };
 
 static bool config_supported(const Config &c) {
+  if (c.tiles != 0)
+    return c.tiles > 0 && c.groups == 1 && c.steps >= 1 && c.steps <= 16 &&
+           fd_config_supported(c.waves, c.seg, c.tiles);
   if (c.steps == 0) return c.groups == 1 && step_config_supported(c.waves, c.seg);
   return c.steps >= 1 && c.steps <= 24 && 2 * c.steps * c.groups < 64 &&
          march_config_supported(c.waves, c.groups, c.seg);
@@ -243,6 +255,27 @@ static Config default_march(int n_max, long items8 = 0) {
   return Config{};
 }
 
+// Built-in choice of the multi-tile finite-difference march: the smallest
+// compiled segment that holds the subdomain on 8 wavefronts (4 for
+// subdomains of at most 48 rows); one tile per wavefront at 12 steps per
+// launch when a launch holds two or more work items per compute unit (the
+// 128-register build: two workgroups per compute unit), otherwise two tiles
+// at 16 steps (half the work items, each with twice the columns per lane).
+// items1: work items of a launch with one tile at 12 steps (0: unknown, many).
+static Config default_fd(int n_max, long items1) {
+  const int waves = n_max <= 48 ? 4 : 8;
+  for (int sm = 2; sm <= 33; ++sm) {
+    if (!march_fits(n_max, waves, sm)) continue;
+    const bool t1 = fd_config_supported(waves, sm, 1), t2 = fd_config_supported(waves, sm, 2);
+    if (!t1 && !t2) continue;
+    const bool many = items1 == 0 || items1 >= 2L * device_cu_count();
+    if (t1 && (!t2 || (many && waves == 8 && (sm == 12 || sm == 17))))
+      return Config{waves, sm, 12, 1, 1};
+    return Config{waves, sm, 16, 1, 2};
+  }
+  return Config{};
+}
+
 static Config g_forced;  // waves == 0: automatic
 static int g_pipe = -1;  // pipelined iterations: -1 automatic, 0 off, F >= 2 in flight
 // Automatic overlap below this many work items per launch (half the compute
@@ -297,9 +330,10 @@ static std::map<std::string, Config> load_tune() {
     if (e == std::string::npos) break;
     std::string key = s.substr(pos + 1, e - pos - 1);
     Config c;
-    const int got = sscanf(s.c_str() + e + 1, " : [ %d , %d , %d , %d ]", &c.waves, &c.seg,
-                           &c.steps, &c.groups);
+    const int got = sscanf(s.c_str() + e + 1, " : [ %d , %d , %d , %d , %d ]", &c.waves,
+                           &c.seg, &c.steps, &c.groups, &c.tiles);
     if (got == 3) c.groups = 1;
+    if (got <= 4) c.tiles = 0;
     if (got >= 3 && config_supported(c)) out[key] = c;
     pos = e + 1;
   }
@@ -323,8 +357,9 @@ static void save_tune(const std::map<std::string, Config> &m) {
   fprintf(fp, "{\n");
   size_t i = 0;
   for (auto &kv : m)
-    fprintf(fp, "  \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves,
-            kv.second.seg, kv.second.steps, kv.second.groups, ++i < m.size() ? "," : "");
+    fprintf(fp, "  \"%s\": [%d, %d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves,
+            kv.second.seg, kv.second.steps, kv.second.groups, kv.second.tiles,
+            ++i < m.size() ? "," : "");
   fprintf(fp, "}\n");
   fclose(fp);
   rename(tmp.c_str(), path.c_str());
@@ -349,11 +384,16 @@ static std::string tune_key(const Geo &g) {
 
 static std::map<std::string, Config> *g_tune = nullptr;
 
+static long count_items(const Geo &g, const Config &c, int colour = -1);
+
 // order: the solve order the configuration will run in (1: red-black, which
 // needs a march configuration; a tuned one-step choice is then passed over).
 static Config choose_config(const Geo &g, int order = 0) {
   if (g_forced.waves > 0) {
     Config c = g_forced;
+    // the multi-tile kernel is finite differences with one segment per
+    // wavefront: otherwise the general march kernel of the same shape
+    if (c.tiles > 0 && (g.scheme == SCHEME_FEM || !march_fits(g.n_max, c.waves, c.seg))) c.tiles = 0;
     if (c.steps >= 1 && !march_fits(g.n_max, c.waves, c.seg, c.groups)) {
       const int sm = march_seg_for(g.n_max, c.waves, c.groups);
       if (sm) {
@@ -372,10 +412,23 @@ static Config choose_config(const Geo &g, int order = 0) {
   auto it = g_tune->find(tune_key(g));
   if (it != g_tune->end()) {
     const Config &c = it->second;
-    const bool usable = c.steps >= 1 ? march_fits(g.n_max, c.waves, c.seg, c.groups)
+    const bool usable = c.tiles > 0 ? g.scheme != SCHEME_FEM && march_fits(g.n_max, c.waves, c.seg)
+                        : c.steps >= 1 ? march_fits(g.n_max, c.waves, c.seg, c.groups)
                                      : (c.seg == 0 || segs_for(g.n_max, c.waves) <= c.seg) &&
                                            !(order == 1 && march_seg_for(g.n_max, 8, 4));
     if (usable) return c;
+  }
+  if (g.scheme == SCHEME_FD && g.J > 0 && g.nx > 0) {
+    Config probe = default_fd(g.n_max, 0);
+    if (probe.waves) {
+      probe.tiles = 1;
+      probe.steps = 12;
+      const long items1 = fd_config_supported(probe.waves, probe.seg, 1)
+                              ? count_items(g, probe, order == 1 ? 0 : -1)
+                              : 0;
+      const Config c = default_fd(g.n_max, items1 > 0 ? items1 : 1);
+      if (c.waves) return c;
+    }
   }
   if (g.J > 0 && g.nx > 0) {
     // overlapped iterations (see pipe_params) supply work items to spare:
@@ -514,6 +567,7 @@ static void add_subdomain(const Geo &g, int j, double p, double q, int waves, in
     int i = 0;
     while (i <= g.nv && -1.0 + i * hv < 0.0) ++i;
     d.vsplit = i - s.lo;
+    d.hsides = sub_hsides(g, j);
   }
   d.lam_lo = j > 0 ? 2 * (j - 1) : -1;
   d.lam_hi = j < g.J - 1 ? 2 * j + 1 : -1;
@@ -681,6 +735,7 @@ static SubDev sub_descriptor(const Geo &g, int j, int inst, int sub_base) {
     int i = 0;
     while (i <= g.nv && -1.0 + i * hv < 0.0) ++i;
     d.vsplit = i - s.lo;
+    d.hsides = sub_hsides(g, j);
   }
   d.lam_lo = j > 0 ? 2 * (j - 1) : -1;
   d.lam_hi = j < g.J - 1 ? 2 * j + 1 : -1;
@@ -774,8 +829,11 @@ static void add_subdomain_march(const Geo &g, int j, double p, double q, int seg
   for (int w = 0; w < P; ++w) {
     const int k0 = (w == P - 1) ? pad : 0;
     // padding rows: no transport, no source, multiplier 1 (they pass the
-    // elimination's starting value, the low boundary data, to row k0)
-    for (int k = 0; k < k0; ++k) mc[(size_t)w * seg + k].fb = 1.0;
+    // elimination's starting value, the low boundary data, to row k0); the
+    // back substitution copies row k0's value down into them (bc = 1: their
+    // forward values are zero in a last segment that is not the first), so
+    // that register 0 of every segment holds its first real row
+    for (int k = 0; k < k0; ++k) mc[(size_t)w * seg + k].fb = mc[(size_t)w * seg + k].bc = 1.0;
     for (int k = k0; k < seg; ++k) {
       const int i = w * seg + k - k0;  // local row
       MarchCoef &c = mc[(size_t)w * seg + k];
@@ -909,12 +967,36 @@ static int tile_width(const Config &c) {
   return c.steps >= 1 ? 64 / c.groups - 2 * halo_of(c) : 64;
 }
 
-static void make_items(const Geo &g, int sub_base, int width, std::vector<Item> &items) {
+// x-columns one work item of subdomain j covers: the finite-difference
+// kernel's tiles have the halo on the upwind sides only, `tiles` per item.
+static int item_width(const Geo &g, int j, const Config &c) {
+  if (c.tiles < 1) return tile_width(c);
+  const int hs = sub_hsides(g, j), H = halo_of(c);
+  return c.tiles * (64 - ((hs & 1) ? H : 0) - ((hs & 2) ? H : 0));
+}
+
+static void make_items(const Geo &g, int sub_base, const Config &c, std::vector<Item> &items) {
   // subdomain-fastest order: consecutive workgroups (and so the XCDs they are
   // dealt to round-robin) take different subdomains of the same x-range
-  const int tiles = (g.nx + width - 1) / width;
-  for (int x = 0; x < tiles; ++x)
-    for (int j = 0; j < g.J; ++j) items.push_back(Item{sub_base + j, x * width});
+  std::vector<int> width(g.J), tiles(g.J);
+  int tmax = 0;
+  for (int j = 0; j < g.J; ++j) {
+    width[j] = item_width(g, j, c);
+    tiles[j] = (g.nx + width[j] - 1) / width[j];
+    tmax = std::max(tmax, tiles[j]);
+  }
+  for (int x = 0; x < tmax; ++x)
+    for (int j = 0; j < g.J; ++j)
+      if (x < tiles[j]) items.push_back(Item{sub_base + j, x * width[j]});
+}
+
+// Work items of one instance (colour 0 / 1: those of the even / odd
+// subdomains only).
+static long count_items(const Geo &g, const Config &c, int colour) {
+  long n = 0;
+  for (int j = 0; j < g.J; ++j)
+    if (colour < 0 || (j & 1) == colour) n += (g.nx + item_width(g, j, c) - 1) / item_width(g, j, c);
+  return n;
 }
 
 static void make_ex(const Geo &g, int inst, std::vector<ExItem> &ex) {
@@ -1131,8 +1213,7 @@ static PipeParams pipe_params(const Geo &g, const Config &c, int order = 0) {
   PipeParams pp;
   if (g_pipe == 0 || c.steps < 1 || g.J < 2) return pp;
   const int L = (g.nt + c.steps - 1) / c.steps;
-  const long tiles = (g.nx + tile_width(c) - 1) / tile_width(c);
-  const long items = order == 1 ? (long)((g.J + 1) / 2) * tiles : (long)g.J * tiles;
+  const long items = order == 1 ? count_items(g, c, 0) : count_items(g, c);
   if (g_pipe < 0 && items >= (order == 1 ? kPipeTarget / 2 : kPipeItems)) return pp;
   long F = g_pipe > 0 ? g_pipe : (kPipeTarget + items - 1) / items;
   F = std::min<long>(F, L);
@@ -1281,12 +1362,12 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
       // red-black half-sweep slots: odd slots march the even subdomains,
       // even slots the odd ones
       std::vector<Item> all;
-      make_items(geo, sub_base, tile_width(pl.cfg), all);
+      make_items(geo, sub_base, pl.cfg, all);
       const int colour = (i & 1) ? 0 : 1;
       for (const Item &it : all)
         if (((it.sub - sub_base) & 1) == colour) h.items.push_back(it);
     } else {
-      make_items(geo, sub_base, tile_width(pl.cfg), h.items);
+      make_items(geo, sub_base, pl.cfg, h.items);
     }
     make_ex(geo, i, h.ex);
   }
@@ -1358,7 +1439,7 @@ static kfp_status launch_iteration_direct(const StepTables &t, int n_inst, const
     } else {
       const int L = march_launches(nt, cfg);
       for (int l = 0; l < L; ++l)
-        HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg),
+        HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, cfg.tiles, l * cfg.steps, cfg.steps, halo_of(cfg),
                              l & 1, par, grid, s));
     }
   }
@@ -1391,7 +1472,7 @@ static kfp_status launch_iteration_rb(const Plan &pl, hipStream_t s, int part = 
       // even subdomains, block l: reads only the traces of the previous
       // iteration and writes only even rows and value planes of block l
       if (tc[0].n_items > 0)
-        HIP_TRY(launch_march(tc[0], cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps,
+        HIP_TRY(launch_march(tc[0], cfg.waves, cfg.groups, cfg.seg, cfg.tiles, l * cfg.steps, cfg.steps,
                              halo_of(cfg), l & 1, 0, tc[0].n_items, s));
       HIP_TRY(hipEventRecord(pl.ev_mar, s));
       HIP_TRY(hipStreamWaitEvent(pl.cs3, pl.ev_mar, 0));
@@ -1401,7 +1482,7 @@ static kfp_status launch_iteration_rb(const Plan &pl, hipStream_t s, int part = 
       HIP_TRY(hipEventRecord(pl.ev_blk, pl.cs3));
       HIP_TRY(hipStreamWaitEvent(pl.cs2, pl.ev_blk, 0));
       if (tc[1].n_items > 0)
-        HIP_TRY(launch_march(tc[1], cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps,
+        HIP_TRY(launch_march(tc[1], cfg.waves, cfg.groups, cfg.seg, cfg.tiles, l * cfg.steps, cfg.steps,
                              halo_of(cfg), l & 1, 0, tc[1].n_items, pl.cs2));
     }
     HIP_TRY(hipEventRecord(pl.ev_join, pl.cs2));
@@ -1490,7 +1571,7 @@ static kfp_status launch_pipe_chunk(Plan &pl, bool timed) {
   const Config &c = pl.cfg;
   for (int l = 0; l < pl.G; ++l) {
     if (timed) HIP_TRY(hipEventRecord(pl.tev[2 * l], pl.cs));
-    HIP_TRY(launch_march(t, c.waves, c.groups, c.seg, 0, c.steps, halo_of(c), 0, 0, t.n_items, pl.cs));
+    HIP_TRY(launch_march(t, c.waves, c.groups, c.seg, c.tiles, 0, c.steps, halo_of(c), 0, 0, t.n_items, pl.cs));
     if (timed) HIP_TRY(hipEventRecord(pl.tev[2 * l + 1], pl.cs));
     HIP_TRY(launch_exchange(t, 0, c.steps, pl.cs));
     HIP_TRY(launch_pipe_tick(pl.ctl.p, pl.blk.p, pl.iter.p, pl.pres.p, pl.hist.p, pl.cs));
@@ -1791,7 +1872,7 @@ static kfp_status mono_solve_impl(const kfp_grid *g, const double *u0, const dou
   } else {
     const int L = march_launches(geo.nt, cfg);
     for (int l = 0; l < L; ++l)
-      HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
+      HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, cfg.tiles, l * cfg.steps, cfg.steps, halo_of(cfg), l & 1,
                            0, t.n_items, pl->cs));
   }
   double *Ufin = (march_launches(geo.nt, cfg) & 1) ? pl->U1.p : pl->U0.p;
@@ -1842,7 +1923,7 @@ static kfp_status mono_solve_static_impl(const kfp_grid *g, const double *u0, co
   if ((st = fem_needs_march(geo, cfg))) return st;
   HostTables h;
   add_instance_cfg(geo, 0.0, 0.0, cfg.waves, cfg.seg, cfg.steps, 0, h);
-  make_items(geo, 0, tile_width(cfg), h.items);
+  make_items(geo, 0, cfg, h.items);
   // the layout of the workspace: 256-byte aligned parts
   size_t used = 0;
   auto take = [&](size_t bytes) {
@@ -1928,7 +2009,7 @@ static kfp_status mono_solve_static_impl(const kfp_grid *g, const double *u0, co
   } else {
     const int L = march_launches(geo.nt, cfg);
     for (int l = 0; l < L; ++l)
-      HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, l * cfg.steps, cfg.steps,
+      HIP_TRY(launch_march(t, cfg.waves, cfg.groups, cfg.seg, cfg.tiles, l * cfg.steps, cfg.steps,
                            halo_of(cfg), l & 1, 0, t.n_items, stream));
   }
   const double *Ufin = (march_launches(geo.nt, cfg) & 1) ? in.U[1] : in.U[0];
@@ -1974,7 +2055,12 @@ static Config batch_config(int n_max) {
   snprintf(key, sizeof key, "%s/batch/nmax%d", arch_name().c_str(), n_max);
   auto it = g_tune->find(key);
   if (it != g_tune->end()) return it->second;
-  // a batch has many work items: the 8-step layout
+  // a batch has many work items: the multi-tile kernel with one tile for
+  // finite differences, the general march kernel's 8-step layout otherwise
+  if (g_scheme == SCHEME_FD) {
+    const Config c = default_fd(n_max, 0);
+    if (c.waves) return c;
+  }
   const Config c = default_march(n_max, 1L << 20);
   return c.waves ? c : default_config(n_max);
 }
@@ -2122,7 +2208,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       add_instance_cfg(geo, bi[i].p, bi[i].q, c.cfg.waves, c.cfg.seg, c.cfg.steps, i, c.h);
       make_ex(geo, i, c.h.ex);
       std::vector<Item> it;
-      make_items(geo, sub_base, tile_width(c.cfg), it);
+      make_items(geo, sub_base, c.cfg, it);
       for (const Item &x : it) {
         const long odd = order == 1 ? ((x.sub - sub_base) & 1) : 0;
         weighted.push_back({(long)c.h.subs[x.sub].n * geo.nt - (odd << 40), x});
@@ -2200,7 +2286,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
           const int grid = std::min(c.grid, tc[h].n_items);
           if (grid > 0)
             for (int l = 0; l < L; ++l)
-              HIP_TRY(launch_march(tc[h], c.cfg.waves, c.cfg.groups, c.cfg.seg, l * c.cfg.steps,
+              HIP_TRY(launch_march(tc[h], c.cfg.waves, c.cfg.groups, c.cfg.seg, c.cfg.tiles, l * c.cfg.steps,
                                    c.cfg.steps, halo_of(c.cfg), l & 1, 0, grid, s));
           HIP_TRY(launch_exchange(t, 0, c.cfg.steps, s, h + 1));
         }
@@ -2210,7 +2296,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
       } else {
         const int L = march_launches(c.nt_max, c.cfg);
         for (int l = 0; l < L; ++l)
-          HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.groups, c.cfg.seg, l * c.cfg.steps, c.cfg.steps,
+          HIP_TRY(launch_march(t, c.cfg.waves, c.cfg.groups, c.cfg.seg, c.cfg.tiles, l * c.cfg.steps, c.cfg.steps,
                                halo_of(c.cfg), l & 1, par, c.grid, s));
         HIP_TRY(launch_exchange(t, par, c.cfg.steps, s));
       }
@@ -2365,6 +2451,15 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
     if (sm)
       for (int k : {2, 3, 4, 6, 8}) cands.push_back(Config{8, sm, k, g});
   }
+  // the multi-tile finite-difference kernel (one segment per wavefront)
+  if (geo.scheme == SCHEME_FD)
+    for (int w : {4, 8})
+      for (int tl : {1, 2})
+        for (int sm = 2; sm <= 33; ++sm)
+          if (march_fits(geo.n_max, w, sm) && fd_config_supported(w, sm, tl)) {
+            for (int k : {4, 8, 12, 16}) cands.push_back(Config{w, sm, k, 1, tl});
+            break;
+          }
   {
     for (const Config &c : cands) {
       const int w = c.waves, sm = c.seg;
@@ -2382,7 +2477,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
           for (int n = 0; n < nsteps; ++n) HIP_TRY(launch_step(t, w, sm, n, 0, t.n_items, pl->cs));
         } else {
           for (int n = 0; n < nsteps; n += c.steps)
-            HIP_TRY(launch_march(t, w, c.groups, sm, n, c.steps, halo_of(c), (n / c.steps) & 1,
+            HIP_TRY(launch_march(t, w, c.groups, sm, c.tiles, n, c.steps, halo_of(c), (n / c.steps) & 1,
                                  0, t.n_items, pl->cs));
         }
         return KFP_OK;
@@ -2654,29 +2749,34 @@ kfp_status kfp_set_pipeline(int32_t inflight) {
   return KFP_OK;
 }
 
-kfp_status kfp_set_launch(int32_t waves, int32_t groups, int32_t seg_max, int32_t steps) {
+kfp_status kfp_set_launch_tiles(int32_t waves, int32_t groups, int32_t seg_max, int32_t steps,
+                                int32_t tiles) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   if (waves == 0) {
     g_forced = Config{};
     return KFP_OK;
   }
-  const Config c{waves, seg_max, steps, groups};
+  const Config c{waves, seg_max, steps, groups, tiles};
   if (!config_supported(c))
     return fail(KFP_EINVAL,
-                "configuration waves=%d groups=%d seg_max=%d steps=%d is not compiled", waves,
-                groups, seg_max, steps);
+                "configuration waves=%d groups=%d seg_max=%d steps=%d tiles=%d is not compiled",
+                waves, groups, seg_max, steps, tiles);
   g_forced = c;
   return KFP_OK;
+}
+
+kfp_status kfp_set_launch(int32_t waves, int32_t groups, int32_t seg_max, int32_t steps) {
+  return kfp_set_launch_tiles(waves, groups, seg_max, steps, 0);
 }
 
 kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps) {
   return kfp_set_launch(waves, 1, seg_max, steps);
 }
 
-kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
-                          int32_t *waves_out, int32_t *groups_out, int32_t *seg_max_out,
-                          int32_t *steps_out) {
+kfp_status kfp_get_launch_tiles(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                                int32_t *waves_out, int32_t *groups_out, int32_t *seg_max_out,
+                                int32_t *steps_out, int32_t *tiles_out) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   Geo geo;
@@ -2687,7 +2787,15 @@ kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t
   if (groups_out) *groups_out = c.groups;
   if (seg_max_out) *seg_max_out = c.seg;
   if (steps_out) *steps_out = c.steps;
+  if (tiles_out) *tiles_out = c.tiles;
   return KFP_OK;
+}
+
+kfp_status kfp_get_launch(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,
+                          int32_t *waves_out, int32_t *groups_out, int32_t *seg_max_out,
+                          int32_t *steps_out) {
+  return kfp_get_launch_tiles(g, J, overlap, tr, waves_out, groups_out, seg_max_out, steps_out,
+                              nullptr);
 }
 
 kfp_status kfp_get_config(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr,

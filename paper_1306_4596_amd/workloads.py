@@ -75,7 +75,7 @@ def run_large(iters: int, configs):
     for cfg in configs:
         if cfg is not None:
             kb.set_config(*cfg)
-        used = kb.get_config(nx, nv, nt, T, J, o, kb.ROBIN)
+        used = kb.get_launch_tiles(nx, nv, nt, T, J, o, kb.ROBIN)
         t0 = time.perf_counter()
         _, _, st = kb.swr_solve(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-300, max_iter=iters)
         torch.cuda.synchronize()
@@ -135,7 +135,8 @@ def main():
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
     ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
     ap.add_argument("--configs", nargs="*", default=[],
-                    help="launch configurations waves,seg,steps (default: the library's choice)")
+                    help="launch configurations waves,seg,steps[,groups[,tiles]] (default: "
+                         "the library's choice)")
     a = ap.parse_args()
     kb.load_library()
     _SCHEME[0] = kb.FEM if a.scheme == "fem" else kb.FD

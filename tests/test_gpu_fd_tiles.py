@@ -1,0 +1,165 @@
+"""GPU parity of the multi-tile finite-difference march kernel (tiles = 1 or
+2 x-tiles per wavefront, the halo on the upwind sides of each subdomain only)
+against the CPU oracle, through the C ABI.
+
+Fixed iteration counts: relative L2 <= 1e-12 on the output and the traces
+(the same arithmetic as the oracle up to the rounding order of the
+segment-partitioned elimination), residual histories at rtol 1e-9.  The
+shapes cover subdomains whose rows all have v < 0 or all v > 0 (one-sided
+halo) and subdomains across v = 0 (both sides), grids narrower than a tile,
+ragged last tiles, items whose second tile lies past the grid, padded last
+segments, single-segment subdomains and workgroups with idle wavefronts.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1306_4596_amd as kfp  # noqa: E402
+from paper_1306_4596_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+D, R = kfp.DIRICHLET, kfp.ROBIN
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(autouse=True)
+def _auto_config():
+    kfp.set_config(0)
+    kfp.set_pipeline(-1)
+    kfp.set_ordering(kfp.PARALLEL)
+    yield
+    kfp.set_config(0)
+    kfp.set_pipeline(-1)
+    kfp.set_ordering(kfp.PARALLEL)
+
+
+CASES = [
+    # nx, nv, nt, T, J, o, (waves, seg, steps, tiles)
+    (96, 128, 24, 0.2, 2, 2, (8, 17, 8, 2)),    # two subdomains across v = 0
+    (96, 128, 24, 0.2, 4, 2, (8, 17, 8, 2)),    # outer subdomains one-sided
+    (200, 128, 30, 0.1, 4, 3, (8, 17, 5, 2)),   # several items, ragged tail
+    (40, 128, 24, 0.2, 4, 2, (8, 17, 6, 2)),    # grid narrower than one tile
+    (5, 64, 10, 0.3, 2, 2, (8, 12, 3, 2)),      # five columns
+    (130, 256, 20, 0.1, 8, 2, (8, 12, 16, 2)),  # 16 steps, one-sided halo of 16
+    (130, 256, 20, 0.1, 8, 2, (8, 12, 16, 1)),
+    (96, 128, 24, 0.2, 4, 2, (8, 17, 8, 1)),
+    (300, 1024, 18, 0.02, 8, 2, (8, 17, 8, 2)),  # the 131-row subdomains of the benchmark
+    (300, 1024, 18, 0.02, 8, 2, (8, 17, 7, 1)),
+    (64, 96, 20, 0.2, 3, 1, (4, 20, 4, 2)),     # odd J: middle subdomain across v = 0
+    (64, 96, 20, 0.2, 3, 1, (4, 20, 9, 1)),
+    (80, 64, 20, 0.2, 4, 2, (4, 12, 4, 2)),     # 19-row subdomains: padded last segment
+    (80, 64, 20, 0.2, 8, 2, (4, 8, 2, 2)),      # 11 rows: two segments, idle wavefronts
+    (80, 32, 20, 0.2, 4, 2, (8, 12, 4, 2)),     # single-segment subdomains, 7 idle waves
+    (70, 512, 16, 0.05, 2, 2, (8, 33, 4, 1)),   # 33-row segments
+    (70, 368, 16, 0.05, 2, 2, (8, 24, 6, 1)),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("tr", [D, R])
+def test_multi_tile_march_matches_oracle(case, tr):
+    nx, nv, nt, T, J, o, (waves, seg, steps, tiles) = case
+    print(f"fd tiles nx={nx} nv={nv} J={J} o={o} cfg={(waves, seg, steps, tiles)} tr={tr}",
+          flush=True)
+    u0, f = inputs.random_fields(nx + 3 * nv + J, nx, nv)
+    s = 1.0 + 0.25 * np.cos(np.arange(nt + 1))
+    p = 4.0 if tr == R else 0.0
+    ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3, s=s)
+    kfp.set_config(waves, seg, steps, tiles=tiles)
+    got = kfp.get_launch_tiles(nx, nv, nt, T, J, o, tr)
+    assert got == (waves, seg, steps, 1, tiles)
+    kfp.set_pipeline(0)
+    uT, lam, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-300, max_iter=3,
+                                want_lambda=True, s=s)
+    assert rel(host(uT), ref.uT) <= 1e-12
+    assert rel(host(lam), ref.lam) <= 1e-12
+    assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("tiles", [1, 2])
+def test_multi_tile_converged_orders_and_overlap(tiles):
+    """Converged solves: parallel, overlapped (pipelined) and red-black
+    iterations, without overlap, two-sided Robin; the iteration counts and
+    the solution match the oracle."""
+    nx, nv, nt, T = 72, 96, 40, 0.2
+    u0, f = inputs.random_fields(77, nx, nv)
+    for J, o, tr, p, q, order, pipe in [(4, 2, R, 4.0, None, 0, 0), (4, 2, R, 4.0, None, 0, 3),
+                                        (4, 0, R, 3.0, None, 0, 0), (3, 2, R, 11.0, 2.5, 0, 0),
+                                        (4, 2, R, 4.0, None, 1, 0), (4, 3, D, 0.0, None, 1, 0),
+                                        (2, 4, D, 0.0, None, 0, 2)]:
+        print(f"converged tiles={tiles} J={J} o={o} tr={tr} order={order} pipe={pipe}",
+              flush=True)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, q=q, tol=1e-11, max_iter=400,
+                               order=order)
+        kfp.set_config(8, 17, 8, tiles=tiles)
+        kfp.set_ordering(order)
+        kfp.set_pipeline(pipe)
+        uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, q=q, tol=1e-11,
+                                  max_iter=400)
+        assert st.iters == ref.iters
+        assert rel(host(uT), ref.uT) <= 1e-10
+
+
+def test_multi_tile_batch_matches_single_solves():
+    specs = [
+        (64, 64, 40, 0.2, 2, 2, R, 4.0),
+        (128, 32, 40, 0.1, 4, 2, R, 2.0),
+        (96, 128, 40, 0.3, 8, 2, D, 0.0),
+        (200, 128, 40, 0.2, 4, 3, R, 8.0),
+        (256, 64, 40, 0.15, 1, 0, R, 1.0),
+    ]
+    insts, refs = [], []
+    kfp.set_config(8, 17, 8, tiles=2)
+    for i, (nx, nv, nt, T, J, o, tr, p) in enumerate(specs):
+        u0, f = inputs.random_fields(300 + i, nx, nv)
+        insts.append(dict(u0=dev(u0), f=dev(f), T=T, nt=nt, J=J, overlap=o, tr=tr, p=p,
+                          want_lambda=True))
+        refs.append(kfp.swr_solve(dev(u0), dev(f), T, nt, J, o, tr, p=p, tol=1e-11,
+                                  max_iter=400, want_lambda=True))
+    out, rc = kfp.swr_batch(insts, tol=1e-11, max_iter=400, history=True)
+    assert rc == 0
+    for (uT, lam, st), (ruT, rlam, rst) in zip(out, refs):
+        assert st.iters == rst.iters
+        assert torch.equal(uT, ruT)
+        if lam is not None:
+            assert torch.equal(lam, rlam)
+    for (nx, nv, nt, T, J, o, tr, p), (uT, _, st), i in zip(specs, out, range(len(specs))):
+        u0, f = inputs.random_fields(300 + i, nx, nv)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-11, max_iter=400)
+        assert st.iters == ref.iters
+        assert rel(host(uT), ref.uT) <= 1e-10
+
+
+def test_multi_tile_mono_and_finite_elements_fall_back():
+    """J = 1 (the monodomain) on the multi-tile kernel; a forced multi-tile
+    configuration runs the general march kernel for the finite-element
+    scheme."""
+    nx, nv, nt, T = 90, 128, 30, 0.2
+    u0, f = inputs.random_fields(5, nx, nv)
+    kfp.set_config(8, 17, 8, tiles=2)
+    out = host(kfp.mono_solve(dev(u0), dev(f), T, nt))
+    assert rel(out, oracle.mono_solve(u0, f, T, nt)) <= 1e-12
+    kfp.set_scheme(kfp.FEM)
+    try:
+        assert kfp.get_launch_tiles(nx, nv, nt, T, 4, 2, R)[4] == 0
+        uT, _, st = kfp.swr_solve(dev(u0), dev(f), T, nt, 4, 2, R, p=4.0, tol=1e-300,
+                                  max_iter=2)
+        ref = oracle.swr_solve(u0, f, T, nt, 4, 2, R, p=4.0, tol=1e-300, max_iter=2,
+                               scheme=oracle.FEM)
+        assert rel(host(uT), ref.uT) <= 1e-12
+    finally:
+        kfp.set_scheme(kfp.FD)
