@@ -1,125 +1,150 @@
 #!/usr/bin/env python3
 """Benchmark of the SWR hot path on one MI355X.
 
-Workload: x in [0,1) periodic with Nx = 1024, v in [-1,1] with Nv = 1024,
-T = 0.5, Nt = 2000, J = 8 equal v-subdomains, overlap 2 cells, Robin
-transmission; f and u0 each a sum of 16 Fourier x Legendre modes with N(0,1)
-coefficients from seed 0.  One step = one complete SWR solve to an absolute
-interface residual below 1e-10 (p = 8).  The p sweep {1, 2, 4, 8, 16} is
-reported beside the timed steps.
+Workload (the largest single-GPU shape): x in [0,1) periodic with
+Nx = 4096, v in [-1,1] with Nv = 4096, T = 1, Nt = 8192, J = 32 equal
+v-subdomains, overlap 2 cells, Robin transmission p = 8; f and u0 each a
+sum of 16 Fourier x Legendre modes with N(0,1) coefficients from seed 0
+(FP64).  One step = one SWR iteration: every subdomain marched over the
+whole window (transport, source, implicit v-diffusion), the interface
+traces exchanged and the residual (6.12) reduced.  K steps are one call
+with K iterations, from zero initial traces, inputs resident in HBM.
 
 Prints ONE JSON line.  `value` is subdomain cell-steps per second over the
-timed steps (inputs resident in HBM).  The roofline block is for the fused
-step kernel, timed live with HIP events on the stream it runs on: its
-achieved bandwidth counts the algorithmic 24 bytes of one time step of one
-cell (read U^n and f, write U^{n+1}, FP64) against the HBM peak, the measure
-a one-step-per-launch streaming kernel is held to.  The multi-step kernel
-moves fewer bytes than that (it keeps U in registers across the steps of a
-launch); `traffic` is the HBM rate its counters saw (bytes per launch from
-rocprofv3 FETCH_SIZE and WRITE_SIZE at the live launch duration), or null
-when the kernel sources differ from the ones those counters were taken on.
-The same solve in red-black order, on 4 time windows, and with the paper's
-own discretisation (linear finite elements, `finite_elements`) is reported
-beside it.  `--scheme fem` times the finite-element solve instead (for its
-kernel profile; the default line is the finite-difference one).
+timed iterations.  The roofline block is for the dominant kernel (the march
+kernel), its average launch duration timed live with HIP events on the
+stream its launches run on: `achieved` is the kernel's compulsory HBM bytes
+per launch (state in and out, the source rows, the incoming traces of the
+launch's levels, the interface-node values it writes) over that duration,
+against the 8 TB/s HBM peak; `traffic` is what the HBM counters saw per
+launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a copy kernel),
+null when the kernel sources differ from those the counters were taken on.
+Beside it: the FP64 rate of the same launches against the 78.6 TFLOP/s
+vector peak, the VALU-busy share of the counter profile, and the copy
+bandwidth the library's copy kernel reaches on this GPU.
+
+Also reported once, beside the timed iterations: the time to an absolute
+residual of 1e-10 in the parallel order from zero traces and in red-black
+order on 4 time windows (each from the extension of its start state); and
+the oracle on the host cores (a bounded sample of one iteration of the same
+shape, extrapolated).  `--scheme fem` times the paper's finite-element
+discretisation instead.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-NX = NV = 1024
-NT, T = 2000, 0.5
-J, OVERLAP, TR = 8, 2, 1
+NX = NV = 4096
+NT, T = 8192, 1.0
+J, OVERLAP, TR = 32, 2, 1
 P_MAIN = 8.0
-P_SWEEP = (1.0, 2.0, 4.0, 8.0, 16.0)
 TOL = 1e-10
 HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-BYTES_PER_CELL_STEP = 24.0  # one-step streaming: read U^n, read f, write U^{n+1} (FP64)
-# FP64 flops per cell-step of the fused step: transport + source (1 mul,
-# 2 fma), forward elimination (1 fma), back substitution (1 fma), segment
-# correction (2 fma) = 13 flops; the reduced separator system is not counted
+SIMDS, CLOCK_GHZ = 1024, 2.4  # 256 compute units x 4 SIMDs
+# FP64 flops per cell-step: transport + source (1 mul, 2 fma), forward
+# elimination (1 fma), back substitution (1 fma), segment correction (2 fma)
 FLOPS_PER_CELL_STEP = 13.0
-# HBM bytes per launch of the march kernel at this workload and launch
-# configuration (8 wavefronts x 17 rows, 16 steps per launch), from
-# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (separate runs, mean over
-# the 8125 dispatches of one solve), each scaled by what the counter reads
-# for the library's copy kernel of 1 GiB in the same process (FETCH_SIZE
-# 524311.38 KiB and WRITE_SIZE 1048576.0 KiB for 1 GiB read and written).
-# Valid only for the kernel sources they were measured on: any change to
-# them and `traffic` is reported as null.
-TRAFFIC = {
-    "config": (8, 17, 16),
-    "sha256": {
-        "paper_1306_4596_amd/csrc/swr_kernels.hip":
-            "1ae494e220af79c34d8d891d3c2baf7dffb2899712c34c24904a3d90276628b1",
-        "paper_1306_4596_amd/csrc/kfp_internal.h":
-            "f534f1f3eaa5537f508b214ee0120298026046655733756352f8c6a1ce030cb5",
-    },
-    "read_bytes": 9402.88 * 1024 * (1048576.0 / 524311.38),
-    "write_bytes": 13728.0 * 1024 * (1048576.0 / 1048576.0),
+# Counter profile of the march kernel at this workload (rocprofv3 --pmc,
+# one pass per counter set; profiles/march_kernel_4096x4096_J32_Nt8192.md):
+# HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by what
+# the counter reads for the library's copy kernel of a known size, and the
+# VALU instructions per launch.  Valid only for the kernel sources and
+# launch configuration they were measured on; otherwise reported as null.
+COUNTERS = {
+    "config": None,
+    "sha256": {},
+    "read_bytes": None,
+    "write_bytes": None,
+    "valu_insts": None,
 }
 
 
-def measured_traffic(config):
-    """HBM bytes per launch from the counters, or None when the kernel
-    sources or the launch configuration differ from the measured ones."""
-    import hashlib
-
-    if tuple(config) != TRAFFIC["config"]:
-        return None
-    for rel, digest in TRAFFIC["sha256"].items():
+def counters_valid(config):
+    if COUNTERS["config"] is None or tuple(config) != tuple(COUNTERS["config"]):
+        return False
+    for rel, digest in COUNTERS["sha256"].items():
         with open(os.path.join(ROOT, rel), "rb") as fp:
             if hashlib.sha256(fp.read()).hexdigest() != digest:
-                return None
-    return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
+                return False
+    return True
+
+
+def compulsory_bytes_per_launch(rows, steps):
+    """HBM bytes a launch of `steps` time steps cannot avoid: every unknown
+    row's state read and written once and its source row read once, the two
+    incoming trace planes of every interface at the launch's levels, and the
+    six interface-node values per interface and level it writes (Robin)."""
+    per_level = 2 * (J - 1) + 6 * (J - 1)
+    return 8.0 * NX * (3.0 * rows + per_level * steps)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--steps", type=int, default=20, help="timed SWR iterations")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed SWR iterations first")
+    ap.add_argument("--no-solves", action="store_true", help="skip the time-to-tolerance solves")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--scheme", choices=["fd", "fem"], default="fd",
-                    help="discretisation of the timed solves (default fd)")
-    ap.add_argument("--traffic-gb", type=float, default=None,  # overrides the measured bytes
-                    help="HBM bytes per step-kernel launch measured by counters (GB)")
-    ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="also run the library's plain copy kernel once over this many MiB "
-                         "(a known byte count to scale HBM counters by)")
+    ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
+    ap.add_argument("--copy-probe-mb", type=int, default=1024,
+                    help="size of the copy-kernel bandwidth probe (MiB)")
     return ap.parse_args()
 
 
-def cpu_baseline():
-    """The oracle, untuned, on the host cores: one SWR iteration of the same
-    1024 x 1024, J = 8, Robin shape over the first 1000 time steps (same dt)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fp:
+            for line in fp:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(gpu_iters):
+    """The oracle, as it stands, on the host cores: one SWR iteration of the
+    same shape over the first steps of the window (same dt), on all threads
+    and on one, extrapolated to a whole iteration and to the GPU's iteration
+    count to 1e-10."""
     import oracle
     from paper_1306_4596_amd import inputs
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    oracle.set_threads(threads)
-    nt_s = 1000
     u0, f = inputs.random_fields(0, NX, NV)
-    t0 = time.perf_counter()
-    oracle.swr_solve(u0, f, T * nt_s / NT, nt_s, J, OVERLAP, TR, p=P_MAIN, tol=1e-300,
-                     max_iter=1)
-    dt = time.perf_counter() - t0
     rows = (NV - 1) + (J - 1) * (OVERLAP + 1)
-    cells = float(nt_s) * NX * rows
-    return {"value": cells / dt, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 SWR iteration, 1024x1024, J=8, Robin p=8, first {nt_s} of 2000 steps "
-                      f"({cells:.3e} cell-steps, {dt:.1f} s)"}
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+
+    def run(nthreads, nt_s):
+        oracle.set_threads(nthreads)
+        t0 = time.perf_counter()
+        oracle.swr_solve(u0, f, T * nt_s / NT, nt_s, J, OVERLAP, TR, p=P_MAIN, tol=1e-300,
+                         max_iter=1)
+        dt = time.perf_counter() - t0
+        return float(nt_s) * NX * rows / dt, dt
+
+    rate, dt = run(threads, 96)
+    rate1, dt1 = run(1, 12)
+    oracle.set_threads(threads)
+    per_iter = float(NT) * NX * rows / rate
+    return {"value": rate, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 SWR iteration of 4096x4096 J=32 Robin p=8 over the first 96 of 8192 "
+                      f"steps on {threads} threads ({96 * NX * rows:.3e} cell-steps, {dt:.1f} s); "
+                      f"the same over 12 steps on 1 thread ({dt1:.1f} s)",
+            "one_core": {"value": rate1, "unit": "cell-steps/s", "cores": 1},
+            "cpu_model": cpu_model(), "compiler": "gcc -O3 -fopenmp",
+            "extrapolated_iteration_s": per_iter,
+            "extrapolated_time_to_tol_s": None if gpu_iters is None else per_iter * gpu_iters,
+            "extrapolated_with_iterations": gpu_iters}
 
 
 def main():
@@ -139,69 +164,71 @@ def main():
     u0, f = inputs.random_fields(0, NX, NV)
     U0 = torch.from_numpy(u0).to(dev)
     F = torch.from_numpy(f).to(dev)
+    del u0, f
     kfp.set_scheme(kfp.FEM if args.scheme == "fem" else kfp.FD)
     rows = kfp.subdomain_rows(NX, NV, NT, T, J, OVERLAP, TR)
-    waves, seg, kper = kfp.get_config(NX, NV, NT, T, J, OVERLAP, TR)
+    launch = kfp.get_launch_tiles(NX, NV, NT, T, J, OVERLAP, TR)  # waves, seg, steps, groups, tiles
 
-    def solve(p):
-        return kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=p, tol=TOL, max_iter=1000,
+    def iterate(k):
+        return kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=1e-300, max_iter=k,
                              history=False)
 
+    # the copy kernel's bandwidth on this GPU (read + write of the buffer)
+    copy_gbps = None
     if args.copy_probe_mb > 0:
         n = args.copy_probe_mb * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
+        kfp.bw_probe(a, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         nbytes = kfp.bw_probe(a, b)
+        e1.record()
         torch.cuda.synchronize()
-        print(f"copy probe: {nbytes} bytes read and written", file=sys.stderr, flush=True)
+        copy_gbps = 2.0 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
         del a, b
-    for _ in range(args.warmup):
-        solve(P_MAIN)
+    if args.warmup > 0:
+        iterate(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    cells = dev_s = step_s = 0.0
-    iters = []
-    for _ in range(args.steps):
-        _, _, st = solve(P_MAIN)
-        cells += st.cell_steps
-        dev_s += st.device_seconds
-        step_s += st.step_seconds
-        iters.append(st.iters)
-        if not st.residual < TOL:
-            raise SystemExit(f"solve did not converge: {st}")
+    _, _, st = iterate(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    value = cells / wall
-    # dominant kernel: the multi-step march kernel (steps per launch >= 1) or
-    # the one-step kernel; its average duration comes from the library's HIP
-    # events around the time-step graph of each iteration, on the stream the
-    # graphs run on (the residual reset inside it is a one-block kernel)
-    if kper >= 1:
-        launches = sum(iters) * (-(-NT // kper))
-        kname = "kfp::march_kernel"
-    else:
-        launches = sum(iters) * (NT + 1)
-        kname = "kfp::step_kernel"
-    avg_launch_s = step_s / launches
-    steps_launch = NT / (launches / sum(iters))
-    cells_launch = NX * rows * steps_launch
-    bytes_launch = BYTES_PER_CELL_STEP * cells_launch
-    achieved = bytes_launch / avg_launch_s / 1e9
-    alu = FLOPS_PER_CELL_STEP * cells_launch / avg_launch_s / 1e12
-    # traffic: the counters' HBM bytes per launch as a rate at the live
-    # launch duration (the unit of `achieved`)
-    tbytes = args.traffic_gb * 1e9 if args.traffic_gb else (
-        measured_traffic((waves, seg, kper)) if args.scheme == "fd" else None)
-    traffic = round(tbytes / avg_launch_s / 1e9, 1) if tbytes else None
+    if st.iters != args.steps:
+        raise SystemExit(f"expected {args.steps} iterations, ran {st.iters}")
+    value = st.cell_steps / wall
+    # the dominant kernel: its launches and their average duration come from
+    # the library's HIP events around the time-step graph of each iteration,
+    # on the stream the graphs run on
+    launches = st.step_launches
+    avg_launch_s = st.step_seconds / launches
+    steps_per_launch = NT * st.iters / launches
+    cells_launch = st.cell_steps / launches
+    alg_bytes = compulsory_bytes_per_launch(rows, steps_per_launch)
+    achieved = alg_bytes / avg_launch_s / 1e9
+    if achieved > HBM_PEAK_GBPS:
+        raise SystemExit(f"compulsory bytes above the HBM peak: {achieved:.0f} GB/s")
+    fp64 = FLOPS_PER_CELL_STEP * cells_launch / avg_launch_s / 1e12
+    have = counters_valid(launch) and args.scheme == "fd"
+    tbytes = (COUNTERS["read_bytes"] + COUNTERS["write_bytes"]) if have else None
+    valu_busy = (COUNTERS["valu_insts"] * 4.0 / (avg_launch_s * CLOCK_GHZ * 1e9 * SIMDS)
+                 if have else None)
+    kname = ("kfp::march_fd_kernel" if launch[4] > 0 else
+             ("kfp::march_kernel" if launch[2] >= 1 else "kfp::step_kernel"))
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": traffic, "traffic_bytes_per_launch": tbytes,
+            "traffic": round(tbytes / avg_launch_s / 1e9, 1) if tbytes else None,
+            "traffic_bytes_per_launch": tbytes,
+            "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "bytes_per_cell_step": BYTES_PER_CELL_STEP, "cell_steps_per_launch": cells_launch,
-            "alg_bytes_per_launch": bytes_launch,
-            "fp64_tflops": round(alu, 3), "fp64_frac": round(alu / FP64_PEAK_TFLOPS, 4),
+            "launches": launches, "steps_per_launch": round(steps_per_launch, 3),
+            "cell_steps_per_launch": cells_launch,
+            "copy_kernel_GBps": round(copy_gbps, 1) if copy_gbps else None,
+            "frac_of_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
+            "fp64_tflops": round(fp64, 3), "fp64_frac": round(fp64 / FP64_PEAK_TFLOPS, 4),
             "flops_per_cell_step": FLOPS_PER_CELL_STEP,
-            "exchange_share_of_device_time": round(1.0 - step_s / dev_s, 4) if dev_s else None}
+            "valu_busy": round(valu_busy, 4) if valu_busy else None,
+            "exchange_share_of_device_time": round(1.0 - st.step_seconds / st.device_seconds, 4)}
     out = {
         "metric": "subdomain cell-timesteps/sec",
         "value": value,
@@ -215,84 +242,40 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "SWR Kolmogorov 1024x1024 Nt=2000 T=0.5 J=8 overlap=2 Robin p=8 "
-                               "tol=1e-10, random Fourier-Legendre f,u0 seed 0",
-                   "nx": NX, "nv": NV, "nt": NT, "J": J, "overlap": OVERLAP, "p": P_MAIN,
-                   "tol": TOL, "waves": waves, "seg_max": seg, "steps_per_launch": kper,
-                   "scheme": "finite differences" if args.scheme == "fd" else
-                             "finite elements"},
-        "iters": iters,
-        "time_to_tol_s": wall / args.steps,
-        "effective_GBps": value * BYTES_PER_CELL_STEP / 1e9,
+        "config": {"workload": "SWR Kolmogorov 4096x4096 Nt=8192 T=1 J=32 overlap=2 Robin p=8, "
+                               "one SWR iteration per step, random Fourier-Legendre f,u0 seed 0",
+                   "nx": NX, "nv": NV, "nt": NT, "T": T, "J": J, "overlap": OVERLAP,
+                   "p": P_MAIN, "rows": rows,
+                   "launch": {"waves": launch[0], "seg_max": launch[1], "steps": launch[2],
+                              "groups": launch[3], "tiles": launch[4]},
+                   "scheme": "finite differences" if args.scheme == "fd" else "finite elements"},
+        "device_s_per_step": st.device_seconds / args.steps,
         "roofline": roof,
     }
-    if not args.no_sweep:
-        sweep = {}
-        for p in P_SWEEP:
-            t1 = time.perf_counter()
-            _, _, st = solve(p)
-            torch.cuda.synchronize()
-            sweep[str(p)] = {"iters": st.iters, "seconds": round(time.perf_counter() - t1, 4),
-                             "residual": st.residual}
-        out["p_sweep"] = sweep
-        # the same solve in red-black order (even subdomains, then odd ones
-        # with the traces just sent): about half the iterations; reported
-        # beside the parallel-order metric, not in it
+    gpu_iters = None
+    if not args.no_solves:
+        solves = {}
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, s0 = kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL, max_iter=1000,
+                                 history=False)
+        torch.cuda.synchronize()
+        gpu_iters = s0.iters
+        solves["parallel_zero"] = {"iters": s0.iters, "seconds": round(time.perf_counter() - t1, 3),
+                                   "residual": s0.residual}
         kfp.set_ordering(kfp.RED_BLACK)
-        solve(P_MAIN)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, _, st = solve(P_MAIN)
-        torch.cuda.synchronize()
-        out["red_black"] = {"iters": st.iters, "time_to_tol_s": round(time.perf_counter() - t1, 4),
-                            "residual": st.residual,
-                            "cell_steps_per_s": st.cell_steps / st.device_seconds}
-        kfp.set_ordering(kfp.PARALLEL)
-        # and on 4 time windows, each started from the extension of the
-        # glued state the window before ends with
-        kfp.swr_solve_windows(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL, max_iter=1000,
-                              n_windows=4, guess=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, its, st = kfp.swr_solve_windows(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL,
+        _, its, s1 = kfp.swr_solve_windows(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL,
                                            max_iter=1000, n_windows=4, guess=True)
         torch.cuda.synchronize()
-        out["time_windows"] = {"n_windows": 4, "iters": its,
-                               "time_to_tol_s": round(time.perf_counter() - t1, 4),
-                               "residual": st.residual,
-                               "cell_steps_per_s": st.cell_steps / st.device_seconds}
-        # the paper's own discretisation (Section 6.2: linear finite elements
-        # with the consistent mass matrix, Neumann ends, diffusion then
-        # transport), parallel and red-black order
-        if args.scheme == "fd":
-            kfp.set_scheme(kfp.FEM)
-            fem = {"rows": kfp.subdomain_rows(NX, NV, NT, T, J, OVERLAP, TR),
-                   "config": list(kfp.get_config(NX, NV, NT, T, J, OVERLAP, TR))}
-            for name, order in (("parallel", kfp.PARALLEL), ("red_black", kfp.RED_BLACK)):
-                kfp.set_ordering(order)
-                solve(P_MAIN)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                _, _, st = solve(P_MAIN)
-                torch.cuda.synchronize()
-                wall1 = time.perf_counter() - t1
-                kl = st.iters * (-(-NT // fem["config"][2]))
-                fem[name] = {"iters": st.iters, "time_to_tol_s": round(wall1, 4),
-                             "residual": st.residual, "cell_steps_per_s": st.cell_steps / wall1}
-                if order == kfp.PARALLEL:
-                    # the same roofline measure as the main line: 24 algorithmic
-                    # bytes per cell-step at the live launch duration
-                    launch_s = st.step_seconds / kl
-                    cl = NX * fem["rows"] * fem["config"][2]
-                    fem[name]["march_launch_us"] = round(launch_s * 1e6, 3)
-                    fem[name]["achieved_GBps"] = round(BYTES_PER_CELL_STEP * cl / launch_s / 1e9, 1)
-                    fem[name]["frac"] = round(BYTES_PER_CELL_STEP * cl / launch_s / 1e9
-                                              / HBM_PEAK_GBPS, 4)
-            kfp.set_ordering(kfp.PARALLEL)
-            kfp.set_scheme(kfp.FD)
-            out["finite_elements"] = fem
+        solves["red_black_4_windows_u0"] = {"iters": its,
+                                            "seconds": round(time.perf_counter() - t1, 3),
+                                            "residual": s1.residual}
+        kfp.set_ordering(kfp.PARALLEL)
+        out["time_to_tol"] = {"tol": TOL, **solves}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(gpu_iters)
     print(json.dumps(out))
 
 

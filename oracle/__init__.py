@@ -34,7 +34,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = f"{_LIB}.{os.getpid()}.tmp"  # one per process: concurrent builds do not mix
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+            ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
         )
         os.replace(tmp, _LIB)
     return _LIB

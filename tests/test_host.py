@@ -242,26 +242,35 @@ def test_partitioned_tables_solve_the_paper_matrix(lib, nx, nv, nt, T, J, o, tr,
         red_off += P - 1
 
 
-def test_bench_traffic_only_for_the_measured_kernel(tmp_path, monkeypatch):
-    """The roofline's counter traffic is reported only for the launch
-    configuration and kernel sources the counters were taken on."""
+def test_bench_counters_only_for_the_measured_kernel(tmp_path, monkeypatch):
+    """The roofline's counter figures (HBM traffic, VALU busy) are reported
+    only for the launch configuration and kernel sources the counters were
+    taken on; the compulsory-bytes model stays below the one-step streaming
+    bytes and grows with the steps of a launch."""
     import importlib
     import sys
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
     bench = importlib.import_module("bench")
-    assert bench.measured_traffic((1, 2, 3)) is None
-    got = bench.measured_traffic(bench.TRAFFIC["config"])
-    assert got is None or got == bench.TRAFFIC["read_bytes"] + bench.TRAFFIC["write_bytes"]
-    # a copy of the tree with one changed source byte reports nothing
-    for rel in bench.TRAFFIC["sha256"]:
-        src = os.path.join(root, rel)
-        dst = tmp_path / rel
-        dst.parent.mkdir(parents=True, exist_ok=True)
-        dst.write_bytes(open(src, "rb").read() + b" ")
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic(bench.TRAFFIC["config"]) is None
+    assert not bench.counters_valid((1, 2, 3, 1, 0))
+    cfg = bench.COUNTERS["config"]
+    if cfg is not None:
+        assert bench.counters_valid(cfg)
+        # a copy of the tree with one changed source byte reports nothing
+        for rel in bench.COUNTERS["sha256"]:
+            src = os.path.join(root, rel)
+            dst = tmp_path / rel
+            dst.parent.mkdir(parents=True, exist_ok=True)
+            dst.write_bytes(open(src, "rb").read() + b" ")
+        monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+        assert not bench.counters_valid(cfg)
+    rows = (bench.NV - 1) + (bench.J - 1) * (bench.OVERLAP + 1)
+    b12 = bench.compulsory_bytes_per_launch(rows, 12)
+    # state in and out plus the source: 24 bytes per cell once per launch
+    assert b12 > 24.0 * bench.NX * rows
+    assert b12 < 24.0 * bench.NX * rows * 12
+    assert bench.compulsory_bytes_per_launch(rows, 16) > b12
 
 
 def test_ordering_launch_and_window_arguments(lib):
