@@ -61,11 +61,19 @@ FLOPS_PER_CELL_STEP = 13.0
 # VALU instructions per launch.  Valid only for the kernel sources and
 # launch configuration they were measured on; otherwise reported as null.
 COUNTERS = {
-    "config": None,
-    "sha256": {},
-    "read_bytes": None,
-    "write_bytes": None,
-    "valu_insts": None,
+    "config": (8, 17, 12, 1, 1),  # waves, seg_max, steps, groups, tiles
+    "sha256": {
+        "paper_1306_4596_amd/csrc/swr_kernels.hip":
+            "c9fcf678102467fd386e5aee6772ac6c1c28bc9ed00eea5292c1ab0747aac7f6",
+        "paper_1306_4596_amd/csrc/kfp_internal.h":
+            "377909b348878a0016731dddcb594c302ce5fcad78a799486bec46768e69b477",
+    },
+    # mean over the 683 dispatches of one iteration: FETCH_SIZE 154958.93 KiB
+    # (x 1048576 / 524301.56, its reading for 1 GiB copied), WRITE_SIZE
+    # 205843.34 KiB (x 1048576 / 1048576.06)
+    "read_bytes": 154958.93475 * 1024 * (1048576.0 / 524301.5625),
+    "write_bytes": 205843.33579 * 1024 * (1048576.0 / 1048576.0625),
+    "valu_insts": 51296461.27,  # SQ_INSTS_VALU per dispatch (wave instructions)
 }
 
 

@@ -37,6 +37,7 @@ struct InstDev {
   int nonovl;                   // 1: no overlap (END_RFV interface rows)
   int xmode;                    // exchange mode when a launch leaves it to the instance
   int scheme;                   // 0 finite differences; 1 finite elements (FEM_* tables)
+  int gconst;                   // 1: g is the same at every level (s constant in time)
 };
 
 // Discretisations of the v-diffusion.  SCHEME_FD: finite differences, one

@@ -83,6 +83,7 @@ __device__ __forceinline__ InstDev load_inst(KConst<InstDev> *p) {
   I.nonovl = p->nonovl;
   I.xmode = p->xmode;
   I.scheme = p->scheme;
+  I.gconst = p->gconst;
   return I;
 }
 
@@ -1240,8 +1241,12 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_fd_kernel(StepTables t, in
     // (loads, steps, stores: the state's registers are assigned within one
     // copy), with no branch on the wave's rows in the step loop (a wave
     // without rows steps zeros)
-    auto march_steps = [&](auto dirc) {
+    // CG: the source factor g is the same at every level (s constant in
+    // time): the source rows are scaled by it once, at load, and the step
+    // adds them as they are (the same products, rounded the same way)
+    auto march_steps = [&](auto dirc, auto cgc) {
       constexpr int DIR = decltype(dirc)::value;
+      constexpr bool CG = decltype(cgc)::value;
       // (row pointers are wave-uniform: each load is a scalar base plus the
       // lane's 32-bit column offset, so no 64-bit address per row is held)
       ColRegs<SEG> d[TPW], fs[TPW];
@@ -1257,25 +1262,35 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_fd_kernel(StepTables t, in
           if (active) {  // a wave without rows reads nothing
             u = srow[(unsigned)col[tt]];
             fv = fa * frow[(unsigned)col[tt]];
+          if constexpr (CG) fv = sh_g[v][0] * fv;
           }
           d[tt].template st<k>(u);
           fs[tt].template st<k>(fv);
         }
       });
-      // value of local row R of every tile to p[tt]: the register is selected
-      // with wave-uniform branches (no run-time register index)
+        // value of local row R of every tile to p[tt]: the register is selected
+      // with wave-uniform branches (no run-time register index), searched in
+      // a window of six registers (interface rows lie near a segment's ends)
+      auto put_reg = [&](auto lo, auto hi, int r, KGlob<double> *p) {
+        static_for<decltype(lo)::value, decltype(hi)::value>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          if (r == k) {
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt)
+              if (out[tt]) p[(unsigned)col[tt]] = d[tt].template ld<k>();
+          }
+        });
+      };
       auto put_row = [&](int R, KGlob<double> *p) {
         const int r = R - base;
-        if (r >= k0 && r < SEG) {
-          static_for<0, SEG>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            if (r == k) {
-  #pragma unroll
-              for (int tt = 0; tt < TPW; ++tt)
-                if (out[tt]) p[(unsigned)col[tt]] = d[tt].template ld<k>();
-            }
-          });
-        }
+        constexpr int WL = SEG < 6 ? SEG : 6, WH = SEG - 6 > WL ? SEG - 6 : WL;
+        if (r < k0 || r >= SEG) return;
+        if (r < WL)
+          put_reg(std::integral_constant<int, 0>{}, std::integral_constant<int, WL>{}, r, p);
+        else if (r >= WH)
+          put_reg(std::integral_constant<int, WH>{}, std::integral_constant<int, SEG>{}, r, p);
+        else
+          put_reg(std::integral_constant<int, WL>{}, std::integral_constant<int, WH>{}, r, p);
       };
       for (int s = 0; s < steps; ++s) {
         const int n = n0 + s;
@@ -1319,7 +1334,8 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_fd_kernel(StepTables t, in
               const double a = from_lower_lane(u), c = from_upper_lane(u);
               nb = (k >= vs) ? a : c;
             }
-            double tk = fma(al, u, fma(be, nb, gn * fs[tt].template ld<k>()));
+            const double sk = CG ? fs[tt].template ld<k>() : gn * fs[tt].template ld<k>();
+            double tk = fma(al, u, fma(be, nb, sk));
             if constexpr (k == SEG - 1) tk += bh[tt];
             y[tt] = fma(fb, y[tt], tk);
             d[tt].template st<k>(y[tt]);
@@ -1421,12 +1437,25 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_fd_kernel(StepTables t, in
         });
       }
     };
-    if (dir == DIR_LO)
-      march_steps(std::integral_constant<int, DIR_LO>{});
-    else if (dir == DIR_UP)
-      march_steps(std::integral_constant<int, DIR_UP>{});
-    else
-      march_steps(std::integral_constant<int, DIR_MIX>{});
+    using CGT = std::true_type;
+    using CGF = std::false_type;
+    const bool cg = I->gconst != 0;
+    if (dir == DIR_LO) {
+      if (cg)
+        march_steps(std::integral_constant<int, DIR_LO>{}, CGT{});
+      else
+        march_steps(std::integral_constant<int, DIR_LO>{}, CGF{});
+    } else if (dir == DIR_UP) {
+      if (cg)
+        march_steps(std::integral_constant<int, DIR_UP>{}, CGT{});
+      else
+        march_steps(std::integral_constant<int, DIR_UP>{}, CGF{});
+    } else {
+      if (cg)
+        march_steps(std::integral_constant<int, DIR_MIX>{}, CGT{});
+      else
+        march_steps(std::integral_constant<int, DIR_MIX>{}, CGF{});
+    }
   }
 }
 

@@ -276,6 +276,13 @@ static Config default_fd(int n_max, long items1) {
   return Config{};
 }
 
+// 1 when the source factor g_n = dt s(t_{n+1}) is the same at every level.
+static int g_is_const(const std::vector<double> &gv) {
+  for (double x : gv)
+    if (x != gv[0]) return 0;
+  return 1;
+}
+
 static Config g_forced;  // waves == 0: automatic
 static int g_pipe = -1;  // pipelined iterations: -1 automatic, 0 off, F >= 2 in flight
 // Automatic overlap below this many work items per launch (half the compute
@@ -1401,6 +1408,7 @@ static kfp_status load_instance(Plan &pl, const double *u0, const double *f, con
   in.active = 1;
   std::vector<double> gv(geo.nt);
   for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
+  in.gconst = g_is_const(gv);
   HIP_TRY(hipMemcpyAsync(pl.g.p, gv.data(), sizeof(double) * geo.nt, hipMemcpyHostToDevice, pl.cs));
   std::vector<InstDev> ins(n_inst, in);
   if (pl.M > 0) {
@@ -1971,6 +1979,7 @@ static kfp_status mono_solve_static_impl(const kfp_grid *g, const double *u0, co
   in.active = 1;
   std::vector<double> gv(geo.nt);
   for (int n = 0; n < geo.nt; ++n) gv[n] = dt * (s ? s[n + 1] : 1.0);
+  in.gconst = g_is_const(gv);
   auto cp = [&](size_t o, const void *src, size_t bytes) {
     return bytes ? hipMemcpyAsync(at(o), src, bytes, hipMemcpyHostToDevice, stream) : hipSuccess;
   };
@@ -2183,6 +2192,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     d.tr = geo.tr;
     d.nonovl = geo.J > 1 && geo.o == 0 && geo.tr == KFP_ROBIN;
     d.scheme = geo.scheme;
+    d.gconst = g_is_const(gv);
     d.active = 1;
     if (b.win) {
       if (in[i].lambda_init) {
