@@ -207,6 +207,27 @@ kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, d
 kfp_status kfp_set_config(int32_t waves, int32_t seg_max, int32_t steps);
 
 /*
+ * kfp_tune_batch -- the launch classes of kfp_swr_batch, tuned.  A batch
+ * groups its instances by the height of their tallest subdomain (each
+ * height is one launch class with one configuration).  For every height
+ * among the n instances, every compiled march configuration that holds it
+ * is timed on the instances of that height (`iters` SWR iterations of
+ * kfp_swr_batch each, device time); the fastest is stored in the tuning
+ * cache under the batch key of that height (and the current
+ * discretisation), where later kfp_swr_batch calls look it up.  The
+ * instances' outputs are overwritten by the timed runs.  groups_out [host]:
+ * the number of heights tuned (may be NULL).  KFP_EINVAL for n < 1, a NULL
+ * array, iters < 1 or an invalid instance (as kfp_swr_batch).
+ * kfp_get_batch_launch -- the configuration kfp_swr_batch would run this
+ * instance's launch class with (tuned, forced or built-in).
+ */
+kfp_status kfp_tune_batch(int32_t n, const kfp_instance *inst, int32_t iters,
+                          int32_t *groups_out, void *stream);
+kfp_status kfp_get_batch_launch(const kfp_instance *inst, int32_t *waves_out,
+                                int32_t *groups_out, int32_t *seg_max_out, int32_t *steps_out,
+                                int32_t *tiles_out);
+
+/*
  * kfp_reload_tune_cache -- forgets the tuning choices held in memory; the
  * next solve re-reads the cache file ($KFP_TUNE_CACHE as it is then).  For a
  * caller that replaces or edits that file while the library is loaded.  A

@@ -24,6 +24,7 @@ from .binding import (  # noqa: F401
     column_stats,
     destandardize,
     get_config,
+    get_batch_launch,
     get_launch,
     get_launch_tiles,
     lib_path,
@@ -44,5 +45,6 @@ from .binding import (  # noqa: F401
     swr_solve,
     swr_solve_windows,
     tune,
+    tune_batch,
     u0_guess,
 )

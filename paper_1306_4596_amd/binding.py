@@ -105,6 +105,8 @@ def load_library():
     lib.kfp_set_config.argtypes = [i32, i32, i32]
     lib.kfp_set_launch.argtypes = [i32, i32, i32, i32]
     lib.kfp_set_launch_tiles.argtypes = [i32, i32, i32, i32, i32]
+    lib.kfp_tune_batch.argtypes = [i32, ctypes.POINTER(Instance), i32, pi, vp]
+    lib.kfp_get_batch_launch.argtypes = [ctypes.POINTER(Instance), pi, pi, pi, pi, pi]
     lib.kfp_get_launch_tiles.argtypes = [G, i32, i32, i32, pi, pi, pi, pi, pi]
     lib.kfp_get_launch.argtypes = [G, i32, i32, i32, pi, pi, pi, pi]
     lib.kfp_set_pipeline.argtypes = [i32]
@@ -121,7 +123,8 @@ def load_library():
                  "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
-                 "kfp_set_launch_tiles", "kfp_get_launch_tiles",
+                 "kfp_set_launch_tiles", "kfp_get_launch_tiles", "kfp_tune_batch",
+                 "kfp_get_batch_launch",
                  "kfp_set_ordering", "kfp_set_scheme", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -367,6 +370,62 @@ def swr_batch(instances, tol=1e-10, max_iter=200, history=False, stream=None):
         h = hists[i][: stats[i].iters].copy() if hists[i] is not None else None
         res.append((outs[i][0], outs[i][1], SWRStats(stats[i], h)))
     return res, rc
+
+
+def _instance_array(instances):
+    """The C instance array of swr_batch-style dicts (outputs allocated):
+    (array, buffers to keep alive, per-instance (uT, lambda or None))."""
+    import torch
+
+    n = len(instances)
+    arr = (Instance * n)()
+    keep, outs = [], []
+    for i, d in enumerate(instances):
+        u0, f = d["u0"], d["f"]
+        nt, J = int(d["nt"]), int(d["J"])
+        nv, nx = _check_fields(u0, f, nt, J, d.get("lambda_init"))
+        uT = torch.empty_like(u0)
+        lam = None
+        if d.get("want_lambda") and J > 1:
+            lam = torch.empty((2 * (J - 1), nt, nx), dtype=torch.float64, device=u0.device)
+        sarr, sp = _host_s(d.get("s"), nt)
+        keep.append(sarr)
+        arr[i].g = _grid(nx, nv, nt, d["T"])
+        arr[i].J = J
+        arr[i].overlap = int(d["overlap"])
+        arr[i].tr = int(d["tr"])
+        arr[i].p = float(d.get("p", 0.0))
+        arr[i].q = float(d["q"]) if d.get("q") is not None else 0.0
+        arr[i].u0 = _ptr(u0).value
+        arr[i].f = _ptr(f).value
+        arr[i].s = sp
+        li = d.get("lambda_init")
+        arr[i].lambda_init = _ptr(li).value if li is not None else None
+        arr[i].uT = _ptr(uT).value
+        arr[i].lambda_out = _ptr(lam).value if lam is not None else None
+        outs.append((uT, lam))
+    return arr, keep, outs
+
+
+def tune_batch(instances, iters=2, stream=None):
+    """Tunes the launch classes of swr_batch for these instances (one class
+    per subdomain height); caches the winners.  Returns the number of
+    heights tuned."""
+    arr, keep, outs = _instance_array(instances)
+    k = ctypes.c_int32()
+    _check(load_library().kfp_tune_batch(len(instances), arr, int(iters), ctypes.byref(k),
+                                         _stream(stream)))
+    return k.value
+
+
+def get_batch_launch(instance):
+    """(waves, seg_max, steps, groups, tiles) of the launch class swr_batch
+    would run this instance (a swr_batch-style dict) in."""
+    arr, keep, outs = _instance_array([instance])
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(load_library().kfp_get_batch_launch(arr, *[ctypes.byref(x) for x in v]))
+    w, g_, s, k, tl = (x.value for x in v)
+    return w, s, k, g_, tl
 
 
 def tune(nx, nv, nt, T, J, overlap, transmission, p=1.0, stream=None):

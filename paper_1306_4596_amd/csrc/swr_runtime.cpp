@@ -2050,6 +2050,25 @@ struct BatchClass {
   int n_red = 0;  // red-black order: the work items of even subdomains come first
 };
 
+static std::string batch_key(int n_max) {
+  char key[96];
+  snprintf(key, sizeof key, "%s/batch/nmax%d%s", arch_name().c_str(), n_max,
+           g_scheme == SCHEME_FEM ? "/fem" : "");
+  return key;
+}
+
+// A configuration the tuner is trying for the batch instances of one
+// height (kfp_tune_batch), ahead of the cache and the built-in choice.
+static std::map<int, Config> g_batch_try;
+
+// Can a batch class of subdomains of at most n_max rows run configuration c
+// in the current discretisation?
+static bool batch_usable(const Config &c, int n_max) {
+  if (!config_supported(c) || c.steps < 1) return false;
+  if (c.tiles > 0) return g_scheme == SCHEME_FD && march_fits(n_max, c.waves, c.seg);
+  return march_fits(n_max, c.waves, c.seg, c.groups);
+}
+
 static Config batch_config(int n_max) {
   if (g_forced.waves > 0) {
     Geo probe;
@@ -2057,13 +2076,14 @@ static Config batch_config(int n_max) {
     probe.n_max = n_max;
     probe.J = 0;
     probe.tr = -1;
+    probe.scheme = g_scheme;
     return choose_config(probe);
   }
+  auto tr = g_batch_try.find(n_max);
+  if (tr != g_batch_try.end()) return tr->second;
   if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
-  char key[96];
-  snprintf(key, sizeof key, "%s/batch/nmax%d", arch_name().c_str(), n_max);
-  auto it = g_tune->find(key);
-  if (it != g_tune->end()) return it->second;
+  auto it = g_tune->find(batch_key(n_max));
+  if (it != g_tune->end() && batch_usable(it->second, n_max)) return it->second;
   // a batch has many work items: the multi-tile kernel with one tile for
   // finite differences, the general march kernel's 8-step layout otherwise
   if (g_scheme == SCHEME_FD) {
@@ -2100,7 +2120,7 @@ static kfp_status swr_batch_impl(int n_inst, const kfp_instance *in, double tol,
     int k = 0;
     for (; k < (int)cls.size(); ++k)
       if (cls[k].cfg.waves == c.waves && cls[k].cfg.seg == c.seg && cls[k].cfg.steps == c.steps &&
-          cls[k].cfg.groups == c.groups)
+          cls[k].cfg.groups == c.groups && cls[k].cfg.tiles == c.tiles)
         break;
     if (k == (int)cls.size()) {
       cls.emplace_back();
@@ -2527,6 +2547,79 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
   return KFP_OK;
 }
 
+// Batch tuning: the instances are grouped by the height of their tallest
+// subdomain (the key of a batch launch class); for each height every
+// compiled march configuration that holds it is timed on the group's
+// instances (`iters` SWR iterations of kfp_swr_batch, device time) and the
+// fastest is stored under the batch key of that height.
+static kfp_status tune_batch_impl(int n, const kfp_instance *in, int iters, int *groups_out,
+                                  hipStream_t user) {
+  if (n < 1 || !in) return fail(KFP_EINVAL, "batch tuning needs n >= 1 instances");
+  if (iters < 1) return fail(KFP_EINVAL, "iters must be >= 1");
+  std::map<int, std::vector<int>> by_h;
+  for (int i = 0; i < n; ++i) {
+    Geo geo;
+    kfp_status st = make_geo(&in[i].g, in[i].J, in[i].overlap, in[i].tr, in[i].p, geo, g_scheme);
+    if (st) return fail(st, "instance %d: %s", i, g_err.c_str());
+    by_h[geo.n_max].push_back(i);
+  }
+  const Config saved = g_forced;
+  g_forced = Config{};
+  g_batch_try.clear();
+  struct Restore {
+    Config c;
+    ~Restore() {
+      g_forced = c;
+      g_batch_try.clear();
+    }
+  } restore{saved};
+  if (!g_tune) g_tune = new std::map<std::string, Config>(load_tune());
+  std::vector<kfp_swr_stats> stats(n);
+  for (auto &hv : by_h) {
+    const int n_max = hv.first;
+    std::vector<kfp_instance> sub;
+    for (int i : hv.second) sub.push_back(in[i]);
+    std::vector<Config> cands;
+    if (g_scheme == SCHEME_FD)
+      for (int w : {4, 8})
+        for (int tl : {1, 2})
+          for (int sm = 2; sm <= 33; ++sm)
+            if (march_fits(n_max, w, sm) && fd_config_supported(w, sm, tl)) {
+              for (int k : {8, 12, 16}) cands.push_back(Config{w, sm, k, 1, tl});
+              break;
+            }
+    for (int w : kWaves) {
+      const int sm = march_seg_for(n_max, w);
+      if (sm)
+        for (int k : {8, 16}) cands.push_back(Config{w, sm, k});
+    }
+    for (int g : {2, 4}) {
+      const int sm = march_seg_for(n_max, 8, g);
+      if (sm)
+        for (int k : {4, 6}) cands.push_back(Config{8, sm, k, g});
+    }
+    Config best;
+    double best_s = INFINITY;
+    for (const Config &c : cands) {
+      if (!batch_usable(c, n_max)) continue;
+      g_batch_try[n_max] = c;
+      for (auto &x : stats) x = kfp_swr_stats{};
+      kfp_status st = swr_batch_impl((int)sub.size(), sub.data(), 1e-300, iters, stats.data(), user);
+      if (st != KFP_OK && st != KFP_ENOCONV) return st;
+      g_err.clear();
+      if (stats[0].device_seconds < best_s) {
+        best_s = stats[0].device_seconds;
+        best = c;
+      }
+    }
+    g_batch_try.erase(n_max);
+    if (best.waves) (*g_tune)[batch_key(n_max)] = best;
+  }
+  save_tune(*g_tune);
+  if (groups_out) *groups_out = (int)by_h.size();
+  return KFP_OK;
+}
+
 }  // namespace kfp
 
 // ====================================================================== ABI ==
@@ -2717,6 +2810,31 @@ kfp_status kfp_tune(const kfp_grid *g, int32_t J, int32_t overlap, int32_t tr, d
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_err.clear();
   return tune_impl(g, J, overlap, tr, p, waves_out, seg_max_out, steps_out, (hipStream_t)stream);
+}
+
+kfp_status kfp_tune_batch(int32_t n, const kfp_instance *inst, int32_t iters,
+                          int32_t *groups_out, void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  return tune_batch_impl(n, inst, iters, groups_out, (hipStream_t)stream);
+}
+
+kfp_status kfp_get_batch_launch(const kfp_instance *inst, int32_t *waves_out,
+                                int32_t *groups_out, int32_t *seg_max_out, int32_t *steps_out,
+                                int32_t *tiles_out) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (!inst) return fail(KFP_EINVAL, "inst is NULL");
+  Geo geo;
+  kfp_status st = make_geo(&inst->g, inst->J, inst->overlap, inst->tr, inst->p, geo, g_scheme);
+  if (st) return st;
+  const Config c = batch_config(geo.n_max);
+  if (waves_out) *waves_out = c.waves;
+  if (groups_out) *groups_out = c.groups;
+  if (seg_max_out) *seg_max_out = c.seg;
+  if (steps_out) *steps_out = c.steps;
+  if (tiles_out) *tiles_out = c.tiles;
+  return KFP_OK;
 }
 
 kfp_status kfp_reload_tune_cache(void) {

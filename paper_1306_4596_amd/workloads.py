@@ -1,6 +1,6 @@
 """Throughput of the SWR path on the workloads beside the benchmark one.
 
-    python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1] [--scheme fd|fem]
+    python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1] [--scheme fd|fem] [--tune]
     python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8] [--scheme fd|fem]
     python -m paper_1306_4596_amd.workloads large-solve
 
@@ -34,7 +34,7 @@ def _scheme():
     return _SCHEME[0]
 
 
-def run_batch(n: int, reps: int = 2, order: int = 0):
+def run_batch(n: int, reps: int = 2, order: int = 0, tune: bool = False):
     import torch
 
     kb.set_ordering(order)
@@ -45,6 +45,12 @@ def run_batch(n: int, reps: int = 2, order: int = 0):
         insts.append(dict(u0=torch.from_numpy(u0).cuda(), f=torch.from_numpy(f).cuda(),
                           T=sp["T"], nt=sp["nt"], J=sp["J"], overlap=sp["overlap"], tr=kb.ROBIN,
                           p=sp["p"]))
+    if tune:
+        t0 = time.perf_counter()
+        heights = kb.tune_batch(insts, iters=2)
+        kb.reload_tune_cache()
+        print(json.dumps({"tuned_heights": heights, "tune_s": time.perf_counter() - t0}),
+              flush=True)
     for rep in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -53,7 +59,9 @@ def run_batch(n: int, reps: int = 2, order: int = 0):
         wall = time.perf_counter() - t0
         cells = sum(r[2].cell_steps for r in res)
         its = [r[2].iters for r in res]
+        classes = sorted(set(kb.get_batch_launch(d) for d in insts))
         print(json.dumps({"workload": f"batch of {n} uneven SWR instances", "order": order,
+                          "tuned": tune, "classes": classes,
                           "scheme": "fem" if kb.FEM == _scheme() else "fd",
                           "rep": rep, "status": rc,
                           "wall_s": wall, "device_s": res[0][2].device_seconds,
@@ -134,6 +142,9 @@ def main():
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
     ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch: tune its launch classes first (kfp_tune_batch; the cache is "
+                         "$KFP_TUNE_CACHE)")
     ap.add_argument("--configs", nargs="*", default=[],
                     help="launch configurations waves,seg,steps[,groups[,tiles]] (default: "
                          "the library's choice)")
@@ -142,7 +153,7 @@ def main():
     _SCHEME[0] = kb.FEM if a.scheme == "fem" else kb.FD
     kb.set_scheme(_SCHEME[0])
     if a.which == "batch":
-        run_batch(a.n, order=a.order)
+        run_batch(a.n, order=a.order, tune=a.tune)
     elif a.which == "large-solve":
         run_large_solve()
     else:

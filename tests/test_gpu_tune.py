@@ -84,3 +84,48 @@ def test_tuned_one_step_choice_is_passed_over_in_red_black_order(tmp_path, monke
         kfp.set_ordering(kfp.PARALLEL)
         monkeypatch.undo()
         kfp.reload_tune_cache()
+
+
+def test_batch_tuner_classes_are_used_by_the_batch(tmp_path, monkeypatch):
+    """kfp_tune_batch times the configurations of every subdomain height of a
+    batch and caches the winners; kfp_swr_batch then runs each launch class
+    in its tuned configuration, with results bit for bit those of single
+    solves in that configuration and matching the oracle."""
+    cache = tmp_path / "batch_tune.json"
+    monkeypatch.setenv("KFP_TUNE_CACHE", str(cache))
+    kfp.reload_tune_cache()
+    specs = [  # nx, nv, nt, T, J, o, tr, p: four subdomain heights
+        (64, 64, 40, 0.2, 2, 2, kfp.ROBIN, 4.0),
+        (128, 32, 40, 0.1, 4, 2, kfp.ROBIN, 2.0),
+        (96, 128, 40, 0.3, 8, 2, kfp.DIRICHLET, 0.0),
+        (200, 128, 40, 0.2, 4, 3, kfp.ROBIN, 8.0),
+        (80, 64, 40, 0.2, 2, 2, kfp.ROBIN, 3.0),
+    ]
+    insts = []
+    for i, (nx, nv, nt, T, J, o, tr, p) in enumerate(specs):
+        u0, f = inputs.random_fields(500 + i, nx, nv)
+        insts.append(dict(u0=torch.from_numpy(u0).cuda(), f=torch.from_numpy(f).cuda(), T=T,
+                          nt=nt, J=J, overlap=o, tr=tr, p=p, want_lambda=True))
+    print("tuning the batch", flush=True)
+    assert kfp.tune_batch(insts, iters=2) == 4
+    kfp.reload_tune_cache()
+    table = json.load(open(cache))
+    batch_keys = [k for k in table if "/batch/nmax" in k]
+    assert len(batch_keys) == 4, table
+    out, rc = kfp.swr_batch(insts, tol=1e-11, max_iter=400)
+    assert rc == 0
+    for i, ((nx, nv, nt, T, J, o, tr, p), (uT, lam, st)) in enumerate(zip(specs, out)):
+        w, seg, k, g, tl = kfp.get_batch_launch(insts[i])
+        # the class configuration is one of the tuned entries
+        assert [w, seg, k, g, tl] in [table[key] for key in batch_keys]
+        kfp.set_config(w, seg, k, groups=g, tiles=tl)
+        ruT, rlam, rst = kfp.swr_solve(insts[i]["u0"], insts[i]["f"], T, nt, J, o, tr, p=p,
+                                       tol=1e-11, max_iter=400, want_lambda=True)
+        kfp.set_config(0)
+        assert st.iters == rst.iters
+        assert torch.equal(uT, ruT)
+        u0, f = inputs.random_fields(500 + i, nx, nv)
+        ref = oracle.swr_solve(u0, f, T, nt, J, o, tr, p=p, tol=1e-11, max_iter=400)
+        assert st.iters == ref.iters
+        assert rel(uT.cpu().numpy(), ref.uT) <= 1e-10
+    kfp.reload_tune_cache()
