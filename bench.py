@@ -25,9 +25,11 @@ bandwidth the library's copy kernel reaches on this GPU.
 
 Also reported once, beside the timed iterations: the time to an absolute
 residual of 1e-10 in the parallel order from zero traces and in red-black
-order on 4 time windows (each from the extension of its start state); and
-the oracle on the host cores (a bounded sample of one iteration of the same
-shape, extrapolated).  `--scheme fem` times the paper's finite-element
+order on 4 time windows (each from the extension of its start state); the
+time to 1e-10 with and without learned initial traces on the learned-traces
+shape (256 x 256, Nt = 512, J = 4), the network trained here on a bounded
+number of seeded solves (`learned_guess`); and the oracle on the host cores
+(a bounded sample of one iteration of the same shape, extrapolated).  `--scheme fem` times the paper's finite-element
 discretisation instead.
 """
 from __future__ import annotations
@@ -103,6 +105,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2, help="untimed SWR iterations first")
     ap.add_argument("--no-solves", action="store_true", help="skip the time-to-tolerance solves")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess leg")
+    ap.add_argument("--learned-train", type=int, default=1024,
+                    help="training solves of the learned-guess leg")
+    ap.add_argument("--learned-eval", type=int, default=64,
+                    help="held-out seeds of the learned-guess leg")
     ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the copy-kernel bandwidth probe (MiB)")
@@ -153,6 +160,57 @@ def cpu_baseline(gpu_iters):
             "extrapolated_iteration_s": per_iter,
             "extrapolated_time_to_tol_s": None if gpu_iters is None else per_iter * gpu_iters,
             "extrapolated_with_iterations": gpu_iters}
+
+
+def learned_leg(ntrain, neval):
+    """Time to 1e-10 with and without learned initial traces on the
+    learned-traces shape (256 x 256, Nt = 512, T = 0.5, J = 4, overlap 2,
+    Robin p = 4).  Two networks (BF16 weights, FP32 accumulation) are
+    trained here, by the library's kernels, on `ntrain` solves the batch
+    path generates: three linear stages (`linear`), and a linear stage, the
+    3 x 512 GELU network on its remainder and a linear refinement stage
+    (`gelu`).  Every held-out seed is then solved from zero traces, from the
+    u0 extension and from each network's traces (wall time of each call,
+    inference included)."""
+    import torch
+
+    from paper_1306_4596_amd import learned
+
+    shape = learned.SHAPE_256
+    t0 = time.perf_counter()
+    X, Y, _ = learned.generate(shape, range(ntrain), base="u0")
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    nets, t_train = {}, {}
+    # a few thousand optimiser steps per linear stage (the map is linear and
+    # well determined by ~1000 solves), 40 epochs for the GELU stage
+    for name, kw, lrs, eps in (("linear", dict(depth=0, refine=2), [1e-3, 3e-3, 3e-3],
+                                [200, 200, 200]),
+                               ("gelu", dict(hidden=512, depth=3, skip=False, refine=1,
+                                             lead_linear=True), [1e-3, 1e-3, 3e-3],
+                                [200, 40, 200])):
+        g = learned.LearnedGuess(shape, **kw)
+        t0 = time.perf_counter()
+        g.fit(X, Y.clone() if name == "linear" else Y, batch=64, lrs=lrs, stage_epochs=eps)
+        torch.cuda.synchronize()
+        t_train[name] = round(time.perf_counter() - t0, 2)
+        nets[name] = g
+    del X, Y
+    ev = learned.evaluate(shape, range(20000, 20000 + neval), nets)
+    summ = learned.summarize(ev)
+    keep = ("iters_mean", "iters_median", "seconds_mean", "seconds_median", "guess_err_median",
+            "max_rel_l2_vs_zero_guess")
+    out = {"workload": "SWR 256x256 Nt=512 T=0.5 J=4 overlap=2 Robin p=4, tol 1e-10",
+           "networks": {"linear": "three BF16 linear stages",
+                        "gelu": "linear stage + 3x512 GELU stage + linear refinement, BF16"},
+           "train_seeds": ntrain, "eval_seeds": neval, "generate_s": round(t_gen, 2),
+           "train_s": t_train}
+    for k in ("zero", "u0", "linear", "gelu"):
+        out[k] = {q: summ[k][q] for q in keep}
+    for k in ("linear", "gelu"):
+        out[f"time_saved_{k}_vs_zero"] = 1.0 - summ[k]["seconds_mean"] / summ["zero"]["seconds_mean"]
+        out[f"time_saved_{k}_vs_u0"] = 1.0 - summ[k]["seconds_mean"] / summ["u0"]["seconds_mean"]
+    return out
 
 
 def main():
@@ -282,6 +340,11 @@ def main():
                                             "residual": s1.residual}
         kfp.set_ordering(kfp.PARALLEL)
         out["time_to_tol"] = {"tol": TOL, **solves}
+    if not args.no_learned:
+        del U0, F
+        kfp.release_workspace()
+        torch.cuda.empty_cache()
+        out["learned_guess"] = learned_leg(args.learned_train, args.learned_eval)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(gpu_iters)
     print(json.dumps(out))

@@ -154,11 +154,14 @@ class LearnedGuess:
     lambda^0 = base + sum over stages of (mean_k + std_k * net_k(x))."""
 
     def __init__(self, shape: Shape, hidden=512, depth=3, seed=0, base="u0", skip=True,
-                 refine=0, nets=None):
+                 refine=0, nets=None, lead_linear=False):
         self.shape = shape
         self.base = base
         if nets is None:
-            nets = [kb.MLP(N_FEAT, hidden, depth, shape.n_out, seed=seed, skip=skip)]
+            # lead_linear: a linear stage first, the (depth x hidden) network
+            # fitted to what it leaves over, then the refinement stages
+            nets = [kb.MLP(N_FEAT, 8, 0, shape.n_out, seed=seed + 100)] if lead_linear else []
+            nets += [kb.MLP(N_FEAT, hidden, depth, shape.n_out, seed=seed, skip=skip)]
             nets += [kb.MLP(N_FEAT, 8, 0, shape.n_out, seed=seed + 1 + k) for k in range(refine)]
         self.nets = nets
         self.means = []
@@ -188,7 +191,7 @@ class LearnedGuess:
         return hist
 
     def fit(self, X, Y, epochs=30, batch=256, lr=1e-3, lr_min=1e-5, log=None, seed=0,
-            refine_epochs=None, refine_lr=None):
+            refine_epochs=None, refine_lr=None, lrs=None, stage_epochs=None):
         """Trains every stage; Y (targets, FP32 [N][n_out]) is overwritten
         (standardised, then replaced by each stage's remainder).  Returns the
         epoch losses of all stages, in order."""
@@ -204,8 +207,9 @@ class LearnedGuess:
                 kb.mul_f32(scale, std)
             self.means.append(mean)
             self.stds.append(std)
-            ep = epochs if k == 0 else (refine_epochs or epochs)
-            rate = lr if k == 0 else (refine_lr or lr)
+            ep = stage_epochs[k] if stage_epochs else (epochs if k == 0 else
+                                                         (refine_epochs or epochs))
+            rate = lrs[k] if lrs else (lr if k == 0 else (refine_lr or lr))
             hist += self._train(net, X, Y, ep, batch, rate, lr_min, rng, log, f"stage {k + 1}")
             if k + 1 < len(self.nets):
                 for b0 in range(0, X.shape[0], batch):
@@ -325,11 +329,15 @@ def summarize(ev):
 
 
 VARIANTS = {
-    # name: (depth, hidden, skip, refine)
-    "mlp": (3, 512, False, 0),        # 3 x 512 GELU
-    "mlp_skip": (3, 512, True, 0),    # 3 x 512 GELU + linear input skip
-    "linear": (0, 8, False, 0),       # one BF16 linear layer
-    "linear_x3": (0, 8, False, 2),    # linear + two refinement stages
+    # name: (depth, hidden, skip, refine, lead_linear)
+    "mlp": (3, 512, False, 0, False),        # 3 x 512 GELU
+    "mlp_skip": (3, 512, True, 0, False),    # 3 x 512 GELU + linear input skip
+    "linear": (0, 8, False, 0, False),       # one BF16 linear layer
+    "linear_x3": (0, 8, False, 2, False),    # linear + two refinement stages
+    "linear_x2": (0, 8, False, 1, False),    # linear + one refinement stage
+    # linear stage, the 3 x 512 GELU network on its remainder, a linear
+    # refinement stage
+    "linear_mlp": (3, 512, False, 1, True),
 }
 
 
@@ -365,16 +373,20 @@ def main():
     guesses, train = {}, {}
     names = [v for v in args.variants.split(",") if v]
     for k, name in enumerate(names):
-        depth, hidden, skip, refine = VARIANTS[name]
+        depth, hidden, skip, refine, lead = VARIANTS[name]
         Y = Y0 if k == len(names) - 1 else Y0.clone()
         g = LearnedGuess(shape, hidden=hidden, depth=depth, base=args.base, skip=skip,
-                         refine=refine)
+                         refine=refine, lead_linear=lead)
         t0 = time.time()
+        # a leading linear stage and the network after it train at --lr, the
+        # refinement stages at --refine-lr
+        lrs = [args.lr, args.lr] + [args.refine_lr] * refine if lead else None
         hist = g.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
-                     refine_lr=args.refine_lr)
+                     refine_lr=args.refine_lr, lrs=lrs)
         torch.cuda.synchronize()
         train[name] = {"seconds": time.time() - t0, "loss_history": hist,
-                       "depth": depth, "hidden": hidden, "skip": skip, "refine": refine}
+                       "depth": depth, "hidden": hidden, "skip": skip, "refine": refine,
+                       "lead_linear": lead}
         del Y
         if args.save:
             g.save(f"{args.save}.{name}")

@@ -1,8 +1,11 @@
 """The learned initial traces, end to end on a reduced shape: solves of the
 method generate the training set, the library's kernels train the networks,
-and on held-out seeds the learned guesses reach the same tolerance and the
-same solution in fewer SWR iterations than the zero and u0-extension
-guesses."""
+and on held-out seeds both learned guesses -- three linear stages, and a
+linear stage with the 3-layer GELU network on its remainder and a linear
+refinement -- reach the same tolerance and the same solution in fewer SWR
+iterations than the zero and the u0-extension guesses.  (The GELU stage
+itself does not improve on the linear stages: the map from the coefficients
+to the converged traces is linear.)"""
 import numpy as np
 import pytest
 
@@ -24,11 +27,14 @@ def test_learned_guess_saves_iterations(tmp_path):
     print("training linear stages", flush=True)
     h1 = lin.fit(X, Y.clone(), epochs=200, batch=32, lr=3e-3, lr_min=1e-6)
     assert h1[199] < 1e-3 * h1[0]
-    # the 3-layer GELU network with the input skip
-    mlp = learned.LearnedGuess(shape, hidden=256, depth=3, skip=True, seed=1)
-    print("training GELU network", flush=True)
-    h2 = mlp.fit(X, Y, epochs=100, batch=32, lr=2e-3, lr_min=1e-6)
-    assert h2[-1] < 0.01 * h2[0]
+    # a linear stage, the 3-layer GELU network on its remainder, a linear
+    # refinement stage
+    mlp = learned.LearnedGuess(shape, hidden=256, depth=3, skip=False, refine=1, seed=1,
+                               lead_linear=True)
+    print("training linear + GELU stages", flush=True)
+    h2 = mlp.fit(X, Y, batch=32, lr_min=1e-6, lrs=[3e-3, 1e-3, 3e-3],
+                 stage_epochs=[200, 60, 200])
+    assert h2[199] < 1e-3 * h2[0]
     ev = learned.evaluate(shape, range(10000, 10012), {"lin": lin, "mlp": mlp}, tol=1e-10)
     it = {k: np.array([r["iters"] for r in v]) for k, v in ev.items()}
     print({k: v.tolist() for k, v in it.items()}, flush=True)
@@ -41,6 +47,7 @@ def test_learned_guess_saves_iterations(tmp_path):
     assert it["lin"].mean() < 0.6 * it["zero"].mean()
     assert it["lin"].mean() < it["u0"].mean() - 5
     assert it["mlp"].mean() < it["zero"].mean()
+    assert it["mlp"].mean() < it["u0"].mean()
     # a saved guess predicts the same traces
     lin.save(str(tmp_path / "g"))
     back = learned.LearnedGuess.load(str(tmp_path / "g"))
