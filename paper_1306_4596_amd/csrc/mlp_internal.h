@@ -21,6 +21,7 @@ struct GemmArgs {
   const float *bias;
   int gelu;
   float *P;
+  int splits;  // K chunks (set by the launcher)
 };
 
 hipError_t launch_gemm_nt(const GemmArgs &g, int splits, hipStream_t s);

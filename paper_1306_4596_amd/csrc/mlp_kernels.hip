@@ -28,12 +28,29 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 // ---------------------------------------------------------------------------
 // GEMM: 128 x 128 output tile per workgroup of 4 wavefronts (2 x 2), each
 // wavefront 64 x 64 = 4 x 4 blocks of v_mfma_f32_16x16x32_bf16; K step 32.
-// grid = (ceil(N/128), ceil(M/128), splits); split z covers K range
-// [z*kchunk, min(K, (z+1)*kchunk)).  splits > 1 writes FP32 partials to
-// P[z][M][N] and the reduce kernel applies the epilogue.
+// One-dimensional grid of tiles_n x tiles_m x splits workgroups; split z
+// covers K range [z*kchunk, min(K, (z+1)*kchunk)).  splits > 1 writes FP32
+// partials to P[z][M][N] and the reduce kernel applies the epilogue.
+// The next K step's tiles are loaded into registers while the current one
+// is multiplied (the loads are in flight during the MFMAs).
 // Requirements (checked on the host): K, lda, ldb multiples of 8.
 // ---------------------------------------------------------------------------
 constexpr int BM = 128, BN = 128, BK = 32, LDS_K = BK + 8;
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
+// w mod 8, each with its own L2).  Tiles that read the same operand block
+// form a group of G consecutive tile indices (split-K: the tiles of one
+// K chunk; otherwise the row tiles of one column tile when there are fewer
+// row tiles, else the column tiles of one row tile).  The remap puts each
+// group on one XCD, its members one after another there, so the shared
+// block comes from HBM once and then from that XCD's L2.  Bijective; the
+// tail that does not fill 8 groups keeps the plain order.
+__device__ __forceinline__ int xcd_tile(int w, int T, int G) {
+  const int T8 = (T / (8 * G)) * (8 * G);
+  if (G > 64 || w >= T8) return w;
+  const int xcd = w & 7, q = w >> 3;
+  return ((q / G) * 8 + xcd) * G + q % G;
+}
 
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 sA[BM * LDS_K];
@@ -42,8 +59,28 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int kbeg = blockIdx.z * g.kchunk;
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const int T = tiles_m * tiles_n * g.splits;
+  int mt, nt, z;
+  if (g.splits > 1) {
+    const int G = tiles_m * tiles_n;
+    const int t = xcd_tile(blockIdx.x, T, G);
+    z = t / G;
+    mt = (t % G) % tiles_m;
+    nt = (t % G) / tiles_m;
+  } else if (tiles_m <= tiles_n) {
+    const int t = xcd_tile(blockIdx.x, T, tiles_m);
+    z = 0;
+    mt = t % tiles_m;
+    nt = t / tiles_m;
+  } else {
+    const int t = xcd_tile(blockIdx.x, T, tiles_n);
+    z = 0;
+    nt = t % tiles_n;
+    mt = t / tiles_n;
+  }
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = z * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
   f32x4 acc[4][4];
 #pragma unroll
@@ -53,22 +90,33 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   bf16x8 zero8;
 #pragma unroll
   for (int i = 0; i < 8; ++i) zero8[i] = (__bf16)0.0f;
+  // each thread moves two 16-byte pieces of A and of B per K step
+  bf16x8 va[2], vb[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int idx = tid + r * 256;
+      const int row = idx >> 2;
+      const int gk = k0 + (idx & 3) * 8;
+      const int gm = m0 + row, gn = n0 + row;
+      va[r] = zero8;
+      vb[r] = zero8;
+      if (gm < g.M && gk < kend) va[r] = *(const bf16x8 *)(g.A + (size_t)gm * g.lda + gk);
+      if (gn < g.N && gk < kend) vb[r] = *(const bf16x8 *)(g.B + (size_t)gn * g.ldb + gk);
+    }
+  };
+  if (kbeg < kend) load(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // each thread moves two 16-byte pieces of A and of B into LDS
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int idx = tid + r * 256;
       const int row = idx >> 2;
       const int kk = (idx & 3) * 8;
-      const int gk = k0 + kk;
-      bf16x8 va = zero8, vb = zero8;
-      const int gm = m0 + row, gn = n0 + row;
-      if (gm < g.M && gk < kend) va = *(const bf16x8 *)(g.A + (size_t)gm * g.lda + gk);
-      if (gn < g.N && gk < kend) vb = *(const bf16x8 *)(g.B + (size_t)gn * g.ldb + gk);
-      *(bf16x8 *)(sA + row * LDS_K + kk) = va;
-      *(bf16x8 *)(sB + row * LDS_K + kk) = vb;
+      *(bf16x8 *)(sA + row * LDS_K + kk) = va[r];
+      *(bf16x8 *)(sB + row * LDS_K + kk) = vb[r];
     }
     __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);  // in flight during this step's MFMAs
     bf16x8 af[4], bfm[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -83,7 +131,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     __syncthreads();
   }
   // accumulator register r of block (i, j) holds row 4*(lane/16) + r, column lane%16
-  const bool partial = gridDim.z > 1;
+  const bool partial = g.splits > 1;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -95,7 +143,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
         if (m >= g.M || n >= g.N) continue;
         float v = acc[i][j][r];
         if (partial) {
-          g.P[((size_t)blockIdx.z * g.M + m) * g.N + n] = v;
+          g.P[((size_t)z * g.M + m) * g.N + n] = v;
           continue;
         }
         if (g.bias) v += g.bias[n];
@@ -281,9 +329,12 @@ __global__ void standardize_kernel(float *__restrict__ X, size_t per, size_t n,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_gemm_nt(const GemmArgs &g, int splits, hipStream_t s) {
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
-  hipLaunchKernelGGL(gemm_nt_kernel, grid, dim3(256), 0, s, g);
+hipError_t launch_gemm_nt(const GemmArgs &g_in, int splits, hipStream_t s) {
+  GemmArgs g = g_in;
+  g.splits = splits;
+  const long T = (long)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * splits;
+  if (T < 1 || T > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gemm_nt_kernel, dim3((unsigned)T), dim3(256), 0, s, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits <= 1) return e;
   hipLaunchKernelGGL(gemm_reduce_kernel, dim3(egrid((size_t)g.M * g.N)), dim3(256), 0, s, g,

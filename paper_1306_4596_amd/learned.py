@@ -341,6 +341,34 @@ VARIANTS = {
 }
 
 
+def bench_train_steps(steps, batch=256, hidden=512, depth=3, skip=False):
+    """Train steps of the network of the 256 x 256 shape on random inputs and
+    targets (no solves): mean wall time per step after one warm-up step,
+    for kernel profiles of the forward, backward and Adam kernels."""
+    import torch
+
+    shape = SHAPE_256
+    net = kb.MLP(N_FEAT, hidden, depth, shape.n_out, seed=0, skip=skip)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((batch, N_FEAT), generator=g, device="cuda", dtype=torch.float32)
+    Y = torch.randn((batch, shape.n_out), generator=g, device="cuda", dtype=torch.float32)
+    net.train_step(X, Y, 1e-4)
+    # the library's copy kernel over 1 GiB: a known byte count for scaling
+    # HBM counters taken on this run
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    kb.bw_probe(a, torch.empty_like(a))
+    del a
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(X, Y, 1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    params = sum(net.shape(k)[0] * net.shape(k)[1] for k in range(net.layers()))
+    return {"batch": batch, "hidden": hidden, "depth": depth, "skip": skip, "n_out": shape.n_out,
+            "params": params, "steps": steps, "ms_per_step": dt * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=20000)
@@ -358,7 +386,12 @@ def main():
                     help="evaluation in these solve orders: 0 parallel, 1 red-black")
     ap.add_argument("--scheme", choices=["fd", "fem"], default="fd",
                     help="discretisation of every solve (default fd)")
+    ap.add_argument("--bench-train-steps", type=int, default=0,
+                    help="only time this many train steps of the 3 x 512 network on random data")
     args = ap.parse_args()
+    if args.bench_train_steps > 0:
+        print(json.dumps(bench_train_steps(args.bench_train_steps, batch=args.batch)), flush=True)
+        return
     kb.set_scheme(kb.FEM if args.scheme == "fem" else kb.FD)
 
     def log(msg):
