@@ -412,19 +412,27 @@ kfp_status kfp_mlp_create_ex(int32_t in, int32_t hidden, int32_t depth, int64_t 
 void kfp_mlp_destroy(kfp_mlp *mlp);
 /* Y[B][out] = net(X[B][in]).  Asynchronous. */
 kfp_status kfp_mlp_forward(kfp_mlp *mlp, int32_t B, const float *X, float *Y, void *stream);
-/* Gradients of the loss at (X, T) into the handle's gradient buffers;
- * loss: [host] or NULL (synchronises when given).  B: multiple of 8. */
+/* Gradients of the loss at (X, T) into the handle's gradient buffers
+ * (allocated by the first call); loss: [host] or NULL (synchronises when
+ * given).  B: multiple of 8. */
 kfp_status kfp_mlp_backward(kfp_mlp *mlp, int32_t B, const float *X, const float *T,
                             double *loss, void *stream);
-/* One Adam step with the stored gradients (learning rate lr). */
+/* One Adam step with the stored gradients (learning rate lr); KFP_EINVAL
+ * before the first kfp_mlp_backward. */
 kfp_status kfp_mlp_adam(kfp_mlp *mlp, float lr, void *stream);
-/* backward + adam */
+/* One training step: the same products and update arithmetic as
+ * kfp_mlp_backward followed by kfp_mlp_adam (the same weights, bit for bit),
+ * with the loss gradient formed in the output layer's epilogue and each
+ * layer's Adam step applied in its weight-gradient product, so neither the
+ * output nor the weight gradient is stored (the gradient buffers keep what
+ * the last kfp_mlp_backward wrote). */
 kfp_status kfp_mlp_train_step(kfp_mlp *mlp, int32_t B, const float *X, const float *T, float lr,
                               double *loss, void *stream);
 /* Layers are 0..depth; [host] outputs. */
 kfp_status kfp_mlp_layer_shape(const kfp_mlp *mlp, int32_t layer, int32_t *in, int64_t *out);
 /* Copy a parameter to (set = 0) or from (set = 1) a device FP32 buffer:
- * which 0 = W [out][in], 1 = b [out], 2 = dW (read only), 3 = db (read only). */
+ * which 0 = W [out][in], 1 = b [out], 2 = dW (read only; KFP_EINVAL before the
+ * first kfp_mlp_backward), 3 = db (read only). */
 kfp_status kfp_mlp_param(kfp_mlp *mlp, int32_t layer, int32_t which, int32_t set, float *buf,
                          void *stream);
 /* Checkpoint: FP32 masters, Adam moments and step count. */

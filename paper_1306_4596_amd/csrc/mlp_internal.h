@@ -6,14 +6,27 @@
 
 namespace kfp {
 
-// C[m][n] = sum_k A[m][k] B[n][k] (+ bias[n]); optional FP32 output C and
-// BF16 output Cb (GELU applied to Cb when gelu != 0).  P: split-K partials.
+// C[m][n] = sum_k A[m][k] B[n][k].  Each operand is stored either with K
+// contiguous (A[m][k] at A + m*lda + k) or K-major (a_kmajor: A[m][k] at
+// A + k*lda + m; likewise B with b_kmajor).  Epilogues:
+//   EPI_STORE  + bias[n]; optional FP32 output C and BF16 output Cb (GELU
+//              applied to Cb when gelu != 0).  P: split-K partials.
+//   EPI_MSE    r = C + bias - T (the squared-error residual): Cb = BF16(scale r),
+//              loss += sum r^2 (FP64 atomic), PB[2*row tile + w][n] = column
+//              sum of scale r over the 64 rows of wavefront row w of the tile.
+//   EPI_ADAM   C is the gradient of W[M][N] (row stride ldw): one Adam step on
+//              W, the moments Mo, Vo and the BF16 copy Wb, in place.
+// The fused epilogues need the whole K in one tile (splits == 1), N a
+// multiple of 8 and ldt, ldcb, ldw multiples of 4.
+enum { EPI_STORE = 0, EPI_MSE = 1, EPI_ADAM = 2 };
+
 struct GemmArgs {
   int M, N, K, kchunk;
   const __bf16 *A;
   long lda;
   const __bf16 *B;
   long ldb;
+  int a_kmajor, b_kmajor, epi;
   float *C;
   long ldc;
   __bf16 *Cb;
@@ -22,20 +35,28 @@ struct GemmArgs {
   int gelu;
   float *P;
   int splits;  // K chunks (set by the launcher)
+  // EPI_MSE
+  const float *T;
+  long ldt;
+  float scale;
+  double *loss;
+  float *PB;
+  // EPI_ADAM
+  float *W, *Mo, *Vo;
+  __bf16 *Wb;
+  long ldw;
+  float lr, b1, b2, eps, c1, c2;
 };
 
-hipError_t launch_gemm_nt(const GemmArgs &g, int splits, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs &g, int splits, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float *s_, __bf16 *d, size_t n, hipStream_t s);
 hipError_t launch_f32_to_bf16_cols(const float *s_, int rows, int cols, __bf16 *d, long ldd,
                                    hipStream_t s);
 hipError_t launch_f64_to_f32(const double *s_, const double *base, float *d, size_t n,
                              hipStream_t s);
-hipError_t launch_mse_grad(const float *Y, const float *T, float *d32, __bf16 *db, size_t n,
-                           float scale, double *loss, hipStream_t s);
 hipError_t launch_gelu_back(const float *dA, const float *Z, float *d32, __bf16 *db, size_t n,
                             hipStream_t s);
 hipError_t launch_colsum(const float *X, int R, int C, float *out, hipStream_t s);
-hipError_t launch_transpose_bf16(const __bf16 *src, __bf16 *dst, int R, int C, hipStream_t s);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, size_t n,
                        float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_destandardize(const float *y, const float *mean, const float *stdv,

@@ -2,10 +2,12 @@
 // (FP32 accumulation) with bias / GELU epilogues and split-K, and the
 // element-wise pieces of the backward pass and of Adam.
 //
-// Every product is cast in "NT" form, C[m][n] = sum_k A[m][k] B[n][k], with
-// both operands stored K-contiguous, so one tile loader serves the forward
-// product (A = activations, B = W[out][in]), the input gradient (B = W^T
-// copy) and the weight gradient (A = dZ^T, B = activations^T).
+// Every product is cast as C[m][n] = sum_k A[m][k] B[n][k] with each operand
+// either K-contiguous or K-major, so the stored layouts serve all three
+// products without transposes: the forward product (A = activations, B =
+// W[out][in], both K-contiguous), the input gradient (A = dZ[batch][out],
+// B = W[out][in] read K-major) and the weight gradient (A = dZ and B = the
+// activations, both K-major with K = batch).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -16,6 +18,8 @@ namespace kfp {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float gelu_f(float z) {
   return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
@@ -23,6 +27,19 @@ __device__ __forceinline__ float gelu_f(float z) {
 __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
          z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// One Adam step (bias-corrected moments) on one FP32 master weight; the
+// same arithmetic in the stand-alone update and in the fused GEMM epilogue.
+__device__ __forceinline__ float adam_update(float &w, float gi, float &m, float &v, float lr,
+                                             float b1, float b2, float eps, float c1, float c2) {
+  const float mi = fmaf(b1, m, (1.f - b1) * gi);
+  const float vi = fmaf(b2, v, ((1.f - b2) * gi) * gi);
+  m = mi;
+  v = vi;
+  const float step = (lr * (mi / c1)) / (sqrtf(vi / c2) + eps);
+  w = w - step;
+  return w;
 }
 
 // ---------------------------------------------------------------------------
@@ -33,9 +50,30 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 // partials to P[z][M][N] and the reduce kernel applies the epilogue.
 // The next K step's tiles are loaded into registers while the current one
 // is multiplied (the loads are in flight during the MFMAs).
-// Requirements (checked on the host): K, lda, ldb multiples of 8.
+//
+// Both operand tiles sit in LDS as [row][k] (row pitch LDS_K), the layout
+// the MFMA fragments read: lane l takes the 8 consecutive k of group l/16
+// for row l%16.  A K-contiguous operand is copied in 16-byte pieces.  A
+// K-major operand is read from HBM along its rows (16 lanes cover 128
+// consecutive rows of one k) and transposed on the way into LDS: each
+// thread loads rows k and k+1 for 8 consecutive tile rows and writes the 8
+// (k, k+1) pairs as 32-bit words.  The four 8-wide k groups of a row are
+// XOR-permuted by bits 4-5 of the row index: the fragment reads and the
+// K-contiguous copies see a permutation that is uniform across each
+// wavefront (no change in bank use), while the pair writes of one
+// wavefront, 8 rows apart, spread over the banks.
+// Requirements (checked on the host): K, lda, ldb multiples of 8; M (N) a
+// multiple of 8 for a K-major A (B).
 // ---------------------------------------------------------------------------
 constexpr int BM = 128, BN = 128, BK = 32, LDS_K = BK + 8;
+// The fused epilogues stage each wavefront's 64 x 64 FP32 block in LDS, 32
+// rows at a time (row pitch EP_PITCH floats: 16-byte aligned rows, and the
+// accumulator writes of one wavefront, rows 4 apart, fall in distinct
+// banks), and walk it row-major, 16 lanes per row with 4 columns each, so
+// every HBM access of the epilogue covers whole 128-byte lines.
+constexpr int EP_PITCH = 68;
+constexpr int SMEM_AB = 2 * BM * LDS_K * 2;
+constexpr int SMEM_EPI = 4 * 32 * EP_PITCH * 4;
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
 // w mod 8, each with its own L2).  Tiles that read the same operand block
@@ -52,9 +90,66 @@ __device__ __forceinline__ int xcd_tile(int w, int T, int G) {
   return ((q / G) * 8 + xcd) * G + q % G;
 }
 
-__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 sA[BM * LDS_K];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[BN * LDS_K];
+__device__ __forceinline__ int kswz(int row) { return (row >> 4) & 3; }
+
+// global -> registers: the two pieces of one operand tile this thread moves
+template <bool KM>
+__device__ __forceinline__ void tile_load(bf16x8 (&v)[2], const __bf16 *__restrict__ p, long ld,
+                                          int r0, int R, int k0, int kend, int tid,
+                                          const bf16x8 &zero8) {
+  if constexpr (!KM) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int idx = tid + r * 256;
+      const int row = r0 + (idx >> 2);
+      const int gk = k0 + (idx & 3) * 8;
+      v[r] = zero8;
+      if (row < R && gk < kend) v[r] = *(const bf16x8 *)(p + (size_t)row * ld + gk);
+    }
+  } else {
+    const int row = r0 + 8 * (tid & 15);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int gk = k0 + 2 * (tid >> 4) + r;
+      v[r] = zero8;
+      if (row < R && gk < kend) v[r] = *(const bf16x8 *)(p + (size_t)gk * ld + row);
+    }
+  }
+}
+
+// registers -> LDS tile [row][k]
+template <bool KM>
+__device__ __forceinline__ void tile_store(__bf16 *__restrict__ s, const bf16x8 (&v)[2],
+                                           int tid) {
+  if constexpr (!KM) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int idx = tid + r * 256;
+      const int row = idx >> 2;
+      *(bf16x8 *)(s + row * LDS_K + (((idx & 3) ^ kswz(row)) * 8)) = v[r];
+    }
+  } else {
+    const int kp = tid >> 4, row0 = 8 * (tid & 15);
+    const int grp = kp >> 2, off = 2 * (kp & 3);
+    // the pieces as raw 16-bit patterns (whole-vector casts: element-wise
+    // casts of a BF16 vector are not relied on)
+    const u16x8 lo = __builtin_bit_cast(u16x8, v[0]);
+    const u16x8 hi = __builtin_bit_cast(u16x8, v[1]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = row0 + j;
+      *(uint32_t *)(s + row * LDS_K + ((grp ^ kswz(row)) * 8) + off) =
+          (uint32_t)lo[j] | ((uint32_t)hi[j] << 16);
+    }
+  }
+}
+
+template <int EPI, bool AK, bool BKM>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16)))
+  unsigned char smem[EPI == EPI_STORE ? SMEM_AB : (SMEM_EPI > SMEM_AB ? SMEM_EPI : SMEM_AB)];
+  __bf16 *sA = (__bf16 *)smem;
+  __bf16 *sB = sA + BM * LDS_K;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -90,38 +185,24 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   bf16x8 zero8;
 #pragma unroll
   for (int i = 0; i < 8; ++i) zero8[i] = (__bf16)0.0f;
-  // each thread moves two 16-byte pieces of A and of B per K step
   bf16x8 va[2], vb[2];
   auto load = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int idx = tid + r * 256;
-      const int row = idx >> 2;
-      const int gk = k0 + (idx & 3) * 8;
-      const int gm = m0 + row, gn = n0 + row;
-      va[r] = zero8;
-      vb[r] = zero8;
-      if (gm < g.M && gk < kend) va[r] = *(const bf16x8 *)(g.A + (size_t)gm * g.lda + gk);
-      if (gn < g.N && gk < kend) vb[r] = *(const bf16x8 *)(g.B + (size_t)gn * g.ldb + gk);
-    }
+    tile_load<AK>(va, g.A, g.lda, m0, g.M, k0, kend, tid, zero8);
+    tile_load<BKM>(vb, g.B, g.ldb, n0, g.N, k0, kend, tid, zero8);
   };
   if (kbeg < kend) load(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int idx = tid + r * 256;
-      const int row = idx >> 2;
-      const int kk = (idx & 3) * 8;
-      *(bf16x8 *)(sA + row * LDS_K + kk) = va[r];
-      *(bf16x8 *)(sB + row * LDS_K + kk) = vb[r];
-    }
+    tile_store<AK>(sA, va, tid);
+    tile_store<BKM>(sB, vb, tid);
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);  // in flight during this step's MFMAs
     bf16x8 af[4], bfm[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      af[i] = *(const bf16x8 *)(sA + (wm * 64 + i * 16 + (lane & 15)) * LDS_K + 8 * (lane >> 4));
-      bfm[i] = *(const bf16x8 *)(sB + (wn * 64 + i * 16 + (lane & 15)) * LDS_K + 8 * (lane >> 4));
+      const int ra = wm * 64 + i * 16 + (lane & 15);
+      const int rb = wn * 64 + i * 16 + (lane & 15);
+      af[i] = *(const bf16x8 *)(sA + ra * LDS_K + (((lane >> 4) ^ kswz(ra)) * 8));
+      bfm[i] = *(const bf16x8 *)(sB + rb * LDS_K + (((lane >> 4) ^ kswz(rb)) * 8));
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -131,25 +212,137 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     __syncthreads();
   }
   // accumulator register r of block (i, j) holds row 4*(lane/16) + r, column lane%16
-  const bool partial = g.splits > 1;
+  if (g.splits > 1) {
+    // split-K partials; the reduce kernel applies the epilogue
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
-        if (m >= g.M || n >= g.N) continue;
-        float v = acc[i][j][r];
-        if (partial) {
-          g.P[((size_t)z * g.M + m) * g.N + n] = v;
-          continue;
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+          const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+          if (m < g.M && n < g.N) g.P[((size_t)z * g.M + m) * g.N + n] = acc[i][j][r];
         }
-        if (g.bias) v += g.bias[n];
-        if (g.C) g.C[(size_t)m * g.ldc + n] = v;
-        if (g.Cb) g.Cb[(size_t)m * g.ldcb + n] = (__bf16)(g.gelu ? gelu_f(v) : v);
+    return;
+  }
+  if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+          const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+          if (m >= g.M || n >= g.N) continue;
+          float v = acc[i][j][r];
+          if (g.bias) v += g.bias[n];
+          if (g.C) g.C[(size_t)m * g.ldc + n] = v;
+          if (g.Cb) g.Cb[(size_t)m * g.ldcb + n] = (__bf16)(g.gelu ? gelu_f(v) : v);
+        }
+  } else {
+    // row (4 it + lane/16) of a staged half, columns cq .. cq + 3 (N is a
+    // multiple of 8, so the four are valid together)
+    float *sE = (float *)smem + wv * 32 * EP_PITCH;
+    const int cq = 4 * (lane & 15);
+    const int n = n0 + wn * 64 + cq;
+    const bool ncol = n < g.N;
+    double lsum = 0.0;
+    f32x4 cs = {0.f, 0.f, 0.f, 0.f};
+    f32x4 bias4 = {0.f, 0.f, 0.f, 0.f};
+    if (EPI == EPI_MSE && g.bias && ncol) bias4 = *(const f32x4 *)(g.bias + n);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // stage rows 32h .. 32h + 31 of this wavefront's block (the previous
+      // barrier has retired every read of the operand tiles or of the
+      // previous half)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            sE[(i * 16 + 4 * (lane >> 4) + r) * EP_PITCH + j * 16 + (lane & 15)] =
+                acc[2 * h + i][j][r];
+      __syncthreads();
+      const int mrow = m0 + wm * 64 + 32 * h + (lane >> 4);
+#pragma unroll
+      for (int it0 = 0; it0 < 8; it0 += 4) {
+        if constexpr (EPI == EPI_MSE) {
+          f32x4 t[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = mrow + 4 * (it0 + u);
+            t[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (ncol && m < g.M) t[u] = *(const f32x4 *)(g.T + (size_t)m * g.ldt + n);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = mrow + 4 * (it0 + u);
+            if (!ncol || m >= g.M) continue;
+            const int rl = 4 * (it0 + u) + (lane >> 4);
+            const f32x4 res = (*(const f32x4 *)(sE + rl * EP_PITCH + cq) + bias4) - t[u];
+            bf16x4 db;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              lsum += (double)res[c] * (double)res[c];
+              const float d = g.scale * res[c];
+              db[c] = (__bf16)d;
+              cs[c] += d;
+            }
+            *(bf16x4 *)(g.Cb + (size_t)m * g.ldcb + n) = db;
+          }
+        } else {
+          f32x4 w4[4], m4[4], v4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = mrow + 4 * (it0 + u);
+            if (!ncol || m >= g.M) continue;
+            const size_t e = (size_t)m * g.ldw + n;
+            w4[u] = *(const f32x4 *)(g.W + e);
+            m4[u] = *(const f32x4 *)(g.Mo + e);
+            v4[u] = *(const f32x4 *)(g.Vo + e);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = mrow + 4 * (it0 + u);
+            if (!ncol || m >= g.M) continue;
+            const int rl = 4 * (it0 + u) + (lane >> 4);
+            const f32x4 gr = *(const f32x4 *)(sE + rl * EP_PITCH + cq);
+            bf16x4 wb;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              float w = w4[u][c], mo = m4[u][c], vo = v4[u][c];
+              adam_update(w, gr[c], mo, vo, g.lr, g.b1, g.b2, g.eps, g.c1, g.c2);
+              w4[u][c] = w;
+              m4[u][c] = mo;
+              v4[u][c] = vo;
+              wb[c] = (__bf16)w;
+            }
+            const size_t e = (size_t)m * g.ldw + n;
+            *(f32x4 *)(g.W + e) = w4[u];
+            *(f32x4 *)(g.Mo + e) = m4[u];
+            *(f32x4 *)(g.Vo + e) = v4[u];
+            *(bf16x4 *)(g.Wb + e) = wb;
+          }
+        }
       }
+      if (h == 0) __syncthreads();
+    }
+    if constexpr (EPI == EPI_MSE) {
+      // lanes l, l^16, l^32, l^48 hold the same columns: sum the 64 rows
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        cs[c] += __shfl_xor(cs[c], 16, 64);
+        cs[c] += __shfl_xor(cs[c], 32, 64);
+      }
+      if (lane < 16 && ncol) *(f32x4 *)(g.PB + (size_t)(mt * 2 + wm) * g.N + n) = cs;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+      if (lane == 0 && lsum != 0.0) atomicAdd(g.loss, lsum);
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits) {
@@ -157,8 +350,19 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     float v = 0.f;
+#pragma unroll 8
     for (int z = 0; z < splits; ++z) v += g.P[(size_t)z * total + e];
     const int m = (int)(e / g.N), n = (int)(e % g.N);
+    if (g.epi == EPI_ADAM) {
+      const size_t o = (size_t)m * g.ldw + n;
+      float w = g.W[o], mo = g.Mo[o], vo = g.Vo[o];
+      adam_update(w, v, mo, vo, g.lr, g.b1, g.b2, g.eps, g.c1, g.c2);
+      g.W[o] = w;
+      g.Mo[o] = mo;
+      g.Vo[o] = vo;
+      g.Wb[o] = (__bf16)w;
+      continue;
+    }
     if (g.bias) v += g.bias[n];
     if (g.C) g.C[(size_t)m * g.ldc + n] = v;
     if (g.Cb) g.Cb[(size_t)m * g.ldcb + n] = (__bf16)(g.gelu ? gelu_f(v) : v);
@@ -199,29 +403,6 @@ __global__ void f64_to_f32_kernel(const double *__restrict__ s, const double *__
   }
 }
 
-// dY = 2 (Y - T) / (B out): FP32 copy (bias gradient) and BF16 copy (products);
-// the squared error is accumulated in FP64.
-__global__ __launch_bounds__(256) void mse_grad_kernel(const float *__restrict__ Y,
-                                                       const float *__restrict__ T,
-                                                       float *__restrict__ d32,
-                                                       __bf16 *__restrict__ db, size_t n,
-                                                       float scale, double *loss) {
-  __shared__ double red[4];
-  double acc = 0.0;
-  GRID_STRIDE(e, n) {
-    const float r = Y[e] - T[e];
-    acc += (double)r * (double)r;
-    const float d = scale * r;
-    d32[e] = d;
-    db[e] = (__bf16)d;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
-}
-
 // dZ = dA * GELU'(Z)
 __global__ void gelu_back_kernel(const float *__restrict__ dA, const float *__restrict__ Z,
                                  float *__restrict__ d32, __bf16 *__restrict__ db, size_t n) {
@@ -232,32 +413,24 @@ __global__ void gelu_back_kernel(const float *__restrict__ dA, const float *__re
   }
 }
 
-// column sums of a row-major [R][C] FP32 matrix (bias gradients), FP64 accumulation
+// column sums of a row-major [R][C] FP32 matrix (bias gradients), FP64
+// accumulation: 64 columns per workgroup, each wavefront summing every
+// fourth row, the four partial sums added in wavefront order
 __global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ X, int R, int C,
                                                      float *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
+  __shared__ double part[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int w = threadIdx.x >> 6;
   double s = 0.0;
-  for (int r = 0; r < R; ++r) s += X[(size_t)r * C + c];
-  out[c] = (float)s;
-}
-
-// tiled transpose of a BF16 matrix: src [R][C] -> dst [C][R]
-__global__ __launch_bounds__(256) void transpose_bf16_kernel(const __bf16 *__restrict__ src,
-                                                             __bf16 *__restrict__ dst, int R,
-                                                             int C) {
-  __shared__ __bf16 tile[64][65];
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int i = ty; i < 64; i += 4) {
-    const int r = r0 + i, c = c0 + tx;
-    if (r < R && c < C) tile[i][tx] = src[(size_t)r * C + c];
+  if (c < C) {
+#pragma unroll 8
+    for (int r = w; r < R; r += 4) s += X[(size_t)r * C + c];
   }
+  part[w][threadIdx.x & 63] = s;
   __syncthreads();
-  for (int i = ty; i < 64; i += 4) {
-    const int c = c0 + i, r = r0 + tx;
-    if (r < R && c < C) dst[(size_t)c * R + r] = tile[tx][i];
-  }
+  if (w == 0 && c < C)
+    out[c] = (float)(((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) +
+                     part[3][threadIdx.x]);
 }
 
 // Adam on FP32 masters; refreshes the BF16 copy.
@@ -266,12 +439,10 @@ __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g,
                             __bf16 *__restrict__ wb, size_t n, float lr, float b1, float b2,
                             float eps, float c1, float c2) {
   GRID_STRIDE(e, n) {
-    const float gi = g[e];
-    const float mi = b1 * m[e] + (1.f - b1) * gi;
-    const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+    float wi = w[e], mi = m[e], vi = v[e];
+    adam_update(wi, g[e], mi, vi, lr, b1, b2, eps, c1, c2);
     m[e] = mi;
     v[e] = vi;
-    const float wi = w[e] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[e] = wi;
     if (wb) wb[e] = (__bf16)wi;
   }
@@ -329,13 +500,27 @@ __global__ void standardize_kernel(float *__restrict__ X, size_t per, size_t n,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_gemm_nt(const GemmArgs &g_in, int splits, hipStream_t s) {
+template <int EPI>
+static void *gemm_entry(int ak, int bk) {
+  if (ak && bk) return (void *)gemm_kernel<EPI, true, true>;
+  if (ak) return (void *)gemm_kernel<EPI, true, false>;
+  if (bk) return (void *)gemm_kernel<EPI, false, true>;
+  return (void *)gemm_kernel<EPI, false, false>;
+}
+
+hipError_t launch_gemm(const GemmArgs &g_in, int splits, hipStream_t s) {
   GemmArgs g = g_in;
   g.splits = splits;
+  if (g.epi == EPI_MSE && splits != 1) return hipErrorInvalidValue;
   const long T = (long)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * splits;
   if (T < 1 || T > 0x7fffffffL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gemm_nt_kernel, dim3((unsigned)T), dim3(256), 0, s, g);
-  hipError_t e = hipGetLastError();
+  void *fn = g.epi == EPI_MSE    ? gemm_entry<EPI_MSE>(g.a_kmajor, g.b_kmajor)
+             : g.epi == EPI_ADAM ? gemm_entry<EPI_ADAM>(g.a_kmajor, g.b_kmajor)
+                                 : gemm_entry<EPI_STORE>(g.a_kmajor, g.b_kmajor);
+  void *args[] = {&g};
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)T), dim3(256), args, 0, s);
+  if (e != hipSuccess) return e;
+  e = hipGetLastError();
   if (e != hipSuccess || splits <= 1) return e;
   hipLaunchKernelGGL(gemm_reduce_kernel, dim3(egrid((size_t)g.M * g.N)), dim3(256), 0, s, g,
                      splits);
@@ -364,13 +549,6 @@ hipError_t launch_f64_to_f32(const double *s_, const double *base, float *d, siz
   return hipGetLastError();
 }
 
-hipError_t launch_mse_grad(const float *Y, const float *T, float *d32, __bf16 *db, size_t n,
-                           float scale, double *loss, hipStream_t s) {
-  hipLaunchKernelGGL(mse_grad_kernel, dim3(egrid(n)), dim3(256), 0, s, Y, T, d32, db, n, scale,
-                     loss);
-  return hipGetLastError();
-}
-
 hipError_t launch_gelu_back(const float *dA, const float *Z, float *d32, __bf16 *db, size_t n,
                             hipStream_t s) {
   hipLaunchKernelGGL(gelu_back_kernel, dim3(egrid(n)), dim3(256), 0, s, dA, Z, d32, db, n);
@@ -378,13 +556,7 @@ hipError_t launch_gelu_back(const float *dA, const float *Z, float *d32, __bf16 
 }
 
 hipError_t launch_colsum(const float *X, int R, int C, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((C + 255) / 256), dim3(256), 0, s, X, R, C, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_transpose_bf16(const __bf16 *src, __bf16 *dst, int R, int C, hipStream_t s) {
-  dim3 grid((C + 63) / 64, (R + 63) / 64);
-  hipLaunchKernelGGL(transpose_bf16_kernel, grid, dim3(256), 0, s, src, dst, R, C);
+  hipLaunchKernelGGL(colsum_kernel, dim3((C + 63) / 64), dim3(256), 0, s, X, R, C, out);
   return hipGetLastError();
 }
 

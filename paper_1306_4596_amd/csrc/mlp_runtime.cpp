@@ -1,6 +1,6 @@
 // Host runtime of the learned initial-trace network: parameter storage
-// (FP32 masters, BF16 copies in both layouts, Adam moments), the forward
-// pass, the backward pass, Adam, checkpoints, and the data helpers
+// (FP32 masters, BF16 copies, Adam moments), the forward pass, the backward
+// pass, Adam, the fused training step, checkpoints, and the data helpers
 // (casts, standardisation) around it.  C ABI in include/kfpswr.h.
 #include <hip/hip_runtime.h>
 
@@ -51,21 +51,21 @@ struct Layer {
   int in = 0;
   long out = 0;
   float *W = nullptr, *b = nullptr;      // FP32 masters: W [out][in]
-  __bf16 *Wb = nullptr, *Wt = nullptr;   // BF16 copies: [out][in], [in][out]
+  __bf16 *Wb = nullptr;                  // BF16 copy [out][in]
   float *mW = nullptr, *vW = nullptr, *mb = nullptr, *vb = nullptr;
-  float *gW = nullptr, *gb = nullptr;    // gradients
+  float *gW = nullptr;                   // weight gradient (allocated by the first backward)
+  float *gb = nullptr;                   // bias gradient
 };
 
 struct Acts {
   int cap = 0;
-  __bf16 *Xb = nullptr, *Xt = nullptr;         // input [B][in0], [in0][B]
+  __bf16 *Xb = nullptr;                        // input [B][in0]
   std::vector<float *> Z;                      // pre-activations [B][h] (hidden layers)
-  std::vector<__bf16 *> Ab, At;                // GELU outputs [B][h] and [h][B]
-  float *Y = nullptr;                          // training output [B][out]
-  float *d32 = nullptr;                        // output gradient FP32 [B][out]
-  __bf16 *db = nullptr, *dt = nullptr;         // output gradient BF16 [B][out], [out][B]
+  std::vector<__bf16 *> Ab;                    // GELU outputs [B][h]
+  __bf16 *db = nullptr;                        // output gradient BF16 [B][out]
+  float *PB = nullptr;                         // its column sums per 64 rows [2*ceil(B/128)][out]
   float *dA = nullptr, *dZ32 = nullptr;        // hidden gradients [B][h]
-  __bf16 *dZb = nullptr, *dZt = nullptr;
+  __bf16 *dZb = nullptr;
   float *P = nullptr;                          // split-K partials
   size_t P_n = 0;
   double *loss = nullptr;
@@ -91,18 +91,13 @@ static void free_acts(Acts &a) {
     if (p) (void)hipFree(p);
   };
   f(a.Xb);
-  f(a.Xt);
   for (auto p : a.Z) f(p);
   for (auto p : a.Ab) f(p);
-  for (auto p : a.At) f(p);
-  f(a.Y);
-  f(a.d32);
   f(a.db);
-  f(a.dt);
+  f(a.PB);
   f(a.dA);
   f(a.dZ32);
   f(a.dZb);
-  f(a.dZt);
   f(a.P);
   f(a.loss);
   a = Acts{};
@@ -110,12 +105,16 @@ static void free_acts(Acts &a) {
 
 static void free_mlp(kfp_mlp *m) {
   for (auto &l : m->L) {
-    for (void *p : {(void *)l.W, (void *)l.b, (void *)l.Wb, (void *)l.Wt, (void *)l.mW,
-                    (void *)l.vW, (void *)l.mb, (void *)l.vb, (void *)l.gW, (void *)l.gb})
+    for (void *p : {(void *)l.W, (void *)l.b, (void *)l.Wb, (void *)l.mW, (void *)l.vW,
+                    (void *)l.mb, (void *)l.vb, (void *)l.gW, (void *)l.gb})
       if (p) (void)hipFree(p);
   }
   free_acts(m->A);
 }
+
+// rows of the per-64-row column sums of the output gradient (two per
+// 128-row tile of the batch)
+static int pb_rows(int B) { return 2 * ((B + 127) / 128); }
 
 static kfp_status ensure_acts(kfp_mlp *m, int B) {
   if (m->A.cap >= B) return KFP_OK;
@@ -123,40 +122,62 @@ static kfp_status ensure_acts(kfp_mlp *m, int B) {
   Acts &a = m->A;
   const int nh = m->depth;
   MHIP(dmalloc(&a.Xb, (size_t)B * m->in));
-  MHIP(dmalloc(&a.Xt, (size_t)B * m->in));
   a.Z.assign(nh, nullptr);
   a.Ab.assign(nh, nullptr);
-  a.At.assign(nh, nullptr);
   for (int l = 0; l < nh; ++l) {
     // the last hidden activations sit beside a copy of the input with skip
     const size_t w = (size_t)m->hidden + ((m->skip && l == nh - 1) ? m->in : 0);
     MHIP(dmalloc(&a.Z[l], (size_t)B * m->hidden));
     MHIP(dmalloc(&a.Ab[l], (size_t)B * w));
-    MHIP(dmalloc(&a.At[l], (size_t)B * w));
   }
-  MHIP(dmalloc(&a.Y, (size_t)B * m->out));
-  MHIP(dmalloc(&a.d32, (size_t)B * m->out));
   MHIP(dmalloc(&a.db, (size_t)B * m->out));
-  MHIP(dmalloc(&a.dt, (size_t)B * m->out));
+  MHIP(dmalloc(&a.PB, (size_t)pb_rows(B) * m->out));
   const size_t hmax = std::max(m->hidden, m->in);
   MHIP(dmalloc(&a.dA, (size_t)B * hmax));
   MHIP(dmalloc(&a.dZ32, (size_t)B * hmax));
   MHIP(dmalloc(&a.dZb, (size_t)B * hmax));
-  MHIP(dmalloc(&a.dZt, (size_t)B * hmax));
   MHIP(dmalloc(&a.loss, 1));
   a.cap = B;
   return KFP_OK;
 }
 
-// C = A B^T (NT) with the split-K decision: long reductions over small
-// outputs are cut into chunks whose partials a second pass sums in order.
+static int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
+// C = A B^T with the split-K decision: long reductions over few output
+// tiles (the input gradient of the wide layer) and short ones over very few
+// tiles (the hidden layers) are cut into chunks whose partials a second
+// pass sums in order and hands to the epilogue (store or Adam; the
+// squared-error epilogue takes the whole K per tile).
 static kfp_status gemm(kfp_mlp *m, GemmArgs g, hipStream_t s) {
-  if (g.K % 8 || g.lda % 8 || g.ldb % 8)
-    return mfail(KFP_EINVAL, "GEMM needs K, lda, ldb multiples of 8 (K=%d)", g.K);
+  if (g.K % 8 || g.lda % 8 || g.ldb % 8 || (g.a_kmajor && g.M % 8) || (g.b_kmajor && g.N % 8))
+    return mfail(KFP_EINVAL,
+                 "GEMM needs K, lda, ldb multiples of 8, and M (N) too for a K-major A (B) "
+                 "(M=%d N=%d K=%d)",
+                 g.M, g.N, g.K);
+  if (g.epi != EPI_STORE && (g.N % 8 || g.ldt % 4 || g.ldcb % 4 || g.ldw % 4))
+    return mfail(KFP_EINVAL, "fused GEMM epilogue needs N a multiple of 8 (N=%d)", g.N);
   const long tiles = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
   int splits = 1;
-  if (tiles < 512 && g.K >= 4096) {
-    splits = (int)std::min<long>((g.K + 2047) / 2048, std::max<long>(1, 2048 / tiles));
+  if (g.epi != EPI_MSE) {
+    // long reductions: one round of resident workgroups (three per compute
+    // unit at this kernel's register use)
+    if (tiles < 512 && g.K >= 4096)
+      splits = (int)std::min<long>((g.K + 2047) / 2048,
+                                   std::max<long>(1, 3L * cu_count() / tiles));
+    else if (tiles < 64 && g.K >= 128)
+      splits = (int)std::min<long>(g.K / 64, std::max<long>(1, 256 / tiles));
   }
   int kchunk = (g.K + splits - 1) / splits;
   kchunk = (kchunk + 31) / 32 * 32;
@@ -175,7 +196,7 @@ static kfp_status gemm(kfp_mlp *m, GemmArgs g, hipStream_t s) {
   } else {
     g.P = nullptr;
   }
-  MHIP(launch_gemm_nt(g, splits, s));
+  MHIP(launch_gemm(g, splits, s));
   return KFP_OK;
 }
 
@@ -191,8 +212,12 @@ static GemmArgs gargs(int M, int N, int K, const __bf16 *A, long lda, const __bf
   return g;
 }
 
-// Forward pass; the output goes to Y (FP32 [B][out]).
-static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream_t s) {
+// Forward pass.  Without targets the output goes to Y (FP32 [B][out]).
+// With targets T the output layer's epilogue forms the squared-error
+// gradient instead: A.db = BF16(scale (y - T)), its column sums per 64 rows
+// in A.PB, and sum (y - T)^2 added to A.loss; y itself is never stored.
+static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream_t s,
+                          const float *T = nullptr, float scale = 0.f) {
   kfp_status st = ensure_acts(m, B);
   if (st) return st;
   Acts &a = m->A;
@@ -212,6 +237,15 @@ static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream
       g.Cb = a.Ab[l];
       g.ldcb = wcat;
       g.gelu = 1;
+    } else if (T) {
+      g.epi = EPI_MSE;
+      g.T = T;
+      g.ldt = L.out;
+      g.scale = scale;
+      g.loss = a.loss;
+      g.PB = a.PB;
+      g.Cb = a.db;
+      g.ldcb = L.out;
     } else {
       g.C = Y;
       g.ldc = L.out;
@@ -226,45 +260,84 @@ static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream
   return KFP_OK;
 }
 
-static kfp_status backward(kfp_mlp *m, int B, const float *X, const float *T, double *loss_out,
-                           hipStream_t s) {
+struct AdamStep {
+  float lr, b1, b2, eps, c1, c2;
+};
+
+static AdamStep adam_next(kfp_mlp *m, float lr) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  m->step += 1;
+  return AdamStep{lr,  b1, b2, eps, 1.f - std::pow(b1, (float)m->step),
+                  1.f - std::pow(b2, (float)m->step)};
+}
+
+// Gradients of the mean squared error at (X, T).  With opt == nullptr they
+// are stored in gW / gb; otherwise each layer's weight-gradient product
+// applies the Adam step in its epilogue and the gradient is never stored.
+// Per layer, from the output back: bias gradient; input gradient (it reads
+// the layer's weights before their update); weight gradient (and update);
+// GELU derivative into the next layer's output gradient.
+static kfp_status backprop(kfp_mlp *m, int B, const float *X, const float *T, double *loss_out,
+                           const AdamStep *opt, hipStream_t s) {
   kfp_status st = ensure_acts(m, B);
   if (st) return st;
-  if ((st = forward(m, B, X, m->A.Y, s))) return st;
-  Acts &a = m->A;
   const int nl = (int)m->L.size();
+  if (!opt) {
+    for (auto &L : m->L)
+      if (!L.gW) MHIP(dmalloc(&L.gW, (size_t)L.out * L.in));
+  }
+  Acts &a = m->A;
   const size_t nout = (size_t)B * m->out;
   MHIP(hipMemsetAsync(a.loss, 0, sizeof(double), s));
-  MHIP(launch_mse_grad(a.Y, T, a.d32, a.db, nout, 2.0f / (float)nout, a.loss, s));
-  // gradient w.r.t. the pre-activation of layer l: FP32 (bias) and BF16
-  const float *d32 = a.d32;
-  const __bf16 *dbf = a.db;
-  __bf16 *dtr = a.dt;
+  if ((st = forward(m, B, X, nullptr, s, T, 2.0f / (float)nout))) return st;
+  const __bf16 *dbf = a.db;  // output gradient of layer l, [B][out_l]
   for (int l = nl - 1; l >= 0; --l) {
     Layer &L = m->L[l];
     const int outw = (int)L.out;
-    MHIP(launch_colsum(d32, B, outw, L.gb, s));
-    // weight gradient: dW[o][i] = sum_b d^T[o][b] act^T[i][b]
-    MHIP(launch_transpose_bf16(dbf, dtr, B, outw, s));
-    const __bf16 *act = (l == 0) ? a.Xb : a.Ab[l - 1];
-    __bf16 *actT = (l == 0) ? a.Xt : a.At[l - 1];
-    MHIP(launch_transpose_bf16(act, actT, B, L.in, s));
-    GemmArgs gw = gargs(outw, L.in, B, dtr, B, actT, B);
-    gw.C = L.gW;
-    gw.ldc = L.in;
-    if ((st = gemm(m, gw, s))) return st;
-    if (l == 0) break;
-    // input gradient: dA[b][i] = sum_o d[b][o] W^T[i][o], over the hidden
-    // inputs only (the input columns of a skip layer end there)
+    if (l == nl - 1)
+      MHIP(launch_colsum(a.PB, pb_rows(B), outw, L.gb, s));
+    else
+      MHIP(launch_colsum(a.dZ32, B, outw, L.gb, s));
+    // input gradient dA[b][i] = sum_o d[b][o] W[o][i] over the hidden inputs
+    // only (the input columns of a skip layer end there); W read K-major
     const int hin = (m->skip && l == nl - 1) ? m->hidden : L.in;
-    GemmArgs gx = gargs(B, hin, outw, dbf, outw, L.Wt, outw);
-    gx.C = a.dA;
-    gx.ldc = hin;
-    if ((st = gemm(m, gx, s))) return st;
+    if (l > 0) {
+      GemmArgs gx = gargs(B, hin, outw, dbf, outw, L.Wb, L.in);
+      gx.b_kmajor = 1;
+      gx.C = a.dA;
+      gx.ldc = hin;
+      if ((st = gemm(m, gx, s))) return st;
+    }
+    // weight gradient dW[o][i] = sum_b d[b][o] act[b][i]: both operands
+    // K-major with K = batch
+    const __bf16 *act = (l == 0) ? a.Xb : a.Ab[l - 1];
+    GemmArgs gw = gargs(outw, L.in, B, dbf, outw, act, L.in);
+    gw.a_kmajor = 1;
+    gw.b_kmajor = 1;
+    if (opt) {
+      gw.epi = EPI_ADAM;
+      gw.W = L.W;
+      gw.Mo = L.mW;
+      gw.Vo = L.vW;
+      gw.Wb = L.Wb;
+      gw.ldw = L.in;
+      gw.lr = opt->lr;
+      gw.b1 = opt->b1;
+      gw.b2 = opt->b2;
+      gw.eps = opt->eps;
+      gw.c1 = opt->c1;
+      gw.c2 = opt->c2;
+    } else {
+      gw.C = L.gW;
+      gw.ldc = L.in;
+    }
+    if ((st = gemm(m, gw, s))) return st;
+    if (opt)
+      MHIP(launch_adam(L.b, L.gb, L.mb, L.vb, nullptr, (size_t)L.out, opt->lr, opt->b1, opt->b2,
+                       opt->eps, opt->c1, opt->c2, s));
+    if (l == 0) break;
     MHIP(launch_gelu_back(a.dA, a.Z[l - 1], a.dZ32, a.dZb, (size_t)B * hin, s));
-    d32 = a.dZ32;
     dbf = a.dZb;
-    dtr = a.dZt;
   }
   if (loss_out) {
     double h = 0.0;
@@ -276,15 +349,14 @@ static kfp_status backward(kfp_mlp *m, int B, const float *X, const float *T, do
 }
 
 static kfp_status adam(kfp_mlp *m, float lr, hipStream_t s) {
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  m->step += 1;
-  const float c1 = 1.f - std::pow(b1, (float)m->step);
-  const float c2 = 1.f - std::pow(b2, (float)m->step);
+  for (auto &L : m->L)
+    if (!L.gW) return mfail(KFP_EINVAL, "adam: no stored gradients (kfp_mlp_backward first)");
+  const AdamStep o = adam_next(m, lr);
   for (auto &L : m->L) {
     const size_t nw = (size_t)L.out * L.in;
-    MHIP(launch_adam(L.W, L.gW, L.mW, L.vW, L.Wb, nw, lr, b1, b2, eps, c1, c2, s));
-    MHIP(launch_adam(L.b, L.gb, L.mb, L.vb, nullptr, (size_t)L.out, lr, b1, b2, eps, c1, c2, s));
-    MHIP(launch_transpose_bf16(L.Wb, L.Wt, (int)L.out, L.in, s));
+    MHIP(launch_adam(L.W, L.gW, L.mW, L.vW, L.Wb, nw, o.lr, o.b1, o.b2, o.eps, o.c1, o.c2, s));
+    MHIP(launch_adam(L.b, L.gb, L.mb, L.vb, nullptr, (size_t)L.out, o.lr, o.b1, o.b2, o.eps, o.c1,
+                     o.c2, s));
   }
   return KFP_OK;
 }
@@ -293,7 +365,6 @@ static kfp_status refresh_copies(kfp_mlp *m, hipStream_t s) {
   for (auto &L : m->L) {
     const size_t nw = (size_t)L.out * L.in;
     MHIP(launch_f32_to_bf16(L.W, L.Wb, nw, s));
-    MHIP(launch_transpose_bf16(L.Wb, L.Wt, (int)L.out, L.in, s));
   }
   return KFP_OK;
 }
@@ -327,9 +398,8 @@ static kfp_status create(int in, int hidden, int depth, long out, int flags,
       return false;
     };
     if (bad(dmalloc(&L.W, nw)) || bad(dmalloc(&L.b, L.out)) || bad(dmalloc(&L.Wb, nw)) ||
-        bad(dmalloc(&L.Wt, nw)) || bad(dmalloc(&L.mW, nw)) || bad(dmalloc(&L.vW, nw)) ||
-        bad(dmalloc(&L.mb, L.out)) || bad(dmalloc(&L.vb, L.out)) || bad(dmalloc(&L.gW, nw)) ||
-        bad(dmalloc(&L.gb, L.out)))
+        bad(dmalloc(&L.mW, nw)) || bad(dmalloc(&L.vW, nw)) || bad(dmalloc(&L.mb, L.out)) ||
+        bad(dmalloc(&L.vb, L.out)) || bad(dmalloc(&L.gb, L.out)))
       return mfail(KFP_ENOMEM, "device allocation of the network failed");
     hipError_t e = hipSuccess;
     if (init) {
@@ -403,7 +473,7 @@ kfp_status kfp_mlp_backward(kfp_mlp *m, int32_t B, const float *X, const float *
   m_err.clear();
   if (!m || !X || !T || B < 8 || B % 8)
     return mfail(KFP_EINVAL, "backward: bad arguments (batch must be a multiple of 8)");
-  return backward(m, B, X, T, loss, (hipStream_t)stream);
+  return backprop(m, B, X, T, loss, nullptr, (hipStream_t)stream);
 }
 
 kfp_status kfp_mlp_adam(kfp_mlp *m, float lr, void *stream) {
@@ -419,9 +489,8 @@ kfp_status kfp_mlp_train_step(kfp_mlp *m, int32_t B, const float *X, const float
   m_err.clear();
   if (!m || !X || !T || B < 8 || B % 8 || !(lr >= 0.f))
     return mfail(KFP_EINVAL, "train_step: bad arguments (batch must be a multiple of 8)");
-  kfp_status st = backward(m, B, X, T, loss, (hipStream_t)stream);
-  if (st) return st;
-  return adam(m, lr, (hipStream_t)stream);
+  const AdamStep o = adam_next(m, lr);
+  return backprop(m, B, X, T, loss, &o, (hipStream_t)stream);
 }
 
 kfp_status kfp_mlp_layer_shape(const kfp_mlp *m, int32_t layer, int32_t *in, int64_t *out) {
@@ -440,15 +509,13 @@ kfp_status kfp_mlp_param(kfp_mlp *m, int32_t layer, int32_t which, int32_t set, 
     return mfail(KFP_EINVAL, "param: bad arguments");
   Layer &L = m->L[layer];
   float *p = which == 0 ? L.W : which == 1 ? L.b : which == 2 ? L.gW : L.gb;
+  if (!p) return mfail(KFP_EINVAL, "param: no stored weight gradient (kfp_mlp_backward first)");
   const size_t n = (which == 0 || which == 2) ? (size_t)L.out * L.in : (size_t)L.out;
   hipStream_t s = (hipStream_t)stream;
   if (set) {
     if (which > 1) return mfail(KFP_EINVAL, "param: gradients are read-only");
     MHIP(hipMemcpyAsync(p, buf, n * sizeof(float), hipMemcpyDeviceToDevice, s));
-    if (which == 0) {
-      MHIP(launch_f32_to_bf16(L.W, L.Wb, n, s));
-      MHIP(launch_transpose_bf16(L.Wb, L.Wt, (int)L.out, L.in, s));
-    }
+    if (which == 0) MHIP(launch_f32_to_bf16(L.W, L.Wb, n, s));
   } else {
     MHIP(hipMemcpyAsync(buf, p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
   }

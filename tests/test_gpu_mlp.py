@@ -54,10 +54,12 @@ def test_forward_matches_oracle(sizes, B, skip):
 
 
 @pytest.mark.parametrize("skip", [False, True])
-@pytest.mark.parametrize("sizes,B", [([16, 32, 32, 40], 16), ([64, 128, 128, 128, 8192], 24)])
+@pytest.mark.parametrize("sizes,B", [([16, 32, 32, 40], 16), ([64, 128, 128, 128, 8192], 24),
+                                     ([24, 136, 264], 200)])
 def test_gradients_match_oracle(sizes, B, skip):
     """The second case has a reduction of length 8192 in the input gradient of
-    the last layer, which takes the split-K path."""
+    the last layer, which takes the split-K path; the third has ragged tiles
+    in every product (a batch of 200 over 128-row tiles, widths 136 and 264)."""
     print(f"mlp grads sizes={sizes} B={B} skip={skip}", flush=True)
     net, params = build(sizes, 5, skip)
     rng = np.random.default_rng(6)
@@ -90,6 +92,38 @@ def test_adam_step_matches_oracle():
     for l, (W, b) in enumerate(om.params):
         assert rel(net.get(l, "W").cpu().numpy(), W) <= 1e-4
         assert rel(net.get(l, "b").cpu().numpy(), b) <= 1e-3
+
+
+@pytest.mark.parametrize("skip", [False, True])
+@pytest.mark.parametrize("B", [40, 160])
+def test_fused_train_step_equals_backward_then_adam(skip, B):
+    """kfp_mlp_train_step applies Adam inside the weight-gradient product and
+    never stores the gradient; kfp_mlp_backward + kfp_mlp_adam store it and
+    update in a separate pass.  Same products, same update arithmetic: the
+    weights agree bit for bit after several steps.  With a batch of 160 the
+    hidden weight gradients take the split-K path, whose reduction pass
+    applies the update."""
+    sizes = [64, 128, 128, 136]
+    a, _ = build(sizes, 11, skip)
+    b, _ = build(sizes, 11, skip)
+    rng = np.random.default_rng(12)
+    X = torch.from_numpy(rng.standard_normal((B, sizes[0])).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((B, sizes[-1])).astype(np.float32)).cuda()
+    for step in range(3):
+        la = a.train_step(X, T, lr=1e-3)
+        lb = b.backward(X, T)
+        b.adam(1e-3)
+        assert la == pytest.approx(lb, rel=1e-12)  # FP64 atomics in either order
+    for l in range(a.layers()):
+        assert torch.equal(a.get(l, "W"), b.get(l, "W")), l
+        assert torch.equal(a.get(l, "b"), b.get(l, "b")), l
+    # the fused step stores no weight gradient
+    c, _ = build(sizes, 11, skip)
+    c.train_step(X, T, lr=1e-3)
+    with pytest.raises(kfp.KfpError):
+        c.get(0, "dW")
+    with pytest.raises(kfp.KfpError):
+        c.adam(1e-3)
 
 
 def test_training_fits_a_linear_map_and_checkpoint_round_trip(tmp_path):
