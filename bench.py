@@ -24,8 +24,11 @@ vector peak, the VALU-busy share of the counter profile, and the copy
 bandwidth the library's copy kernel reaches on this GPU.
 
 Also reported once, beside the timed iterations: the time to an absolute
-residual of 1e-10 in the parallel order from zero traces and in red-black
-order on 4 time windows (each from the extension of its start state); the
+residual of 1e-10 in the parallel order from zero traces, from the u0
+extension and from a learned guess (trained here on coarse solves of the
+same J, overlap, T and p, carried to the full grid through the traces'
+x-Fourier coefficients), and in red-black order on 4 time windows (each
+from the extension of its start state); the
 time to 1e-10 with and without learned initial traces on the learned-traces
 shape (256 x 256, Nt = 512, J = 4), the network trained here on a bounded
 number of seeded solves (`learned_guess`); and the oracle on the host cores
@@ -98,6 +101,12 @@ def compulsory_bytes_per_launch(rows, steps):
     return 8.0 * NX * (3.0 * rows + per_level * steps)
 
 
+def progress(msg):
+    """A line on stderr as each part of the run finishes (stdout carries
+    only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +119,10 @@ def parse():
                     help="training solves of the learned-guess leg")
     ap.add_argument("--learned-eval", type=int, default=64,
                     help="held-out seeds of the learned-guess leg")
+    ap.add_argument("--no-learned-large", action="store_true",
+                    help="skip the u0-extension and learned starts of the benchmark shape")
+    ap.add_argument("--learned-large-train", type=int, default=256,
+                    help="coarse training solves of the benchmark shape's learned guess")
     ap.add_argument("--scheme", choices=["fd", "fem"], default="fd")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the copy-kernel bandwidth probe (MiB)")
@@ -162,6 +175,51 @@ def cpu_baseline(gpu_iters):
             "extrapolated_with_iterations": gpu_iters}
 
 
+def large_starts(U0, F, zero, ntrain):
+    """The benchmark shape solved to 1e-10 in the parallel order from the
+    u0 extension and from the learned guess: linear BF16 stages trained
+    inside this run on `ntrain` coarse solves (512 x 512 x 1024, the same
+    J, overlap, T and p; seeds 1..ntrain, the workload's seed 0 held out),
+    predicting the x-Fourier coefficients of the traces, evaluated on the
+    full grid by kfp_trace_synth.  Times include the guess."""
+    import torch
+
+    import paper_1306_4596_amd as kfp
+    from paper_1306_4596_amd import inputs, workloads
+
+    out = {}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lam0 = kfp.u0_guess(U0, NT, J, OVERLAP, TR, P_MAIN)
+    _, _, su = kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL, max_iter=1000,
+                             lambda_init=lam0, history=False)
+    torch.cuda.synchronize()
+    out["parallel_u0"] = {"iters": su.iters, "seconds": round(time.perf_counter() - t1, 3),
+                          "residual": su.residual}
+    progress(f"parallel order from the u0 extension: {su.iters} iterations")
+    del lam0
+    kfp.release_workspace()
+    g, rec = workloads.learned_large_guess(ntrain, log=progress)
+    progress(f"coarse guess trained ({rec['generate_s']} s generating, {rec['train_s']} s training)")
+    kfp.release_workspace()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lam0 = g.predict(inputs.coefficients(0), NT, NX)[0]
+    _, _, sl = kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=TOL, max_iter=1000,
+                             lambda_init=lam0, history=False)
+    torch.cuda.synchronize()
+    secs = round(time.perf_counter() - t1, 3)
+    out["parallel_learned"] = {"iters": sl.iters, "seconds": secs, "residual": sl.residual,
+                               "training": rec}
+    progress(f"parallel order from the learned guess: {sl.iters} iterations")
+    out["time_saved_learned_vs_zero"] = 1.0 - secs / zero["seconds"]
+    out["time_saved_learned_vs_u0"] = 1.0 - secs / out["parallel_u0"]["seconds"]
+    del lam0, g
+    kfp.release_workspace()
+    torch.cuda.empty_cache()
+    return out
+
+
 def learned_leg(ntrain, neval):
     """Time to 1e-10 with and without learned initial traces on the
     learned-traces shape (256 x 256, Nt = 512, T = 0.5, J = 4, overlap 2,
@@ -178,7 +236,7 @@ def learned_leg(ntrain, neval):
 
     shape = learned.SHAPE_256
     t0 = time.perf_counter()
-    X, Y, _ = learned.generate(shape, range(ntrain), base="u0")
+    X, Y, _ = learned.generate(shape, range(ntrain), base="u0", log=progress)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     nets, t_train = {}, {}
@@ -195,8 +253,9 @@ def learned_leg(ntrain, neval):
         torch.cuda.synchronize()
         t_train[name] = round(time.perf_counter() - t0, 2)
         nets[name] = g
+        progress(f"learned-traces shape: network {name} trained ({t_train[name]} s)")
     del X, Y
-    ev = learned.evaluate(shape, range(20000, 20000 + neval), nets)
+    ev = learned.evaluate(shape, range(20000, 20000 + neval), nets, log=progress)
     summ = learned.summarize(ev)
     keep = ("iters_mean", "iters_median", "seconds_mean", "seconds_median", "guess_err_median",
             "max_rel_l2_vs_zero_guess")
@@ -256,10 +315,12 @@ def main():
     if args.warmup > 0:
         iterate(args.warmup)
     torch.cuda.synchronize()
+    progress(f"warm-up done ({args.warmup} iterations)")
     t0 = time.perf_counter()
     _, _, st = iterate(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    progress(f"timed {args.steps} iterations: {wall:.3f} s")
     if st.iters != args.steps:
         raise SystemExit(f"expected {args.steps} iterations, ran {st.iters}")
     value = st.cell_steps / wall
@@ -329,6 +390,9 @@ def main():
         gpu_iters = s0.iters
         solves["parallel_zero"] = {"iters": s0.iters, "seconds": round(time.perf_counter() - t1, 3),
                                    "residual": s0.residual}
+        progress(f"parallel order from zero: {s0.iters} iterations")
+        if not args.no_learned_large:
+            solves.update(large_starts(U0, F, solves["parallel_zero"], args.learned_large_train))
         kfp.set_ordering(kfp.RED_BLACK)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -338,6 +402,7 @@ def main():
         solves["red_black_4_windows_u0"] = {"iters": its,
                                             "seconds": round(time.perf_counter() - t1, 3),
                                             "residual": s1.residual}
+        progress(f"red-black order on 4 windows: {its} iterations")
         kfp.set_ordering(kfp.PARALLEL)
         out["time_to_tol"] = {"tol": TOL, **solves}
     if not args.no_learned:
@@ -347,6 +412,7 @@ def main():
         out["learned_guess"] = learned_leg(args.learned_train, args.learned_eval)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(gpu_iters)
+        progress("CPU baseline done")
     print(json.dumps(out))
 
 

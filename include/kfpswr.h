@@ -459,6 +459,27 @@ kfp_status kfp_standardize(float *X, int32_t rows, int64_t cols, const float *me
 kfp_status kfp_destandardize(const float *Y, int32_t rows, int64_t cols, const float *mean,
                              const float *stdv, const double *base, double *lam, void *stream);
 
+/* Traces as x-Fourier coefficients.  Every operator of the discretisation is
+ * circulant in the periodic x direction (upwind transport (6.4)/(6.5) and a
+ * v-solve that is the same for every column), so fields made of the
+ * discrete modes cos/sin(2 pi m x_i), x_i = i/nx, give traces made of
+ * exactly those modes at every level.  Device pointers, asynchronous;
+ * modes: [host] nmodes (1..8) frequencies, each 1 <= m < nx/2.
+ * kfp_trace_modes: for each row r of lam[rows][nx] (FP64),
+ *   coef[r][2k]   = (2/nx) sum_i lam[r][i] cos(2 pi m_k i/nx),
+ *   coef[r][2k+1] = (2/nx) sum_i lam[r][i] sin(2 pi m_k i/nx).
+ * kfp_trace_synth: the inverse on another grid: lam[p][n][i] (FP64,
+ *   [planes][nt][nx]) = sum_k a_k cos(2 pi m_k i/nx) + b_k sin(2 pi m_k i/nx),
+ *   with (a_k, b_k) of level n (time (n+1)/nt of the window) interpolated
+ *   linearly between the levels of coef[planes][ntc][2 nmodes] (level kc at
+ *   time (kc+1)/ntc), held at the first and last level outside them.
+ * Used to carry traces predicted on a coarse grid to a fine one. */
+kfp_status kfp_trace_modes(const double *lam, int64_t rows, int32_t nx, int32_t nmodes,
+                           const int32_t *modes, double *coef, void *stream);
+kfp_status kfp_trace_synth(const double *coef, int32_t planes, int32_t ntc, int32_t nmodes,
+                           const int32_t *modes, int32_t nt, int32_t nx, double *lam,
+                           void *stream);
+
 /* Frees all cached workspace (plans, graphs, trace windows). */
 void kfp_release_workspace(void);
 

@@ -23,6 +23,8 @@ from .binding import (  # noqa: F401
     cast_f64_f32,
     column_stats,
     destandardize,
+    trace_modes,
+    trace_synth,
     get_config,
     get_batch_launch,
     get_launch,

@@ -568,6 +568,11 @@ def _mlp_sigs(lib):
     lib.kfp_mul_f32.argtypes = [vp, vp, i64, vp]
     lib.kfp_standardize.argtypes = [vp, i32, i64, vp, vp, vp]
     lib.kfp_destandardize.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
+    pi32 = ctypes.POINTER(i32)
+    lib.kfp_trace_modes.argtypes = [vp, i64, i32, i32, pi32, vp, vp]
+    lib.kfp_trace_synth.argtypes = [vp, i32, i32, i32, pi32, i32, i32, vp, vp]
+    lib.kfp_trace_modes.restype = ctypes.c_int
+    lib.kfp_trace_synth.restype = ctypes.c_int
     for n in ("kfp_mlp_create", "kfp_mlp_create_ex", "kfp_mlp_forward", "kfp_mlp_backward", "kfp_mlp_adam",
               "kfp_mlp_train_step", "kfp_mlp_layer_shape", "kfp_mlp_param", "kfp_mlp_save",
               "kfp_mlp_load", "kfp_cast_f64_f32", "kfp_column_stats", "kfp_standardize",
@@ -760,3 +765,50 @@ def destandardize(Y, mean, std, out=None, base=None, stream=None):
     _check(lib.kfp_destandardize(_fptr(Y, torch.float32), int(rows), int(cols), _fptr(mean),
                                  _fptr(std), bp, _fptr(lam, torch.float64), _stream(stream)))
     return lam
+
+
+def _modes_arg(modes):
+    m = [int(x) for x in modes]
+    if not 1 <= len(m) <= 8:
+        raise ValueError("1..8 x frequencies")
+    return len(m), (ctypes.c_int32 * len(m))(*m)
+
+
+def trace_modes(lam, modes, out=None, stream=None):
+    """x-Fourier coefficients of trace rows: lam [..., nx] FP64 ->
+    [..., 2 len(modes)] with (cos, sin) coefficient pairs per frequency."""
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    if lam.dim() < 1:
+        raise ValueError("trace_modes: lam needs an x dimension")
+    nx = int(lam.shape[-1])
+    rows = lam.numel() // max(nx, 1)
+    nm, arr = _modes_arg(modes)
+    shape = tuple(lam.shape[:-1]) + (2 * nm,)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=lam.device)
+    _expect(out, shape, "out")
+    _check(lib.kfp_trace_modes(_fptr(lam, torch.float64), int(rows), nx, nm, arr,
+                               _fptr(out, torch.float64), _stream(stream)))
+    return out
+
+
+def trace_synth(coef, modes, nt, nx, out=None, stream=None):
+    """Traces [planes][nt][nx] FP64 from x-Fourier coefficients
+    coef [planes][ntc][2 len(modes)], linear in time between coefficient
+    levels (see kfp_trace_synth)."""
+    import torch
+
+    lib = _mlp_sigs(load_library())
+    nm, arr = _modes_arg(modes)
+    if coef.dim() != 3 or coef.shape[2] != 2 * nm:
+        raise ValueError(f"trace_synth: coef must be [planes][ntc][{2 * nm}]")
+    planes, ntc = int(coef.shape[0]), int(coef.shape[1])
+    shape = (planes, int(nt), int(nx))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=coef.device)
+    _expect(out, shape, "out")
+    _check(lib.kfp_trace_synth(_fptr(coef, torch.float64), planes, ntc, nm, arr, int(nt),
+                               int(nx), _fptr(out, torch.float64), _stream(stream)))
+    return out

@@ -68,6 +68,15 @@ hipError_t launch_colstats(const float *X, int R, size_t C, float *mean, float *
                            hipStream_t s);
 hipError_t launch_standardize(float *X, size_t per, size_t n, const float *mean, const float *stdv,
                               hipStream_t s);
+// x frequencies of a trace's Fourier coefficients (at most 8)
+struct TraceModes {
+  int n;
+  int m[8];
+};
+hipError_t launch_trace_modes(const double *lam, long rows, int nx, const TraceModes &md,
+                              double *coef, hipStream_t s);
+hipError_t launch_trace_synth(const double *coef, int planes, int ntc, int nt, int nx,
+                              const TraceModes &md, double *lam, hipStream_t s);
 hipError_t launch_init_normal(float *w, size_t n, float stdv, unsigned long long seed,
                               hipStream_t s);
 

@@ -631,4 +631,140 @@ hipError_t launch_init_normal(float *w, size_t n, float stdv, unsigned long long
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Trace planes as x-Fourier coefficients.  Every operator of the scheme is
+// circulant in the periodic x direction, so a field made of the discrete
+// modes cos/sin(2 pi m x_i), x_i = i/nx, keeps exactly those modes in every
+// trace; a trace row is then its 2 NM coefficients.  The angle 2 pi m i/nx
+// is reduced to the exact integer residue (m i) mod nx before sincospi.
+// ---------------------------------------------------------------------------
+template <int NM>
+__global__ __launch_bounds__(256) void trace_modes_kernel(const double *__restrict__ lam,
+                                                          long rows, int nx, TraceModes md,
+                                                          double *__restrict__ coef) {
+  __shared__ double part[4][2 * NM];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (long r = blockIdx.x; r < rows; r += gridDim.x) {
+    const double *row = lam + r * nx;
+    double acc[2 * NM];
+#pragma unroll
+    for (int j = 0; j < 2 * NM; ++j) acc[j] = 0.0;
+    for (int i = threadIdx.x; i < nx; i += 256) {
+      const double x = row[i];
+#pragma unroll
+      for (int k = 0; k < NM; ++k) {
+        const long q = ((long)md.m[k] * i) % nx;
+        double sn, cs;
+        sincospi(2.0 * (double)q / (double)nx, &sn, &cs);
+        acc[2 * k] += x * cs;
+        acc[2 * k + 1] += x * sn;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * NM; ++j) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 2 * NM; ++j) part[w][j] = acc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NM) {
+      const int j = threadIdx.x;
+      coef[r * 2 * NM + j] =
+          (2.0 / nx) * (((part[0][j] + part[1][j]) + part[2][j]) + part[3][j]);
+    }
+    __syncthreads();
+  }
+}
+
+// lam[p][n][i] from coef[p][ntc][2 NM]: the coefficients of fine level n
+// (time (n+1)/nt of the window) interpolated linearly between coarse levels
+// (level kc at time (kc+1)/ntc), held at the first and last coarse level
+// outside them.  Workgroup: 256 columns x 16 plane-levels per pass.
+template <int NM>
+__global__ __launch_bounds__(256) void trace_synth_kernel(const double *__restrict__ coef,
+                                                          int planes, int ntc, int nt, int nx,
+                                                          TraceModes md,
+                                                          double *__restrict__ lam) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double cs[NM], sn[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    const long q = ((long)md.m[k] * (i < nx ? i : 0)) % nx;
+    sincospi(2.0 * (double)q / (double)nx, &sn[k], &cs[k]);
+  }
+  const long rows = (long)planes * nt;
+  for (long r0 = (long)blockIdx.y * 16; r0 < rows; r0 += (long)gridDim.y * 16) {
+    const int rend = (int)(rows - r0 < 16 ? rows - r0 : 16);
+    for (int rr = 0; rr < rend; ++rr) {
+      const long r = r0 + rr;
+      const int p = (int)(r / nt), n = (int)(r % nt);
+      const double sc = (double)(n + 1) * ntc / nt - 1.0;
+      int k0, k1;
+      double wt;
+      if (sc <= 0.0) {
+        k0 = k1 = 0;
+        wt = 0.0;
+      } else if (sc >= ntc - 1) {
+        k0 = k1 = ntc - 1;
+        wt = 0.0;
+      } else {
+        k0 = (int)sc;
+        k1 = k0 + 1;
+        wt = sc - k0;
+      }
+      const double *c0 = coef + ((long)p * ntc + k0) * 2 * NM;
+      const double *c1 = coef + ((long)p * ntc + k1) * 2 * NM;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NM; ++k) {
+        const double a = c0[2 * k] + wt * (c1[2 * k] - c0[2 * k]);
+        const double b = c0[2 * k + 1] + wt * (c1[2 * k + 1] - c0[2 * k + 1]);
+        v += a * cs[k] + b * sn[k];
+      }
+      if (i < nx) lam[r * nx + i] = v;
+    }
+  }
+}
+
+hipError_t launch_trace_modes(const double *lam, long rows, int nx, const TraceModes &md,
+                              double *coef, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)(rows < 65536 ? rows : 65536);
+#define KFP_TM(N)                                                                       \
+  case N:                                                                               \
+    hipLaunchKernelGGL(trace_modes_kernel<N>, dim3(grid), dim3(256), 0, s, lam, rows, nx, \
+                       md, coef);                                                       \
+    break;
+  switch (md.n) {
+    KFP_TM(1) KFP_TM(2) KFP_TM(3) KFP_TM(4) KFP_TM(5) KFP_TM(6) KFP_TM(7) KFP_TM(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef KFP_TM
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_synth(const double *coef, int planes, int ntc, int nt, int nx,
+                              const TraceModes &md, double *lam, hipStream_t s) {
+  const long rows = (long)planes * nt;
+  if (rows <= 0 || nx <= 0) return hipSuccess;
+  const long ychunks = (rows + 15) / 16;
+  dim3 grid((unsigned)((nx + 255) / 256), (unsigned)(ychunks < 65535 ? ychunks : 65535));
+#define KFP_TS(N)                                                                          \
+  case N:                                                                                  \
+    hipLaunchKernelGGL(trace_synth_kernel<N>, grid, dim3(256), 0, s, coef, planes, ntc, nt, \
+                       nx, md, lam);                                                       \
+    break;
+  switch (md.n) {
+    KFP_TS(1) KFP_TS(2) KFP_TS(3) KFP_TS(4) KFP_TS(5) KFP_TS(6) KFP_TS(7) KFP_TS(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef KFP_TS
+  return hipGetLastError();
+}
+
 }  // namespace kfp

@@ -645,4 +645,44 @@ kfp_status kfp_destandardize(const float *Y, int32_t rows, int64_t cols, const f
   return KFP_OK;
 }
 
+static kfp_status trace_modes_arg(int32_t nx, int32_t nmodes, const int32_t *modes,
+                                  TraceModes *md) {
+  if (nx < 1 || nmodes < 1 || nmodes > 8 || !modes)
+    return mfail(KFP_EINVAL, "trace modes: nx >= 1 and 1..8 frequencies are required");
+  md->n = nmodes;
+  for (int k = 0; k < 8; ++k) md->m[k] = 0;
+  for (int k = 0; k < nmodes; ++k) {
+    if (modes[k] < 1 || 2 * modes[k] >= nx)
+      return mfail(KFP_EINVAL, "trace modes: frequency %d outside 1 .. nx/2 - 1 (nx = %d)",
+                   modes[k], nx);
+    md->m[k] = modes[k];
+  }
+  return KFP_OK;
+}
+
+kfp_status kfp_trace_modes(const double *lam, int64_t rows, int32_t nx, int32_t nmodes,
+                           const int32_t *modes, double *coef, void *stream) {
+  m_err.clear();
+  TraceModes md;
+  kfp_status st = trace_modes_arg(nx, nmodes, modes, &md);
+  if (st) return st;
+  if (rows < 0 || ((!lam || !coef) && rows > 0))
+    return mfail(KFP_EINVAL, "trace modes: bad arguments");
+  MHIP(launch_trace_modes(lam, (long)rows, nx, md, coef, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_trace_synth(const double *coef, int32_t planes, int32_t ntc, int32_t nmodes,
+                           const int32_t *modes, int32_t nt, int32_t nx, double *lam,
+                           void *stream) {
+  m_err.clear();
+  TraceModes md;
+  kfp_status st = trace_modes_arg(nx, nmodes, modes, &md);
+  if (st) return st;
+  if (planes < 1 || ntc < 1 || nt < 1 || !coef || !lam)
+    return mfail(KFP_EINVAL, "trace synth: bad arguments");
+  MHIP(launch_trace_synth(coef, planes, ntc, nt, nx, md, lam, (hipStream_t)stream));
+  return KFP_OK;
+}
+
 }  // extern "C"

@@ -17,6 +17,7 @@ import numpy as np
 # 16 fixed Fourier x Legendre modes: index k = 4 (mx - 1) + l, mx in 1..4, l in 0..3.
 N_MODES = 16
 N_COEF = 4 * N_MODES  # [a (cos, f), b (sin, f), c (cos, u0), d (sin, u0)]
+X_FREQS = (1, 2, 3, 4)  # the x frequencies m_x of the modes
 
 
 def grid(nx: int, nv: int):

@@ -57,6 +57,10 @@ class Shape:
 
 # 256 x 256, Nt = 512, J = 4, overlap 2, Robin p = 4
 SHAPE_256 = Shape(256, 256, 512, 0.5, 4, 2, kb.ROBIN, 4.0)
+# 4096 x 4096, Nt = 8192, T = 1, J = 32, overlap 2, Robin p = 8, and the
+# coarse grid its learned guess is trained on (same J, overlap, T and p)
+SHAPE_4096 = Shape(4096, 4096, 8192, 1.0, 32, 2, kb.ROBIN, 8.0)
+SHAPE_4096_COARSE = Shape(512, 512, 1024, 1.0, 32, 2, kb.ROBIN, 8.0)
 
 
 def coef_matrix(seeds):
@@ -154,15 +158,17 @@ class LearnedGuess:
     lambda^0 = base + sum over stages of (mean_k + std_k * net_k(x))."""
 
     def __init__(self, shape: Shape, hidden=512, depth=3, seed=0, base="u0", skip=True,
-                 refine=0, nets=None, lead_linear=False):
+                 refine=0, nets=None, lead_linear=False, n_out=None):
         self.shape = shape
         self.base = base
+        self.n_out = n_out or shape.n_out
         if nets is None:
+            no = self.n_out
             # lead_linear: a linear stage first, the (depth x hidden) network
             # fitted to what it leaves over, then the refinement stages
-            nets = [kb.MLP(N_FEAT, 8, 0, shape.n_out, seed=seed + 100)] if lead_linear else []
-            nets += [kb.MLP(N_FEAT, hidden, depth, shape.n_out, seed=seed, skip=skip)]
-            nets += [kb.MLP(N_FEAT, 8, 0, shape.n_out, seed=seed + 1 + k) for k in range(refine)]
+            nets = [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 100)] if lead_linear else []
+            nets += [kb.MLP(N_FEAT, hidden, depth, no, seed=seed, skip=skip)]
+            nets += [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 1 + k) for k in range(refine)]
         self.nets = nets
         self.means = []
         self.stds = []
@@ -222,6 +228,11 @@ class LearnedGuess:
         """Initial traces lambda^0 (FP64 [B][2(J-1)][nt][nx]) for coefficient
         rows; u0 ([B][nv+1][nx] or [nv+1][nx], FP64 on the GPU) is needed when
         the networks correct the u0-extension guess."""
+        s = self.shape
+        return self.predict_flat(coef, u0).reshape(-1, 2 * (s.J - 1), s.nt, s.nx)
+
+    def predict_flat(self, coef, u0=None):
+        """The summed stages (plus the base guess) as FP64 [B][n_out]."""
         import torch
 
         X = features(coef).cuda()
@@ -237,7 +248,7 @@ class LearnedGuess:
             lam = lam.reshape(X.shape[0], -1)
         for net, mean, std in zip(self.nets, self.means, self.stds):
             lam = kb.destandardize(net.forward(X), mean, std, base=lam)
-        return lam.reshape(-1, 2 * (s.J - 1), s.nt, s.nx)
+        return lam
 
     def save(self, prefix):
         import torch
@@ -254,10 +265,109 @@ class LearnedGuess:
 
         d = torch.load(prefix + ".std.pt", weights_only=True)
         nets = [kb.MLP.load(f"{prefix}.net{k}") for k in range(d["stages"])]
-        g = cls(Shape(**d["shape"]), base=d["base"], nets=nets)
+        g = cls(Shape(**d["shape"]), base=d["base"], nets=nets,
+                n_out=int(d["means"][0].numel()))
         g.means = [m.cuda() for m in d["means"]]
         g.stds = [x.cuda() for x in d["stds"]]
         return g
+
+
+def generate_modes(shape: Shape, seeds, modes=inputs.X_FREQS, batch=64, tol=1e-10,
+                   max_iter=1000, log=None):
+    """Training targets of every seed as x-Fourier coefficients: the
+    converged traces of each plane and level reduced to their (cos, sin)
+    pairs at `modes` (the frequencies of the fields, so nothing is lost),
+    FP32 [N][2(J-1) * nt * 2 len(modes)]; plus the network inputs and the
+    iteration counts."""
+    import torch
+
+    seeds = list(seeds)
+    N = len(seeds)
+    C = coef_matrix(seeds)
+    X = features(C).cuda()
+    nout = 2 * (shape.J - 1) * shape.nt * 2 * len(modes)
+    Y = torch.empty((N, nout), dtype=torch.float32, device="cuda")
+    iters = np.zeros(N, dtype=np.int32)
+    fm = FieldMaker(shape)
+    t0 = time.time()
+    for b0 in range(0, N, batch):
+        b1 = min(N, b0 + batch)
+        u0s, fs = fm.make(C[b0:b1])
+        U0 = torch.from_numpy(u0s).cuda()
+        F = torch.from_numpy(fs).cuda()
+        insts = [dict(u0=U0[i], f=F[i], T=shape.T, nt=shape.nt, J=shape.J, overlap=shape.overlap,
+                      tr=shape.tr, p=shape.p, want_lambda=True) for i in range(b1 - b0)]
+        res, rc = kb.swr_batch(insts, tol=tol, max_iter=max_iter)
+        if rc != 0:
+            raise RuntimeError("training solve did not converge")
+        for i, (_, lam, st) in enumerate(res):
+            c = kb.trace_modes(lam, modes)
+            kb.cast_f64_f32(c.reshape(-1), Y[b0 + i])
+            iters[b0 + i] = st.iters
+        del res, U0, F
+        if log:
+            log(f"generated {b1}/{N} coarse traces ({time.time() - t0:.1f} s, "
+                f"mean iterations {iters[:b1].mean():.1f})")
+    torch.cuda.synchronize()
+    return X, Y, iters
+
+
+class ModalGuess:
+    """A learned guess trained on a coarse grid and carried to a finer one.
+
+    The traces of fields made of the x frequencies `modes` consist of
+    exactly those frequencies, so each plane and level of the coarse
+    converged traces is stored as its (cos, sin) coefficient pairs.  Linear
+    BF16 stages (as LearnedGuess with depth 0) map the coefficients of the
+    fields to them; kfp_trace_synth evaluates the prediction on the fine
+    grid (exact in x, linear in time between coarse levels).  The coarse
+    grid has the fine one's J, overlap, T and transmission, so the trace
+    planes correspond; what is left is the coarse grid's discretisation
+    error, which the SWR iteration on the fine grid removes."""
+
+    def __init__(self, coarse: Shape, modes=inputs.X_FREQS, refine=1, seed=0, guess=None):
+        self.coarse = coarse
+        self.modes = tuple(int(m) for m in modes)
+        nout = 2 * (coarse.J - 1) * coarse.nt * 2 * len(self.modes)
+        self.g = guess or LearnedGuess(coarse, hidden=8, depth=0, seed=seed, base="zero",
+                                       skip=False, refine=refine, n_out=nout)
+
+    def fit(self, X, Y, **kw):
+        return self.g.fit(X, Y, **kw)
+
+    def coefficients(self, coef):
+        """Predicted coarse coefficients, FP64 [B][2(J-1)][ntc][2 len(modes)]."""
+        c = self.coarse
+        return self.g.predict_flat(coef).reshape(-1, 2 * (c.J - 1), c.nt, 2 * len(self.modes))
+
+    def predict(self, coef, nt, nx):
+        """Initial traces on the fine grid, FP64 [B][2(J-1)][nt][nx]."""
+        import torch
+
+        cc = self.coefficients(coef)
+        out = torch.empty((cc.shape[0], cc.shape[1], int(nt), int(nx)), dtype=torch.float64,
+                          device="cuda")
+        for b in range(cc.shape[0]):
+            kb.trace_synth(cc[b].contiguous(), self.modes, nt, nx, out=out[b])
+        return out
+
+
+def train_modal_guess(coarse: Shape, seeds, epochs=400, batch=64, lr=3e-3, refine=1, log=None):
+    """Generates the coarse training solves of `seeds` and fits a ModalGuess
+    to them; returns (guess, seconds generating, seconds training, mean
+    coarse iterations)."""
+    import torch
+
+    t0 = time.time()
+    X, Y, iters = generate_modes(coarse, seeds, log=log)
+    t_gen = time.time() - t0
+    g = ModalGuess(coarse, refine=refine)
+    t0 = time.time()
+    g.fit(X, Y, epochs=epochs, batch=batch, lr=lr, log=None)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    del X, Y
+    return g, t_gen, t_train, float(iters.mean())
 
 
 def evaluate(shape: Shape, seeds, guess=None, tol=1e-10, max_iter=500, log=None):

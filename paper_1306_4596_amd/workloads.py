@@ -100,18 +100,38 @@ def run_large(iters: int, configs):
     kb.set_config(0)
 
 
-def run_large_solve():
+def learned_large_guess(n_train, coarse=None, log=None):
+    """The learned guess of the 4096 x 4096 workload: a modal guess trained
+    on `n_train` coarse solves (seeds 1..n_train; the workload's own seed 0
+    is held out).  Returns the guess and a JSON-ready record."""
+    from . import learned
+
+    c = coarse or learned.SHAPE_4096_COARSE
+    g, t_gen, t_train, cit = learned.train_modal_guess(c, range(1, n_train + 1), log=log)
+    rec = {"coarse_grid": [c.nx, c.nv, c.nt], "train_seeds": n_train, "generate_s": round(t_gen, 2),
+           "train_s": round(t_train, 2), "coarse_iters_mean": cit,
+           "network": "linear BF16 stages on the x-Fourier coefficients of the coarse traces",
+           "modes": list(g.modes)}
+    return g, rec
+
+
+def run_large_solve(learned_train=0, orders=(0, 1)):
     import torch
 
     nx = nv = 4096
     nt, T, J, o, p = 8192, 1.0, 32, 2, 8.0
+    g = None
+    if learned_train > 0:
+        g, rec = learned_large_guess(learned_train, log=lambda m: print(m, flush=True))
+        print(json.dumps({"learned_guess": rec}), flush=True)
     u0, f = inputs.random_fields(0, nx, nv)
     U0 = torch.from_numpy(u0).cuda()
     F = torch.from_numpy(f).cuda()
     del u0, f
-    for order in (0, 1):
+    coef0 = inputs.coefficients(0)
+    for order in orders:
         kb.set_ordering(order)
-        for guess in ("zero", "u0", "windows4"):
+        for guess in ("zero", "u0") + (("learned",) if g else ()) + ("windows4",):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if guess == "windows4":
@@ -119,7 +139,10 @@ def run_large_solve():
                                                   max_iter=400, n_windows=4, guess=True)
                 iters = its
             else:
-                lam0 = kb.u0_guess(U0, nt, J, o, kb.ROBIN, p) if guess == "u0" else None
+                if guess == "learned":
+                    lam0 = g.predict(coef0, nt, nx)[0]
+                else:
+                    lam0 = kb.u0_guess(U0, nt, J, o, kb.ROBIN, p) if guess == "u0" else None
                 _, _, st = kb.swr_solve(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
                                         max_iter=400, lambda_init=lam0, history=False)
                 iters = st.iters
@@ -145,6 +168,10 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="batch: tune its launch classes first (kfp_tune_batch; the cache is "
                          "$KFP_TUNE_CACHE)")
+    ap.add_argument("--learned-train", type=int, default=0,
+                    help="large-solve: also solve from a learned guess trained on this many "
+                         "coarse solves")
+    ap.add_argument("--orders", default="0,1", help="large-solve: solve orders (0 parallel, 1 red-black)")
     ap.add_argument("--configs", nargs="*", default=[],
                     help="launch configurations waves,seg,steps[,groups[,tiles]] (default: "
                          "the library's choice)")
@@ -155,7 +182,7 @@ def main():
     if a.which == "batch":
         run_batch(a.n, order=a.order, tune=a.tune)
     elif a.which == "large-solve":
-        run_large_solve()
+        run_large_solve(a.learned_train, tuple(int(x) for x in a.orders.split(",") if x))
     else:
         cfgs = [tuple(int(x) for x in c.split(",")) for c in a.configs] or [None]
         run_large(a.iters, cfgs)

@@ -452,3 +452,28 @@ def test_network_io_shapes():
     ]:
         with pytest.raises(ValueError, match=frag):
             binding.check_mlp_io(64, 10, X, T, out)
+
+
+def test_trace_mode_arguments(lib):
+    """The x-Fourier trace helpers reject bad frequencies and sizes before
+    any device call."""
+    i32 = ctypes.c_int32
+    lib.kfp_trace_modes.argtypes = [ctypes.c_void_p, ctypes.c_int64, i32, i32,
+                                    ctypes.POINTER(i32), ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfp_trace_synth.argtypes = [ctypes.c_void_p, i32, i32, i32, ctypes.POINTER(i32), i32,
+                                    i32, ctypes.c_void_p, ctypes.c_void_p]
+    m = (i32 * 4)(1, 2, 3, 4)
+    assert lib.kfp_trace_modes(FAKE, 4, 8, 4, m, FAKE, None) == binding.KFP_EINVAL  # 2*4 >= 8
+    assert "frequency" in lib.kfp_last_error().decode()
+    assert lib.kfp_trace_modes(FAKE, 4, 64, 0, m, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_modes(FAKE, 4, 64, 9, m, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_modes(FAKE, 4, 64, 4, None, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_modes(None, 4, 64, 4, m, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_modes(FAKE, -1, 64, 4, m, FAKE, None) == binding.KFP_EINVAL
+    z = (i32 * 1)(0)
+    assert lib.kfp_trace_modes(FAKE, 4, 64, 1, z, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_synth(FAKE, 0, 4, 4, m, 8, 64, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_synth(FAKE, 2, 0, 4, m, 8, 64, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_synth(FAKE, 2, 4, 4, m, 0, 64, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_synth(FAKE, 2, 4, 4, m, 8, 6, FAKE, None) == binding.KFP_EINVAL
+    assert lib.kfp_trace_synth(None, 2, 4, 4, m, 8, 64, FAKE, None) == binding.KFP_EINVAL
