@@ -101,6 +101,16 @@ def compulsory_bytes_per_launch(rows, steps):
     return 8.0 * NX * (3.0 * rows + per_level * steps)
 
 
+def optional(name, fn, *a):
+    """Runs one reported-beside leg; a failure is recorded in its place
+    (and on stderr) instead of ending the run before the JSON line."""
+    try:
+        return fn(*a)
+    except Exception as e:  # noqa: BLE001 - any failure of a side leg
+        progress(f"{name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def progress(msg):
     """A line on stderr as each part of the run finishes (stdout carries
     only the JSON result)."""
@@ -392,7 +402,9 @@ def main():
                                    "residual": s0.residual}
         progress(f"parallel order from zero: {s0.iters} iterations")
         if not args.no_learned_large:
-            solves.update(large_starts(U0, F, solves["parallel_zero"], args.learned_large_train))
+            r = optional("u0 and learned starts", large_starts, U0, F, solves["parallel_zero"],
+                         args.learned_large_train)
+            solves.update(r if "error" not in r else {"learned_starts": r})
         kfp.set_ordering(kfp.RED_BLACK)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -409,9 +421,10 @@ def main():
         del U0, F
         kfp.release_workspace()
         torch.cuda.empty_cache()
-        out["learned_guess"] = learned_leg(args.learned_train, args.learned_eval)
+        out["learned_guess"] = optional("learned-traces leg", learned_leg, args.learned_train,
+                                        args.learned_eval)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(gpu_iters)
+        out["cpu_baseline"] = optional("CPU baseline", cpu_baseline, gpu_iters)
         progress("CPU baseline done")
     print(json.dumps(out))
 
