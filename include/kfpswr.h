@@ -359,6 +359,22 @@ kfp_status kfp_swr_solve_windows(const kfp_grid *g, const double *u0, const doub
                                  int32_t *window_iters, kfp_swr_stats *stats, void *stream);
 
 /*
+ * kfp_swr_solve_windows_init -- as kfp_swr_solve_windows, with each window's
+ * initial traces taken from lambda_init ([2(J-1)][nt][nx] FP64, device, the
+ * traces of the whole [0, T]): window w starts from its own levels of every
+ * plane.  Converged windows compose to the monodomain solution, so traces
+ * predicted for the whole interval (a learned guess) serve every window.
+ * lambda_init NULL with J > 1: KFP_EINVAL.  The call allocates one window
+ * of traces besides the two intermediate fields.
+ */
+kfp_status kfp_swr_solve_windows_init(const kfp_grid *g, const double *u0, const double *f,
+                                      const double *s, int32_t J, int32_t overlap, int32_t tr,
+                                      double p, double q, double tol, int32_t max_iter,
+                                      int32_t n_windows, const double *lambda_init, double *uT,
+                                      int32_t *window_iters, kfp_swr_stats *stats,
+                                      void *stream);
+
+/*
  * kfp_set_kernel_timing -- with on != 0, overlapped-iteration solves launch
  * their kernels directly (not from a replayed graph) with HIP events around
  * every time-step kernel launch, so that kfp_swr_stats.step_seconds holds

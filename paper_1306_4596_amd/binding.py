@@ -97,6 +97,9 @@ def load_library():
     lib.kfp_swr_solve_windows.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, f64, i32, i32,
                                           i32, vp, ctypes.POINTER(i32), ctypes.POINTER(Stats),
                                           vp]
+    lib.kfp_swr_solve_windows_init.argtypes = [G, vp, vp, D, i32, i32, i32, f64, f64, f64, i32,
+                                               i32, vp, vp, ctypes.POINTER(i32),
+                                               ctypes.POINTER(Stats), vp]
     lib.kfp_u0_guess.argtypes = [G, vp, i32, i32, i32, f64, vp, vp]
     lib.kfp_swr_batch.argtypes = [i32, ctypes.POINTER(Instance), f64, i32,
                                   ctypes.POINTER(Stats), vp]
@@ -120,6 +123,7 @@ def load_library():
     lib.kfp_last_error.argtypes = []
     lib.kfp_release_workspace.restype = None
     for name in ("kfp_mono_solve", "kfp_mono_solve_static", "kfp_swr_solve", "kfp_swr_solve_pq", "kfp_swr_solve_windows",
+                 "kfp_swr_solve_windows_init",
                  "kfp_u0_guess",
                  "kfp_u0_guess_pq", "kfp_swr_batch", "kfp_tune",
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
@@ -281,14 +285,16 @@ def swr_solve(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter
 
 
 def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, max_iter=200,
-                      n_windows=1, s=None, q=None, guess=False, stream=None):
+                      n_windows=1, s=None, q=None, guess=False, stream=None, lambda_init=None):
     """SWR on n_windows consecutive time windows (each from the glued end
-    state of the one before).  Returns (uT, per-window iteration counts,
-    SWRStats summed over the windows)."""
+    state of the one before).  lambda_init: traces of the whole [0, T]
+    ([2(J-1)][nt][nx]); each window starts from its levels of them (guess is
+    then ignored).  Returns (uT, per-window iteration counts, SWRStats summed
+    over the windows)."""
     import numpy as np
     import torch
 
-    nv, nx = _check_fields(u0, f, nt, J)
+    nv, nx = _check_fields(u0, f, nt, J, lambda_init=lambda_init)
     if int(n_windows) < 1:
         raise ValueError("n_windows must be >= 1")
     uT = torch.empty_like(u0)
@@ -296,10 +302,16 @@ def swr_solve_windows(u0, f, T, nt, J, overlap, transmission, p=0.0, tol=1e-10, 
     its = (ctypes.c_int32 * int(n_windows))()
     st = Stats()
     g = _grid(nx, nv, nt, T)
-    rc = load_library().kfp_swr_solve_windows(
-        ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J), int(overlap), int(transmission),
-        float(p), float(p if q is None else q), float(tol), int(max_iter), int(n_windows),
-        1 if guess else 0, _ptr(uT), its, ctypes.byref(st), _stream(stream))
+    if lambda_init is not None:
+        rc = load_library().kfp_swr_solve_windows_init(
+            ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J), int(overlap), int(transmission),
+            float(p), float(p if q is None else q), float(tol), int(max_iter), int(n_windows),
+            _ptr(lambda_init), _ptr(uT), its, ctypes.byref(st), _stream(stream))
+    else:
+        rc = load_library().kfp_swr_solve_windows(
+            ctypes.byref(g), _ptr(u0), _ptr(f), sp, int(J), int(overlap), int(transmission),
+            float(p), float(p if q is None else q), float(tol), int(max_iter), int(n_windows),
+            1 if guess else 0, _ptr(uT), its, ctypes.byref(st), _stream(stream))
     _check(rc, allow_noconv=True)
     return uT, [int(x) for x in its], SWRStats(st, None)
 

@@ -2673,11 +2673,13 @@ static kfp_status u0_guess_impl(const kfp_grid *g, const double *u0, int32_t J, 
 // window before (window 0 from u0), with the source levels of its steps, so
 // only one window's traces are held.  guess: initial traces of each window
 // 0 zero, 1 the extension Q(start state) of kfp_u0_guess.
+// lam_full: initial traces of the whole [0, T] ([2(J-1)][nt][nx]); window w
+// starts from its levels (guess is then ignored).
 static kfp_status swr_windows_impl(const kfp_grid *g, const double *u0, const double *f,
                                    const double *s, int J, int o, int tr, double p, double q,
                                    double tol, int max_iter, int W, int guess, double *uT,
                                    int32_t *window_iters, kfp_swr_stats *stats,
-                                   hipStream_t user) {
+                                   hipStream_t user, const double *lam_full = nullptr) {
   const double t_start = now_s();
   Geo geo;
   kfp_status st = make_geo(g, J, o, tr, p, geo, g_scheme);
@@ -2700,7 +2702,10 @@ static kfp_status swr_windows_impl(const kfp_grid *g, const double *u0, const do
     }
   } b;
   if (W > 1) HIP_TRY(hipMalloc((void **)&b.tmp, 2 * field * sizeof(double)));
-  const bool use_guess = guess == 1 && J > 1;
+  const bool use_full = lam_full != nullptr && J > 1;
+  const bool use_guess = guess == 1 && J > 1 && !use_full;
+  if (use_full)
+    HIP_TRY(hipMalloc((void **)&b.lam, (size_t)2 * (J - 1) * ntw_max * g->nx * sizeof(double)));
   if (use_guess) {
     HIP_TRY(hipMalloc((void **)&b.lam, (size_t)2 * (J - 1) * ntw_max * g->nx * sizeof(double)));
     std::vector<int> ab;
@@ -2724,10 +2729,16 @@ static kfp_status swr_windows_impl(const kfp_grid *g, const double *u0, const do
     double *out = (w == W - 1) ? uT : b.tmp + (size_t)(w & 1) * field;
     if (use_guess)
       HIP_TRY(launch_u0_guess(start, g->nx, ntw, J, b.ab, tr, p, q, 2.0 / g->nv, b.lam, user));
+    if (use_full)  // the window's levels of every plane, packed
+      HIP_TRY(hipMemcpy2DAsync(b.lam, (size_t)ntw * g->nx * sizeof(double),
+                               lam_full + (size_t)n0 * g->nx,
+                               (size_t)g->nt * g->nx * sizeof(double),
+                               (size_t)ntw * g->nx * sizeof(double), (size_t)2 * (J - 1),
+                               hipMemcpyDeviceToDevice, user));
     kfp_swr_stats sw{};
     if (stats && stats->res_history) sw.res_history = stats->res_history + (size_t)w * max_iter;
     st = swr_solve_impl(&gw, start, f, s ? s + n0 : nullptr, J, o, tr, p, q, tol, max_iter,
-                        use_guess ? b.lam : nullptr, out, nullptr, &sw, user);
+                        (use_guess || use_full) ? b.lam : nullptr, out, nullptr, &sw, user);
     if (st != KFP_OK && st != KFP_ENOCONV) return st;
     if (st == KFP_ENOCONV) worst = KFP_ENOCONV;
     if (window_iters) window_iters[w] = sw.iters;
@@ -2765,6 +2776,21 @@ kfp_status kfp_swr_solve_windows(const kfp_grid *g, const double *u0, const doub
     return fail(KFP_EINVAL, "Robin transmission needs q > 0 (got %g)", q);
   return swr_windows_impl(g, u0, f, s, J, overlap, tr, p, q, tol, max_iter, n_windows, guess,
                           uT, window_iters, stats, (hipStream_t)stream);
+}
+
+kfp_status kfp_swr_solve_windows_init(const kfp_grid *g, const double *u0, const double *f,
+                                      const double *s, int32_t J, int32_t overlap, int32_t tr,
+                                      double p, double q, double tol, int32_t max_iter,
+                                      int32_t n_windows, const double *lambda_init, double *uT,
+                                      int32_t *window_iters, kfp_swr_stats *stats,
+                                      void *stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_err.clear();
+  if (tr == KFP_ROBIN && !(q > 0.0 && std::isfinite(q)))
+    return fail(KFP_EINVAL, "Robin transmission needs q > 0 (got %g)", q);
+  if (!lambda_init && J > 1) return fail(KFP_EINVAL, "lambda_init must be non-NULL");
+  return swr_windows_impl(g, u0, f, s, J, overlap, tr, p, q, tol, max_iter, n_windows, 0, uT,
+                          window_iters, stats, (hipStream_t)stream, lambda_init);
 }
 
 kfp_status kfp_u0_guess(const kfp_grid *g, const double *u0, int32_t J, int32_t overlap,

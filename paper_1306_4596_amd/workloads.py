@@ -131,13 +131,20 @@ def run_large_solve(learned_train=0, orders=(0, 1)):
     coef0 = inputs.coefficients(0)
     for order in orders:
         kb.set_ordering(order)
-        for guess in ("zero", "u0") + (("learned",) if g else ()) + ("windows4",):
+        for guess in (("zero", "u0") + (("learned",) if g else ()) + ("windows4",) +
+                      (("windows4_learned",) if g else ())):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if guess == "windows4":
                 _, its, st = kb.swr_solve_windows(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
                                                   max_iter=400, n_windows=4, guess=True)
                 iters = its
+            elif guess == "windows4_learned":  # each window from its levels of the guess
+                lam0 = g.predict(coef0, nt, nx)[0]
+                _, its, st = kb.swr_solve_windows(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
+                                                  max_iter=400, n_windows=4, lambda_init=lam0)
+                iters = its
+                del lam0
             else:
                 if guess == "learned":
                     lam0 = g.predict(coef0, nt, nx)[0]

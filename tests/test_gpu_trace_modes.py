@@ -9,6 +9,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402
 import paper_1306_4596_amd as kfp  # noqa: E402
 from paper_1306_4596_amd import inputs, learned  # noqa: E402
 
@@ -112,3 +113,33 @@ def test_coarse_learned_guess_shortens_the_fine_solve():
     assert gerr < 0.25
     assert st_l.iters < st_zero.iters
     assert float((u_l - u_zero).norm() / u_zero.norm()) <= 1e-10
+
+
+@pytest.mark.parametrize("W,order", [(3, kfp.PARALLEL), (4, kfp.RED_BLACK)])
+def test_windows_from_whole_interval_traces(W, order):
+    """kfp_swr_solve_windows_init: each window starts from its levels of
+    traces given for the whole interval.  From zero traces it is the
+    windowed solve from zero bit for bit; from the converged traces of the
+    single-window solve every window starts at its own solution (a few
+    iterations); both compose to the monodomain solution of the oracle."""
+    nx, nv, nt, T, J, o, p = 64, 96, 120, 0.3, 4, 2, 4.0
+    print(f"windows from whole-interval traces W={W} order={order}", flush=True)
+    u0, f = inputs.random_fields(11, nx, nv)
+    U0, F = torch.from_numpy(u0).cuda(), torch.from_numpy(f).cuda()
+    try:
+        kfp.set_ordering(order)
+        kw = dict(p=p, tol=1e-11, max_iter=400, n_windows=W)
+        u_z, it_z, _ = kfp.swr_solve_windows(U0, F, T, nt, J, o, kfp.ROBIN, **kw)
+        zeros = torch.zeros((2 * (J - 1), nt, nx), dtype=torch.float64, device="cuda")
+        u_0, it_0, _ = kfp.swr_solve_windows(U0, F, T, nt, J, o, kfp.ROBIN, lambda_init=zeros, **kw)
+        assert it_0 == it_z and torch.equal(u_0, u_z)
+        _, lam_star, _ = kfp.swr_solve(U0, F, T, nt, J, o, kfp.ROBIN, p=p, tol=1e-13,
+                                       max_iter=600, want_lambda=True)
+        u_s, it_s, _ = kfp.swr_solve_windows(U0, F, T, nt, J, o, kfp.ROBIN, lambda_init=lam_star,
+                                             **kw)
+        assert max(it_s) <= 3 < min(it_z)
+    finally:
+        kfp.set_ordering(kfp.PARALLEL)
+    m = oracle.mono_solve(u0, f, T, nt)
+    for u in (u_z, u_s):
+        assert np.linalg.norm(u.cpu().numpy() - m) / np.linalg.norm(m) <= 1e-9

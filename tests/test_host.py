@@ -477,3 +477,19 @@ def test_trace_mode_arguments(lib):
     assert lib.kfp_trace_synth(FAKE, 2, 4, 4, m, 0, 64, FAKE, None) == binding.KFP_EINVAL
     assert lib.kfp_trace_synth(FAKE, 2, 4, 4, m, 8, 6, FAKE, None) == binding.KFP_EINVAL
     assert lib.kfp_trace_synth(None, 2, 4, 4, m, 8, 64, FAKE, None) == binding.KFP_EINVAL
+
+
+def test_windows_with_initial_traces_arguments(lib):
+    """kfp_swr_solve_windows_init validates like kfp_swr_solve_windows and
+    needs the initial traces when there are interfaces."""
+    g = G(64, 64, 10, 0.1)
+    its = (ctypes.c_int32 * 4)()
+
+    def win(n_windows, lam=FAKE, J=2, u0=FAKE):
+        return lib.kfp_swr_solve_windows_init(ctypes.byref(g), u0, FAKE, None, J, 2, 1, 4.0, 4.0,
+                                              1e-10, 10, n_windows, lam, FAKE, its, None, None)
+    assert win(2, lam=None) == binding.KFP_EINVAL
+    assert "lambda_init" in lib.kfp_last_error().decode()
+    assert win(0) == binding.KFP_EINVAL and "n_windows" in lib.kfp_last_error().decode()
+    assert win(11) == binding.KFP_EINVAL
+    assert win(2, u0=None) == binding.KFP_EINVAL
