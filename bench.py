@@ -230,6 +230,33 @@ def large_starts(U0, F, zero, ntrain):
     return out
 
 
+def p_sweep():
+    """The 1024 x 1024, Nt = 2000, T = 0.5, J = 8, overlap 2 shape (random
+    fields seed 0) solved to 1e-10 from zero traces in the parallel order for
+    each Robin parameter p in {1, 2, 4, 8, 16}: iterations and seconds."""
+    import torch
+
+    import paper_1306_4596_amd as kfp
+    from paper_1306_4596_amd import inputs
+
+    nx = nv = 1024
+    u0, f = inputs.random_fields(0, nx, nv)
+    U0, F = torch.from_numpy(u0).cuda(), torch.from_numpy(f).cuda()
+    kfp.swr_solve(U0, F, 0.5, 2000, 8, 2, TR, p=8.0, tol=1e-300, max_iter=1)  # plan, graphs
+    out = {"workload": "SWR 1024x1024 Nt=2000 T=0.5 J=8 overlap=2 Robin, seed 0, tol 1e-10"}
+    for p in (1.0, 2.0, 4.0, 8.0, 16.0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, st = kfp.swr_solve(U0, F, 0.5, 2000, 8, 2, TR, p=p, tol=TOL, max_iter=2000,
+                                 history=False)
+        torch.cuda.synchronize()
+        out[f"p={p:g}"] = {"iters": st.iters, "seconds": round(time.perf_counter() - t1, 4),
+                           "residual": st.residual}
+    progress("p sweep at 1024 x 1024 done")
+    kfp.release_workspace()
+    return out
+
+
 def learned_leg(ntrain, neval):
     """Time to 1e-10 with and without learned initial traces on the
     learned-traces shape (256 x 256, Nt = 512, T = 0.5, J = 4, overlap 2,
@@ -417,6 +444,8 @@ def main():
         progress(f"red-black order on 4 windows: {its} iterations")
         kfp.set_ordering(kfp.PARALLEL)
         out["time_to_tol"] = {"tol": TOL, **solves}
+    if not args.no_solves:
+        out["p_sweep_1024"] = optional("p sweep", p_sweep)
     if not args.no_learned:
         del U0, F
         kfp.release_workspace()
