@@ -28,7 +28,9 @@ residual of 1e-10 in the parallel order from zero traces, from the u0
 extension and from a learned guess (trained here on coarse solves of the
 same J, overlap, T and p, carried to the full grid through the traces'
 x-Fourier coefficients), and in red-black order on 4 time windows (each
-from the extension of its start state); the
+from the extension of its start state); the HBM fraction of the same march
+kernel taking one time step per launch (the fused step kernel in its
+streaming form, `fused_one_step`); the
 time to 1e-10 with and without learned initial traces on the learned-traces
 shape (256 x 256, Nt = 512, J = 4), the network trained here on a bounded
 number of seeded solves (`learned_guess`); and the oracle on the host cores
@@ -228,6 +230,40 @@ def large_starts(U0, F, zero, ntrain):
     kfp.release_workspace()
     torch.cuda.empty_cache()
     return out
+
+
+def fused_one_step(U0, F, rows, copy_gbps):
+    """The same shape with the multi-tile march kernel taking ONE time step
+    per launch (8 wavefronts x 17 rows, one tile, a halo of one column): the
+    fused step kernel in its streaming form, every cell-step moving its
+    state and source through HBM.  One timed iteration (8192 launches);
+    compulsory bytes per launch over the live average launch duration,
+    against the 8 TB/s peak and the copy kernel's rate."""
+    import torch
+
+    import paper_1306_4596_amd as kfp
+
+    kfp.set_config(8, 17, 1, 1, 1)
+    try:
+        kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=1e-300, max_iter=1,
+                      history=False)  # plan and graphs
+        torch.cuda.synchronize()
+        _, _, st = kfp.swr_solve(U0, F, T, NT, J, OVERLAP, TR, p=P_MAIN, tol=1e-300, max_iter=1,
+                                 history=False)
+        torch.cuda.synchronize()
+    finally:
+        kfp.set_config(0)
+        kfp.release_workspace()
+    launch_s = st.step_seconds / st.step_launches
+    alg = compulsory_bytes_per_launch(rows, 1)
+    gbps = alg / launch_s / 1e9
+    progress(f"one step per launch: {launch_s * 1e6:.1f} us per launch, {gbps:.0f} GB/s")
+    return {"kernel": "kfp::march_fd_kernel, 1 step per launch", "launches": st.step_launches,
+            "avg_launch_us": round(launch_s * 1e6, 3), "alg_bytes_per_launch": alg,
+            "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "frac_of_copy": round(gbps / copy_gbps, 4) if copy_gbps else None,
+            "cell_steps_per_s": st.cell_steps / st.step_seconds}
 
 
 def p_sweep():
@@ -445,6 +481,8 @@ def main():
         kfp.set_ordering(kfp.PARALLEL)
         out["time_to_tol"] = {"tol": TOL, **solves}
     if not args.no_solves:
+        out["fused_one_step"] = optional("one step per launch", fused_one_step, U0, F, rows,
+                                         copy_gbps)
         out["p_sweep_1024"] = optional("p sweep", p_sweep)
     if not args.no_learned:
         del U0, F
