@@ -66,6 +66,11 @@ CASES = [
     (80, 32, 20, 0.2, 4, 2, (8, 12, 4, 2)),     # single-segment subdomains, 7 idle waves
     (70, 512, 16, 0.05, 2, 2, (8, 33, 4, 1)),   # 33-row segments
     (70, 368, 16, 0.05, 2, 2, (8, 24, 6, 1)),
+    # one step per launch (halo of one column): the streaming form the
+    # benchmark reports as its fused one-step kernel
+    (300, 1024, 18, 0.02, 8, 2, (8, 17, 1, 1)),
+    (96, 128, 24, 0.2, 2, 2, (8, 17, 1, 1)),    # across v = 0: one column each side
+    (130, 256, 20, 0.1, 8, 2, (8, 12, 1, 2)),
 ]
 
 
