@@ -12,8 +12,11 @@ namespace kfp {
 //   EPI_STORE  + bias[n]; optional FP32 output C and BF16 output Cb (GELU
 //              applied to Cb when gelu != 0).  P: split-K partials.
 //   EPI_MSE    r = C + bias - T (the squared-error residual): Cb = BF16(scale r),
-//              loss += sum r^2 (FP64 atomic), PB[2*row tile + w][n] = column
-//              sum of scale r over the 64 rows of wavefront row w of the tile.
+//              loss_part[4*(column tile*row tiles + row tile) + wavefront] =
+//              that wavefront's sum of r^2 in FP64 (summed afterwards by
+//              launch_sum_f64: one slot per wavefront, no atomics, a fixed
+//              order), PB[2*row tile + w][n] = column sum of scale r over the
+//              64 rows of wavefront row w of the tile.
 //   EPI_ADAM   C is the gradient of W[M][N] (row stride ldw): one Adam step on
 //              W, the moments Mo, Vo and the BF16 copy Wb, in place.
 // The fused epilogues need the whole K in one tile (splits == 1), N a
@@ -39,7 +42,7 @@ struct GemmArgs {
   const float *T;
   long ldt;
   float scale;
-  double *loss;
+  double *loss_part;
   float *PB;
   // EPI_ADAM
   float *W, *Mo, *Vo;
@@ -57,6 +60,8 @@ hipError_t launch_f64_to_f32(const double *s_, const double *base, float *d, siz
 hipError_t launch_gelu_back(const float *dA, const float *Z, float *d32, __bf16 *db, size_t n,
                             hipStream_t s);
 hipError_t launch_colsum(const float *X, int R, int C, float *out, hipStream_t s);
+// out[0] = sum of x[0 .. n) in FP64 (one workgroup of 1024 threads, a fixed order)
+hipError_t launch_sum_f64(const double *x, size_t n, double *out, hipStream_t s);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, size_t n,
                        float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_destandardize(const float *y, const float *mean, const float *stdv,

@@ -44,28 +44,34 @@ __device__ __forceinline__ float adam_update(float &w, float gi, float &m, float
 
 // ---------------------------------------------------------------------------
 // GEMM: 128 x 128 output tile per workgroup of 4 wavefronts (2 x 2), each
-// wavefront 64 x 64 = 4 x 4 blocks of v_mfma_f32_16x16x32_bf16; K step 32.
+// wavefront 64 x 64 = 4 x 4 blocks of v_mfma_f32_16x16x32_bf16; K step 64.
 // One-dimensional grid of tiles_n x tiles_m x splits workgroups; split z
 // covers K range [z*kchunk, min(K, (z+1)*kchunk)).  splits > 1 writes FP32
 // partials to P[z][M][N] and the reduce kernel applies the epilogue.
 // The next K step's tiles are loaded into registers while the current one
-// is multiplied (the loads are in flight during the MFMAs).
+// is multiplied (the loads are in flight during the MFMAs).  The products
+// here are HBM-bound with little arithmetic per byte, so a step's wait on
+// its loads is close to a whole memory latency: the K step is 64 (16 KiB
+// of operand tiles per workgroup in flight) to halve the number of waits.
 //
 // Both operand tiles sit in LDS as [row][k] (row pitch LDS_K), the layout
-// the MFMA fragments read: lane l takes the 8 consecutive k of group l/16
-// for row l%16.  A K-contiguous operand is copied in 16-byte pieces.  A
-// K-major operand is read from HBM along its rows (16 lanes cover 128
-// consecutive rows of one k) and transposed on the way into LDS: each
-// thread loads rows k and k+1 for 8 consecutive tile rows and writes the 8
-// (k, k+1) pairs as 32-bit words.  The four 8-wide k groups of a row are
-// XOR-permuted by bits 4-5 of the row index: the fragment reads and the
+// the MFMA fragments read: for the 32-wide k half h, lane l takes the 8
+// consecutive k of group 4h + l/16 for row l%16.  A K-contiguous operand is
+// copied in 16-byte pieces.  A K-major operand is read from HBM along its
+// rows (16 lanes cover 128 consecutive rows of one k) and transposed on the
+// way into LDS: each thread loads rows k and k+1 for 8 consecutive tile rows
+// and writes the 8 (k, k+1) pairs as 32-bit words.  Within each 32-wide half
+// the four 8-wide k groups of a row are XOR-permuted by bits 4-5 of the row
+// index: the fragment reads and the
 // K-contiguous copies see a permutation that is uniform across each
 // wavefront (no change in bank use), while the pair writes of one
 // wavefront, 8 rows apart, spread over the banks.
 // Requirements (checked on the host): K, lda, ldb multiples of 8; M (N) a
 // multiple of 8 for a K-major A (B).
 // ---------------------------------------------------------------------------
-constexpr int BM = 128, BN = 128, BK = 32, LDS_K = BK + 8;
+constexpr int BM = 128, BN = 128, BK = 64, LDS_K = BK + 8;
+// 16-byte pieces of one operand tile per thread
+constexpr int NP = BM * BK / 8 / 256;
 // The fused epilogues stage each wavefront's 64 x 64 FP32 block in LDS, 32
 // rows at a time (row pitch EP_PITCH floats: 16-byte aligned rows, and the
 // accumulator writes of one wavefront, rows 4 apart, fall in distinct
@@ -94,23 +100,24 @@ __device__ __forceinline__ int kswz(int row) { return (row >> 4) & 3; }
 
 // global -> registers: the two pieces of one operand tile this thread moves
 template <bool KM>
-__device__ __forceinline__ void tile_load(bf16x8 (&v)[2], const __bf16 *__restrict__ p, long ld,
+__device__ __forceinline__ void tile_load(bf16x8 (&v)[NP], const __bf16 *__restrict__ p, long ld,
                                           int r0, int R, int k0, int kend, int tid,
                                           const bf16x8 &zero8) {
   if constexpr (!KM) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < NP; ++r) {
       const int idx = tid + r * 256;
-      const int row = r0 + (idx >> 2);
-      const int gk = k0 + (idx & 3) * 8;
+      const int row = r0 + idx / (BK / 8);
+      const int gk = k0 + (idx % (BK / 8)) * 8;
       v[r] = zero8;
       if (row < R && gk < kend) v[r] = *(const bf16x8 *)(p + (size_t)row * ld + gk);
     }
   } else {
+    // pieces 2q and 2q + 1: rows k and k + 1 of k pair (tid / 16) + 16 q
     const int row = r0 + 8 * (tid & 15);
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int gk = k0 + 2 * (tid >> 4) + r;
+    for (int r = 0; r < NP; ++r) {
+      const int gk = k0 + 2 * ((tid >> 4) + 16 * (r >> 1)) + (r & 1);
       v[r] = zero8;
       if (row < R && gk < kend) v[r] = *(const bf16x8 *)(p + (size_t)gk * ld + row);
     }
@@ -119,33 +126,37 @@ __device__ __forceinline__ void tile_load(bf16x8 (&v)[2], const __bf16 *__restri
 
 // registers -> LDS tile [row][k]
 template <bool KM>
-__device__ __forceinline__ void tile_store(__bf16 *__restrict__ s, const bf16x8 (&v)[2],
+__device__ __forceinline__ void tile_store(__bf16 *__restrict__ s, const bf16x8 (&v)[NP],
                                            int tid) {
   if constexpr (!KM) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < NP; ++r) {
       const int idx = tid + r * 256;
-      const int row = idx >> 2;
-      *(bf16x8 *)(s + row * LDS_K + (((idx & 3) ^ kswz(row)) * 8)) = v[r];
+      const int row = idx / (BK / 8);
+      *(bf16x8 *)(s + row * LDS_K + (((idx % (BK / 8)) ^ kswz(row)) * 8)) = v[r];
     }
   } else {
-    const int kp = tid >> 4, row0 = 8 * (tid & 15);
-    const int grp = kp >> 2, off = 2 * (kp & 3);
-    // the pieces as raw 16-bit patterns (whole-vector casts: element-wise
-    // casts of a BF16 vector are not relied on)
-    const u16x8 lo = __builtin_bit_cast(u16x8, v[0]);
-    const u16x8 hi = __builtin_bit_cast(u16x8, v[1]);
+    const int row0 = 8 * (tid & 15);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int row = row0 + j;
-      *(uint32_t *)(s + row * LDS_K + ((grp ^ kswz(row)) * 8) + off) =
-          (uint32_t)lo[j] | ((uint32_t)hi[j] << 16);
+    for (int q = 0; q < NP / 2; ++q) {
+      const int kp = (tid >> 4) + 16 * q;
+      const int grp = kp >> 2, off = 2 * (kp & 3);
+      // the pieces as raw 16-bit patterns (whole-vector casts: element-wise
+      // casts of a BF16 vector are not relied on)
+      const u16x8 lo = __builtin_bit_cast(u16x8, v[2 * q]);
+      const u16x8 hi = __builtin_bit_cast(u16x8, v[2 * q + 1]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int row = row0 + j;
+        *(uint32_t *)(s + row * LDS_K + ((grp ^ kswz(row)) * 8) + off) =
+            (uint32_t)lo[j] | ((uint32_t)hi[j] << 16);
+      }
     }
   }
 }
 
 template <int EPI, bool AK, bool BKM>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16)))
   unsigned char smem[EPI == EPI_STORE ? SMEM_AB : (SMEM_EPI > SMEM_AB ? SMEM_EPI : SMEM_AB)];
   __bf16 *sA = (__bf16 *)smem;
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   bf16x8 zero8;
 #pragma unroll
   for (int i = 0; i < 8; ++i) zero8[i] = (__bf16)0.0f;
-  bf16x8 va[2], vb[2];
+  bf16x8 va[NP], vb[NP];
   auto load = [&](int k0) {
     tile_load<AK>(va, g.A, g.lda, m0, g.M, k0, kend, tid, zero8);
     tile_load<BKM>(vb, g.B, g.ldb, n0, g.N, k0, kend, tid, zero8);
@@ -196,19 +207,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     tile_store<BKM>(sB, vb, tid);
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);  // in flight during this step's MFMAs
-    bf16x8 af[4], bfm[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ra = wm * 64 + i * 16 + (lane & 15);
-      const int rb = wn * 64 + i * 16 + (lane & 15);
-      af[i] = *(const bf16x8 *)(sA + ra * LDS_K + (((lane >> 4) ^ kswz(ra)) * 8));
-      bfm[i] = *(const bf16x8 *)(sB + rb * LDS_K + (((lane >> 4) ^ kswz(rb)) * 8));
+    for (int h = 0; h < BK / 32; ++h) {
+      bf16x8 af[4], bfm[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ra = wm * 64 + i * 16 + (lane & 15);
+        const int rb = wn * 64 + i * 16 + (lane & 15);
+        af[i] = *(const bf16x8 *)(sA + ra * LDS_K + ((4 * h + ((lane >> 4) ^ kswz(ra))) * 8));
+        bfm[i] = *(const bf16x8 *)(sB + rb * LDS_K + ((4 * h + ((lane >> 4) ^ kswz(rb))) * 8));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfm[j], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfm[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   // accumulator register r of block (i, j) holds row 4*(lane/16) + r, column lane%16
@@ -340,7 +355,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       if (lane < 16 && ncol) *(f32x4 *)(g.PB + (size_t)(mt * 2 + wm) * g.N + n) = cs;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-      if (lane == 0 && lsum != 0.0) atomicAdd(g.loss, lsum);
+      // one slot per wavefront: an atomic sum into one address serialises
+      // every wavefront of the launch on one L2 channel
+      if (lane == 0) g.loss_part[((size_t)nt * tiles_m + mt) * 4 + wv] = lsum;
     }
   }
 }
@@ -380,6 +397,34 @@ static int egrid(size_t n) {
 #define GRID_STRIDE(e, n) \
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (n); \
        e += (size_t)gridDim.x * blockDim.x)
+
+// One workgroup of 1024 threads; each thread keeps 16 independent loads in
+// flight per pass, then the wavefront and workgroup sums in a fixed order.
+__global__ __launch_bounds__(1024) void sum_f64_kernel(const double *__restrict__ x, size_t n,
+                                                       double *__restrict__ out) {
+  __shared__ double part[16];
+  const int tid = threadIdx.x;
+  double v = 0.0;
+  for (size_t base = 0; base < n; base += 16 * 1024) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const size_t e = base + (size_t)u * 1024 + tid;
+      t[u] = e < n ? x[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v += t[u];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) part[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += part[w];
+    out[0] = s;
+  }
+}
 
 __global__ void f32_to_bf16_kernel(const float *__restrict__ s, __bf16 *__restrict__ d, size_t n) {
   GRID_STRIDE(e, n) d[e] = (__bf16)s[e];
@@ -557,6 +602,11 @@ hipError_t launch_gelu_back(const float *dA, const float *Z, float *d32, __bf16 
 
 hipError_t launch_colsum(const float *X, int R, int C, float *out, hipStream_t s) {
   hipLaunchKernelGGL(colsum_kernel, dim3((C + 63) / 64), dim3(256), 0, s, X, R, C, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_f64(const double *x, size_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_f64_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
   return hipGetLastError();
 }
 

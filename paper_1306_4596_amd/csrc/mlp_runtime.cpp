@@ -68,7 +68,9 @@ struct Acts {
   __bf16 *dZb = nullptr;
   float *P = nullptr;                          // split-K partials
   size_t P_n = 0;
-  double *loss = nullptr;
+  double *loss = nullptr;       // sum of squared residuals of the last forward with targets
+  double *loss_part = nullptr;  // its per-wavefront partials [4 * output-layer tiles]
+  size_t loss_part_n = 0;
 };
 
 }  // namespace kfp
@@ -100,6 +102,7 @@ static void free_acts(Acts &a) {
   f(a.dZb);
   f(a.P);
   f(a.loss);
+  f(a.loss_part);
   a = Acts{};
 }
 
@@ -137,6 +140,8 @@ static kfp_status ensure_acts(kfp_mlp *m, int B) {
   MHIP(dmalloc(&a.dZ32, (size_t)B * hmax));
   MHIP(dmalloc(&a.dZb, (size_t)B * hmax));
   MHIP(dmalloc(&a.loss, 1));
+  a.loss_part_n = (size_t)4 * ((B + 127) / 128) * ((m->out + 127) / 128);
+  MHIP(dmalloc(&a.loss_part, a.loss_part_n));
   a.cap = B;
   return KFP_OK;
 }
@@ -180,7 +185,7 @@ static kfp_status gemm(kfp_mlp *m, GemmArgs g, hipStream_t s) {
       splits = (int)std::min<long>(g.K / 64, std::max<long>(1, 256 / tiles));
   }
   int kchunk = (g.K + splits - 1) / splits;
-  kchunk = (kchunk + 31) / 32 * 32;
+  kchunk = (kchunk + 63) / 64 * 64;  // whole K steps of the kernel
   splits = (g.K + kchunk - 1) / kchunk;
   g.kchunk = kchunk;
   if (splits > 1) {
@@ -215,7 +220,7 @@ static GemmArgs gargs(int M, int N, int K, const __bf16 *A, long lda, const __bf
 // Forward pass.  Without targets the output goes to Y (FP32 [B][out]).
 // With targets T the output layer's epilogue forms the squared-error
 // gradient instead: A.db = BF16(scale (y - T)), its column sums per 64 rows
-// in A.PB, and sum (y - T)^2 added to A.loss; y itself is never stored.
+// in A.PB, and sum (y - T)^2 in A.loss; y itself is never stored.
 static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream_t s,
                           const float *T = nullptr, float scale = 0.f) {
   kfp_status st = ensure_acts(m, B);
@@ -242,7 +247,7 @@ static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream
       g.T = T;
       g.ldt = L.out;
       g.scale = scale;
-      g.loss = a.loss;
+      g.loss_part = a.loss_part;
       g.PB = a.PB;
       g.Cb = a.db;
       g.ldcb = L.out;
@@ -251,6 +256,11 @@ static kfp_status forward(kfp_mlp *m, int B, const float *X, float *Y, hipStream
       g.ldc = L.out;
     }
     if ((st = gemm(m, g, s))) return st;
+    if (l == nl - 1 && T) {
+      // the slots this batch's tiles wrote (the buffer is sized for the capacity)
+      const size_t parts = (size_t)4 * ((B + 127) / 128) * ((L.out + 127) / 128);
+      MHIP(launch_sum_f64(a.loss_part, parts, a.loss, s));
+    }
     if (concat) MHIP(launch_f32_to_bf16_cols(X, B, m->in, a.Ab[l] + L.out, wcat, s));
     if (l < nl - 1) {
       cur = a.Ab[l];
@@ -288,7 +298,6 @@ static kfp_status backprop(kfp_mlp *m, int B, const float *X, const float *T, do
   }
   Acts &a = m->A;
   const size_t nout = (size_t)B * m->out;
-  MHIP(hipMemsetAsync(a.loss, 0, sizeof(double), s));
   if ((st = forward(m, B, X, nullptr, s, T, 2.0f / (float)nout))) return st;
   const __bf16 *dbf = a.db;  // output gradient of layer l, [B][out_l]
   for (int l = nl - 1; l >= 0; --l) {

@@ -76,6 +76,23 @@ def test_gradients_match_oracle(sizes, B, skip):
         assert rel(db, gb) <= 2e-3, (l, rel(db, gb))
 
 
+def test_loss_after_a_larger_batch():
+    """The output layer leaves one partial loss sum per wavefront of each
+    tile; a batch smaller than an earlier one has fewer tiles, and its loss
+    must be the oracle's (no partial of the earlier batch counted)."""
+    sizes = [24, 136, 264]
+    net, params = build(sizes, 7)
+    rng = np.random.default_rng(8)
+    ref = omlp.MLP(params, bf16=True)
+    for B in (200, 40, 136):
+        print(f"mlp loss B={B}", flush=True)
+        x = rng.standard_normal((B, sizes[0])).astype(np.float32)
+        t = rng.standard_normal((B, sizes[-1])).astype(np.float32)
+        loss = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+        rloss, _ = ref.backward(x.astype(np.float64), t.astype(np.float64))
+        assert abs(loss - rloss) <= 1e-4 * rloss, (B, loss, rloss)
+
+
 def test_adam_step_matches_oracle():
     sizes = [16, 32, 40]
     net, params = build(sizes, 7)

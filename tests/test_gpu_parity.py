@@ -6,6 +6,7 @@ monodomain march, where both sides run the same arithmetic up to the
 rounding order of the Thomas elimination (divisions on the CPU, precomputed
 reciprocals and a segment partition on the GPU).
 """
+import ctypes
 import os
 
 import numpy as np
@@ -15,7 +16,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import paper_1306_4596_amd as kfp  # noqa: E402
-from paper_1306_4596_amd import inputs  # noqa: E402
+from paper_1306_4596_amd import binding, inputs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -769,3 +770,18 @@ def test_cfg1_shape_fixed_iterations_short_window():
     assert rel(host(uT), ref.uT) <= 1e-12
     assert rel(host(lam), ref.lam) <= 1e-12
     assert np.allclose(st.res_history, ref.res_hist, rtol=1e-9)
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, (1 << 20) + 48])
+def test_bw_probe_copies(nbytes):
+    """The bandwidth probe is a plain copy: bit-exact, whole and ragged
+    workgroups, and nothing written past the requested bytes."""
+    n = nbytes // 8
+    src = torch.arange(n + 4, dtype=torch.float64, device="cuda") * 0.5 + 1.0
+    dst = torch.full((n + 4,), -7.0, dtype=torch.float64, device="cuda")
+    binding._check(binding.load_library().kfp_bw_probe(ctypes.c_void_p(src.data_ptr()),
+                                                       ctypes.c_void_p(dst.data_ptr()),
+                                                       int(nbytes), None))
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n], src[:n])
+    assert bool((dst[n:] == -7.0).all())
