@@ -1,12 +1,15 @@
 """Throughput of the SWR path on the workloads beside the benchmark one.
 
     python -m paper_1306_4596_amd.workloads batch [--n 256] [--order 0|1] [--scheme fd|fem] [--tune]
+    python -m paper_1306_4596_amd.workloads medium [--configs 8,17,16] [--scheme fd|fem]
     python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8] [--scheme fd|fem]
     python -m paper_1306_4596_amd.workloads large-solve
 
 `batch`: uneven instances (Nx, Nv from {128, 256, 512, 1024}, J from
 {2, 4, 8, 16}, Nt = 512, T = 0.25, overlap 2, Robin p = 4) solved together
-by kfp_swr_batch to 1e-10, in the parallel order or (--order 1) red-black.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J = 32,
+by kfp_swr_batch to 1e-10, in the parallel order or (--order 1) red-black.
+`medium`: Nx = Nv = 1024, Nt = 2000, T = 0.5, J = 8, overlap 2, Robin p = 8
+solved to 1e-10 from zero traces.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J = 32,
 overlap 2, Robin p = 8, a fixed number of SWR iterations, once per launch
 configuration.  `large-solve`: the same shape solved to 1e-10 from zero
 traces and from the u0 extension, in the parallel and the red-black order,
@@ -100,6 +103,45 @@ def run_large(iters: int, configs):
     kb.set_config(0)
 
 
+def run_medium(configs, reps: int = 2):
+    """The 1024 x 1024, Nt = 2000, T = 0.5, J = 8, overlap 2, Robin p = 8
+    shape (seed 0) solved to 1e-10 from zero traces, once per launch
+    configuration, after one untimed solve."""
+    import torch
+
+    nx = nv = 1024
+    nt, T, J, o, p = 2000, 0.5, 8, 2, 8.0
+    u0, f = inputs.random_fields(0, nx, nv)
+    U0 = torch.from_numpy(u0).cuda()
+    F = torch.from_numpy(f).cuda()
+    rows = kb.subdomain_rows(nx, nv, nt, T, J, o, kb.ROBIN)
+    # the library's copy kernel over 1 GiB: a known byte count for scaling
+    # HBM counters taken on this run
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    kb.bw_probe(a, torch.empty_like(a))
+    del a
+    for cfg in configs:
+        if cfg is not None:
+            kb.set_config(*cfg)
+        used = kb.get_launch_tiles(nx, nv, nt, T, J, o, kb.ROBIN)
+        for rep in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st = kb.swr_solve(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10, max_iter=1000)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            print(json.dumps({"workload": "1024x1024 Nt=2000 T=0.5 J=8 overlap=2 Robin p=8 to 1e-10",
+                              "scheme": "fem" if kb.FEM == _scheme() else "fd", "rep": rep,
+                              "iterations": st.iters, "residual": st.residual, "config": used,
+                              "rows": rows, "wall_s": wall, "device_s": st.device_seconds,
+                              "step_kernel_s": st.step_seconds,
+                              "step_launch_us": st.step_seconds / max(st.step_launches, 1) * 1e6,
+                              "cell_steps_per_s": st.cell_steps / wall}),
+                  flush=True)
+        kb.release_workspace()
+    kb.set_config(0)
+
+
 def learned_large_guess(n_train, coarse=None, log=None):
     """The learned guess of the 4096 x 4096 workload: a modal guess trained
     on `n_train` coarse solves (seeds 1..n_train; the workload's own seed 0
@@ -167,7 +209,7 @@ def run_large_solve(learned_train=0, orders=(0, 1)):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "large", "large-solve"])
+    ap.add_argument("which", choices=["batch", "medium", "large", "large-solve"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
@@ -188,6 +230,8 @@ def main():
     kb.set_scheme(_SCHEME[0])
     if a.which == "batch":
         run_batch(a.n, order=a.order, tune=a.tune)
+    elif a.which == "medium":
+        run_medium([tuple(int(x) for x in c.split(",")) for c in a.configs] or [None])
     elif a.which == "large-solve":
         run_large_solve(a.learned_train, tuple(int(x) for x in a.orders.split(",") if x))
     else:
