@@ -71,15 +71,15 @@ COUNTERS = {
     "config": (8, 17, 12, 1, 1),  # waves, seg_max, steps, groups, tiles
     "sha256": {
         "paper_1306_4596_amd/csrc/swr_kernels.hip":
-            "69bf55479047fae5db345435100b21e9c1d5eef407fcd171c984998a008f0210",
+            "6dbe1688911197c71c63445bfa425e057fccaca2dd0c94b16e34a61795571af5",
         "paper_1306_4596_amd/csrc/kfp_internal.h":
             "377909b348878a0016731dddcb594c302ce5fcad78a799486bec46768e69b477",
     },
-    # mean over the 683 dispatches of one iteration: FETCH_SIZE 154942.50 KiB
-    # (x 1048576 / 524302.16, its reading for 1 GiB copied), WRITE_SIZE
-    # 205803.64 KiB (x 1048576 / 1048576.0)
-    "read_bytes": 154942.498 * 1024 * (1048576.0 / 524302.156),
-    "write_bytes": 205803.636 * 1024 * (1048576.0 / 1048576.0),
+    # mean over the 683 dispatches of one iteration: FETCH_SIZE 154698.56 KiB
+    # (x 1048576 / 524302.38, its reading for 1 GiB copied), WRITE_SIZE
+    # 205866.34 KiB (x 1048576 / 1048576.0)
+    "read_bytes": 154698.564 * 1024 * (1048576.0 / 524302.375),
+    "write_bytes": 205866.341 * 1024 * (1048576.0 / 1048576.0),
     "valu_insts": 51296461.27,  # SQ_INSTS_VALU per dispatch (wave instructions)
 }
 

@@ -1467,6 +1467,9 @@ __global__ __launch_bounds__(NW * 64, OCC) void march_fd_kernel(StepTables t, in
 // 2j+1 when j+1 is even); 2: only those sent by odd subdomains, and the
 // residual (red-black order: run after the even, then the odd half-sweep).
 // A launch with mode 0 takes each instance's own mode (InstDev::xmode).
+// nodes per thread and chunk in the exchange's common case
+constexpr int kExU = 4;
+
 __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, int S, int mode_in) {
   __shared__ unsigned long long red[4];
   const ExItem ex = load_const(as_const(t.ex) + blockIdx.y);
@@ -1491,6 +1494,47 @@ __global__ __launch_bounds__(256) void exchange_kernel(StepTables t, int par, in
   double *lout = par ? I.lam[0] : I.lam[1];
   const bool robin = I.tr == 1;
   unsigned long long r = 0ull;
+  if (robin && !I.nonovl && I.scheme != SCHEME_FEM) {
+    // overlapping Robin with finite differences (the common case): chunks of
+    // kExU x 256 nodes, all six value-plane reads of a chunk issued before
+    // any trace store (the stores may alias nothing here, but the compiler
+    // cannot know that, and would otherwise wait on each node's loads in
+    // turn); the arithmetic per node is the one of the general loop below
+    for (size_t c0 = e_begin + (size_t)blockIdx.x * (256 * kExU); c0 < e_end;
+         c0 += (size_t)gridDim.x * (256 * kExU)) {
+      double ua[kExU], ubh[kExU], ua1[kExU], ub1h[kExU], ublo[kExU], uahi[kExU];
+#pragma unroll
+      for (int u = 0; u < kExU; ++u) {
+        const size_t e = c0 + (size_t)u * 256 + threadIdx.x;
+        const size_t ee = e < e_end ? e : e_begin;  // past the end: a node read, not used
+        ua[u] = V[V_A_LO * plane + ee];
+        ubh[u] = V[V_B_HI * plane + ee];
+        ua1[u] = V[V_A1_LO * plane + ee];
+        ub1h[u] = V[V_B1_HI * plane + ee];
+        ublo[u] = V[V_B_LO * plane + ee];
+        uahi[u] = V[V_A_HI * plane + ee];
+      }
+#pragma unroll
+      for (int u = 0; u < kExU; ++u) {
+        const size_t e = c0 + (size_t)u * 256 + threadIdx.x;
+        if (e >= e_end) continue;
+        const double toR = I.q * ua[u] - (ua1[u] - ua[u]) / I.hv;
+        const double toL = I.p * ubh[u] + (ubh[u] - ub1h[u]) / I.hv;
+        if (mode == 0 || (j & 1) == mode - 1) lout[(size_t)(2 * j) * plane + e] = toR;
+        if (mode == 0 || ((j + 1) & 1) == mode - 1) lout[(size_t)(2 * j + 1) * plane + e] = toL;
+        if (mode == 1 && lout != lin) {
+          const size_t other = (size_t)(2 * j + ((j & 1) ? 0 : 1)) * plane + e;
+          lout[other] = lin[other];
+        }
+        const unsigned long long ra =
+            (unsigned long long)__double_as_longlong(fabs(ua[u] - uahi[u]));
+        const unsigned long long rb =
+            (unsigned long long)__double_as_longlong(fabs(ublo[u] - ubh[u]));
+        r = ra > r ? ra : r;
+        r = rb > r ? rb : r;
+      }
+    }
+  } else
   for (size_t e = e_begin + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < e_end;
        e += (size_t)gridDim.x * blockDim.x) {
     const double ua = V[V_A_LO * plane + e];
@@ -1912,8 +1956,11 @@ hipError_t launch_march(const StepTables &t, int waves, int groups, int seg_max,
 hipError_t launch_exchange(const StepTables &t, int par, int S, hipStream_t s, int mode) {
   if (t.n_ex == 0) return hipSuccess;
   if (mode < 0 || mode > 2) return hipErrorInvalidValue;
-  // a block of S levels is S * nx nodes per interface: fewer workgroups then
-  const unsigned gx = t.blk ? 32u : 256u;
+  // a block of S levels is S * nx nodes per interface: fewer workgroups then.
+  // A whole window: 1024 workgroups per interface (at 4096 x 8192 nodes per
+  // interface, 8 chunks of 1024 nodes per workgroup; measured against 256
+  // and 2048 workgroups, and 2 or 8 nodes per thread)
+  const unsigned gx = t.blk ? 32u : 1024u;
   hipLaunchKernelGGL(exchange_kernel, dim3(gx, t.n_ex), dim3(256), 0, s, t, par, S, mode);
   return hipGetLastError();
 }
