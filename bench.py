@@ -238,7 +238,8 @@ def fused_one_step(U0, F, rows, copy_gbps):
     fused step kernel in its streaming form, every cell-step moving its
     state and source through HBM.  One timed iteration (8192 launches);
     compulsory bytes per launch over the live average launch duration,
-    against the 8 TB/s peak and the copy kernel's rate."""
+    against the 8 TB/s peak, the copy kernel's rate and the streaming rate
+    of a plain kernel with the same tile shape (kfp_tile_probe)."""
     import torch
 
     import paper_1306_4596_amd as kfp
@@ -258,11 +259,27 @@ def fused_one_step(U0, F, rows, copy_gbps):
     alg = compulsory_bytes_per_launch(rows, 1)
     gbps = alg / launch_s / 1e9
     progress(f"one step per launch: {launch_s * 1e6:.1f} us per launch, {gbps:.0f} GB/s")
+    # the streaming ceiling of the same access shape: the library's tile probe
+    # (state and source read, state written, no solve) over [nv+1][nx] arrays
+    # in 8 wavefronts x 17 rows per 64-column tile, 20 launches on the
+    # current stream
+    V = torch.empty_like(U0)
+    kfp.tile_probe(U0, F, V, 8, 17)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        nbytes = kfp.tile_probe(U0, F, V, 8, 17)
+    e1.record()
+    torch.cuda.synchronize()
+    tile_gbps = nbytes / (e0.elapsed_time(e1) * 1e-3 / 20) / 1e9
+    del V
     return {"kernel": "kfp::march_fd_kernel, 1 step per launch", "launches": st.step_launches,
             "avg_launch_us": round(launch_s * 1e6, 3), "alg_bytes_per_launch": alg,
             "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(gbps / HBM_PEAK_GBPS, 4),
             "frac_of_copy": round(gbps / copy_gbps, 4) if copy_gbps else None,
+            "tile_stream_GBps": round(tile_gbps, 1),
+            "frac_of_tile_stream": round(gbps / tile_gbps, 4),
             "cell_steps_per_s": st.cell_steps / st.step_seconds}
 
 

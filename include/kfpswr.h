@@ -395,6 +395,19 @@ kfp_status kfp_subdomain_rows(const kfp_grid *g, int32_t J, int32_t overlap, int
  */
 kfp_status kfp_bw_probe(const void *src, void *dst, int64_t bytes, void *stream);
 
+/*
+ * kfp_tile_probe -- V = U + F/2 over [rows][nx] FP64 arrays (row-major, row
+ * stride nx; device pointers; V must not overlap U or F), read and written in
+ * the tile shape of the register march at one time step per launch: a
+ * workgroup of `waves` wavefronts per 64-column x tile, `rows_per_wave` rows
+ * per wavefront, one column per lane.  Used to measure the streaming ceiling
+ * of that access shape.  Supported (waves, rows_per_wave): (8, 17), (8, 9),
+ * (4, 1); others, null pointers, rows < 0, nx < 1 or more than 65535 row
+ * blocks give KFP_EINVAL before any device work.  Asynchronous on `stream`.
+ */
+kfp_status kfp_tile_probe(const double *U, const double *F, double *V, int64_t rows, int32_t nx,
+                          int32_t waves, int32_t rows_per_wave, void *stream);
+
 /* ======================================================================
  * Learned initial interface traces.
  *

@@ -20,6 +20,7 @@ from .binding import (  # noqa: F401
     SWRStats,
     axpy_f32,
     bw_probe,
+    tile_probe,
     cast_f64_f32,
     column_stats,
     destandardize,

@@ -119,6 +119,7 @@ def load_library():
     lib.kfp_get_config.argtypes = [G, i32, i32, i32, pi, pi, pi]
     lib.kfp_subdomain_rows.argtypes = [G, i32, i32, i32, ctypes.POINTER(ctypes.c_int64)]
     lib.kfp_bw_probe.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.kfp_tile_probe.argtypes = [vp, vp, vp, ctypes.c_int64, i32, i32, i32, vp]
     lib.kfp_last_error.restype = ctypes.c_char_p
     lib.kfp_last_error.argtypes = []
     lib.kfp_release_workspace.restype = None
@@ -129,7 +130,8 @@ def load_library():
                  "kfp_set_config", "kfp_set_launch", "kfp_get_launch", "kfp_set_pipeline",
                  "kfp_set_launch_tiles", "kfp_get_launch_tiles", "kfp_tune_batch",
                  "kfp_get_batch_launch",
-                 "kfp_set_ordering", "kfp_set_scheme", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe"):
+                 "kfp_set_ordering", "kfp_set_scheme", "kfp_set_kernel_timing", "kfp_get_config", "kfp_subdomain_rows", "kfp_bw_probe",
+                 "kfp_tile_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -511,6 +513,23 @@ def bw_probe(src, dst, stream=None):
                                        ctypes.c_void_p(dst.data_ptr()), int(nbytes),
                                        _stream(stream)))
     return nbytes
+
+
+def tile_probe(U, F, V, waves=8, rows_per_wave=17, stream=None):
+    """V = U + F/2 over [rows][nx] FP64 tensors in the tile shape of the
+    register march at one step per launch (kfp_tile_probe).  Returns the
+    bytes moved (three streams of 8 B per cell)."""
+    import torch
+
+    for name, t in (("U", U), ("F", F), ("V", V)):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+            raise ValueError(f"{name} must be a contiguous 2-D float64 CUDA tensor")
+    if tuple(F.shape) != tuple(U.shape) or tuple(V.shape) != tuple(U.shape):
+        raise ValueError("U, F and V must have the same shape")
+    rows, nx = int(U.shape[0]), int(U.shape[1])
+    _check(load_library().kfp_tile_probe(_ptr(U), _ptr(F), _ptr(V), rows, nx, int(waves),
+                                         int(rows_per_wave), _stream(stream)))
+    return 24 * rows * nx
 
 
 def set_pipeline(inflight=-1):

@@ -22,6 +22,7 @@
 #include "../../include/kfpswr.h"
 #include "../../include/kfpswr_debug.h"
 #include "kfp_internal.h"
+#include "probe_internal.h"
 
 namespace kfp {
 
@@ -2973,6 +2974,20 @@ kfp_status kfp_bw_probe(const void *src, void *dst, int64_t bytes, void *stream)
   g_err.clear();
   if (!src || !dst || bytes < 0 || bytes % 16) return fail(KFP_EINVAL, "bad probe arguments");
   HIP_TRY(launch_bw_probe(src, dst, (size_t)bytes, (hipStream_t)stream));
+  return KFP_OK;
+}
+
+kfp_status kfp_tile_probe(const double *U, const double *F, double *V, int64_t rows, int32_t nx,
+                          int32_t waves, int32_t rows_per_wave, void *stream) {
+  g_err.clear();
+  if (!U || !F || !V || rows < 0 || nx < 1)
+    return fail(KFP_EINVAL, "bad tile probe arguments");
+  if (!tile_probe_supported(waves, rows_per_wave))
+    return fail(KFP_EINVAL, "tile probe shape (%d, %d) is not built", (int)waves,
+                (int)rows_per_wave);
+  if ((rows + (int64_t)waves * rows_per_wave - 1) / ((int64_t)waves * rows_per_wave) > 65535)
+    return fail(KFP_EINVAL, "tile probe: too many rows");
+  HIP_TRY(launch_tile_probe(U, F, V, (long)rows, nx, waves, rows_per_wave, (hipStream_t)stream));
   return KFP_OK;
 }
 

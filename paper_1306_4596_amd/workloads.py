@@ -4,6 +4,7 @@
     python -m paper_1306_4596_amd.workloads medium [--configs 8,17,16] [--scheme fd|fem]
     python -m paper_1306_4596_amd.workloads large [--iters 1] [--configs 8,17,16 8,17,8] [--scheme fd|fem]
     python -m paper_1306_4596_amd.workloads large-solve
+    python -m paper_1306_4596_amd.workloads tile-probe
 
 `batch`: uneven instances (Nx, Nv from {128, 256, 512, 1024}, J from
 {2, 4, 8, 16}, Nt = 512, T = 0.25, overlap 2, Robin p = 4) solved together
@@ -13,7 +14,9 @@ solved to 1e-10 from zero traces.  `large`: Nx = Nv = 4096, Nt = 8192, T = 1, J 
 overlap 2, Robin p = 8, a fixed number of SWR iterations, once per launch
 configuration.  `large-solve`: the same shape solved to 1e-10 from zero
 traces and from the u0 extension, in the parallel and the red-black order,
-and on 4 time windows.  `--scheme fem` runs `batch` or `large` with the
+and on 4 time windows.  `tile-probe`: the streaming rate of the tile
+shapes of the register march (kfp_tile_probe) over [4188][4096] arrays,
+beside the copy kernel.  `--scheme fem` runs `batch` or `large` with the
 paper's finite-element discretisation instead of finite differences.  Each
 prints one JSON line per measurement.  Inputs are seeded and synthetic
 (inputs.py).
@@ -142,6 +145,36 @@ def run_medium(configs, reps: int = 2):
     kb.set_config(0)
 
 
+def run_tile_probe(rows: int = 4188, nx: int = 4096, reps: int = 20):
+    """Streaming rate of kfp_tile_probe (state and source read, state
+    written) over [rows][nx] FP64 arrays in each built tile shape, against
+    the library's copy kernel over 1 GiB."""
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(0)
+    U = torch.rand((rows, nx), generator=g, device="cuda", dtype=torch.float64)
+    F = torch.rand((rows, nx), generator=g, device="cuda", dtype=torch.float64)
+    V = torch.empty_like(U)
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def rate(fn):
+        fn()
+        e0.record()
+        for _ in range(reps):
+            nbytes = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) * 1e-3 / reps) / 1e12
+
+    out = {"workload": f"tile probe [{rows}][{nx}] FP64, {reps} launches each",
+           "copy_1GiB_TBps": round(rate(lambda: 2 * kb.bw_probe(a, b)), 3)}
+    for waves, rpw in ((8, 17), (8, 9), (4, 1)):
+        out[f"{waves}x{rpw}_TBps"] = round(rate(lambda: kb.tile_probe(U, F, V, waves, rpw)), 3)
+    print(json.dumps(out), flush=True)
+
+
 def learned_large_guess(n_train, coarse=None, log=None):
     """The learned guess of the 4096 x 4096 workload: a modal guess trained
     on `n_train` coarse solves (seeds 1..n_train; the workload's own seed 0
@@ -209,7 +242,7 @@ def run_large_solve(learned_train=0, orders=(0, 1)):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "medium", "large", "large-solve"])
+    ap.add_argument("which", choices=["batch", "medium", "large", "large-solve", "tile-probe"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--order", type=int, default=0, choices=[0, 1])
@@ -230,6 +263,8 @@ def main():
     kb.set_scheme(_SCHEME[0])
     if a.which == "batch":
         run_batch(a.n, order=a.order, tune=a.tune)
+    elif a.which == "tile-probe":
+        run_tile_probe()
     elif a.which == "medium":
         run_medium([tuple(int(x) for x in c.split(",")) for c in a.configs] or [None])
     elif a.which == "large-solve":

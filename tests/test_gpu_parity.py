@@ -785,3 +785,19 @@ def test_bw_probe_copies(nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[:n], src[:n])
     assert bool((dst[n:] == -7.0).all())
+
+
+@pytest.mark.parametrize("waves,rpw", [(8, 17), (8, 9), (4, 1)])
+def test_tile_probe_writes_u_plus_half_f(waves, rpw):
+    """The tile-shaped streaming probe: V = U + F/2 (one FMA, exact here for
+    these binary fractions), a ragged last tile and row block, nothing
+    written past the last row."""
+    rows, nx = 300, 200
+    U = torch.arange(rows * nx, dtype=torch.float64, device="cuda").reshape(rows, nx) * 0.25
+    F = torch.full((rows, nx), 3.0, dtype=torch.float64, device="cuda")
+    Vb = torch.full((rows + 1, nx), -7.0, dtype=torch.float64, device="cuda")
+    V = Vb[:rows]
+    assert kfp.tile_probe(U, F, V, waves, rpw) == 24 * rows * nx
+    torch.cuda.synchronize()
+    assert torch.equal(V, U + 1.5)
+    assert bool((Vb[rows] == -7.0).all())

@@ -87,6 +87,12 @@ def test_mono_and_batch_invalid_arguments(lib):
     assert lib.kfp_set_config(4, 24, 40) == binding.KFP_EINVAL
     assert lib.kfp_set_config(4, 48, 4) == binding.KFP_EINVAL
     assert lib.kfp_bw_probe(FAKE, FAKE, 10, None) == binding.KFP_EINVAL
+    # the tile probe: unbuilt shapes, null pointers and empty widths are refused
+    assert lib.kfp_tile_probe(FAKE, FAKE, FAKE, 10, 64, 8, 16, None) == binding.KFP_EINVAL
+    assert lib.kfp_tile_probe(None, FAKE, FAKE, 10, 64, 8, 17, None) == binding.KFP_EINVAL
+    assert lib.kfp_tile_probe(FAKE, FAKE, FAKE, 10, 0, 8, 17, None) == binding.KFP_EINVAL
+    assert lib.kfp_tile_probe(FAKE, FAKE, FAKE, -1, 64, 8, 17, None) == binding.KFP_EINVAL
+    assert lib.kfp_tile_probe(FAKE, FAKE, FAKE, 8 * 17 * 65536, 64, 8, 17, None) == binding.KFP_EINVAL
 
 
 def test_static_mono_validation(lib):
