@@ -190,7 +190,7 @@ def learned_large_guess(n_train, coarse=None, log=None):
     return g, rec
 
 
-def run_large_solve(learned_train=0, orders=(0, 1)):
+def run_large_solve(learned_train=0, orders=(0, 1), windows=(4,)):
     import torch
 
     nx = nv = 4096
@@ -206,20 +206,22 @@ def run_large_solve(learned_train=0, orders=(0, 1)):
     coef0 = inputs.coefficients(0)
     for order in orders:
         kb.set_ordering(order)
-        for guess in (("zero", "u0") + (("learned",) if g else ()) + ("windows4",) +
-                      (("windows4_learned",) if g else ())):
+        starts = (("zero", "u0") + (("learned",) if g else ()) +
+                  tuple(f"windows{w}" for w in windows) + (("windows4_learned",) if g else ()))
+        for guess in starts:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if guess == "windows4":
-                _, its, st = kb.swr_solve_windows(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
-                                                  max_iter=400, n_windows=4, guess=True)
-                iters = its
-            elif guess == "windows4_learned":  # each window from its levels of the guess
+            if guess == "windows4_learned":  # each window from its levels of the guess
                 lam0 = g.predict(coef0, nt, nx)[0]
                 _, its, st = kb.swr_solve_windows(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
                                                   max_iter=400, n_windows=4, lambda_init=lam0)
                 iters = its
                 del lam0
+            elif guess.startswith("windows"):  # each window from its start state's extension
+                _, its, st = kb.swr_solve_windows(U0, F, T, nt, J, o, kb.ROBIN, p=p, tol=1e-10,
+                                                  max_iter=400, n_windows=int(guess[7:]),
+                                                  guess=True)
+                iters = its
             else:
                 if guess == "learned":
                     lam0 = g.predict(coef0, nt, nx)[0]
@@ -254,6 +256,8 @@ def main():
                     help="large-solve: also solve from a learned guess trained on this many "
                          "coarse solves")
     ap.add_argument("--orders", default="0,1", help="large-solve: solve orders (0 parallel, 1 red-black)")
+    ap.add_argument("--windows", default="4",
+                    help="large-solve: time-window counts of the windowed solves (comma-separated)")
     ap.add_argument("--configs", nargs="*", default=[],
                     help="launch configurations waves,seg,steps[,groups[,tiles]] (default: "
                          "the library's choice)")
@@ -268,7 +272,8 @@ def main():
     elif a.which == "medium":
         run_medium([tuple(int(x) for x in c.split(",")) for c in a.configs] or [None])
     elif a.which == "large-solve":
-        run_large_solve(a.learned_train, tuple(int(x) for x in a.orders.split(",") if x))
+        run_large_solve(a.learned_train, tuple(int(x) for x in a.orders.split(",") if x),
+                        tuple(int(x) for x in a.windows.split(",") if x))
     else:
         cfgs = [tuple(int(x) for x in c.split(",")) for c in a.configs] or [None]
         run_large(a.iters, cfgs)
