@@ -72,19 +72,19 @@ N_WINDOWS = 32
 # VALU instructions per launch.  Valid only for the kernel sources and
 # launch configuration they were measured on; otherwise reported as null.
 COUNTERS = {
-    "config": (8, 17, 12, 1, 1),  # waves, seg_max, steps, groups, tiles
+    "config": (8, 17, 15, 1, 1),  # waves, seg_max, steps, groups, tiles
     "sha256": {
         "paper_1306_4596_amd/csrc/swr_kernels.hip":
             "6dbe1688911197c71c63445bfa425e057fccaca2dd0c94b16e34a61795571af5",
         "paper_1306_4596_amd/csrc/kfp_internal.h":
             "377909b348878a0016731dddcb594c302ce5fcad78a799486bec46768e69b477",
     },
-    # mean over the 683 dispatches of one iteration: FETCH_SIZE 154698.56 KiB
-    # (x 1048576 / 524302.38, its reading for 1 GiB copied), WRITE_SIZE
-    # 205866.34 KiB (x 1048576 / 1048576.0)
-    "read_bytes": 154698.564 * 1024 * (1048576.0 / 524302.375),
-    "write_bytes": 205866.341 * 1024 * (1048576.0 / 1048576.0),
-    "valu_insts": 51296461.27,  # SQ_INSTS_VALU per dispatch (wave instructions)
+    # mean over the 547 dispatches of one iteration: FETCH_SIZE 162705.71 KiB
+    # (x 1048576 / 524302.22, its reading for 1 GiB copied), WRITE_SIZE
+    # 224562.33 KiB (x 1048576 / 1048576.0)
+    "read_bytes": 162705.706 * 1024 * (1048576.0 / 524302.219),
+    "write_bytes": 224562.331 * 1024 * (1048576.0 / 1048576.0),
+    "valu_insts": 66870632.75,  # SQ_INSTS_VALU per dispatch (wave instructions)
 }
 
 
