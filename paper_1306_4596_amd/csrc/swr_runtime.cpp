@@ -2493,7 +2493,7 @@ static kfp_status tune_impl(const kfp_grid *g, int J, int o, int tr, double p, i
       for (int tl : {1, 2})
         for (int sm = 2; sm <= 33; ++sm)
           if (march_fits(geo.n_max, w, sm) && fd_config_supported(w, sm, tl)) {
-            for (int k : {4, 8, 12, 16}) cands.push_back(Config{w, sm, k, 1, tl});
+            for (int k : {4, 8, 12, 15, 16}) cands.push_back(Config{w, sm, k, 1, tl});
             break;
           }
   {
@@ -2591,7 +2591,7 @@ static kfp_status tune_batch_impl(int n, const kfp_instance *in, int iters, int 
         for (int tl : {1, 2})
           for (int sm = 2; sm <= 33; ++sm)
             if (march_fits(n_max, w, sm) && fd_config_supported(w, sm, tl)) {
-              for (int k : {8, 12, 16}) cands.push_back(Config{w, sm, k, 1, tl});
+              for (int k : {8, 12, 15, 16}) cands.push_back(Config{w, sm, k, 1, tl});
               break;
             }
     for (int w : kWaves) {
