@@ -30,7 +30,9 @@ same J, overlap, T and p, carried to the full grid through the traces'
 x-Fourier coefficients), and in red-black order on 32 time windows (each
 from the extension of its start state); the HBM fraction of the same march
 kernel taking one time step per launch (the fused step kernel in its
-streaming form, `fused_one_step`); the
+streaming form, `fused_one_step`), also against the copy kernel and against
+a plain streaming kernel of the same tile shape (`kfp_tile_probe`); the
+1024 x 1024, J = 8 solve to 1e-10 for p = 1, 2, 4, 8, 16 (`p_sweep_1024`); the
 time to 1e-10 with and without learned initial traces on the learned-traces
 shape (256 x 256, Nt = 512, J = 4), the network trained here on a bounded
 number of seeded solves (`learned_guess`); and the oracle on the host cores
