@@ -321,9 +321,9 @@ def learned_leg(ntrain, neval):
     learned-traces shape (256 x 256, Nt = 512, T = 0.5, J = 4, overlap 2,
     Robin p = 4).  Two networks (BF16 weights, FP32 accumulation) are
     trained here, by the library's kernels, on `ntrain` solves the batch
-    path generates: three linear stages (`linear`), and a linear stage, the
-    3 x 512 GELU network on its remainder and a linear refinement stage
-    (`gelu`).  Every held-out seed is then solved from zero traces, from the
+    path generates: three linear stages (`linear`), and the same three
+    linear stages followed by the 3 x 512 GELU network fitted to their
+    remainder (`gelu`).  Every held-out seed is then solved from zero traces, from the
     u0 extension and from each network's traces (wall time of each call,
     inference included)."""
     import torch
@@ -337,12 +337,13 @@ def learned_leg(ntrain, neval):
     t_gen = time.perf_counter() - t0
     nets, t_train = {}, {}
     # a few thousand optimiser steps per linear stage (the map is linear and
-    # well determined by ~1000 solves), 40 epochs for the GELU stage
+    # well determined by ~1000 solves); the GELU network last, on what the
+    # three linear stages leave, 10 epochs at a lower rate
     for name, kw, lrs, eps in (("linear", dict(depth=0, refine=2), [1e-3, 3e-3, 3e-3],
                                 [200, 200, 200]),
-                               ("gelu", dict(hidden=512, depth=3, skip=False, refine=1,
-                                             lead_linear=True), [1e-3, 1e-3, 3e-3],
-                                [200, 40, 200])):
+                               ("gelu", dict(hidden=512, depth=3, skip=False, refine=2,
+                                             gelu_last=True), [1e-3, 3e-3, 3e-3, 3e-4],
+                                [200, 200, 200, 10])):
         g = learned.LearnedGuess(shape, **kw)
         t0 = time.perf_counter()
         g.fit(X, Y.clone() if name == "linear" else Y, batch=64, lrs=lrs, stage_epochs=eps)
@@ -357,7 +358,7 @@ def learned_leg(ntrain, neval):
             "max_rel_l2_vs_zero_guess")
     out = {"workload": "SWR 256x256 Nt=512 T=0.5 J=4 overlap=2 Robin p=4, tol 1e-10",
            "networks": {"linear": "three BF16 linear stages",
-                        "gelu": "linear stage + 3x512 GELU stage + linear refinement, BF16"},
+                        "gelu": "three linear stages + 3x512 GELU stage on their remainder, BF16"},
            "train_seeds": ntrain, "eval_seeds": neval, "generate_s": round(t_gen, 2),
            "train_s": t_train}
     for k in ("zero", "u0", "linear", "gelu"):

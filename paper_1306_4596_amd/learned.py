@@ -155,20 +155,31 @@ class LearnedGuess:
     skip); each further stage is a linear network (depth 0) fitted to what
     the stages before it leave over, in its own standardised units.  Two
     BF16 stages reach far below the ~2^-9 relative rounding floor of one.
+    With gelu_last the linear stages (one plus `refine`) come first and the
+    (depth x hidden) network is fitted last, to what they leave: placed
+    earlier, it fits the training set's remainder so closely that the
+    linear refinements after it have nothing left to learn that carries to
+    unseen inputs.
     lambda^0 = base + sum over stages of (mean_k + std_k * net_k(x))."""
 
     def __init__(self, shape: Shape, hidden=512, depth=3, seed=0, base="u0", skip=True,
-                 refine=0, nets=None, lead_linear=False, n_out=None):
+                 refine=0, nets=None, lead_linear=False, n_out=None, gelu_last=False):
         self.shape = shape
         self.base = base
         self.n_out = n_out or shape.n_out
         if nets is None:
             no = self.n_out
-            # lead_linear: a linear stage first, the (depth x hidden) network
-            # fitted to what it leaves over, then the refinement stages
-            nets = [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 100)] if lead_linear else []
-            nets += [kb.MLP(N_FEAT, hidden, depth, no, seed=seed, skip=skip)]
-            nets += [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 1 + k) for k in range(refine)]
+            if gelu_last:
+                nets = [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 100)]
+                nets += [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 1 + k) for k in range(refine)]
+                nets += [kb.MLP(N_FEAT, hidden, depth, no, seed=seed, skip=skip)]
+            else:
+                # lead_linear: a linear stage first, the (depth x hidden)
+                # network fitted to what it leaves over, then the refinement
+                # stages
+                nets = [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 100)] if lead_linear else []
+                nets += [kb.MLP(N_FEAT, hidden, depth, no, seed=seed, skip=skip)]
+                nets += [kb.MLP(N_FEAT, 8, 0, no, seed=seed + 1 + k) for k in range(refine)]
         self.nets = nets
         self.means = []
         self.stds = []
@@ -448,6 +459,8 @@ VARIANTS = {
     # linear stage, the 3 x 512 GELU network on its remainder, a linear
     # refinement stage
     "linear_mlp": (3, 512, False, 1, True),
+    # three linear stages, then the 3 x 512 GELU network on their remainder
+    "linear_x3_mlp": (3, 512, False, 2, False, True),
 }
 
 
@@ -516,20 +529,25 @@ def main():
     guesses, train = {}, {}
     names = [v for v in args.variants.split(",") if v]
     for k, name in enumerate(names):
-        depth, hidden, skip, refine, lead = VARIANTS[name]
+        depth, hidden, skip, refine, lead, *more = VARIANTS[name]
+        last = bool(more and more[0])
         Y = Y0 if k == len(names) - 1 else Y0.clone()
         g = LearnedGuess(shape, hidden=hidden, depth=depth, base=args.base, skip=skip,
-                         refine=refine, lead_linear=lead)
+                         refine=refine, lead_linear=lead, gelu_last=last)
         t0 = time.time()
         # a leading linear stage and the network after it train at --lr, the
-        # refinement stages at --refine-lr
-        lrs = [args.lr, args.lr] + [args.refine_lr] * refine if lead else None
+        # refinement stages at --refine-lr; with the network last, the linear
+        # stages as usual and the network at a tenth of --lr
+        if last:
+            lrs = [args.lr] + [args.refine_lr] * refine + [0.1 * args.lr]
+        else:
+            lrs = [args.lr, args.lr] + [args.refine_lr] * refine if lead else None
         hist = g.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
                      refine_lr=args.refine_lr, lrs=lrs)
         torch.cuda.synchronize()
         train[name] = {"seconds": time.time() - t0, "loss_history": hist,
                        "depth": depth, "hidden": hidden, "skip": skip, "refine": refine,
-                       "lead_linear": lead}
+                       "lead_linear": lead, "gelu_last": last}
         del Y
         if args.save:
             g.save(f"{args.save}.{name}")
