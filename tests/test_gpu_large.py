@@ -61,23 +61,26 @@ def test_largest_shape_two_iterations(scheme):
 FULL = dict(nx=4096, nv=4096, nt=8192, T=1.0, J=32, o=2, p=8.0)
 
 
-def test_full_size_translation_in_x_bitwise():
+@pytest.mark.parametrize("scheme", [oracle.FD, oracle.FEM])
+def test_full_size_translation_in_x_bitwise(scheme):
     """The benchmark workload at full size (4096 x 4096, Nt = 8192, T = 1,
     J = 32, overlap 2, Robin p = 8, seed 0) in the launch configuration the
-    benchmark times.  The scheme is the same in every column (periodic in
-    x, coefficients depending on v only), so rolling u0 and f by k columns
+    benchmark times (finite differences; the paper's finite elements in
+    theirs).  The scheme is the same in every column (periodic in x,
+    coefficients depending on v only), so rolling u0 and f by k columns
     rolls the iterate, every trace plane and nothing else: two iterations
     with k = 37 (not a multiple of any tile width, so every column changes
     tile, halo position and wrap) must match the rolled ones bit for bit."""
     c = FULL
     nx, nv, nt, T, J, o, p = c["nx"], c["nv"], c["nt"], c["T"], c["J"], c["o"], c["p"]
+    kfp.set_scheme(kfp.FEM if scheme == oracle.FEM else kfp.FD)
     cfg = kfp.get_launch_tiles(nx, nv, nt, T, J, o, kfp.ROBIN)
-    assert cfg == (8, 17, 15, 1, 1), cfg
+    assert cfg == ((8, 17, 8, 1, 0) if scheme == oracle.FEM else (8, 17, 15, 1, 1)), cfg
     u0, f = inputs.random_fields(0, nx, nv)
     U0, F = torch.from_numpy(u0).cuda(), torch.from_numpy(f).cuda()
     del u0, f
     k = 37
-    print("full size, two iterations ...", flush=True)
+    print(f"full size, scheme {scheme}, two iterations ...", flush=True)
     uT, lam, st = kfp.swr_solve(U0, F, T, nt, J, o, kfp.ROBIN, p=p, tol=1e-300, max_iter=2,
                                 want_lambda=True)
     print("full size, rolled fields, two iterations ...", flush=True)
